@@ -1,0 +1,1220 @@
+/*
+ * PMKLC CPU oracle — TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 implementation of what the PMKLC hot path computes,
+ * written from the paper (arXiv 2507.12805).  Only the tests, the smoke
+ * check and the bench's CPU-baseline leg may load it; the GPU library never
+ * does, and the two share no code, header, table or helper.
+ *
+ * What each part follows:
+ *   - (s,k)-mer encoding: Sec. 4.1 and Fig. 3 (bases A0 C1 G2 T3, window k,
+ *     step s, first base most significant: "CGG" -> 26).
+ *   - Online learning loop: Sec. 2 steps (1)-(4): context of t symbols,
+ *     model -> distribution -> entropy coder, then cross-entropy and
+ *     back-propagation; the first t symbols use a uniform distribution.
+ *   - Mixer: Eq. (1), P = softmax(alpha*(S0*Lu + S1*Lr) + (1-alpha)*S2*Lm),
+ *     alpha self-learned (Sec. 4.2.5).
+ *   - Loss: Eq. (2), cross-entropy against the one-hot target (Sec. 4.2.6).
+ *   - Blocks and step-wise model passing: Sec. 4.3 (even partition; after
+ *     5% of a block the dynamic model seeds the next block).
+ *   - Entropy coder: the paper names an entropy encoder only (Sec. 4); this
+ *     oracle uses the integer arithmetic coder of Witten, Neal and Cleary
+ *     (CACM 30(6), 1987) with 32-bit registers and a 2^16 frequency total.
+ * Readings of points the paper leaves open (segment layout of a block,
+ * MLP model shape, frequency quantisation, container layout) are the ones
+ * listed with the design notes of this repository; each is restated at the
+ * function that implements it.
+ *
+ * Parity status: every function here is pinned by a test against something
+ * other than itself (brute force, closed forms, torch FP64 autograd, finite
+ * differences, zlib), except the learned-model compression ratio on the
+ * synthetic data, which the paper cannot pin (its datasets are not
+ * available): parity unpinned for that value.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_OK 0
+#define OR_ERR_ARG -1
+#define OR_ERR_BASE -2
+#define OR_ERR_SMALL -3
+#define OR_ERR_CORRUPT -4
+#define OR_ERR_MODEL -5
+#define OR_ERR_NOMEM -8
+
+#define TOTAL_BITS 16
+#define TOTAL (1u << TOTAL_BITS)
+
+/* ------------------------------------------------------------------ */
+/* Bases and (s,k)-mers (Sec. 4.1, Fig. 3)                             */
+/* ------------------------------------------------------------------ */
+
+/* A->0 C->1 G->2 T->3; N -> 4; anything else -> 255. */
+static int base_code(uint8_t c) {
+    switch (c) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    case 'N': return 4;
+    default: return 255;
+    }
+}
+static const uint8_t LETTER[4] = {'A', 'C', 'G', 'T'};
+
+/* Number of (s,k)-mers in n bases: windows start at 0, s, 2s, ... and must
+ * fit entirely (a window never runs past the end). */
+uint64_t or_skmer_count(uint64_t n, int s, int k) {
+    if (s < 1 || k < 1 || n < (uint64_t)k) return 0;
+    return (n - (uint64_t)k) / (uint64_t)s + 1;
+}
+
+/* Sec. 4.1: e_j = sum_{m<k} 4^(k-1-m) * b_{j*s+m}.  Input is ASCII ACGT only
+ * (the paper's GD alphabet); anything else is an error. */
+int or_encode_skmer(const uint8_t *ascii, uint64_t n, int s, int k, uint8_t *tokens,
+                    uint64_t cap, uint64_t *n_tokens) {
+    if (s < 1 || k < 1 || k > 4 || s > k) return OR_ERR_ARG;
+    for (uint64_t i = 0; i < n; i++)
+        if (base_code(ascii[i]) > 3) return OR_ERR_BASE;
+    uint64_t l = or_skmer_count(n, s, k);
+    if (n_tokens) *n_tokens = l;
+    if (l > cap) return OR_ERR_SMALL;
+    for (uint64_t j = 0; j < l; j++) {
+        uint32_t e = 0;
+        for (int m = 0; m < k; m++) {
+            uint32_t pw = 1;
+            for (int q = 0; q < k - 1 - m; q++) pw *= 4;
+            e += pw * (uint32_t)base_code(ascii[j * (uint64_t)s + (uint64_t)m]);
+        }
+        tokens[j] = (uint8_t)e;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Frequency quantisation: probabilities -> integer CDF, total 2^16.     */
+/* The paper only says that the mixed probability drives the entropy     */
+/* coder.  Reading: f_v = 1 + floor(p_v * (2^16 - V)), the residual      */
+/* 2^16 - sum f goes to the most probable symbol (lowest index on ties). */
+/* ------------------------------------------------------------------ */
+void or_quantise(const double *p, int V, uint32_t *cum) {
+    int64_t sum = 0;
+    int amax = 0;
+    int64_t f[256];
+    for (int v = 0; v < V; v++) {
+        f[v] = 1 + (int64_t)floor(p[v] * (double)(TOTAL - (uint32_t)V));
+        sum += f[v];
+        if (p[v] > p[amax]) amax = v;
+    }
+    f[amax] += (int64_t)TOTAL - sum;
+    cum[0] = 0;
+    for (int v = 0; v < V; v++) cum[v + 1] = cum[v] + (uint32_t)f[v];
+}
+
+/* ------------------------------------------------------------------ */
+/* Arithmetic coder (Witten-Neal-Cleary 1987), 32-bit, total 2^16.      */
+/* Bits are written most significant first within each byte.           */
+/* ------------------------------------------------------------------ */
+#define HALF 0x80000000u
+#define QUARTER 0x40000000u
+
+typedef struct {
+    uint32_t low, high;
+    uint64_t pending;
+    uint8_t *buf;
+    uint64_t cap;   /* bytes */
+    uint64_t nbits;
+} or_enc;
+
+static int enc_bit(or_enc *e, int bit) {
+    uint64_t byte = e->nbits >> 3;
+    if (byte >= e->cap) {
+        uint64_t nc = e->cap ? 2 * e->cap : 64;
+        uint8_t *nb = (uint8_t *)realloc(e->buf, nc);
+        if (!nb) return OR_ERR_NOMEM;
+        memset(nb + e->cap, 0, nc - e->cap);
+        e->buf = nb;
+        e->cap = nc;
+    }
+    if (bit) e->buf[byte] |= (uint8_t)(0x80u >> (e->nbits & 7));
+    e->nbits++;
+    return OR_OK;
+}
+static int enc_bit_plus_pending(or_enc *e, int bit) {
+    int rc = enc_bit(e, bit);
+    for (; rc == OR_OK && e->pending; e->pending--) rc = enc_bit(e, !bit);
+    return rc;
+}
+static void enc_init(or_enc *e) { memset(e, 0, sizeof *e); e->high = 0xFFFFFFFFu; }
+
+static int enc_symbol(or_enc *e, uint32_t cum_lo, uint32_t cum_hi) {
+    uint64_t r = (uint64_t)e->high - e->low + 1;
+    uint32_t lo = e->low;
+    e->high = lo + (uint32_t)((r * cum_hi) >> TOTAL_BITS) - 1;
+    e->low = lo + (uint32_t)((r * cum_lo) >> TOTAL_BITS);
+    for (;;) {
+        int rc = OR_OK;
+        if (e->high < HALF) {
+            rc = enc_bit_plus_pending(e, 0);
+        } else if (e->low >= HALF) {
+            rc = enc_bit_plus_pending(e, 1);
+            e->low -= HALF;
+            e->high -= HALF;
+        } else if (e->low >= QUARTER && e->high < 3u * QUARTER) {
+            e->pending++;
+            e->low -= QUARTER;
+            e->high -= QUARTER;
+        } else {
+            break;
+        }
+        if (rc) return rc;
+        e->low <<= 1;
+        e->high = (e->high << 1) | 1u;
+    }
+    return OR_OK;
+}
+static int enc_finish(or_enc *e) {
+    e->pending++;
+    return enc_bit_plus_pending(e, e->low < QUARTER ? 0 : 1);
+}
+
+typedef struct {
+    uint32_t low, high, value;
+    const uint8_t *buf;
+    uint64_t nbytes, pos;
+} or_dec;
+
+static int dec_bit(or_dec *d) {
+    uint64_t byte = d->pos >> 3;
+    int b = byte < d->nbytes ? (d->buf[byte] >> (7 - (d->pos & 7))) & 1 : 0;
+    d->pos++;
+    return b;
+}
+static void dec_init(or_dec *d, const uint8_t *buf, uint64_t nbytes) {
+    d->low = 0;
+    d->high = 0xFFFFFFFFu;
+    d->buf = buf;
+    d->nbytes = nbytes;
+    d->pos = 0;
+    d->value = 0;
+    for (int i = 0; i < 32; i++) d->value = (d->value << 1) | (uint32_t)dec_bit(d);
+}
+/* cum has V+1 entries. Returns the symbol. */
+static int dec_symbol(or_dec *d, const uint32_t *cum, int V) {
+    uint64_t r = (uint64_t)d->high - d->low + 1;
+    uint32_t lo = d->low;
+    /* largest s with lo + floor(r*cum[s]/T) <= value */
+    int a = 0, b = V; /* invariant: bound(a) <= value < bound(b) */
+    while (b - a > 1) {
+        int m = (a + b) / 2;
+        uint32_t bm = lo + (uint32_t)((r * cum[m]) >> TOTAL_BITS);
+        if (bm <= d->value) a = m; else b = m;
+    }
+    int s = a;
+    d->high = lo + (uint32_t)((r * cum[s + 1]) >> TOTAL_BITS) - 1;
+    d->low = lo + (uint32_t)((r * cum[s]) >> TOTAL_BITS);
+    for (;;) {
+        if (d->high < HALF) {
+        } else if (d->low >= HALF) {
+            d->low -= HALF;
+            d->high -= HALF;
+            d->value -= HALF;
+        } else if (d->low >= QUARTER && d->high < 3u * QUARTER) {
+            d->low -= QUARTER;
+            d->high -= QUARTER;
+            d->value -= QUARTER;
+        } else {
+            break;
+        }
+        d->low <<= 1;
+        d->high = (d->high << 1) | 1u;
+        d->value = (d->value << 1) | (uint32_t)dec_bit(d);
+    }
+    return s;
+}
+
+/* Standalone coder entry points (used by the coder pins). */
+int or_wnc_encode(const uint32_t *cum_lo, const uint32_t *cum_hi, uint64_t m, uint8_t **out,
+                  uint64_t *nbits) {
+    or_enc e;
+    enc_init(&e);
+    for (uint64_t i = 0; i < m; i++) {
+        if (cum_hi[i] <= cum_lo[i] || cum_hi[i] > TOTAL) { free(e.buf); return OR_ERR_ARG; }
+        int rc = enc_symbol(&e, cum_lo[i], cum_hi[i]);
+        if (rc) { free(e.buf); return rc; }
+    }
+    int rc = enc_finish(&e);
+    if (rc) { free(e.buf); return rc; }
+    *out = e.buf;
+    *nbits = e.nbits;
+    return OR_OK;
+}
+/* cdfs: m rows of V+1 cumulative counts. */
+int or_wnc_decode(const uint8_t *in, uint64_t nbytes, const uint32_t *cdfs, int V, uint64_t m,
+                  uint32_t *symbols) {
+    or_dec d;
+    dec_init(&d, in, nbytes);
+    for (uint64_t i = 0; i < m; i++) symbols[i] = (uint32_t)dec_symbol(&d, cdfs + i * (uint64_t)(V + 1), V);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* CRC-32 (IEEE 802.3 polynomial, reflected; same value as zlib.crc32).  */
+/* ------------------------------------------------------------------ */
+uint32_t or_crc32(const uint8_t *p, uint64_t n) {
+    uint32_t c = 0xFFFFFFFFu;
+    for (uint64_t i = 0; i < n; i++) {
+        c ^= p[i];
+        for (int b = 0; b < 8; b++) c = (c >> 1) ^ (0xEDB88320u & (0u - (c & 1u)));
+    }
+    return c ^ 0xFFFFFFFFu;
+}
+
+/* ------------------------------------------------------------------ */
+/* Model: embedding + MLP (the configuration's reading of DM / SPuM).    */
+/* Flat parameter order: Emb[V][E], then per layer l: W_l[d_l][d_{l+1}]   */
+/* (input-major) and b_l[d_{l+1}]; d_0 = t*E, d_{nh+1} = V.              */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int V, E, t, D, nh;
+    int dims[6];
+    uint64_t off_emb, off_W[5], off_b[5], n;
+} or_shape;
+
+static int shape_init(or_shape *sh, int k, int t, int E, int nh, const int32_t *hidden) {
+    if (k < 1 || k > 4 || t < 1 || E < 1 || nh < 0 || nh > 4) return OR_ERR_ARG;
+    sh->V = 1 << (2 * k);
+    sh->E = E;
+    sh->t = t;
+    sh->D = t * E;
+    sh->nh = nh;
+    sh->dims[0] = sh->D;
+    for (int l = 0; l < nh; l++) {
+        if (hidden[l] < 1) return OR_ERR_ARG;
+        sh->dims[l + 1] = hidden[l];
+    }
+    sh->dims[nh + 1] = sh->V;
+    uint64_t off = 0;
+    sh->off_emb = off;
+    off += (uint64_t)sh->V * E;
+    for (int l = 0; l <= nh; l++) {
+        sh->off_W[l] = off;
+        off += (uint64_t)sh->dims[l] * sh->dims[l + 1];
+        sh->off_b[l] = off;
+        off += (uint64_t)sh->dims[l + 1];
+    }
+    sh->n = off;
+    return OR_OK;
+}
+
+uint64_t or_param_count(int k, int t, int E, int nh, const int32_t *hidden) {
+    or_shape sh;
+    if (shape_init(&sh, k, t, E, nh, hidden)) return 0;
+    return sh.n;
+}
+
+/* SplitMix64 (Steele, Lea, Flood 2014) in counter form: the i-th draw is
+ * mix(seed + (i+1) * golden_gamma). */
+static uint64_t splitmix_at(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Initial weights: u = top 24 bits / 2^24, w = fp32((2u - 1) * a) with
+ * a = 1 for the embedding and a = 1/sqrt(fan_in) for every linear weight
+ * and bias.  The oracle keeps the FP64 value of the FP32 number. */
+static void init_params(const or_shape *sh, uint64_t seed, double *w) {
+    for (uint64_t i = 0; i < sh->n; i++) {
+        double a = 1.0;
+        for (int l = 0; l <= sh->nh; l++)
+            if (i >= sh->off_W[l] && i < sh->off_b[l] + (uint64_t)sh->dims[l + 1])
+                a = 1.0 / sqrt((double)sh->dims[l]);
+        double u = (double)(splitmix_at(seed, i) >> 40) * (1.0 / 16777216.0);
+        w[i] = (double)(float)((2.0 * u - 1.0) * a);
+    }
+}
+int or_init_params(int k, int t, int E, int nh, const int32_t *hidden, uint64_t seed, double *w) {
+    or_shape sh;
+    int rc = shape_init(&sh, k, t, E, nh, hidden);
+    if (rc) return rc;
+    init_params(&sh, seed, w);
+    return OR_OK;
+}
+
+/* Forward of one row: x = concat(Emb[ctx_0..ctx_{t-1}]) (oldest first),
+ * h_{l+1} = ReLU(h_l W_l + b_l), logits = h_nh W_nh + b_nh.
+ * acts must hold sum_{l<=nh} dims[l] doubles (layer inputs), logits V. */
+static void mlp_forward_row(const or_shape *sh, const double *w, const uint8_t *ctx, double *acts,
+                            double *logits) {
+    double *x = acts;
+    for (int p = 0; p < sh->t; p++)
+        for (int e = 0; e < sh->E; e++) x[p * sh->E + e] = w[sh->off_emb + (uint64_t)ctx[p] * sh->E + e];
+    double *in = acts;
+    for (int l = 0; l <= sh->nh; l++) {
+        int di = sh->dims[l], dn = sh->dims[l + 1];
+        double *out = (l == sh->nh) ? logits : in + di;
+        const double *W = w + sh->off_W[l];
+        const double *b = w + sh->off_b[l];
+        for (int o = 0; o < dn; o++) out[o] = b[o];
+        for (int d = 0; d < di; d++) {
+            double xv = in[d];
+            const double *Wr = W + (uint64_t)d * dn;
+            for (int o = 0; o < dn; o++) out[o] += xv * Wr[o];
+        }
+        if (l < sh->nh)
+            for (int o = 0; o < dn; o++) out[o] = out[o] > 0.0 ? out[o] : 0.0;
+        in = out;
+    }
+}
+static uint64_t acts_len(const or_shape *sh) {
+    uint64_t s = 0;
+    for (int l = 0; l <= sh->nh; l++) s += (uint64_t)sh->dims[l];
+    return s;
+}
+
+/* Backward of one row given dlogits; accumulates into grad (same layout as
+ * the parameters).  ReLU'(0) = 0. Uses the pre-update weights. */
+static void mlp_backward_row(const or_shape *sh, const double *w, const uint8_t *ctx, const double *acts,
+                             const double *dlogits, double *grad, double *scratch) {
+    /* scratch: two buffers of max dim */
+    int maxd = 0;
+    for (int l = 0; l <= sh->nh + 1; l++) if (sh->dims[l] > maxd) maxd = sh->dims[l];
+    double *dout = scratch, *din = scratch + maxd;
+    memcpy(dout, dlogits, sizeof(double) * (size_t)sh->V);
+    /* layer inputs: layer l input starts at acts + sum_{q<l} dims[q] */
+    uint64_t in_off[6];
+    in_off[0] = 0;
+    for (int l = 1; l <= sh->nh; l++) in_off[l] = in_off[l - 1] + (uint64_t)sh->dims[l - 1];
+    for (int l = sh->nh; l >= 0; l--) {
+        int di = sh->dims[l], dn = sh->dims[l + 1];
+        const double *in = acts + in_off[l];
+        const double *W = w + sh->off_W[l];
+        double *gW = grad + sh->off_W[l];
+        double *gb = grad + sh->off_b[l];
+        for (int o = 0; o < dn; o++) gb[o] += dout[o];
+        for (int d = 0; d < di; d++) {
+            double s = 0.0;
+            const double *Wr = W + (uint64_t)d * dn;
+            double *gWr = gW + (uint64_t)d * dn;
+            for (int o = 0; o < dn; o++) {
+                gWr[o] += in[d] * dout[o];
+                s += Wr[o] * dout[o];
+            }
+            din[d] = s;
+        }
+        if (l > 0) /* through the ReLU that produced this layer's input */
+            for (int d = 0; d < di; d++) din[d] = in[d] > 0.0 ? din[d] : 0.0;
+        double *tmp = dout; dout = din; din = tmp;
+    }
+    /* dout now holds dL/dx (t*E); scatter into the embedding rows */
+    for (int p = 0; p < sh->t; p++)
+        for (int e = 0; e < sh->E; e++) grad[sh->off_emb + (uint64_t)ctx[p] * sh->E + e] += dout[p * sh->E + e];
+}
+
+/* One learning step over bs rows (Sec. 2 steps (3)-(4); Eq. (1), Eq. (2)).
+ *   ctx: bs x t tokens (oldest first), tgt: bs targets.
+ *   w: DM parameters; ws: static parameters or NULL (S0 = 0).
+ *   a_alpha: pre-sigmoid mixing parameter (used only when ws != NULL).
+ * Outputs: P (bs x V, may be NULL), grad (n params, zeroed here, may be
+ * NULL = forward only), *g_alpha, *loss = mean cross-entropy in nats.
+ * The per-step loss is the mean over the bs rows (Eq. (2) summed over one
+ * step, divided by bs). */
+static int step_grad(const or_shape *sh, const double *w, const double *ws, double a_alpha, const uint8_t *ctx,
+                     const uint8_t *tgt, int bs, double *P, double *grad, double *g_alpha, double *loss) {
+    int V = sh->V;
+    uint64_t al = acts_len(sh);
+    int maxd = 0;
+    for (int l = 0; l <= sh->nh + 1; l++) if (sh->dims[l] > maxd) maxd = sh->dims[l];
+    double *acts = (double *)malloc(sizeof(double) * (al + al + 4 * (uint64_t)V + 2 * (uint64_t)maxd));
+    if (!acts) return OR_ERR_NOMEM;
+    double *acts_s = acts + al;
+    double *lm = acts_s + al, *lu = lm + V, *z = lu + V, *dz = z + V, *scratch = dz + V;
+    double alpha = 1.0 / (1.0 + exp(-a_alpha));
+    if (grad) memset(grad, 0, sizeof(double) * sh->n);
+    double ga = 0.0, L = 0.0;
+    for (int j = 0; j < bs; j++) {
+        const uint8_t *c = ctx + (uint64_t)j * sh->t;
+        mlp_forward_row(sh, w, c, acts, lm);
+        if (ws) {
+            mlp_forward_row(sh, ws, c, acts_s, lu);
+            for (int v = 0; v < V; v++) z[v] = alpha * lu[v] + (1.0 - alpha) * lm[v];
+        } else {
+            for (int v = 0; v < V; v++) z[v] = lm[v];
+        }
+        double mx = z[0];
+        for (int v = 1; v < V; v++) if (z[v] > mx) mx = z[v];
+        double sum = 0.0;
+        for (int v = 0; v < V; v++) sum += exp(z[v] - mx);
+        double *Pj = P ? P + (uint64_t)j * V : dz;
+        for (int v = 0; v < V; v++) Pj[v] = exp(z[v] - mx) / sum;
+        if (loss) L += -log(Pj[tgt[j]]);
+        if (grad) {
+            for (int v = 0; v < V; v++) dz[v] = (Pj[v] - (v == tgt[j] ? 1.0 : 0.0)) / (double)bs;
+            if (ws) {
+                for (int v = 0; v < V; v++) ga += dz[v] * (lu[v] - lm[v]);
+                for (int v = 0; v < V; v++) dz[v] *= (1.0 - alpha);
+            }
+            mlp_backward_row(sh, w, c, acts, dz, grad, scratch);
+        }
+    }
+    if (g_alpha) *g_alpha = ws ? ga * alpha * (1.0 - alpha) : 0.0;
+    if (loss) *loss = L / (double)bs;
+    free(acts);
+    return OR_OK;
+}
+
+/* Exported single step for the forward/backward pins. */
+int or_step(int k, int t, int E, int nh, const int32_t *hidden, const double *w, const double *ws,
+            double a_alpha, const uint8_t *ctx, const uint8_t *tgt, int bs, double *P, double *grad,
+            double *g_alpha, double *loss) {
+    or_shape sh;
+    int rc = shape_init(&sh, k, t, E, nh, hidden);
+    if (rc) return rc;
+    return step_grad(&sh, w, ws, a_alpha, ctx, tgt, bs, P, grad, g_alpha, loss);
+}
+
+/* ------------------------------------------------------------------ */
+/* Optimisers.  The paper says only "back-propagation" (Sec. 2 (4)); the  */
+/* configurations fix plain SGD, or Adam with bias correction.           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int kind; /* 0 SGD, 1 Adam */
+    double lr, b1, b2, eps;
+} or_opt;
+
+static void opt_apply(const or_opt *o, double *w, const double *g, double *m, double *v, uint64_t n, uint64_t tau) {
+    if (o->kind == 0) {
+        for (uint64_t i = 0; i < n; i++) w[i] -= o->lr * g[i];
+    } else {
+        double c1 = 1.0 - pow(o->b1, (double)tau), c2 = 1.0 - pow(o->b2, (double)tau);
+        for (uint64_t i = 0; i < n; i++) {
+            m[i] = o->b1 * m[i] + (1.0 - o->b1) * g[i];
+            v[i] = o->b2 * v[i] + (1.0 - o->b2) * g[i] * g[i];
+            double mh = m[i] / c1, vh = v[i] / c2;
+            w[i] -= o->lr * mh / (sqrt(vh) + o->eps);
+        }
+    }
+}
+/* Exported for the optimiser pins (tau = 1-based update count). */
+void or_opt_step(int kind, double lr, double b1, double b2, double eps, double *w, const double *g, double *m,
+                 double *v, uint64_t n, uint64_t tau) {
+    or_opt o = {kind, lr, b1, b2, eps};
+    opt_apply(&o, w, g, m, v, n, tau);
+}
+
+/* ------------------------------------------------------------------ */
+/* Configuration and block plan.                                       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t s, k, t, bs, E, nh;
+    int32_t hidden[4];
+    int32_t optimizer;
+    float lr, beta1, beta2, eps;
+    int32_t selector;        /* bit0: static public model, bit2: dynamic model; 0 = uniform */
+    uint32_t smp_ppm;        /* step-wise model passing point, parts per million of the block's steps; 0 = off */
+    uint64_t seed;
+    int32_t n_blocks;
+    const uint64_t *block_len; /* raw bytes per block, or NULL = equal split */
+    int32_t n_files;
+    const uint64_t *file_blocks; /* blocks per file, or NULL = one file */
+    const double *init_override; /* test hook: initial DM parameters (+ a_alpha) of every chain head, or NULL */
+} or_config;
+
+#define SEL_SPUM 1
+#define SEL_SPRM 2
+#define SEL_DM 4
+
+typedef struct {
+    uint64_t raw_off, raw_len;
+    /* derived */
+    uint64_t n_runs;
+    uint64_t *run_start, *run_len; /* block-relative raw coordinates */
+    uint64_t nb;                    /* stripped bases */
+    uint8_t *codes;                 /* stripped bases 0..3 */
+    uint64_t l, L, rem, tail;
+    uint8_t *tok;
+    int has_pred;                   /* previous block of the same file exists */
+    /* coded output */
+    uint8_t **seg_buf;
+    uint64_t *seg_bytes;
+    uint8_t *extras;
+    uint64_t extras_bytes;
+    double *snap;                   /* parameters (+ alpha) after the SMP step */
+} or_block;
+
+static int model_on(const or_config *c) { return (c->selector & SEL_DM) != 0; }
+static int static_on(const or_config *c) { return (c->selector & SEL_SPUM) != 0; }
+
+static uint64_t smp_steps(uint32_t ppm, uint64_t L) {
+    return (uint64_t)(((unsigned __int128)ppm * L + 999999u) / 1000000u);
+}
+
+/* Run one block's learning/coding loop.  Sec. 2: for each target, the
+ * model predicts from the previous t tokens, the coder codes it, then the
+ * cross-entropy gradient updates the model.  Reading of the batch size bs:
+ * the block's first bs*L tokens form bs contiguous segments of L tokens;
+ * step i predicts token i of every segment at once (one row per segment)
+ * and makes one update with the mean loss of those bs rows.  The first t
+ * tokens of every segment are coded with the uniform distribution and do
+ * not train the model.
+ *   mode 0: encode (blk->tok known), mode 1: decode (fills blk->tok).
+ *   init: initial DM parameters followed by a_alpha.
+ *   probe: optional callback storage for P of sampled steps (trace API). */
+typedef struct {
+    uint64_t stop;        /* run only this many steps (0 = all) */
+    double *P_out;        /* (n_steps_probe) x bs x V, or NULL */
+    const uint64_t *steps;
+    uint64_t n_steps;
+    double *w_final;      /* n params + 1, or NULL */
+    double *loss_out;     /* L values, or NULL */
+} or_probe;
+
+static int run_block(const or_config *cfg, const or_shape *sh, const double *ws, or_block *blk, const double *init,
+                     int mode, const uint8_t *stream_region, or_probe *probe) {
+    int V = sh->V, bs = cfg->bs, t = cfg->t;
+    uint64_t L = blk->L, n = sh->n;
+    uint32_t ucum[257];
+    for (int v = 0; v <= V; v++) ucum[v] = (uint32_t)((uint64_t)v * TOTAL / (uint64_t)V);
+    or_opt opt = {cfg->optimizer, (double)cfg->lr, (double)cfg->beta1, (double)cfg->beta2, (double)cfg->eps};
+    int rc = OR_OK;
+    double *w = NULL, *g = NULL, *m = NULL, *vv = NULL, *P = NULL;
+    uint8_t *ctx = NULL, *tgt = NULL;
+    uint32_t *cum = NULL;
+    or_enc *enc = NULL;
+    or_dec *dec = NULL;
+    if (L == 0) {
+        if (blk->snap && init) memcpy(blk->snap, init, sizeof(double) * (n + 1));
+        return OR_OK;
+    }
+    w = (double *)malloc(sizeof(double) * (n + 1));
+    g = (double *)malloc(sizeof(double) * (n + 1));
+    m = (double *)calloc(n + 1, sizeof(double));
+    vv = (double *)calloc(n + 1, sizeof(double));
+    P = (double *)malloc(sizeof(double) * (uint64_t)bs * V);
+    ctx = (uint8_t *)malloc((uint64_t)bs * t);
+    tgt = (uint8_t *)malloc((uint64_t)bs);
+    cum = (uint32_t *)malloc(sizeof(uint32_t) * (uint64_t)(V + 1) * bs);
+    if (mode == 0) enc = (or_enc *)calloc((uint64_t)bs, sizeof(or_enc));
+    else dec = (or_dec *)calloc((uint64_t)bs, sizeof(or_dec));
+    if (!w || !g || !m || !vv || !P || !ctx || !tgt || !cum || (!enc && !dec)) { rc = OR_ERR_NOMEM; goto done; }
+    if (init) memcpy(w, init, sizeof(double) * (n + 1));
+    else memset(w, 0, sizeof(double) * (n + 1));
+    if (mode == 0) {
+        for (int j = 0; j < bs; j++) enc_init(&enc[j]);
+    } else {
+        const uint8_t *p = stream_region;
+        for (int j = 0; j < bs; j++) {
+            dec_init(&dec[j], p, blk->seg_bytes[j]);
+            p += blk->seg_bytes[j];
+        }
+    }
+    uint64_t S = smp_steps(cfg->smp_ppm, L);
+    if (blk->snap && S == 0) memcpy(blk->snap, w, sizeof(double) * (n + 1));
+    uint64_t tau = 0, probe_i = 0;
+    int use_model = model_on(cfg);
+    uint64_t L_run = (probe && probe->stop && probe->stop < L) ? probe->stop : L;
+    for (uint64_t i = 0; i < L_run; i++) {
+        int uniform = !use_model || i < (uint64_t)t;
+        double loss = 0.0, ga = 0.0;
+        if (!uniform) {
+            for (int j = 0; j < bs; j++)
+                for (int p = 0; p < t; p++) ctx[(uint64_t)j * t + p] = blk->tok[(uint64_t)j * L + i - (uint64_t)t + (uint64_t)p];
+            /* forward (and, for encode, the gradient needs the target: do the
+             * forward first, code, then the backward with the known target) */
+            rc = step_grad(sh, w, ws, w[n], ctx, tgt, bs, P, NULL, NULL, NULL);
+            if (rc) goto done;
+            for (int j = 0; j < bs; j++) or_quantise(P + (uint64_t)j * V, V, cum + (uint64_t)j * (V + 1));
+        }
+        for (int j = 0; j < bs; j++) {
+            const uint32_t *c = uniform ? ucum : cum + (uint64_t)j * (V + 1);
+            uint64_t pos = (uint64_t)j * L + i;
+            if (mode == 0) {
+                int e = blk->tok[pos];
+                rc = enc_symbol(&enc[j], c[e], c[e + 1]);
+                if (rc) goto done;
+            } else {
+                blk->tok[pos] = (uint8_t)dec_symbol(&dec[j], c, V);
+            }
+            tgt[j] = blk->tok[pos];
+        }
+        if (!uniform) {
+            rc = step_grad(sh, w, ws, w[n], ctx, tgt, bs, P, g, &ga, &loss);
+            if (rc) goto done;
+            g[n] = ga;
+            tau++;
+            opt_apply(&opt, w, g, m, vv, ws ? n + 1 : n, tau);
+            if (probe && probe->loss_out) probe->loss_out[i] = loss;
+        }
+        if (probe && probe->P_out && probe_i < probe->n_steps && probe->steps[probe_i] == i) {
+            double *dst = probe->P_out + probe_i * (uint64_t)bs * V;
+            if (uniform)
+                for (uint64_t q = 0; q < (uint64_t)bs * V; q++) dst[q] = 1.0 / V;
+            else
+                memcpy(dst, P, sizeof(double) * (uint64_t)bs * V);
+            probe_i++;
+        }
+        if (blk->snap && i + 1 == S) memcpy(blk->snap, w, sizeof(double) * (n + 1));
+    }
+    if (mode == 0) {
+        blk->seg_buf = (uint8_t **)calloc((uint64_t)bs, sizeof(uint8_t *));
+        blk->seg_bytes = (uint64_t *)calloc((uint64_t)bs, sizeof(uint64_t));
+        if (!blk->seg_buf || !blk->seg_bytes) { rc = OR_ERR_NOMEM; goto done; }
+        for (int j = 0; j < bs; j++) {
+            rc = enc_finish(&enc[j]);
+            if (rc) goto done;
+            blk->seg_buf[j] = enc[j].buf;
+            blk->seg_bytes[j] = (enc[j].nbits + 7) / 8;
+            enc[j].buf = NULL;
+        }
+    }
+    if (probe && probe->w_final) memcpy(probe->w_final, w, sizeof(double) * (n + 1));
+done:
+    if (enc) { for (int j = 0; j < bs; j++) free(enc[j].buf); free(enc); }
+    free(dec);
+    free(w); free(g); free(m); free(vv); free(P); free(ctx); free(tgt); free(cum);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Container (compressed binary file).  All integers little-endian;     */
+/* varints are unsigned LEB128.                                         */
+/* ------------------------------------------------------------------ */
+typedef struct { uint8_t *p; uint64_t n, cap; int err; } or_buf;
+
+static void buf_put(or_buf *b, const void *src, uint64_t n) {
+    if (b->err) return;
+    if (b->n + n > b->cap) {
+        uint64_t nc = b->cap ? b->cap : 256;
+        while (nc < b->n + n) nc *= 2;
+        uint8_t *np = (uint8_t *)realloc(b->p, nc);
+        if (!np) { b->err = 1; return; }
+        b->p = np;
+        b->cap = nc;
+    }
+    memcpy(b->p + b->n, src, n);
+    b->n += n;
+}
+static void put_le(or_buf *b, uint64_t v, int nbytes) {
+    uint8_t t[8];
+    for (int i = 0; i < nbytes; i++) t[i] = (uint8_t)(v >> (8 * i));
+    buf_put(b, t, (uint64_t)nbytes);
+}
+static void put_varint(or_buf *b, uint64_t v) {
+    uint8_t t[10];
+    int n = 0;
+    do {
+        uint8_t c = v & 0x7F;
+        v >>= 7;
+        t[n++] = (uint8_t)(c | (v ? 0x80 : 0));
+    } while (v);
+    buf_put(b, t, (uint64_t)n);
+}
+static void put_f32(or_buf *b, float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    put_le(b, u, 4);
+}
+
+typedef struct { const uint8_t *p; uint64_t n, pos; int err; } or_rd;
+static uint64_t get_le(or_rd *r, int nbytes) {
+    if (r->pos + (uint64_t)nbytes > r->n) { r->err = 1; return 0; }
+    uint64_t v = 0;
+    for (int i = 0; i < nbytes; i++) v |= (uint64_t)r->p[r->pos + i] << (8 * i);
+    r->pos += (uint64_t)nbytes;
+    return v;
+}
+static uint64_t get_varint(or_rd *r) {
+    uint64_t v = 0;
+    for (int sh = 0; sh < 64; sh += 7) {
+        if (r->pos >= r->n) { r->err = 1; return 0; }
+        uint8_t c = r->p[r->pos++];
+        v |= (uint64_t)(c & 0x7F) << sh;
+        if (!(c & 0x80)) return v;
+    }
+    r->err = 1;
+    return 0;
+}
+static float get_f32(or_rd *r) {
+    uint32_t u = (uint32_t)get_le(r, 4);
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+#define PATH_ORACLE 0
+#define PATH_UNIFORM 255
+
+static int cfg_check(const or_config *c, or_shape *sh) {
+    if (c->s < 1 || c->k < 1 || c->k > 4 || c->s > c->k) return OR_ERR_ARG;
+    if (c->bs < 1 || c->bs > 65535 || c->t < 1 || c->t > 65535 || c->E < 1 || c->E > 65535) return OR_ERR_ARG;
+    if (c->n_blocks < 1) return OR_ERR_ARG;
+    if (c->selector & ~(SEL_SPUM | SEL_DM)) return OR_ERR_ARG;
+    if (c->selector && !(c->selector & SEL_DM)) return OR_ERR_ARG;
+    if (c->smp_ppm > 1000000u) return OR_ERR_ARG;
+    return shape_init(sh, c->k, c->t, c->E, c->nh, c->hidden);
+}
+
+/* Split the N runs out of a block and map ACGT to 0..3. */
+static int block_strip(const uint8_t *raw, or_block *b) {
+    uint64_t runs = 0, nn = 0;
+    for (uint64_t i = 0; i < b->raw_len; i++) {
+        int c = base_code(raw[i]);
+        if (c == 255) return OR_ERR_BASE;
+        if (c == 4) {
+            nn++;
+            if (i == 0 || raw[i - 1] != 'N') runs++;
+        }
+    }
+    b->n_runs = runs;
+    b->nb = b->raw_len - nn;
+    b->run_start = (uint64_t *)malloc(sizeof(uint64_t) * (runs + 1));
+    b->run_len = (uint64_t *)malloc(sizeof(uint64_t) * (runs + 1));
+    b->codes = (uint8_t *)malloc(b->nb + 1);
+    if (!b->run_start || !b->run_len || !b->codes) return OR_ERR_NOMEM;
+    uint64_t r = 0, q = 0;
+    for (uint64_t i = 0; i < b->raw_len; i++) {
+        int c = base_code(raw[i]);
+        if (c == 4) {
+            if (i == 0 || raw[i - 1] != 'N') { b->run_start[r] = i; b->run_len[r] = 0; r++; }
+            b->run_len[r - 1]++;
+        } else {
+            b->codes[q++] = (uint8_t)c;
+        }
+    }
+    return OR_OK;
+}
+
+static void block_geometry(const or_config *c, or_block *b) {
+    b->l = or_skmer_count(b->nb, c->s, c->k);
+    b->L = b->l / (uint64_t)c->bs;
+    b->rem = b->l - b->L * (uint64_t)c->bs;
+    uint64_t covered = b->l ? (b->l - 1) * (uint64_t)c->s + (uint64_t)c->k : 0;
+    b->tail = b->nb - covered;
+}
+
+static void block_free(or_block *b, int bs) {
+    free(b->run_start); free(b->run_len); free(b->codes); free(b->tok); free(b->extras); free(b->snap);
+    if (b->seg_buf) for (int j = 0; j < bs; j++) free(b->seg_buf[j]);
+    free(b->seg_buf); free(b->seg_bytes);
+}
+
+/* Extras: tail bases (2 bits each) then remainder tokens (2k bits each),
+ * most significant bit first. */
+static void pack_bits(uint8_t *dst, uint64_t *bitpos, uint32_t val, int nbits) {
+    for (int i = nbits - 1; i >= 0; i--) {
+        if ((val >> i) & 1u) dst[*bitpos >> 3] |= (uint8_t)(0x80u >> (*bitpos & 7));
+        (*bitpos)++;
+    }
+}
+static uint32_t unpack_bits(const uint8_t *src, uint64_t *bitpos, int nbits) {
+    uint32_t v = 0;
+    for (int i = 0; i < nbits; i++) {
+        v = (v << 1) | (uint32_t)((src[*bitpos >> 3] >> (7 - (*bitpos & 7))) & 1u);
+        (*bitpos)++;
+    }
+    return v;
+}
+
+static int plan_blocks(const or_config *cfg, uint64_t n, or_block **out) {
+    int nb = cfg->n_blocks;
+    or_block *B = (or_block *)calloc((uint64_t)nb, sizeof(or_block));
+    if (!B) return OR_ERR_NOMEM;
+    uint64_t off = 0;
+    for (int b = 0; b < nb; b++) {
+        uint64_t len;
+        if (cfg->block_len) len = cfg->block_len[b];
+        else len = (b == nb - 1) ? n - (n / (uint64_t)nb) * (uint64_t)(nb - 1) : n / (uint64_t)nb;
+        B[b].raw_off = off;
+        B[b].raw_len = len;
+        off += len;
+    }
+    if (off != n) { free(B); return OR_ERR_ARG; }
+    /* file membership: a block has an SMP predecessor when the previous
+     * block belongs to the same file */
+    int fb = 0, f = 0, left = cfg->file_blocks ? (int)cfg->file_blocks[0] : nb;
+    int nf = cfg->file_blocks ? cfg->n_files : 1;
+    uint64_t tot = 0;
+    for (int q = 0; q < nf; q++) tot += cfg->file_blocks ? cfg->file_blocks[q] : (uint64_t)nb;
+    if (tot != (uint64_t)nb) { free(B); return OR_ERR_ARG; }
+    for (int b = 0; b < nb; b++) {
+        while (left == 0 && f + 1 < nf) { f++; left = (int)cfg->file_blocks[f]; fb = 0; }
+        B[b].has_pred = fb > 0;
+        fb++;
+        left--;
+    }
+    *out = B;
+    return OR_OK;
+}
+
+static void write_header(or_buf *o, const or_config *cfg, int path, uint32_t static_crc, uint64_t n) {
+    const uint8_t magic[4] = {'P', 'M', 'K', 'C'};
+    buf_put(o, magic, 4);
+    put_le(o, 1, 1);
+    put_le(o, (uint64_t)path, 1);
+    put_le(o, (uint64_t)cfg->s, 1);
+    put_le(o, (uint64_t)cfg->k, 1);
+    put_le(o, (uint64_t)cfg->t, 2);
+    put_le(o, (uint64_t)cfg->bs, 2);
+    put_le(o, (uint64_t)cfg->E, 2);
+    put_le(o, (uint64_t)cfg->nh, 1);
+    put_le(o, (uint64_t)cfg->optimizer, 1);
+    for (int l = 0; l < 4; l++) put_le(o, l < cfg->nh ? (uint64_t)cfg->hidden[l] : 0, 2);
+    put_f32(o, cfg->lr);
+    put_f32(o, cfg->beta1);
+    put_f32(o, cfg->beta2);
+    put_f32(o, cfg->eps);
+    put_le(o, (uint64_t)cfg->selector, 1);
+    put_le(o, 0, 3);
+    put_le(o, cfg->smp_ppm, 4);
+    put_le(o, cfg->seed, 8);
+    put_le(o, static_crc, 4);
+    put_le(o, 0, 4);
+    put_le(o, n, 8);
+    put_le(o, (uint64_t)cfg->n_blocks, 4);
+    put_le(o, (uint64_t)(cfg->file_blocks ? cfg->n_files : 1), 4);
+}
+
+/* Process all blocks: DM-only or static+DM, SMP chains within files.
+ * Blocks without SMP run in parallel (OpenMP); with SMP each file's chain
+ * runs in order (block b+1 starts from block b's snapshot). */
+static int process_blocks(const or_config *cfg, const or_shape *sh, const double *ws, or_block *B, int mode,
+                          const uint8_t *const *stream_ptr) {
+    int nb = cfg->n_blocks;
+    uint64_t n = sh->n;
+    double *init = (double *)malloc(sizeof(double) * (n + 1));
+    if (!init) return OR_ERR_NOMEM;
+    if (cfg->init_override) {
+        memcpy(init, cfg->init_override, sizeof(double) * (n + 1));
+    } else {
+        init_params(sh, cfg->seed, init);
+        init[n] = 0.0; /* a_alpha: alpha = sigmoid(0) = 1/2 */
+    }
+    int smp = cfg->smp_ppm > 0 && model_on(cfg);
+    int rc_all = OR_OK;
+    if (!smp) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int b = 0; b < nb; b++) {
+            int rc = run_block(cfg, sh, ws, &B[b], init, mode, stream_ptr ? stream_ptr[b] : NULL, NULL);
+            if (rc) {
+#pragma omp critical
+                rc_all = rc;
+            }
+        }
+    } else {
+        /* chain heads */
+        int nheads = 0;
+        for (int b = 0; b < nb; b++) nheads += !B[b].has_pred;
+        int *heads = (int *)malloc(sizeof(int) * (uint64_t)(nheads + 1));
+        if (!heads) { free(init); return OR_ERR_NOMEM; }
+        for (int b = 0, q = 0; b < nb; b++) if (!B[b].has_pred) heads[q++] = b;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int h = 0; h < nheads; h++) {
+            const double *cur = init;
+            for (int b = heads[h]; b < nb && (b == heads[h] || B[b].has_pred); b++) {
+                B[b].snap = (double *)malloc(sizeof(double) * (n + 1));
+                int rc = B[b].snap ? run_block(cfg, sh, ws, &B[b], cur, mode, stream_ptr ? stream_ptr[b] : NULL, NULL)
+                                   : OR_ERR_NOMEM;
+                if (rc) {
+#pragma omp critical
+                    rc_all = rc;
+                    break;
+                }
+                cur = B[b].snap;
+            }
+        }
+        free(heads);
+    }
+    free(init);
+    return rc_all;
+}
+
+int or_compress(const or_config *cfg, const uint8_t *in, uint64_t n, const float *static_w, uint64_t static_len,
+                uint8_t **out, uint64_t *out_len) {
+    or_shape sh;
+    int rc = cfg_check(cfg, &sh);
+    if (rc) return rc;
+    double *ws = NULL;
+    uint32_t scrc = 0;
+    if (static_on(cfg)) {
+        if (!static_w || static_len != sh.n) return OR_ERR_MODEL;
+        ws = (double *)malloc(sizeof(double) * sh.n);
+        if (!ws) return OR_ERR_NOMEM;
+        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
+        scrc = or_crc32((const uint8_t *)static_w, sh.n * 4);
+    }
+    or_block *B = NULL;
+    rc = plan_blocks(cfg, n, &B);
+    if (rc) { free(ws); return rc; }
+    int nb = cfg->n_blocks;
+    for (int b = 0; b < nb && !rc; b++) {
+        rc = block_strip(in + B[b].raw_off, &B[b]);
+        if (rc) break;
+        block_geometry(cfg, &B[b]);
+        B[b].tok = (uint8_t *)malloc(B[b].l + 1);
+        if (!B[b].tok) { rc = OR_ERR_NOMEM; break; }
+        /* tokenise the stripped bases of this block (Sec. 4.1) */
+        for (uint64_t j = 0; j < B[b].l; j++) {
+            uint32_t e = 0;
+            for (int m = 0; m < cfg->k; m++) e = e * 4u + B[b].codes[j * (uint64_t)cfg->s + (uint64_t)m];
+            B[b].tok[j] = (uint8_t)e;
+        }
+    }
+    if (!rc) rc = process_blocks(cfg, &sh, ws, B, 0, NULL);
+    if (!rc) {
+        or_buf o = {0};
+        int path = cfg->selector ? PATH_ORACLE : PATH_UNIFORM;
+        write_header(&o, cfg, path, scrc, n);
+        if (cfg->file_blocks) for (int f = 0; f < cfg->n_files; f++) put_varint(&o, cfg->file_blocks[f]);
+        else put_varint(&o, (uint64_t)nb);
+        for (int b = 0; b < nb; b++) {
+            or_block *k = &B[b];
+            put_varint(&o, k->raw_len);
+            put_varint(&o, k->n_runs);
+            uint64_t prev_end = 0;
+            for (uint64_t r = 0; r < k->n_runs; r++) {
+                put_varint(&o, k->run_start[r] - prev_end);
+                put_varint(&o, k->run_len[r]);
+                prev_end = k->run_start[r] + k->run_len[r];
+            }
+            uint64_t bits = 2 * k->tail + 2 * (uint64_t)cfg->k * k->rem;
+            uint8_t *ex = (uint8_t *)calloc((bits + 7) / 8 + 1, 1);
+            if (!ex) { o.err = 1; break; }
+            uint64_t bp = 0;
+            for (uint64_t q = k->nb - k->tail; q < k->nb; q++) pack_bits(ex, &bp, k->codes[q], 2);
+            for (uint64_t q = k->L * (uint64_t)cfg->bs; q < k->l; q++) pack_bits(ex, &bp, k->tok[q], 2 * cfg->k);
+            buf_put(&o, ex, (bits + 7) / 8);
+            free(ex);
+            if (k->L > 0)
+                for (int j = 0; j < cfg->bs; j++) put_varint(&o, k->seg_bytes[j]);
+        }
+        for (int b = 0; b < nb; b++)
+            if (B[b].L > 0)
+                for (int j = 0; j < cfg->bs; j++) buf_put(&o, B[b].seg_buf[j], B[b].seg_bytes[j]);
+        if (o.err) { free(o.p); rc = OR_ERR_NOMEM; }
+        else { *out = o.p; *out_len = o.n; }
+    }
+    for (int b = 0; b < nb; b++) block_free(&B[b], cfg->bs);
+    free(B);
+    free(ws);
+    return rc;
+}
+
+int or_decompress(const uint8_t *cbf, uint64_t len, const float *static_w, uint64_t static_len, uint8_t **out,
+                  uint64_t *out_len) {
+    or_rd r = {cbf, len, 0, 0};
+    if (len < 80 || memcmp(cbf, "PMKC", 4) != 0) return OR_ERR_CORRUPT;
+    r.pos = 4;
+    if (get_le(&r, 1) != 1) return OR_ERR_CORRUPT;
+    int path = (int)get_le(&r, 1);
+    or_config c;
+    memset(&c, 0, sizeof c);
+    c.s = (int32_t)get_le(&r, 1);
+    c.k = (int32_t)get_le(&r, 1);
+    c.t = (int32_t)get_le(&r, 2);
+    c.bs = (int32_t)get_le(&r, 2);
+    c.E = (int32_t)get_le(&r, 2);
+    c.nh = (int32_t)get_le(&r, 1);
+    c.optimizer = (int32_t)get_le(&r, 1);
+    for (int l = 0; l < 4; l++) c.hidden[l] = (int32_t)get_le(&r, 2);
+    c.lr = get_f32(&r);
+    c.beta1 = get_f32(&r);
+    c.beta2 = get_f32(&r);
+    c.eps = get_f32(&r);
+    c.selector = (int32_t)get_le(&r, 1);
+    get_le(&r, 3);
+    c.smp_ppm = (uint32_t)get_le(&r, 4);
+    c.seed = get_le(&r, 8);
+    uint32_t scrc = (uint32_t)get_le(&r, 4);
+    get_le(&r, 4);
+    uint64_t n = get_le(&r, 8);
+    c.n_blocks = (int32_t)get_le(&r, 4);
+    c.n_files = (int32_t)get_le(&r, 4);
+    if (r.err) return OR_ERR_CORRUPT;
+    if (c.nh > 4) return OR_ERR_CORRUPT;
+    if (!(path == PATH_ORACLE && c.selector) && !(path == PATH_UNIFORM && !c.selector)) return OR_ERR_MODEL;
+    or_shape sh;
+    if (cfg_check(&c, &sh)) return OR_ERR_CORRUPT;
+    if (c.n_files < 1 || (uint64_t)c.n_files > len || (uint64_t)c.n_blocks * 2 > len) return OR_ERR_CORRUPT;
+    uint64_t *fblocks = (uint64_t *)malloc(sizeof(uint64_t) * (uint64_t)c.n_files);
+    uint64_t *blen = (uint64_t *)malloc(sizeof(uint64_t) * (uint64_t)c.n_blocks);
+    if (!fblocks || !blen) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
+    for (int f = 0; f < c.n_files; f++) fblocks[f] = get_varint(&r);
+    c.file_blocks = fblocks;
+    double *ws = NULL;
+    int rc = OR_OK;
+    if (static_on(&c)) {
+        if (!static_w || static_len != sh.n || or_crc32((const uint8_t *)static_w, sh.n * 4) != scrc) {
+            free(fblocks); free(blen);
+            return OR_ERR_MODEL;
+        }
+        ws = (double *)malloc(sizeof(double) * sh.n);
+        if (!ws) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
+        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
+    }
+    /* first pass over the block table to learn raw lengths */
+    or_block *B = (or_block *)calloc((uint64_t)c.n_blocks, sizeof(or_block));
+    const uint8_t **sp = (const uint8_t **)calloc((uint64_t)c.n_blocks, sizeof(uint8_t *));
+    uint8_t *dst = NULL;
+    if (!B || !sp) { rc = OR_ERR_NOMEM; goto fail; }
+    uint64_t off = 0;
+    for (int b = 0; b < c.n_blocks; b++) {
+        or_block *k = &B[b];
+        k->raw_off = off;
+        k->raw_len = get_varint(&r);
+        if (r.err || k->raw_len > n - off) { rc = OR_ERR_CORRUPT; goto fail; }
+        off += k->raw_len;
+        blen[b] = k->raw_len;
+        k->n_runs = get_varint(&r);
+        if (r.err || k->n_runs > k->raw_len) { rc = OR_ERR_CORRUPT; goto fail; }
+        k->run_start = (uint64_t *)malloc(sizeof(uint64_t) * (k->n_runs + 1));
+        k->run_len = (uint64_t *)malloc(sizeof(uint64_t) * (k->n_runs + 1));
+        if (!k->run_start || !k->run_len) { rc = OR_ERR_NOMEM; goto fail; }
+        uint64_t prev_end = 0, nn = 0;
+        for (uint64_t q = 0; q < k->n_runs; q++) {
+            uint64_t gap = get_varint(&r), rl = get_varint(&r);
+            k->run_start[q] = prev_end + gap;
+            k->run_len[q] = rl;
+            prev_end = k->run_start[q] + rl;
+            nn += rl;
+            if (r.err || prev_end > k->raw_len || rl == 0) { rc = OR_ERR_CORRUPT; goto fail; }
+        }
+        k->nb = k->raw_len - nn;
+        block_geometry(&c, k);
+        uint64_t bits = 2 * k->tail + 2 * (uint64_t)c.k * k->rem;
+        uint64_t eb = (bits + 7) / 8;
+        if (r.pos + eb > len) { rc = OR_ERR_CORRUPT; goto fail; }
+        k->extras = (uint8_t *)malloc(eb + 1);
+        k->codes = (uint8_t *)malloc(k->nb + 1);
+        k->tok = (uint8_t *)malloc(k->l + 1);
+        if (!k->extras || !k->codes || !k->tok) { rc = OR_ERR_NOMEM; goto fail; }
+        memcpy(k->extras, cbf + r.pos, eb);
+        k->extras_bytes = eb;
+        r.pos += eb;
+        if (k->L > 0) {
+            k->seg_bytes = (uint64_t *)calloc((uint64_t)c.bs, sizeof(uint64_t));
+            if (!k->seg_bytes) { rc = OR_ERR_NOMEM; goto fail; }
+            for (int j = 0; j < c.bs; j++) k->seg_bytes[j] = get_varint(&r);
+            if (r.err) { rc = OR_ERR_CORRUPT; goto fail; }
+        }
+    }
+    if (off != n) { rc = OR_ERR_CORRUPT; goto fail; }
+    {
+        uint64_t p = r.pos;
+        for (int b = 0; b < c.n_blocks; b++) {
+            sp[b] = cbf + p;
+            if (B[b].L > 0)
+                for (int j = 0; j < c.bs; j++) {
+                    if (B[b].seg_bytes[j] > len - p) { rc = OR_ERR_CORRUPT; goto fail; }
+                    p += B[b].seg_bytes[j];
+                }
+        }
+        if (p != len) { rc = OR_ERR_CORRUPT; goto fail; }
+    }
+    {
+        int fb_tot = 0;
+        for (int f = 0; f < c.n_files; f++) fb_tot += (int)fblocks[f];
+        if (fb_tot != c.n_blocks) { rc = OR_ERR_CORRUPT; goto fail; }
+        /* recompute SMP predecessor flags */
+        int f = 0, left = (int)fblocks[0], fbi = 0;
+        for (int b = 0; b < c.n_blocks; b++) {
+            while (left == 0 && f + 1 < c.n_files) { f++; left = (int)fblocks[f]; fbi = 0; }
+            B[b].has_pred = fbi > 0;
+            fbi++;
+            left--;
+        }
+    }
+    rc = process_blocks(&c, &sh, ws, B, 1, sp);
+    if (rc) goto fail;
+    dst = (uint8_t *)malloc(n + 1);
+    if (!dst) { rc = OR_ERR_NOMEM; goto fail; }
+    for (int b = 0; b < c.n_blocks; b++) {
+        or_block *k = &B[b];
+        /* remainder tokens and tail bases from the extras */
+        uint64_t bp = 0;
+        uint8_t tailc[8];
+        for (uint64_t q = 0; q < k->tail; q++) tailc[q] = (uint8_t)unpack_bits(k->extras, &bp, 2);
+        for (uint64_t q = k->L * (uint64_t)c.bs; q < k->l; q++) k->tok[q] = (uint8_t)unpack_bits(k->extras, &bp, 2 * c.k);
+        /* tokens -> bases: the first token gives k bases, each later one its last s */
+        uint64_t qb = 0;
+        for (uint64_t j = 0; j < k->l; j++) {
+            int from = j == 0 ? 0 : c.k - c.s;
+            for (int m = from; m < c.k; m++) k->codes[qb++] = (uint8_t)((k->tok[j] >> (2 * (c.k - 1 - m))) & 3u);
+        }
+        for (uint64_t q = 0; q < k->tail; q++) k->codes[qb++] = tailc[q];
+        /* re-insert N runs */
+        uint8_t *o = dst + k->raw_off;
+        uint64_t ri = 0, ci = 0;
+        for (uint64_t i = 0; i < k->raw_len; i++) {
+            if (ri < k->n_runs && i >= k->run_start[ri] && i < k->run_start[ri] + k->run_len[ri]) {
+                o[i] = 'N';
+                if (i + 1 == k->run_start[ri] + k->run_len[ri]) ri++;
+            } else {
+                o[i] = LETTER[k->codes[ci++]];
+            }
+        }
+    }
+    *out = dst;
+    *out_len = n;
+    dst = NULL;
+fail:
+    free(dst);
+    if (B) for (int b = 0; b < c.n_blocks; b++) block_free(&B[b], c.bs);
+    free(B);
+    free(sp);
+    free(ws);
+    free(fblocks);
+    free(blen);
+    return rc;
+}
+
+/* Trace of one block's compression: P for the requested steps (sorted),
+ * per-step loss, and the parameters (+ a_alpha) after `stop` steps (0 = all
+ * L steps).  The segment length L is that of the whole block.  The block is
+ * tokenised from ACGT-only input; init = seeded parameters, or `init`
+ * when not NULL (n params + a_alpha). */
+int or_trace_block(const or_config *cfg, const uint8_t *tokens, uint64_t l, const float *static_w,
+                   const double *init, uint64_t stop, const uint64_t *steps, uint64_t n_steps, double *P_out,
+                   double *loss_out, double *w_final) {
+    or_shape sh;
+    int rc = cfg_check(cfg, &sh);
+    if (rc) return rc;
+    double *ws = NULL;
+    if (static_on(cfg)) {
+        ws = (double *)malloc(sizeof(double) * sh.n);
+        if (!ws) return OR_ERR_NOMEM;
+        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
+    }
+    or_block blk;
+    memset(&blk, 0, sizeof blk);
+    blk.l = l;
+    blk.L = l / (uint64_t)cfg->bs;
+    blk.tok = (uint8_t *)malloc(l + 1);
+    double *w0 = (double *)malloc(sizeof(double) * (sh.n + 1));
+    if (!blk.tok || !w0) { free(blk.tok); free(w0); free(ws); return OR_ERR_NOMEM; }
+    memcpy(blk.tok, tokens, l);
+    if (init) memcpy(w0, init, sizeof(double) * (sh.n + 1));
+    else { init_params(&sh, cfg->seed, w0); w0[sh.n] = 0.0; }
+    or_probe pr = {stop, P_out, steps, n_steps, w_final, loss_out};
+    rc = run_block(cfg, &sh, ws, &blk, w0, 0, NULL, &pr);
+    block_free(&blk, cfg->bs);
+    free(w0);
+    free(ws);
+    return rc;
+}
+
+void or_free(void *p) { free(p); }
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
