@@ -1,0 +1,162 @@
+/*
+ * pmklc.h — C ABI of the MI355X PMKLC hot path (arXiv 2507.12805).
+ *
+ * The library compresses DNA (ASCII A/C/G/T/N) losslessly with the paper's
+ * pipeline: the GPU (s,k)-mer encoder (Sec. 4.1), per-block online-learned
+ * probability prediction (dynamic model, optionally mixed with a frozen
+ * static model by Eq. (1), trained every step on the cross-entropy of
+ * Eq. (2), Sec. 2 steps (1)-(4)), and an arithmetic coder driven by the
+ * quantised probabilities, over many data blocks at once (Sec. 4.3).
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers (HBM of the current HIP
+ *     device); *_host are host pointers. The caller owns and allocates every
+ *     buffer; the library keeps no pointer after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls are synchronous with respect to the host: they return after the
+ *     work they queued has finished (output sizes depend on the data).
+ *   - Every call returns a pmklc_status and never aborts. On
+ *     PMKLC_ERR_BUFFER_TOO_SMALL the size out-parameter receives the size
+ *     that is needed; on any other error out-parameters are left unchanged.
+ *   - Output bytes are a pure function of (input, configuration, static
+ *     weights, library version): they do not depend on the stream, buffer
+ *     addresses, launch shapes or timing.
+ *   - Layout of model parameters (flat FP32, little-endian): Emb[V][E], then
+ *     per linear layer l = 0..n_hidden: W_l[d_l][d_{l+1}] (input-major) and
+ *     b_l[d_{l+1}], with d_0 = t*E, d_l = hidden[l-1], d_{n_hidden+1} = V,
+ *     V = 4^k. Where a parameter vector carries the mixing weight, the
+ *     pre-sigmoid value a (alpha = 1/(1+exp(-a))) follows as one more float.
+ */
+#ifndef PMKLC_H
+#define PMKLC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMKLC_OK = 0,
+  PMKLC_ERR_INVALID_ARG = -1,      /* bad configuration or argument */
+  PMKLC_ERR_INVALID_BASE = -2,     /* input byte outside the accepted alphabet */
+  PMKLC_ERR_BUFFER_TOO_SMALL = -3, /* a caller buffer is too small (size reported) */
+  PMKLC_ERR_CORRUPT = -4,          /* container malformed or truncated */
+  PMKLC_ERR_MODEL_MISMATCH = -5,   /* static weights or numeric path differ from the container's */
+  PMKLC_ERR_DEVICE = -6,           /* a HIP call failed */
+  PMKLC_ERR_UNSUPPORTED = -7       /* valid configuration that this build has no kernel for */
+} pmklc_status;
+
+enum { PMKLC_SGD = 0, PMKLC_ADAM = 1 };
+enum { PMKLC_FP32 = 0, PMKLC_BF16 = 1 };          /* arithmetic of the model GEMMs */
+enum { PMKLC_BATCHED = 0, PMKLC_PLAIN = 1 };      /* all blocks in one launch | one block per launch */
+/* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. */
+enum {
+  PMKLC_SEL_UNIFORM = 0,   /* no model: every token coded with the uniform distribution */
+  PMKLC_SEL_SPUM = 1,      /* S0: frozen static public model */
+  PMKLC_SEL_SPRM = 2,      /* S1: static private model (not built; rejected) */
+  PMKLC_SEL_DM = 4         /* S2: dynamic model */
+};
+
+typedef struct pmklc_config {
+  uint32_t struct_size;     /* sizeof(pmklc_config) */
+  uint32_t s, k;            /* (s,k)-mer step and window, 1 <= s <= k <= 4 (Sec. 4.1) */
+  uint32_t t;               /* context length in tokens (Sec. 2 step (2)) */
+  uint32_t bs;              /* tokens per step = contiguous segments per block */
+  uint32_t embed;           /* embedding width E */
+  uint32_t n_hidden;        /* hidden layers, 0..2 */
+  uint32_t hidden[4];       /* hidden widths */
+  uint32_t optimizer;       /* PMKLC_SGD | PMKLC_ADAM */
+  float lr, beta1, beta2, eps;
+  uint32_t precision;       /* PMKLC_FP32 | PMKLC_BF16 */
+  uint32_t schedule;        /* PMKLC_BATCHED | PMKLC_PLAIN */
+  uint32_t selector;        /* PMKLC_SEL_* mask: 0, DM, or SPUM|DM */
+  uint32_t smp_ppm;         /* step-wise model passing point in parts per million of a
+                               block's steps (paper: 5% = 50000); 0 = off (Sec. 4.3) */
+  uint64_t seed;            /* seed of the dynamic model's initial weights */
+  uint32_t n_blocks;        /* data blocks (Sec. 4.3 data chunker) */
+  const uint64_t *block_len_host;   /* raw bytes per block, or NULL = equal split */
+  uint32_t n_files;         /* files in the input; model passing never crosses a file */
+  const uint64_t *file_blocks_host; /* blocks per file, or NULL = one file */
+  const float *static_host; /* frozen static model (parameter layout above, no alpha) */
+  uint64_t static_len;      /* number of floats in static_host */
+} pmklc_config;
+
+/* Sec. 4.1 (GskE): maps ASCII bases A,C,G,T (0,1,2,3) to (s,k)-mer ids
+ * e_j = sum_{m<k} 4^(k-1-m) * b_{j*s+m}, j = 0 .. floor((n-k)/s), one byte
+ * per id. bases_dev: n bytes; tokens_dev: capacity `cap` bytes. *n_tokens
+ * receives floor((n-k)/s)+1 (0 if n < k). Any byte other than A,C,G,T
+ * (including N) gives PMKLC_ERR_INVALID_BASE. */
+pmklc_status pmklc_encode_skmer(const uint8_t *bases_dev, uint64_t n, uint32_t s, uint32_t k,
+                                uint8_t *tokens_dev, uint64_t cap, uint64_t *n_tokens, void *stream);
+
+/* Upper bounds for pmklc_compress on n input bytes: *max_out = container
+ * bytes, *ws_bytes = device workspace bytes. */
+pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t *max_out,
+                                  uint64_t *ws_bytes);
+
+/* Sec. 2 (compression steps (1)-(4)) over the blocks of Sec. 4.3.
+ * in_dev: n bytes of ASCII A/C/G/T/N (N runs are stored aside; any other
+ * byte gives PMKLC_ERR_INVALID_BASE). ws_dev: workspace of at least the
+ * bound's ws_bytes. out_host: container, capacity out_cap; *out_len its
+ * length. */
+pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
+                            uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
+                            void *stream);
+
+/* Reads a container's header: *n_bases = decompressed size, *ws_bytes =
+ * device workspace needed by pmklc_decompress. */
+pmklc_status pmklc_decompress_info(const uint8_t *cbf_host, uint64_t len, uint64_t *n_bases,
+                                   uint64_t *ws_bytes);
+
+/* Sec. 2 (decompression): the same models, updated the same way, restore
+ * the input from the container. static_host must be the static model the
+ * container was made with (checked by CRC-32), else
+ * PMKLC_ERR_MODEL_MISMATCH. out_dev receives n_bases bytes. */
+pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float *static_host,
+                              uint64_t static_len, void *ws_dev, uint64_t ws_bytes, uint8_t *out_dev,
+                              uint64_t out_cap, uint64_t *out_len, void *stream);
+
+const char *pmklc_status_string(pmklc_status s);
+
+/* ---- Exports for parity tests (same device code as the hot path) ---- */
+
+/* Frequency quantisation of probabilities: for each of `rows` rows of V
+ * FP32 probabilities, f_v = 1 + floor(p_v * (2^16 - V)) with the product
+ * taken exactly, the residual 2^16 - sum(f) added to the largest p (lowest
+ * index on ties); cdf_dev receives rows x (V+1) cumulative counts (u32). */
+pmklc_status pmklc_quantise(const float *probs_dev, uint32_t rows, uint32_t V, uint32_t *cdf_dev,
+                            void *stream);
+
+/* Arithmetic coder (Witten, Neal, Cleary 1987; 32-bit, total 2^16) over m
+ * symbols given as [cum_lo, cum_hi) pairs (u32 device arrays). out_dev:
+ * capacity `cap` bytes, bits most significant first; *nbits receives the
+ * stream length in bits. */
+pmklc_status pmklc_wnc_encode(const uint32_t *cum_lo_dev, const uint32_t *cum_hi_dev, uint64_t m,
+                              uint8_t *out_dev, uint64_t cap, uint64_t *nbits, void *stream);
+
+/* Inverse of pmklc_wnc_encode: cdfs_dev holds m rows of V+1 cumulative
+ * counts; symbols_dev receives m u32 symbols. */
+pmklc_status pmklc_wnc_decode(const uint8_t *in_dev, uint64_t nbytes, const uint32_t *cdfs_dev, uint32_t V,
+                              uint64_t m, uint32_t *symbols_dev, void *stream);
+
+/* Runs the learning loop of one block over l tokens (tokens_dev), exactly
+ * as pmklc_compress does for a block, coding into a discarded stream.
+ * init_dev: initial parameters + a (n_params+1 floats) or NULL for the
+ * seeded ones. static_dev: static parameters (device) or NULL. stop: run
+ * only the first `stop` steps (0 = all). probe_steps_host: sorted step
+ * indices whose FP32 probabilities [bs][V] are written to probs_dev
+ * (n_probe x bs x V). params_dev receives the parameters + a after the
+ * last step run (n_params+1 floats). */
+pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_dev, uint64_t l,
+                               const float *static_dev, const float *init_dev, uint64_t stop,
+                               const uint64_t *probe_steps_host, uint32_t n_probe, float *probs_dev,
+                               float *params_dev, void *stream);
+
+/* Number of model parameters (without the mixing weight) for cfg. */
+uint64_t pmklc_param_count(const pmklc_config *cfg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

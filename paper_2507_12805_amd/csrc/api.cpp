@@ -1,0 +1,1061 @@
+// Host side of libpmklc: configuration checks, block planning (Sec. 4.3),
+// workspace layout, container writing/parsing, and the orchestration of
+// the HIP kernels behind the C ABI in include/pmklc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/pmklc.h"
+#include "pmklc_internal.h"
+
+using namespace pmklc;
+
+namespace {
+
+constexpr uint8_t kPathFP32 = 1, kPathBF16 = 2, kPathUniform = 255;
+constexpr int kHeaderBytes = 80;
+
+#define HIP_TRY(x)                                     \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return PMKLC_ERR_DEVICE;     \
+  } while (0)
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ------------------------------------------------------------- CRC-32
+// IEEE 802.3 polynomial, reflected (the zlib value), table-driven.
+struct Crc32Table {
+  uint32_t t[256];
+  Crc32Table() {
+    for (uint32_t i = 0; i < 256; i++) {
+      uint32_t c = i;
+      for (int b = 0; b < 8; b++) c = (c & 1u) ? 0xEDB88320u ^ (c >> 1) : c >> 1;
+      t[i] = c;
+    }
+  }
+};
+uint32_t crc32(const void *p, uint64_t n) {
+  static const Crc32Table tab;
+  const uint8_t *s = static_cast<const uint8_t *>(p);
+  uint32_t c = 0xFFFFFFFFu;
+  for (uint64_t i = 0; i < n; i++) c = tab.t[(c ^ s[i]) & 0xFFu] ^ (c >> 8);
+  return c ^ 0xFFFFFFFFu;
+}
+
+// ------------------------------------------------------------ byte I/O
+struct Writer {
+  uint8_t *p;
+  uint64_t cap, n = 0;
+  bool over = false;
+  void put(const void *src, uint64_t len) {
+    if (n + len > cap) { over = true; n += len; return; }
+    memcpy(p + n, src, len);
+    n += len;
+  }
+  void le(uint64_t v, int bytes) {
+    uint8_t b[8];
+    for (int i = 0; i < bytes; i++) b[i] = (uint8_t)(v >> (8 * i));
+    put(b, (uint64_t)bytes);
+  }
+  void f32(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    le(u, 4);
+  }
+  void varint(uint64_t v) {
+    uint8_t b[10];
+    int k = 0;
+    while (v >= 0x80) { b[k++] = (uint8_t)(v | 0x80); v >>= 7; }
+    b[k++] = (uint8_t)v;
+    put(b, (uint64_t)k);
+  }
+};
+int varint_len(uint64_t v) {
+  int k = 1;
+  while (v >= 0x80) { v >>= 7; k++; }
+  return k;
+}
+struct Reader {
+  const uint8_t *p;
+  uint64_t n, pos = 0;
+  bool bad = false;
+  uint64_t le(int bytes) {
+    if (pos + (uint64_t)bytes > n) { bad = true; return 0; }
+    uint64_t v = 0;
+    for (int i = 0; i < bytes; i++) v |= (uint64_t)p[pos + i] << (8 * i);
+    pos += (uint64_t)bytes;
+    return v;
+  }
+  float f32() {
+    uint32_t u = (uint32_t)le(4);
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+  }
+  uint64_t varint() {
+    uint64_t v = 0;
+    for (int sh = 0; sh < 64; sh += 7) {
+      if (pos >= n) { bad = true; return 0; }
+      uint8_t c = p[pos++];
+      v |= (uint64_t)(c & 0x7F) << sh;
+      if (!(c & 0x80)) return v;
+    }
+    bad = true;
+    return 0;
+  }
+};
+
+// ------------------------------------------------------- configuration
+struct Model {
+  Dims d;
+  LdsLayout lay;
+  int nt;
+};
+
+pmklc_status check_cfg(const pmklc_config *c) {
+  if (!c || c->struct_size != sizeof(pmklc_config)) return PMKLC_ERR_INVALID_ARG;
+  if (c->s < 1 || c->k < 1 || c->k > 4 || c->s > c->k) return PMKLC_ERR_INVALID_ARG;
+  if (c->t < 1 || c->t > 65535 || c->bs < 1 || c->bs > 65535 || c->embed < 1 || c->embed > 65535)
+    return PMKLC_ERR_INVALID_ARG;
+  if (c->n_hidden > 4) return PMKLC_ERR_INVALID_ARG;
+  for (uint32_t l = 0; l < c->n_hidden; l++)
+    if (c->hidden[l] < 1 || c->hidden[l] > 65535) return PMKLC_ERR_INVALID_ARG;
+  if (c->optimizer > 1 || c->precision > 1 || c->schedule > 1) return PMKLC_ERR_INVALID_ARG;
+  if (c->selector != PMKLC_SEL_UNIFORM && c->selector != PMKLC_SEL_DM &&
+      c->selector != (PMKLC_SEL_SPUM | PMKLC_SEL_DM)) {
+    return (c->selector & PMKLC_SEL_SPRM) ? PMKLC_ERR_UNSUPPORTED : PMKLC_ERR_INVALID_ARG;
+  }
+  if (c->smp_ppm > 1000000u) return PMKLC_ERR_INVALID_ARG;
+  if (c->n_blocks < 1) return PMKLC_ERR_INVALID_ARG;
+  return PMKLC_OK;
+}
+
+uint64_t param_count(uint32_t k, uint32_t t, uint32_t E, uint32_t nh, const uint32_t *hidden) {
+  uint64_t V = 1ull << (2 * k);
+  uint64_t prev = (uint64_t)t * E, n = V * E;
+  for (uint32_t l = 0; l < nh; l++) { n += prev * hidden[l] + hidden[l]; prev = hidden[l]; }
+  n += prev * V + V;
+  return n;
+}
+
+// Shape + LDS plan of the step kernel; UNSUPPORTED when this build's kernel
+// cannot hold it (see the design notes: tile and LDS limits).
+pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh,
+                        const uint32_t *hidden, uint32_t selector, uint32_t opt, float lr, float b1, float b2,
+                        float eps, Model &m) {
+  (void)s;
+  Dims &d = m.d;
+  memset(&d, 0, sizeof d);
+  d.V = 1 << (2 * k);
+  d.E = (int)E;
+  d.t = (int)t;
+  d.D = (int)(t * E);
+  d.bs = (int)bs;
+  d.nh = (int)nh;
+  d.model_on = (selector & PMKLC_SEL_DM) ? 1 : 0;
+  d.static_on = (selector & PMKLC_SEL_SPUM) ? 1 : 0;
+  d.optimizer = (int)opt;
+  d.lr = lr; d.b1 = b1; d.b2 = b2; d.eps = eps;
+  if (!d.model_on) {
+    // uniform coding needs no model; keep a minimal valid shape
+    d.nh = 0;
+  }
+  if (d.model_on) {
+    if (nh > 2) return PMKLC_ERR_UNSUPPORTED;
+    if (E % 4 || bs % 4 || d.V % 4) return PMKLC_ERR_UNSUPPORTED;
+    for (uint32_t l = 0; l < nh; l++) if (hidden[l] % 4) return PMKLC_ERR_UNSUPPORTED;
+    if ((uint64_t)t * E > (1u << 20)) return PMKLC_ERR_UNSUPPORTED;
+  }
+  d.dim[0] = d.D;
+  for (int l = 0; l < d.nh; l++) { d.H[l] = (int)hidden[l]; d.dim[l + 1] = (int)hidden[l]; }
+  d.dim[d.nh + 1] = d.V;
+  uint64_t off = 0;
+  d.off_emb = 0;
+  off += (uint64_t)d.V * E;
+  for (int l = 0; l <= d.nh; l++) {
+    d.off_W[l] = (int)off;
+    off += (uint64_t)d.dim[l] * d.dim[l + 1];
+    d.off_b[l] = (int)off;
+    off += (uint64_t)d.dim[l + 1];
+  }
+  if (off > (1ull << 30)) return PMKLC_ERR_UNSUPPORTED;
+  d.P = (int)off;
+  d.stride = (int)align_up(off + 1, 64);
+  d.CH = 32;
+  int rs = 1;
+  while (rs < d.t + d.CH) rs <<= 1;
+  d.RS = rs;
+  // LDS plan
+  LdsLayout &L = m.lay;
+  memset(&L, 0, sizeof L);
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) { uint64_t at = o; o = align_up(o + bytes, 16); return (int)at; };
+  int hmax = 0;
+  for (int l = 0; l < d.nh; l++) hmax = std::max(hmax, d.H[l]);
+  L.emb = take(4ull * d.V * E);
+  L.embs = take(d.static_on ? 4ull * d.V * E : 0);
+  L.ring = take((uint64_t)bs * d.RS);
+  L.act[0] = take(d.nh >= 1 ? 4ull * bs * d.H[0] : 0);
+  L.act[1] = take(d.nh >= 2 ? 4ull * bs * d.H[1] : 0);
+  L.lm = take(4ull * bs * d.V);
+  L.lu = take(d.static_on ? 4ull * bs * d.V : 0);
+  L.cdf = take(4ull * bs * (d.V + 1));
+  L.tgt = take(bs);
+  L.dh[0] = take(d.nh >= 1 ? 4ull * bs * hmax : 0);
+  L.dh[1] = take(d.nh >= 2 ? 4ull * bs * hmax : 0);
+  L.demb = take(8ull * d.V * E);
+  L.misc = take(4ull * bs + 64);
+  L.total = (int)o;
+  if (o > 160 * 1024) return PMKLC_ERR_UNSUPPORTED;
+  m.nt = bs <= 256 ? 256 : 512;
+  if (bs > 512) return PMKLC_ERR_UNSUPPORTED;
+  return PMKLC_OK;
+}
+
+pmklc_status make_model(const pmklc_config *c, Model &m) {
+  return make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, c->selector, c->optimizer, c->lr,
+                    c->beta1, c->beta2, c->eps, m);
+}
+
+// -------------------------------------------------------------- planning
+struct Plan {
+  std::vector<uint64_t> raw_len, raw_off;
+  std::vector<int32_t> pred;       // SMP predecessor or -1
+  std::vector<uint64_t> file_blocks;
+};
+
+pmklc_status plan_blocks(uint64_t n, uint32_t n_blocks, const uint64_t *block_len, uint32_t n_files,
+                         const uint64_t *file_blocks, bool smp, Plan &p) {
+  p.raw_len.resize(n_blocks);
+  p.raw_off.resize(n_blocks);
+  uint64_t off = 0;
+  for (uint32_t b = 0; b < n_blocks; b++) {
+    uint64_t len = block_len ? block_len[b] : (b + 1 == n_blocks ? n - (n / n_blocks) * (n_blocks - 1) : n / n_blocks);
+    if (len > 0xFFFFFFFFull) return PMKLC_ERR_INVALID_ARG;   // run tables are 32-bit per block
+    p.raw_off[b] = off;
+    p.raw_len[b] = len;
+    off += len;
+  }
+  if (off != n) return PMKLC_ERR_INVALID_ARG;
+  if (file_blocks && n_files > 0) p.file_blocks.assign(file_blocks, file_blocks + n_files);
+  else p.file_blocks.assign(1, n_blocks);
+  uint64_t tot = 0;
+  for (uint64_t v : p.file_blocks) tot += v;
+  if (tot != n_blocks) return PMKLC_ERR_INVALID_ARG;
+  p.pred.assign(n_blocks, -1);
+  uint64_t b = 0;
+  for (uint64_t fb : p.file_blocks) {
+    for (uint64_t q = 0; q < fb; q++, b++)
+      if (smp && q > 0) p.pred[b] = (int32_t)(b - 1);
+  }
+  return PMKLC_OK;
+}
+
+uint64_t smp_steps(uint32_t ppm, uint64_t L) { return (uint64_t)(((unsigned __int128)ppm * L + 999999u) / 1000000u); }
+uint64_t tokens_of(uint64_t nb, uint32_t s, uint32_t k) { return nb >= k ? (nb - k) / s + 1 : 0; }
+uint32_t slot_words_for(uint64_t L) { return (uint32_t)((17 * L + 2 + 31) / 32 + 1); }
+
+// ------------------------------------------------------------ workspace
+struct Arena {
+  uint8_t *base;
+  uint64_t cap, used = 0;
+  bool over = false;
+  template <class T>
+  T *take(uint64_t count) {
+    uint64_t at = align_up(used, 256);
+    used = at + align_up(count * sizeof(T), 256);
+    if (used > cap) over = true;
+    return base ? reinterpret_cast<T *>(base + at) : nullptr;
+  }
+};
+
+struct Work {
+  uint64_t *chunk_block, *chunk_run0;
+  ChunkStat *stats;
+  SeqBlock *seq;
+  BlockDesc *desc;
+  uint32_t *run_start, *run_len, *run_sp, *run_cum;
+  uint8_t *tok, *extras;
+  float *params, *adam_m, *adam_v, *init, *stat, *snap;
+  int *snap_flag, *ctr;   // ctr[0] queue, ctr[1] err
+  uint32_t *slots, *seg_bits, *seg_words;
+  uint64_t *seg_src, *seg_dst;
+  uint32_t *seg_bytes;
+  uint8_t *staging;
+};
+
+struct Sizes {
+  uint64_t n_chunks, runs, tokens, slot_words, staging;
+};
+
+void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool adam, bool smp, Work &w) {
+  const uint64_t stride = (uint64_t)m.d.stride;
+  w.ctr = A.take<int>(64);
+  w.chunk_block = A.take<uint64_t>(z.n_chunks + 1);
+  w.chunk_run0 = A.take<uint64_t>(z.n_chunks + 1);
+  w.stats = A.take<ChunkStat>(z.n_chunks + 1);
+  w.seq = A.take<SeqBlock>(n_blocks);
+  w.desc = A.take<BlockDesc>(n_blocks);
+  w.run_start = A.take<uint32_t>(z.runs + 1);
+  w.run_len = A.take<uint32_t>(z.runs + 1);
+  w.run_sp = A.take<uint32_t>(z.runs + 1);
+  w.run_cum = A.take<uint32_t>(z.runs + 1);
+  w.tok = A.take<uint8_t>(z.tokens + 16);
+  w.extras = A.take<uint8_t>((uint64_t)n_blocks * ((uint64_t)m.d.bs + 8));
+  w.params = A.take<float>((uint64_t)n_blocks * stride);
+  w.adam_m = adam ? A.take<float>((uint64_t)n_blocks * stride) : nullptr;
+  w.adam_v = adam ? A.take<float>((uint64_t)n_blocks * stride) : nullptr;
+  w.init = A.take<float>(stride);
+  w.stat = m.d.static_on ? A.take<float>(stride) : nullptr;
+  w.snap = smp ? A.take<float>((uint64_t)n_blocks * stride) : nullptr;
+  w.snap_flag = A.take<int>(n_blocks);
+  w.slots = A.take<uint32_t>(z.slot_words + 1);
+  w.seg_bits = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
+  w.seg_words = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
+  w.seg_src = A.take<uint64_t>((uint64_t)n_blocks * m.d.bs);
+  w.seg_dst = A.take<uint64_t>((uint64_t)n_blocks * m.d.bs);
+  w.seg_bytes = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
+  w.staging = A.take<uint8_t>(z.staging + 16);
+}
+
+template <class T>
+hipError_t h2d(T *dst, const std::vector<T> &v, hipStream_t st) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+template <class T>
+hipError_t d2h(std::vector<T> &v, const T *src, uint64_t count, hipStream_t st) {
+  v.resize(count);
+  if (!count) return hipSuccess;
+  return hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, st);
+}
+
+uint8_t path_of(uint32_t selector, uint32_t precision) {
+  if (!(selector & PMKLC_SEL_DM)) return kPathUniform;
+  return precision == PMKLC_BF16 ? kPathBF16 : kPathFP32;
+}
+
+void write_header(Writer &o, const pmklc_config *c, uint8_t path, uint32_t scrc, uint64_t n, uint32_t n_files) {
+  o.put("PMKC", 4);
+  o.le(1, 1);
+  o.le(path, 1);
+  o.le(c->s, 1);
+  o.le(c->k, 1);
+  o.le(c->t, 2);
+  o.le(c->bs, 2);
+  o.le(c->embed, 2);
+  o.le(c->n_hidden, 1);
+  o.le(c->optimizer, 1);
+  for (uint32_t l = 0; l < 4; l++) o.le(l < c->n_hidden ? c->hidden[l] : 0, 2);
+  o.f32(c->lr);
+  o.f32(c->beta1);
+  o.f32(c->beta2);
+  o.f32(c->eps);
+  o.le(c->selector, 1);
+  o.le(0, 3);
+  o.le(c->smp_ppm, 4);
+  o.le(c->seed, 8);
+  o.le(scrc, 4);
+  o.le(0, 4);
+  o.le(n, 8);
+  o.le(c->n_blocks, 4);
+  o.le(n_files, 4);
+}
+
+// MSB-first bit packer for the per-block extras
+struct BitPack {
+  std::vector<uint8_t> b;
+  uint64_t nbits = 0;
+  void put(uint32_t v, int n) {
+    for (int i = n - 1; i >= 0; i--) {
+      if ((nbits >> 3) >= b.size()) b.push_back(0);
+      if ((v >> i) & 1u) b[nbits >> 3] |= (uint8_t)(0x80u >> (nbits & 7));
+      nbits++;
+    }
+  }
+};
+uint32_t get_bits(const uint8_t *p, uint64_t &bit, int n) {
+  uint32_t v = 0;
+  for (int i = 0; i < n; i++, bit++) v = (v << 1) | ((p[bit >> 3] >> (7 - (bit & 7))) & 1u);
+  return v;
+}
+
+void fill_blockdesc(const Model &m, const std::vector<SeqBlock> &sb, const Plan &p, uint32_t smp_ppm,
+                    std::vector<BlockDesc> &bd, uint64_t &slot_total) {
+  const uint32_t nb = (uint32_t)sb.size();
+  bd.resize(nb);
+  slot_total = 0;
+  std::vector<int> has_succ(nb, 0);
+  for (uint32_t b = 0; b < nb; b++) if (p.pred[b] >= 0) has_succ[p.pred[b]] = 1;
+  for (uint32_t b = 0; b < nb; b++) {
+    BlockDesc &d = bd[b];
+    d.tok_off = sb[b].tok_off;
+    d.L = (uint32_t)sb[b].L;
+    d.slot_words = slot_words_for(sb[b].L);
+    d.slot_off = slot_total;
+    slot_total += (uint64_t)d.slot_words * (uint64_t)m.d.bs;
+    d.S = (uint32_t)smp_steps(smp_ppm, sb[b].L);
+    d.pred = p.pred[b];
+    d.has_snap = has_succ[b];
+    d.pad = 0;
+  }
+}
+
+pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
+                      hipStream_t st) {
+  StepArgs a;
+  memset(&a, 0, sizeof a);
+  a.d = m.d;
+  a.lay = m.lay;
+  a.mode = mode;
+  a.n_blocks = (int)bd.size();
+  a.blocks = w.desc;
+  a.tokens = w.tok;
+  a.params = w.params;
+  a.adam_m = w.adam_m;
+  a.adam_v = w.adam_v;
+  a.init = w.init;
+  a.stat = w.stat;
+  a.snap = w.snap;
+  a.snap_flag = w.snap_flag;
+  a.queue = w.ctr;
+  a.err = w.ctr + 1;
+  a.slots = w.slots;
+  a.seg_bits = w.seg_bits;
+  a.seg_words = w.seg_words;
+  a.spin_limit = 1ll << 26;   // ~10 s of waiting before giving up with an error
+  HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(w.snap_flag, 0, bd.size() * sizeof(int), st));
+  if (bd.empty()) return PMKLC_OK;
+  if (schedule == PMKLC_PLAIN) {
+    // one block per launch, in block order (the per-block baseline)
+    for (size_t b = 0; b < bd.size(); b++) {
+      StepArgs one = a;
+      one.n_blocks = 1;
+      one.blocks = w.desc + b;
+      // parameters/slots/bits are indexed by the block number: offset them
+      one.params = w.params + b * (size_t)m.d.stride;
+      one.adam_m = w.adam_m ? w.adam_m + b * (size_t)m.d.stride : nullptr;
+      one.adam_v = w.adam_v ? w.adam_v + b * (size_t)m.d.stride : nullptr;
+      one.seg_bits = w.seg_bits + b * (size_t)m.d.bs;
+      one.seg_words = w.seg_words + b * (size_t)m.d.bs;
+      one.queue = w.ctr + 2 + (int)(b % 60);
+      if (bd[b].pred >= 0 || bd[b].has_snap) return PMKLC_ERR_UNSUPPORTED;
+      HIP_TRY(hipMemsetAsync(one.queue, 0, sizeof(int), st));
+      HIP_TRY(launch_step(one, 1, m.nt, st));
+    }
+  } else {
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int grid = (int)std::min<uint64_t>(bd.size(), (uint64_t)std::max(ncu, 1));
+    HIP_TRY(launch_step(a, grid, m.nt, st));
+  }
+  return PMKLC_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *pmklc_status_string(pmklc_status s) {
+  switch (s) {
+    case PMKLC_OK: return "ok";
+    case PMKLC_ERR_INVALID_ARG: return "invalid argument";
+    case PMKLC_ERR_INVALID_BASE: return "invalid base";
+    case PMKLC_ERR_BUFFER_TOO_SMALL: return "buffer too small";
+    case PMKLC_ERR_CORRUPT: return "corrupt container";
+    case PMKLC_ERR_MODEL_MISMATCH: return "model mismatch";
+    case PMKLC_ERR_DEVICE: return "device error";
+    case PMKLC_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown";
+}
+
+uint64_t pmklc_param_count(const pmklc_config *c) {
+  if (!c || c->k < 1 || c->k > 4 || c->n_hidden > 4) return 0;
+  return param_count(c->k, c->t, c->embed, c->n_hidden, c->hidden);
+}
+
+pmklc_status pmklc_encode_skmer(const uint8_t *bases_dev, uint64_t n, uint32_t s, uint32_t k, uint8_t *tokens_dev,
+                                uint64_t cap, uint64_t *n_tokens, void *stream) {
+  if (s < 1 || k < 1 || k > 4 || s > k || !n_tokens || (n && !bases_dev)) return PMKLC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t l = tokens_of(n, s, k);
+  if (l > cap) { *n_tokens = l; return PMKLC_ERR_BUFFER_TOO_SMALL; }
+  if (l && !tokens_dev) return PMKLC_ERR_INVALID_ARG;
+  if (n == 0) { *n_tokens = 0; return PMKLC_OK; }
+  int *err = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&err), sizeof(int), st));
+  int herr = 0;
+  hipError_t e = hipMemsetAsync(err, 0, sizeof(int), st);
+  if (e == hipSuccess) e = launch_skmer_direct(bases_dev, n, (int)s, (int)k, tokens_dev, l, err, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFreeAsync(err, st);
+  if (e != hipSuccess) return PMKLC_ERR_DEVICE;
+  if (herr) return PMKLC_ERR_INVALID_BASE;
+  *n_tokens = l;
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t *max_out, uint64_t *ws_bytes) {
+  pmklc_status rc = check_cfg(cfg);
+  if (rc) return rc;
+  Model m;
+  rc = make_model(cfg, m);
+  if (rc) return rc;
+  Plan p;
+  rc = plan_blocks(n, cfg->n_blocks, cfg->block_len_host, cfg->n_files, cfg->file_blocks_host,
+                   cfg->smp_ppm > 0 && (cfg->selector & PMKLC_SEL_DM), p);
+  if (rc) return rc;
+  Sizes z{};
+  uint64_t meta = kHeaderBytes + 10ull * p.file_blocks.size();
+  for (uint32_t b = 0; b < cfg->n_blocks; b++) {
+    uint64_t rl = p.raw_len[b];
+    z.n_chunks += (rl + kScanChunk - 1) / kScanChunk;
+    z.runs += (rl + 1) / 2;
+    uint64_t l = tokens_of(rl, cfg->s, cfg->k);
+    uint64_t L = l / cfg->bs;
+    z.tokens += l;
+    z.slot_words += (uint64_t)slot_words_for(L) * cfg->bs;
+    uint64_t runs = (rl + 1) / 2;
+    meta += 10 + 10 + 20 * runs + (2ull * cfg->k * cfg->bs + 8 + 7) / 8 + 1 + 10ull * cfg->bs;
+  }
+  z.staging = 4 * z.slot_words;
+  Arena A{nullptr, ~0ull};
+  Work w;
+  layout(A, m, cfg->n_blocks, z, cfg->optimizer == PMKLC_ADAM, cfg->smp_ppm > 0, w);
+  if (max_out) *max_out = meta + z.staging;
+  if (ws_bytes) *ws_bytes = A.used + 256;
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
+                            uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
+                            void *stream) {
+  pmklc_status rc = check_cfg(cfg);
+  if (rc) return rc;
+  if (!out_len || (n && !in_dev) || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+  Model m;
+  rc = make_model(cfg, m);
+  if (rc) return rc;
+  if ((cfg->selector & PMKLC_SEL_SPUM) &&
+      (!cfg->static_host || cfg->static_len != (uint64_t)m.d.P))
+    return PMKLC_ERR_MODEL_MISMATCH;
+  if (cfg->precision != PMKLC_FP32 && (cfg->selector & PMKLC_SEL_DM)) return PMKLC_ERR_UNSUPPORTED;
+  const bool smp = cfg->smp_ppm > 0 && (cfg->selector & PMKLC_SEL_DM);
+  Plan p;
+  rc = plan_blocks(n, cfg->n_blocks, cfg->block_len_host, cfg->n_files, cfg->file_blocks_host, smp, p);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t nblk = cfg->n_blocks;
+  const uint32_t s = cfg->s, k = cfg->k, bs = cfg->bs;
+
+  // worst-case sizes (same as the bound), so the layout is fixed before the scan
+  Sizes z{};
+  std::vector<SeqBlock> sb(nblk);
+  std::vector<uint64_t> chunk_block;
+  for (uint32_t b = 0; b < nblk; b++) {
+    sb[b] = SeqBlock{};
+    sb[b].raw_off = p.raw_off[b];
+    sb[b].raw_len = p.raw_len[b];
+    sb[b].chunk0 = z.n_chunks;
+    uint64_t nc = (p.raw_len[b] + kScanChunk - 1) / kScanChunk;
+    for (uint64_t c = 0; c < nc; c++) chunk_block.push_back(b);
+    z.n_chunks += nc;
+    z.runs += (p.raw_len[b] + 1) / 2;
+    uint64_t l = tokens_of(p.raw_len[b], s, k);
+    z.tokens += l;
+    z.slot_words += (uint64_t)slot_words_for(l / bs) * bs;
+  }
+  z.staging = 4 * z.slot_words;
+  Arena A{static_cast<uint8_t *>(ws_dev), ws_bytes};
+  Work w;
+  layout(A, m, nblk, z, cfg->optimizer == PMKLC_ADAM, smp, w);
+  if (A.over) return PMKLC_ERR_BUFFER_TOO_SMALL;
+
+  // ---- A1: scan (validate, count N runs)
+  std::vector<ChunkStat> stats;
+  HIP_TRY(h2d(w.chunk_block, chunk_block, st));
+  HIP_TRY(h2d(w.seq, sb, st));
+  HIP_TRY(launch_scan(in_dev, w.seq, w.chunk_block, z.n_chunks, w.stats, st));
+  HIP_TRY(d2h(stats, w.stats, z.n_chunks, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  std::vector<uint64_t> chunk_run0(z.n_chunks);
+  uint64_t run_total = 0, tok_total = 0, ex_total = 0, max_l = 0;
+  for (uint32_t b = 0; b < nblk; b++) {
+    uint64_t nN = 0, nr = 0;
+    uint64_t nc = (p.raw_len[b] + kScanChunk - 1) / kScanChunk;
+    for (uint64_t c = sb[b].chunk0; c < sb[b].chunk0 + nc; c++) {
+      if (stats[c].bad) return PMKLC_ERR_INVALID_BASE;
+      chunk_run0[c] = nr;
+      nr += stats[c].n_runs;
+      nN += stats[c].n_N;
+    }
+    SeqBlock &q = sb[b];
+    q.run0 = run_total;
+    q.n_runs = nr;
+    run_total += nr;
+    q.nb = q.raw_len - nN;
+    q.l = tokens_of(q.nb, s, k);
+    q.tok_off = tok_total;
+    tok_total += q.l;
+    q.L = q.l / bs;
+    q.tail_off = q.l ? (q.l - 1) * s + k : 0;
+    q.ex_off = ex_total;
+    ex_total += bs + 8;
+    max_l = std::max(max_l, q.l);
+  }
+  // ---- A1/A2: runs, tokens, extras
+  HIP_TRY(h2d(w.seq, sb, st));
+  HIP_TRY(h2d(w.chunk_run0, chunk_run0, st));
+  if (run_total) {
+    HIP_TRY(launch_runs(in_dev, w.seq, w.chunk_block, z.n_chunks, w.stats, w.chunk_run0, w.run_start, w.run_len, st));
+    HIP_TRY(launch_run_sp(w.seq, (int)nblk, w.run_start, w.run_len, w.run_sp, w.run_cum, st));
+  }
+  HIP_TRY(launch_tokenise(in_dev, w.seq, (int)nblk, max_l, w.run_sp, w.run_cum, (int)s, (int)k, w.tok, st));
+  HIP_TRY(launch_extras(in_dev, w.seq, (int)nblk, w.run_sp, w.run_cum, (int)s, (int)k, (int)bs, w.tok, w.extras, st));
+
+  // ---- A3-A11: model loop + coder
+  std::vector<BlockDesc> bd;
+  uint64_t slot_total = 0;
+  fill_blockdesc(m, sb, p, cfg->smp_ppm, bd, slot_total);
+  HIP_TRY(h2d(w.desc, bd, st));
+  uint32_t scrc = 0;
+  if (m.d.model_on) {
+    HIP_TRY(launch_init_params(m.d, cfg->seed, w.init, st));
+    if (m.d.static_on) {
+      scrc = crc32(cfg->static_host, 4ull * m.d.P);
+      HIP_TRY(hipMemcpyAsync(w.stat, cfg->static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
+    }
+  }
+  rc = run_step(m, w, 0, bd, cfg->schedule, st);
+  if (rc) return rc;
+  std::vector<uint32_t> seg_bits, run_start, run_len;
+  std::vector<uint8_t> extras;
+  std::vector<int> ctr;
+  HIP_TRY(d2h(seg_bits, w.seg_bits, (uint64_t)nblk * bs, st));
+  HIP_TRY(d2h(extras, w.extras, ex_total, st));
+  HIP_TRY(d2h(run_start, w.run_start, run_total, st));
+  HIP_TRY(d2h(run_len, w.run_len, run_total, st));
+  HIP_TRY(d2h(ctr, w.ctr, 2, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ctr[1]) return PMKLC_ERR_DEVICE;
+
+  // ---- A12: container
+  Writer meta{out_host, out_cap};
+  write_header(meta, cfg, path_of(cfg->selector, cfg->precision), scrc, n, (uint32_t)p.file_blocks.size());
+  for (uint64_t fb : p.file_blocks) meta.varint(fb);
+  std::vector<uint64_t> seg_src, seg_dst;
+  std::vector<uint32_t> seg_bytes;
+  uint64_t stream_total = 0;
+  for (uint32_t b = 0; b < nblk; b++) {
+    const SeqBlock &q = sb[b];
+    meta.varint(q.raw_len);
+    meta.varint(q.n_runs);
+    uint64_t prev_end = 0;
+    for (uint64_t r = 0; r < q.n_runs; r++) {
+      uint64_t st0 = run_start[q.run0 + r], ln = run_len[q.run0 + r];
+      meta.varint(st0 - prev_end);
+      meta.varint(ln);
+      prev_end = st0 + ln;
+    }
+    BitPack bp;
+    const uint8_t *ex = extras.data() + q.ex_off;
+    uint64_t ntail = q.nb - q.tail_off, nrem = q.l - q.L * bs;
+    for (uint64_t i = 0; i < ntail; i++) bp.put(ex[i], 2);
+    for (uint64_t i = 0; i < nrem; i++) bp.put(ex[ntail + i], 2 * (int)k);
+    meta.put(bp.b.data(), (bp.nbits + 7) / 8);
+    if (q.L > 0) {
+      for (uint32_t j = 0; j < bs; j++) {
+        uint32_t nbytes = (seg_bits[(uint64_t)b * bs + j] + 7) / 8;
+        meta.varint(nbytes);
+        seg_src.push_back(bd[b].slot_off + (uint64_t)j * bd[b].slot_words);
+        seg_dst.push_back(stream_total);
+        seg_bytes.push_back(nbytes);
+        stream_total += nbytes;
+      }
+    }
+  }
+  const uint64_t total = meta.n + stream_total;
+  if (total > out_cap || meta.over) { *out_len = total; return PMKLC_ERR_BUFFER_TOO_SMALL; }
+  if (stream_total) {
+    HIP_TRY(h2d(w.seg_src, seg_src, st));
+    HIP_TRY(h2d(w.seg_dst, seg_dst, st));
+    HIP_TRY(h2d(w.seg_bytes, seg_bytes, st));
+    HIP_TRY(launch_gather_streams(w.slots, w.seg_src, w.seg_dst, w.seg_bytes, seg_src.size(), w.staging, st));
+    HIP_TRY(hipMemcpyAsync(out_host + meta.n, w.staging, stream_total, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+  }
+  *out_len = total;
+  return PMKLC_OK;
+}
+
+// --------------------------------------------------------------- decode
+namespace {
+struct Parsed {
+  pmklc_config c;
+  uint32_t hidden[4];
+  uint8_t path;
+  uint32_t scrc;
+  uint64_t n;
+  std::vector<uint64_t> file_blocks;
+  std::vector<SeqBlock> sb;
+  std::vector<uint32_t> run_start, run_len, run_cum;
+  std::vector<uint8_t> extras;        // per block: tail codes then remainder tokens (bs + 8 bytes each)
+  std::vector<uint32_t> seg_bytes;    // [blocks with L>0][bs] in block order, flat per block b at b*bs
+  uint64_t stream_off;                // first stream byte in the container
+};
+
+pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
+  if (!p || len < (uint64_t)kHeaderBytes || memcmp(p, "PMKC", 4) != 0) return PMKLC_ERR_CORRUPT;
+  Reader r{p, len};
+  r.pos = 4;
+  if (r.le(1) != 1) return PMKLC_ERR_CORRUPT;
+  pmklc_config &c = o.c;
+  memset(&c, 0, sizeof c);
+  c.struct_size = sizeof(pmklc_config);
+  o.path = (uint8_t)r.le(1);
+  c.s = (uint32_t)r.le(1);
+  c.k = (uint32_t)r.le(1);
+  c.t = (uint32_t)r.le(2);
+  c.bs = (uint32_t)r.le(2);
+  c.embed = (uint32_t)r.le(2);
+  c.n_hidden = (uint32_t)r.le(1);
+  c.optimizer = (uint32_t)r.le(1);
+  for (int l = 0; l < 4; l++) c.hidden[l] = (uint32_t)r.le(2);
+  c.lr = r.f32();
+  c.beta1 = r.f32();
+  c.beta2 = r.f32();
+  c.eps = r.f32();
+  c.selector = (uint32_t)r.le(1);
+  r.le(3);
+  c.smp_ppm = (uint32_t)r.le(4);
+  c.seed = r.le(8);
+  o.scrc = (uint32_t)r.le(4);
+  r.le(4);
+  o.n = r.le(8);
+  c.n_blocks = (uint32_t)r.le(4);
+  uint32_t nf = (uint32_t)r.le(4);
+  if (r.bad) return PMKLC_ERR_CORRUPT;
+  c.precision = o.path == kPathBF16 ? PMKLC_BF16 : PMKLC_FP32;
+  if (check_cfg(&c)) return PMKLC_ERR_CORRUPT;
+  if (o.path != path_of(c.selector, c.precision)) return PMKLC_ERR_MODEL_MISMATCH;
+  if (nf < 1 || (uint64_t)nf > len || (uint64_t)c.n_blocks * 2 > len) return PMKLC_ERR_CORRUPT;
+  o.file_blocks.resize(nf);
+  uint64_t tot = 0;
+  for (uint32_t f = 0; f < nf; f++) { o.file_blocks[f] = r.varint(); tot += o.file_blocks[f]; }
+  if (r.bad || tot != c.n_blocks) return PMKLC_ERR_CORRUPT;
+  c.n_files = nf;
+  if (!full) return PMKLC_OK;
+  const uint32_t nblk = c.n_blocks, bs = c.bs, s = c.s, k = c.k;
+  o.sb.resize(nblk);
+  o.extras.assign((uint64_t)nblk * (bs + 8), 0);
+  o.seg_bytes.assign((uint64_t)nblk * bs, 0);
+  uint64_t off = 0, tok_total = 0;
+  for (uint32_t b = 0; b < nblk; b++) {
+    SeqBlock &q = o.sb[b];
+    q = SeqBlock{};
+    q.raw_off = off;
+    q.raw_len = r.varint();
+    if (r.bad || q.raw_len > o.n - off || q.raw_len > 0xFFFFFFFFull) return PMKLC_ERR_CORRUPT;
+    off += q.raw_len;
+    q.n_runs = r.varint();
+    if (r.bad || q.n_runs > q.raw_len) return PMKLC_ERR_CORRUPT;
+    q.run0 = o.run_start.size();
+    uint64_t prev_end = 0, nN = 0;
+    for (uint64_t i = 0; i < q.n_runs; i++) {
+      uint64_t gap = r.varint(), ln = r.varint();
+      uint64_t st0 = prev_end + gap;
+      if (r.bad || ln == 0 || st0 + ln > q.raw_len || (i > 0 && gap == 0)) return PMKLC_ERR_CORRUPT;
+      nN += ln;
+      o.run_start.push_back((uint32_t)st0);
+      o.run_len.push_back((uint32_t)ln);
+      o.run_cum.push_back((uint32_t)nN);
+      prev_end = st0 + ln;
+    }
+    q.nb = q.raw_len - nN;
+    q.l = tokens_of(q.nb, s, k);
+    q.L = q.l / bs;
+    q.tail_off = q.l ? (q.l - 1) * s + k : 0;
+    q.tok_off = tok_total;
+    tok_total += q.l;
+    q.ex_off = (uint64_t)b * (bs + 8);
+    uint64_t ntail = q.nb - q.tail_off, nrem = q.l - q.L * bs;
+    uint64_t bits = 2 * ntail + 2ull * k * nrem;
+    uint64_t eb = (bits + 7) / 8;
+    if (r.pos + eb > len) return PMKLC_ERR_CORRUPT;
+    uint64_t bit = 0;
+    const uint8_t *src = p + r.pos;
+    for (uint64_t i = 0; i < ntail; i++) o.extras[q.ex_off + i] = (uint8_t)get_bits(src, bit, 2);
+    for (uint64_t i = 0; i < nrem; i++) o.extras[q.ex_off + ntail + i] = (uint8_t)get_bits(src, bit, 2 * (int)k);
+    r.pos += eb;
+    if (q.L > 0) {
+      for (uint32_t j = 0; j < bs; j++) {
+        uint64_t v = r.varint();
+        if (r.bad || v > len) return PMKLC_ERR_CORRUPT;
+        o.seg_bytes[(uint64_t)b * bs + j] = (uint32_t)v;
+      }
+      if (q.L > 0xFFFFFFFFull) return PMKLC_ERR_CORRUPT;
+    }
+  }
+  if (off != o.n) return PMKLC_ERR_CORRUPT;
+  o.stream_off = r.pos;
+  uint64_t sum = 0;
+  for (uint32_t v : o.seg_bytes) sum += v;
+  if (o.stream_off + sum != len) return PMKLC_ERR_CORRUPT;
+  for (uint32_t b = 0; b < nblk; b++) {
+    if (o.sb[b].L == 0) continue;
+    for (uint32_t j = 0; j < bs; j++)
+      if (o.seg_bytes[(uint64_t)b * bs + j] > 4ull * slot_words_for(o.sb[b].L)) return PMKLC_ERR_CORRUPT;
+  }
+  return PMKLC_OK;
+}
+
+Sizes dec_sizes(const Parsed &o) {
+  Sizes z{};
+  z.runs = o.run_start.size();
+  for (const SeqBlock &q : o.sb) {
+    z.tokens += q.l;
+    z.slot_words += (uint64_t)slot_words_for(q.L) * o.c.bs;
+  }
+  for (uint32_t v : o.seg_bytes) z.staging += v;
+  return z;
+}
+}  // namespace
+
+pmklc_status pmklc_decompress_info(const uint8_t *cbf_host, uint64_t len, uint64_t *n_bases, uint64_t *ws_bytes) {
+  Parsed o;
+  pmklc_status rc = parse(cbf_host, len, o, true);
+  if (rc) return rc;
+  Model m;
+  rc = make_model(&o.c, m);
+  if (rc) return rc;
+  Plan p;
+  rc = plan_blocks(o.n, o.c.n_blocks, nullptr, 0, nullptr, false, p);
+  (void)p;
+  Arena A{nullptr, ~0ull};
+  Work w;
+  layout(A, m, o.c.n_blocks, dec_sizes(o), o.c.optimizer == PMKLC_ADAM, o.c.smp_ppm > 0, w);
+  if (n_bases) *n_bases = o.n;
+  if (ws_bytes) *ws_bytes = A.used + 256;
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float *static_host, uint64_t static_len,
+                              void *ws_dev, uint64_t ws_bytes, uint8_t *out_dev, uint64_t out_cap, uint64_t *out_len,
+                              void *stream) {
+  if (!out_len || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+  Parsed o;
+  pmklc_status rc = parse(cbf_host, len, o, true);
+  if (rc) return rc;
+  Model m;
+  rc = make_model(&o.c, m);
+  if (rc) return rc;
+  if (m.d.static_on) {
+    if (!static_host || static_len != (uint64_t)m.d.P || crc32(static_host, 4ull * m.d.P) != o.scrc)
+      return PMKLC_ERR_MODEL_MISMATCH;
+  }
+  if (o.c.precision != PMKLC_FP32 && m.d.model_on) return PMKLC_ERR_UNSUPPORTED;
+  if (o.n > out_cap) { *out_len = o.n; return PMKLC_ERR_BUFFER_TOO_SMALL; }
+  if (o.n && !out_dev) return PMKLC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t nblk = o.c.n_blocks, bs = o.c.bs;
+  const bool smp = o.c.smp_ppm > 0 && m.d.model_on;
+  Sizes z = dec_sizes(o);
+  Arena A{static_cast<uint8_t *>(ws_dev), ws_bytes};
+  Work w;
+  layout(A, m, nblk, z, o.c.optimizer == PMKLC_ADAM, smp, w);
+  if (A.over) return PMKLC_ERR_BUFFER_TOO_SMALL;
+  Plan p;
+  std::vector<uint64_t> bl(nblk);
+  for (uint32_t b = 0; b < nblk; b++) bl[b] = o.sb[b].raw_len;
+  rc = plan_blocks(o.n, nblk, bl.data(), (uint32_t)o.file_blocks.size(), o.file_blocks.data(), smp, p);
+  if (rc) return PMKLC_ERR_CORRUPT;
+  std::vector<BlockDesc> bd;
+  uint64_t slot_total = 0;
+  fill_blockdesc(m, o.sb, p, o.c.smp_ppm, bd, slot_total);
+  // streams -> aligned slots
+  std::vector<uint64_t> seg_src, seg_dst;
+  std::vector<uint32_t> seg_bytes, seg_words((uint64_t)nblk * bs, 0);
+  uint64_t so = 0;
+  for (uint32_t b = 0; b < nblk; b++) {
+    if (o.sb[b].L == 0) continue;
+    for (uint32_t j = 0; j < bs; j++) {
+      uint32_t nbt = o.seg_bytes[(uint64_t)b * bs + j];
+      seg_src.push_back(so);
+      seg_dst.push_back(bd[b].slot_off + (uint64_t)j * bd[b].slot_words);
+      seg_bytes.push_back(nbt);
+      seg_words[(uint64_t)b * bs + j] = (nbt + 3) / 4;
+      so += nbt;
+    }
+  }
+  std::vector<uint32_t> seg_words_c;
+  for (uint32_t b = 0; b < nblk; b++) {
+    if (o.sb[b].L == 0) continue;
+    for (uint32_t j = 0; j < bs; j++) seg_words_c.push_back(seg_words[(uint64_t)b * bs + j]);
+  }
+  if (so) {
+    HIP_TRY(hipMemcpyAsync(w.staging, cbf_host + o.stream_off, so, hipMemcpyHostToDevice, st));
+    HIP_TRY(h2d(w.seg_src, seg_src, st));
+    HIP_TRY(h2d(w.seg_dst, seg_dst, st));
+    HIP_TRY(h2d(w.seg_bytes, seg_bytes, st));
+    HIP_TRY(h2d(w.seg_bits, seg_words_c, st));   // per listed segment: words to fill
+    HIP_TRY(launch_scatter_streams(w.staging, w.seg_src, w.seg_dst, w.seg_bytes, w.seg_bits, seg_src.size(), w.slots,
+                                   st));
+  }
+  HIP_TRY(h2d(w.seg_words, seg_words, st));
+  HIP_TRY(h2d(w.desc, bd, st));
+  HIP_TRY(h2d(w.seq, o.sb, st));
+  HIP_TRY(h2d(w.extras, o.extras, st));
+  HIP_TRY(h2d(w.run_start, o.run_start, st));
+  HIP_TRY(h2d(w.run_len, o.run_len, st));
+  HIP_TRY(h2d(w.run_cum, o.run_cum, st));
+  if (m.d.model_on) {
+    HIP_TRY(launch_init_params(m.d, o.c.seed, w.init, st));
+    if (m.d.static_on) HIP_TRY(hipMemcpyAsync(w.stat, static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
+  }
+  rc = run_step(m, w, 1, bd, PMKLC_BATCHED, st);
+  if (rc) return rc;
+  uint64_t max_raw = 0;
+  for (const SeqBlock &q : o.sb) max_raw = std::max(max_raw, q.raw_len);
+  HIP_TRY(launch_detok(w.seq, (int)nblk, max_raw, w.run_start, w.run_len, w.run_cum, (int)o.c.s, (int)o.c.k, (int)bs,
+                       w.tok, w.extras, out_dev, st));
+  std::vector<int> ctr;
+  HIP_TRY(d2h(ctr, w.ctr, 2, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (ctr[1]) return PMKLC_ERR_DEVICE;
+  *out_len = o.n;
+  return PMKLC_OK;
+}
+
+// ------------------------------------------------------------ test exports
+pmklc_status pmklc_quantise(const float *probs_dev, uint32_t rows, uint32_t V, uint32_t *cdf_dev, void *stream) {
+  if (V < 2 || V > 256 || (rows && (!probs_dev || !cdf_dev))) return PMKLC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_quantise(probs_dev, rows, V, cdf_dev, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_wnc_encode(const uint32_t *cum_lo_dev, const uint32_t *cum_hi_dev, uint64_t m, uint8_t *out_dev,
+                              uint64_t cap, uint64_t *nbits, void *stream) {
+  if (!nbits || !out_dev || (m && (!cum_lo_dev || !cum_hi_dev)) || (reinterpret_cast<uintptr_t>(out_dev) & 3u))
+    return PMKLC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint64_t need = (17 * m + 2 + 7) / 8;
+  uint64_t need_words = (17 * m + 2 + 31) / 32;
+  if (cap / 4 < need_words) { *nbits = 8 * need; return PMKLC_ERR_BUFFER_TOO_SMALL; }
+  uint64_t *nb_dev = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&nb_dev), 16, st));
+  int *err = reinterpret_cast<int *>(nb_dev + 1);
+  uint64_t hb = 0;
+  int herr = 0;
+  hipError_t e = hipMemsetAsync(nb_dev, 0, 16, st);
+  if (e == hipSuccess)
+    e = launch_wnc_encode(cum_lo_dev, cum_hi_dev, m, reinterpret_cast<uint32_t *>(out_dev),
+                          (uint32_t)std::min<uint64_t>(cap / 4, 0xFFFFFFFFu), nb_dev, err, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hb, nb_dev, 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFreeAsync(nb_dev, st);
+  if (e != hipSuccess) return PMKLC_ERR_DEVICE;
+  if (herr) return PMKLC_ERR_DEVICE;
+  *nbits = hb;
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_wnc_decode(const uint8_t *in_dev, uint64_t nbytes, const uint32_t *cdfs_dev, uint32_t V,
+                              uint64_t m, uint32_t *symbols_dev, void *stream) {
+  if (V < 2 || V > 256 || (m && (!cdfs_dev || !symbols_dev)) || (nbytes && !in_dev) ||
+      (reinterpret_cast<uintptr_t>(in_dev) & 3u) || (nbytes & 3u))
+    return PMKLC_ERR_INVALID_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_wnc_decode(reinterpret_cast<const uint32_t *>(in_dev), (uint32_t)(nbytes / 4), cdfs_dev, V, m,
+                            symbols_dev, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_dev, uint64_t l, const float *static_dev,
+                               const float *init_dev, uint64_t stop, const uint64_t *probe_steps_host, uint32_t n_probe,
+                               float *probs_dev, float *params_dev, void *stream) {
+  pmklc_status rc = check_cfg(cfg);
+  if (rc) return rc;
+  if (!(cfg->selector & PMKLC_SEL_DM) || !tokens_dev) return PMKLC_ERR_INVALID_ARG;
+  if (cfg->precision != PMKLC_FP32) return PMKLC_ERR_UNSUPPORTED;
+  Model m;
+  rc = make_model(cfg, m);
+  if (rc) return rc;
+  if (m.d.static_on && !static_dev) return PMKLC_ERR_MODEL_MISMATCH;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const uint32_t bs = cfg->bs;
+  uint64_t L = l / bs;
+  if (L > 0xFFFFFFFFull) return PMKLC_ERR_UNSUPPORTED;
+  Sizes z{};
+  z.tokens = 0;
+  z.slot_words = (uint64_t)slot_words_for(L) * bs;
+  Arena A{nullptr, ~0ull};
+  Work w;
+  layout(A, m, 1, z, cfg->optimizer == PMKLC_ADAM, false, w);
+  uint8_t *base = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&base), A.used + 256, st));
+  Arena B{base, A.used + 256};
+  layout(B, m, 1, z, cfg->optimizer == PMKLC_ADAM, false, w);
+  uint64_t *probe_dev = nullptr;
+  StepArgs a;
+  memset(&a, 0, sizeof a);
+  std::vector<BlockDesc> bd(1);
+  bd[0] = BlockDesc{0, 0, (uint32_t)L, slot_words_for(L), 0, -1, 0, 0};
+  std::vector<uint64_t> probe(probe_steps_host, probe_steps_host + n_probe);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  if (n_probe) {
+    chk(hipMallocAsync(reinterpret_cast<void **>(&probe_dev), 8ull * n_probe, st));
+    chk(h2d(probe_dev, probe, st));
+  }
+  chk(h2d(w.desc, bd, st));
+  if (init_dev) chk(hipMemcpyAsync(w.init, init_dev, 4ull * (m.d.P + 1), hipMemcpyDeviceToDevice, st));
+  else chk(launch_init_params(m.d, cfg->seed, w.init, st));
+  chk(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
+  a.d = m.d;
+  a.lay = m.lay;
+  a.mode = 0;
+  a.n_blocks = 1;
+  a.blocks = w.desc;
+  a.tokens = const_cast<uint8_t *>(tokens_dev);
+  a.params = w.params;
+  a.adam_m = w.adam_m;
+  a.adam_v = w.adam_v;
+  a.init = w.init;
+  a.stat = static_dev;
+  a.snap_flag = w.snap_flag;
+  a.queue = w.ctr;
+  a.err = w.ctr + 1;
+  a.slots = w.slots;
+  a.seg_bits = w.seg_bits;
+  a.seg_words = w.seg_words;
+  a.stop = stop;
+  a.probe_steps = probe_dev;
+  a.n_probe = (int)n_probe;
+  a.probe_P = probs_dev;
+  a.params_out = params_dev;
+  a.spin_limit = 1ll << 30;
+  if (e == hipSuccess) chk(launch_step(a, 1, m.nt, st));
+  int herr[2] = {0, 0};
+  chk(hipMemcpyAsync(herr, w.ctr, 8, hipMemcpyDeviceToHost, st));
+  chk(hipStreamSynchronize(st));
+  (void)hipFreeAsync(base, st);
+  if (probe_dev) (void)hipFreeAsync(probe_dev, st);
+  (void)hipStreamSynchronize(st);
+  if (e != hipSuccess || herr[1]) return PMKLC_ERR_DEVICE;
+  return PMKLC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Library-private declarations shared by the HIP sources of libpmklc.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmklc {
+
+constexpr int kTotalBits = 16;
+constexpr uint32_t kTotal = 1u << kTotalBits;  // frequency total of the coder
+constexpr int kMaxLayers = 3;                  // up to two hidden layers + output
+constexpr int kFixShift = 44;                  // fixed-point scale of the embedding-gradient sums
+
+// Runtime shape of one model (dynamic or static, which share a shape).
+struct Dims {
+  int V, E, t, D, bs, nh;
+  int H[2];
+  int dim[kMaxLayers + 1];      // dim[0] = D, ..., dim[nh+1] = V
+  int off_emb;
+  int off_W[kMaxLayers], off_b[kMaxLayers];
+  int P;                        // parameters without the mixing weight
+  int stride;                   // floats per block parameter slab (>= P+1, multiple of 64)
+  int RS;                       // context ring length (power of two >= t + CH)
+  int CH;                       // tokens staged per row at a time (encode)
+  int static_on;                // frozen static model mixed in (Eq. 1)
+  int model_on;                 // dynamic model present (else every token is uniform)
+  int optimizer;                // 0 SGD, 1 Adam
+  float lr, b1, b2, eps;
+};
+
+// LDS layout (byte offsets into dynamic shared memory).
+struct LdsLayout {
+  int emb, embs, ring, act[2], lm, lu, cdf, tgt, dh[2], demb, misc, total;
+};
+
+// One data block as the step kernel sees it.
+struct BlockDesc {
+  uint64_t tok_off;      // first token of the block in the token array
+  uint64_t slot_off;     // first 32-bit word of the block's segment slots
+  uint32_t L;            // steps = tokens per segment
+  uint32_t slot_words;   // words per segment slot
+  uint32_t S;            // model passing point (steps); used when has_snap
+  int32_t pred;          // block whose snapshot initialises this one, or -1
+  int32_t has_snap;      // a successor waits on this block's snapshot
+  int32_t pad;
+};
+
+struct StepArgs {
+  Dims d;
+  LdsLayout lay;
+  int mode;                       // 0 encode, 1 decode
+  int n_blocks;
+  const BlockDesc *blocks;
+  uint8_t *tokens;                // encode: input; decode: output
+  float *params;                  // [n_blocks][stride] live parameters (+ a at index P)
+  float *adam_m, *adam_v;         // [n_blocks][stride] or null
+  const float *init;              // [stride] seeded initial parameters (+ a)
+  const float *stat;              // [P] static parameters or null
+  float *snap;                    // [n_blocks][stride] model-passing snapshots or null
+  int *snap_flag;                 // [n_blocks] 1 when the snapshot is written
+  int *queue;                     // work counter (zeroed before launch)
+  int *err;                       // error word (0 = ok)
+  uint32_t *slots;                // encode: segment slots; decode: aligned streams
+  uint32_t *seg_bits;             // encode: bits per segment [n_blocks][bs]
+  uint32_t *seg_words;            // decode: words available per segment [n_blocks][bs]
+  // trace/probe (block 0 only)
+  uint64_t stop;                  // 0 = all steps
+  const uint64_t *probe_steps;    // device, sorted
+  int n_probe;
+  float *probe_P;                 // [n_probe][bs][V]
+  float *params_out;              // [P+1] parameters after the last step, or null
+  long long spin_limit;           // bound on model-passing waits (iterations)
+};
+
+hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);
+hipError_t launch_init_params(const Dims &d, uint64_t seed, float *out, hipStream_t st);
+hipError_t launch_quantise(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf, hipStream_t st);
+hipError_t launch_wnc_encode(const uint32_t *lo, const uint32_t *hi, uint64_t m, uint32_t *out_words,
+                             uint32_t cap_words, uint64_t *nbits_dev, int *err, hipStream_t st);
+hipError_t launch_wnc_decode(const uint32_t *words, uint32_t nwords, const uint32_t *cdfs, uint32_t V,
+                             uint64_t m, uint32_t *sym, hipStream_t st);
+
+// ---- sequence kernels (tokeniser, scan, inverse) ----
+struct SeqBlock {              // per block, shared by the scan / tokenise / inverse kernels
+  uint64_t raw_off, raw_len;   // raw input bytes
+  uint64_t chunk0;             // first scan chunk of the block
+  uint64_t run0, n_runs;       // first run in the run table, count
+  uint64_t nb;                 // bases after N removal
+  uint64_t tok_off, l;         // token array offset, token count
+  uint64_t tail_off;           // first tail base (stripped coordinates)
+  uint64_t ex_off;             // offset of the block's extras (tail codes then remainder tokens)
+  uint64_t L;                  // steps
+};
+
+constexpr int kScanChunk = 4096;   // raw bytes per scan chunk
+
+struct ChunkStat {             // per scan chunk
+  uint32_t n_N, n_runs, bad, pad;
+};
+
+hipError_t launch_skmer_direct(const uint8_t *in, uint64_t n, int s, int k, uint8_t *tok, uint64_t l, int *err,
+                               hipStream_t st);
+hipError_t launch_scan(const uint8_t *in, const SeqBlock *blk, const uint64_t *chunk_block, uint64_t n_chunks,
+                       ChunkStat *stats, hipStream_t st);
+// run_end: filled with run ends; run_sp_kernel turns them into lengths
+hipError_t launch_runs(const uint8_t *in, const SeqBlock *blk, const uint64_t *chunk_block, uint64_t n_chunks,
+                       const ChunkStat *stats, const uint64_t *chunk_run0, uint32_t *run_start, uint32_t *run_len,
+                       hipStream_t st);
+hipError_t launch_run_sp(const SeqBlock *blk, int n_blocks, const uint32_t *run_start, uint32_t *run_len,
+                         uint32_t *run_sp, uint32_t *run_cum, hipStream_t st);
+hipError_t launch_tokenise(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t max_l,
+                           const uint32_t *run_sp, const uint32_t *run_cum, int s, int k, uint8_t *tok,
+                           hipStream_t st);
+hipError_t launch_extras(const uint8_t *in, const SeqBlock *blk, int n_blocks, const uint32_t *run_sp,
+                         const uint32_t *run_cum, int s, int k, int bs, const uint8_t *tok, uint8_t *extras,
+                         hipStream_t st);
+hipError_t launch_detok(const SeqBlock *blk, int n_blocks, uint64_t max_raw, const uint32_t *run_start,
+                        const uint32_t *run_len, const uint32_t *run_cum, int s, int k, int bs, const uint8_t *tok,
+                        const uint8_t *extras, uint8_t *out, hipStream_t st);
+// streams: segment i is seg_bytes[i] bytes at byte offset src[i] (or words
+// src_word[i]) -> dst
+hipError_t launch_gather_streams(const uint32_t *slots, const uint64_t *seg_src_word, const uint64_t *seg_dst,
+                                 const uint32_t *seg_bytes, uint64_t n_seg, uint8_t *dst, hipStream_t st);
+hipError_t launch_scatter_streams(const uint8_t *src, const uint64_t *seg_src, const uint64_t *seg_dst_word,
+                                  const uint32_t *seg_bytes, const uint32_t *seg_words, uint64_t n_seg,
+                                  uint32_t *slots, hipStream_t st);
+
+}  // namespace pmklc

@@ -1,0 +1,311 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bit-exact: (s,k)-mer tokens, integer CDFs given identical FP32
+probabilities, coded bytes given identical CDF streams, the whole container
+under the uniform model, GPU-alone round trips, determinism across launch
+schedules. Tolerances: per-symbol probabilities within 1e-4 of the FP64
+oracle for the FP32 path (teacher-forced at identical weights, and along a
+whole block's trajectory); compression ratio within 0.5% of the oracle's.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from synth.workloads import model_small
+from tests import cbf
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+PAIRS = [(s, k) for k in range(1, 5) for s in range(1, k + 1)]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2507_12805_amd as P
+    P.load()
+    return P
+
+
+def _dna(n, seed=0, order=3, n_rate=0.0, rho=0.0):
+    return synth.generate(synth.Recipe(n=n, order=order, seed=seed, n_rate=n_rate, n_max=30, rho=rho))
+
+
+def _cuda(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+# ------------------------------------------------------------------ GskE
+@pytest.mark.parametrize("s,k", PAIRS)
+def test_skmer_matches_oracle(gpu, orc, s, k):
+    for n in [0, 1, 3, 4, 5, 17, 1023, 4097, 100003]:
+        a = _dna(n, seed=n + 7 * k + s)
+        got = gpu.encode_skmer(_cuda(a), s, k).cpu().numpy()
+        assert np.array_equal(got, orc.encode_skmer(a, s, k)), (s, k, n)
+
+
+def test_skmer_unaligned_input_and_errors(gpu, orc):
+    a = _dna(20000, seed=3)
+    x = _cuda(a)
+    for off in [1, 2, 3]:
+        got = gpu.encode_skmer(x[off:], 3, 3).cpu().numpy()
+        assert np.array_equal(got, orc.encode_skmer(a[off:], 3, 3))
+    bad = a.copy()
+    bad[12345] = ord("N")
+    with pytest.raises(gpu.PmklcError) as e:
+        gpu.encode_skmer(_cuda(bad), 3, 3)
+    assert e.value.code == -2
+    bad[12345] = ord("a")
+    with pytest.raises(gpu.PmklcError):
+        gpu.encode_skmer(_cuda(bad), 1, 1)
+    with pytest.raises(gpu.PmklcError) as e:
+        gpu.encode_skmer(x, 4, 3)
+    assert e.value.code == -1
+
+
+def test_skmer_table8_size_sampled(gpu, orc):
+    """The (s,k) sweep input size of the paper's Table 8 (554,197,554 bases):
+    every (s,k) pair on the full sequence, checked on sampled windows."""
+    n = 554_197_554
+    a = synth.generate(synth.recipe_cfg1(seed=8, n=n))
+    x = _cuda(a)
+    rng = np.random.default_rng(0)
+    for s, k in PAIRS:
+        tok = gpu.encode_skmer(x, s, k)
+        l = (n - k) // s + 1
+        assert tok.numel() == l
+        idx = np.sort(rng.integers(0, l, size=2000))
+        idx[-1] = l - 1
+        got = tok[_cuda(idx.astype(np.int64))].cpu().numpy()
+        want = np.array([orc.encode_skmer(a[j * s:j * s + k], s, k)[0] for j in idx])
+        assert np.array_equal(got, want), (s, k)
+        del tok
+
+
+# ----------------------------------------------------- quantiser, coder
+@pytest.mark.parametrize("V", [4, 16, 64, 256])
+def test_quantiser_bit_exact(gpu, orc, V):
+    rng = np.random.default_rng(V)
+    P = rng.dirichlet([0.1] * V, size=3000).astype(np.float32)
+    P[0] = 0.0
+    P[0, 5 % V] = 1.0
+    P[1] = np.float32(1.0 / V)
+    got = gpu.quantise(_cuda(P)).cpu().numpy().astype(np.uint32)
+    want = orc.quantise(P.astype(np.float64))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("V,skew", [(4, 0.5), (64, 0.05), (256, 0.2)])
+def test_coder_bytes_bit_exact(gpu, orc, V, skew):
+    rng = np.random.default_rng(11 * V)
+    m = 5000
+    P = rng.dirichlet([skew] * V, size=m)
+    cdf = orc.quantise(P)
+    sym = np.array([rng.choice(V, p=P[i]) for i in range(m)])
+    lo, hi = cdf[np.arange(m), sym], cdf[np.arange(m), sym + 1]
+    data_g, nb_g = gpu.wnc_encode(lo, hi)
+    data_o, nb_o = orc.wnc_encode(lo, hi)
+    assert nb_g == nb_o and data_g == data_o
+    dec = gpu.wnc_decode(data_g, cdf).cpu().numpy()
+    assert np.array_equal(dec, sym)
+
+
+# --------------------------------------------------------- containers
+def _tiny(**kw):
+    c = model_small(t=4, E=4, hidden=[8], bs=8)
+    c.update(kw)
+    return c
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_uniform_container_bit_exact_with_oracle(gpu, orc, k):
+    a = _dna(50003, seed=k, n_rate=0.001)
+    cfg = _tiny(s=k, k=k, selector="uniform", n_blocks=5)
+    blob_g = gpu.compress(cfg, _cuda(a))
+    blob_o = orc.compress(cfg, a)
+    assert blob_g == blob_o
+    assert np.array_equal(gpu.decompress(blob_g).cpu().numpy(), a)
+
+
+ROUNDTRIP = {
+    "cfg1": (dict(), 1 << 18, 1, 0.0),
+    "tiny_multi_N": (dict(t=4, E=4, hidden=[8], bs=8, n_blocks=3), 30011, 1, 0.003),
+    "s1k3_static": (dict(s=1, k=3, t=8, E=4, hidden=[16], bs=16, selector="spum_dm", n_blocks=2), 20000, 2, 0.001),
+    "two_hidden_adam": (dict(t=6, E=8, hidden=[16, 12], bs=8, optimizer="adam", n_blocks=2), 24000, 3, 0.0),
+    "s2k3": (dict(s=2, k=3, t=5, E=4, hidden=[8], bs=12), 9001, 4, 0.0),
+    "k4": (dict(s=4, k=4, t=3, E=4, hidden=[8], bs=4), 8000, 5, 0.0),
+}
+
+
+@pytest.mark.parametrize("name", list(ROUNDTRIP))
+def test_gpu_roundtrip_and_ratio(gpu, orc, name):
+    kw, n, seed, nrate = ROUNDTRIP[name]
+    cfg = model_small(**kw)
+    a = _dna(n, seed=seed, n_rate=nrate, rho=0.05)
+    static = None
+    if cfg["selector"] == "spum_dm":
+        static = orc.init_params(cfg, seed=123).astype(np.float32)
+    blob = gpu.compress(cfg, _cuda(a), static=static)
+    back = gpu.decompress(blob, static=static).cpu().numpy()
+    assert np.array_equal(back, a)
+    assert gpu.compress(cfg, _cuda(a), static=static) == blob          # deterministic
+    blob_o = orc.compress(cfg, a, static=static)
+    assert len(blob) == pytest.approx(len(blob_o), rel=0.005, abs=2)
+    pg, po = cbf.parse(blob), cbf.parse(blob_o)
+    assert pg["header"]["path"] == 1 and po["header"]["path"] == 0
+    for bg, bo in zip(pg["blocks"], po["blocks"]):     # identical metadata
+        assert (bg["raw_len"], bg["runs"], bg["extras"]) == (bo["raw_len"], bo["runs"], bo["extras"])
+
+
+def test_plain_and_batched_schedules_give_identical_bytes(gpu):
+    a = _dna(40000, seed=9)
+    cfg = _tiny(n_blocks=4)
+    b1 = gpu.compress(dict(cfg, schedule="batched"), _cuda(a))
+    b2 = gpu.compress(dict(cfg, schedule="plain"), _cuda(a))
+    assert b1 == b2
+
+
+def test_smp_chain_roundtrip_and_snapshot(gpu, orc):
+    a = _dna(30000, seed=10, n_rate=0.001)
+    cfg = _tiny(block_len=[5000, 7000, 3000, 9000, 6000], file_blocks=[3, 2], smp_ppm=50000)
+    blob = gpu.compress(cfg, _cuda(a))
+    assert np.array_equal(gpu.decompress(blob).cpu().numpy(), a)
+    blob_o = orc.compress(cfg, a)
+    assert len(blob) == pytest.approx(len(blob_o), rel=0.005)
+    assert blob != gpu.compress(dict(cfg, smp_ppm=0), _cuda(a))
+
+
+@pytest.mark.parametrize("raw", ["", "A", "AC", "ACG", "N" * 40, "ANNNNNC", "ACGT" * 9, "NACGTN" * 30])
+def test_edge_cases(gpu, orc, raw):
+    a = np.frombuffer(raw.encode(), dtype=np.uint8).copy()
+    for nblk in [1, 3]:
+        cfg = _tiny(n_blocks=nblk)
+        blob = gpu.compress(cfg, _cuda(a) if len(a) else np.zeros(0, np.uint8))
+        assert np.array_equal(gpu.decompress(blob).cpu().numpy()[:len(a)], a)
+        pg, po = cbf.parse(blob), cbf.parse(orc.compress(cfg, a))
+        for bg, bo in zip(pg["blocks"], po["blocks"]):
+            assert (bg["raw_len"], bg["runs"], bg["extras"], bg["L"]) == (bo["raw_len"], bo["runs"], bo["extras"],
+                                                                          bo["L"])
+            if bg["L"] <= cfg["t"]:      # only uniform steps: identical streams
+                assert bg["streams"] == bo["streams"]
+
+
+def test_errors(gpu):
+    cfg = _tiny()
+    with pytest.raises(gpu.PmklcError) as e:
+        gpu.compress(cfg, _cuda(np.frombuffer(b"ACGTACGTXACGT", dtype=np.uint8).copy()))
+    assert e.value.code == -2
+    a = _dna(5000, seed=1)
+    blob = gpu.compress(cfg, _cuda(a))
+    for bad in [blob[:50], blob[:-2], b"QQQQ" + blob[4:]]:
+        with pytest.raises(gpu.PmklcError) as e:
+            gpu.decompress(bad)
+        assert e.value.code in (-4, -5)
+    cs = _tiny(selector="spum_dm")
+    st = np.random.default_rng(0).normal(0, 0.1, gpu.param_count(cs)).astype(np.float32)
+    b2 = gpu.compress(cs, _cuda(a), static=st)
+    wrong = st.copy()
+    wrong[3] += 1
+    with pytest.raises(gpu.PmklcError) as e:
+        gpu.decompress(b2, static=wrong)
+    assert e.value.code == -5
+
+
+# ------------------------------------------------- probability parity
+def test_teacher_forced_probabilities_and_gradient(gpu, orc):
+    """At identical weights the GPU's FP32 step gives P within 1e-4 of the
+    FP64 oracle, and its SGD update matches w - lr * grad_oracle."""
+    rec, cfg = synth.recipe_cfg1(), model_small()
+    a = synth.generate(rec)
+    tok = orc.encode_skmer(a, 3, 3)
+    L = len(tok) // cfg["bs"]
+    for i in [cfg["t"], cfg["t"] + 1, L // 2, L - 1]:
+        _, w_i = gpu.model_trace(cfg, tok, stop=i)
+        P_i, w_i1 = gpu.model_trace(cfg, tok, steps=[i], stop=i + 1)
+        w64 = w_i.cpu().numpy().astype(np.float64)
+        n = len(w64) - 1
+        rows = np.arange(cfg["bs"]) * L + i
+        ctx = np.stack([tok[r - cfg["t"]:r] for r in rows])
+        Po, g, _, _ = orc.step(cfg, w64[:n], ctx, tok[rows])
+        assert np.max(np.abs(P_i[0].cpu().numpy() - Po)) <= 1e-4
+        expect = w64[:n] - cfg["lr"] * g
+        assert np.max(np.abs(w_i1.cpu().numpy()[:n] - expect)) <= 1e-6
+
+
+def test_trajectory_probabilities_cfg1(gpu, orc):
+    """Whole-block trajectory of the first workload (256 KiB, one block):
+    sampled steps' P within 1e-4 of the FP64 oracle, code ratio within 0.5%."""
+    rec, cfg = synth.recipe_cfg1(), model_small()
+    a = synth.generate(rec)
+    tok = orc.encode_skmer(a, 3, 3)
+    L = len(tok) // cfg["bs"]
+    steps = [0, cfg["t"], cfg["t"] + 5, 100, L // 2, L - 2, L - 1]
+    Pg, wg = gpu.model_trace(cfg, tok, steps=steps)
+    Po, _, wo = orc.trace_block(cfg, tok, steps=steps)
+    d = np.abs(Pg.cpu().numpy() - Po)
+    assert d.max() <= 1e-4, d.max()
+    assert np.max(np.abs(wg.cpu().numpy() - wo)) <= 1e-4
+    blob_g = gpu.compress(cfg, _cuda(a))
+    blob_o = orc.compress(cfg, a)
+    assert abs(len(blob_g) - len(blob_o)) <= 0.005 * len(blob_o)
+
+
+def test_static_mixer_probabilities(gpu, orc):
+    """Eq. 1 with the frozen static model (the second workload's model
+    shape) on a short sequence: P within 1e-4 along the trajectory."""
+    cfg = model_small(s=1, k=3, hidden=[128], selector="spum_dm")
+    static = np.fromfile(os.path.join(GOLD, "static_cfg2.f32"), dtype=np.float32)
+    a = synth.generate(synth.recipe_cfg2(seed=22, n=64 * 400 + 2))
+    a = a[a != ord("N")]
+    tok = orc.encode_skmer(a, 1, 3)
+    L = len(tok) // cfg["bs"]
+    steps = [cfg["t"], 100, L - 1]
+    Pg, wg = gpu.model_trace(cfg, tok, steps=steps, static=static)
+    Po, _, wo = orc.trace_block(cfg, tok, steps=steps, static=static)
+    assert np.abs(Pg.cpu().numpy() - Po).max() <= 1e-4
+    assert abs(float(wg[-1]) - wo[-1]) <= 1e-4      # learned mixing weight
+
+
+# ---------------------------------------------------- full-size workload
+def test_full_size_static_workload_roundtrip(gpu, orc):
+    """The 64 MiB, 16-block static + dynamic workload at full size, in the
+    bench's launch configuration: bit-exact GPU round trip, metadata equal to
+    the oracle's, and teacher-forced P at sampled steps of block 0."""
+    from synth.workloads import cfg2
+    rec, cfg = cfg2()
+    static = np.fromfile(os.path.join(GOLD, "static_cfg2.f32"), dtype=np.float32)
+    a = synth.generate(rec)
+    x = _cuda(a)
+    blob = gpu.compress(cfg, x, static=static)
+    back = gpu.decompress(blob, static=static)
+    assert bool((back == x).all())
+    p = cbf.parse(blob)
+    assert p["header"]["n_blocks"] == 16
+    # block metadata (N runs) against the oracle's scan of the same bytes
+    blk_len = len(a) // 16
+    for b in [0, 7, 15]:
+        seg = a[b * blk_len:(b + 1) * blk_len]
+        isn = np.r_[False, seg == ord("N"), False]
+        starts = np.flatnonzero(~isn[:-1] & isn[1:])
+        ends = np.flatnonzero(isn[:-1] & ~isn[1:])
+        assert p["blocks"][b]["runs"] == list(zip(starts.tolist(), (ends - starts).tolist()))
+    # teacher-forced probabilities at sampled steps of block 0
+    seg = a[:blk_len]
+    tok = orc.encode_skmer(seg[seg != ord("N")], 1, 3)
+    L = len(tok) // cfg["bs"]
+    for i in [cfg["t"], 1000]:
+        _, w_i = gpu.model_trace(cfg, tok, static=static, stop=i)
+        P_i, _ = gpu.model_trace(cfg, tok, static=static, steps=[i], stop=i + 1)
+        w64 = w_i.cpu().numpy().astype(np.float64)
+        n = len(w64) - 1
+        rows = np.arange(cfg["bs"]) * L + i
+        ctx = np.stack([tok[r - cfg["t"]:r] for r in rows])
+        Po, _, _, _ = orc.step(cfg, w64[:n], ctx, tok[rows], ws=static.astype(np.float64), a_alpha=w64[n])
+        assert np.max(np.abs(P_i[0].cpu().numpy() - Po)) <= 1e-4
