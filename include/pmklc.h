@@ -153,6 +153,19 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
                                const uint64_t *probe_steps_host, uint32_t n_probe, float *probs_dev,
                                float *params_dev, void *stream);
 
+/* Timing of the last pmklc_compress / pmklc_decompress on this thread,
+ * measured with HIP events on the call's stream around the step kernel
+ * (the per-block learning + coding loop), plus the work it did. */
+typedef struct pmklc_timing {
+  float step_ms;          /* step kernel(s): first launch start to last launch end */
+  float call_ms;          /* whole call, host entry to return */
+  uint64_t model_rows;    /* rows (tokens) that went through the model: sum_b bs * max(0, L_b - t) */
+  uint64_t coded_tokens;  /* tokens coded by the arithmetic coders: sum_b bs * L_b */
+  uint64_t max_steps;     /* longest block's step count (the critical path) */
+  uint32_t launches;      /* step-kernel launches */
+} pmklc_timing;
+pmklc_status pmklc_last_timing(pmklc_timing *t);
+
 /* Number of model parameters (without the mixing weight) for cfg. */
 uint64_t pmklc_param_count(const pmklc_config *cfg);
 

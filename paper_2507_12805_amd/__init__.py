@@ -43,6 +43,11 @@ class _Config(ctypes.Structure):
                 ("static_host", ctypes.POINTER(ctypes.c_float)), ("static_len", ctypes.c_uint64)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("step_ms", ctypes.c_float), ("call_ms", ctypes.c_float), ("model_rows", ctypes.c_uint64),
+                ("coded_tokens", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("launches", ctypes.c_uint32)]
+
+
 _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
 _u32 = ctypes.c_uint32
@@ -69,6 +74,8 @@ def load():
     L.pmklc_wnc_encode.argtypes = [_vp, _vp, _u64, _vp, _u64, _u64p, _vp]
     L.pmklc_wnc_decode.argtypes = [_vp, _u64, _vp, _u32, _u64, _vp, _vp]
     L.pmklc_model_trace.argtypes = [cp, _vp, _u64, _vp, _vp, _u64, _u64p, _u32, _vp, _vp, _vp]
+    L.pmklc_last_timing.argtypes = [ctypes.POINTER(Timing)]
+    L.pmklc_last_timing.restype = ctypes.c_int
     L.pmklc_param_count.argtypes = [cp]
     L.pmklc_param_count.restype = _u64
     for f in ["pmklc_encode_skmer", "pmklc_compress_bound", "pmklc_compress", "pmklc_decompress_info",
@@ -149,6 +156,14 @@ def make_config(cfg: dict, static=None):
         c.static_host = s.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         c.static_len = s.size
     return c, keep
+
+
+def last_timing() -> dict:
+    """HIP-event timing of the step kernel in the last compress/decompress
+    call on this thread, and the work it did."""
+    t = Timing()
+    _check(load().pmklc_last_timing(ctypes.byref(t)), "pmklc_last_timing")
+    return {f: getattr(t, f) for f, _ in Timing._fields_}
 
 
 def param_count(cfg: dict) -> int:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -405,8 +406,27 @@ void fill_blockdesc(const Model &m, const std::vector<SeqBlock> &sb, const Plan 
   }
 }
 
+thread_local pmklc_timing g_last = {};
+
+struct StepTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~StepTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+void count_work(const Model &m, const std::vector<BlockDesc> &bd, pmklc_timing &t) {
+  t.model_rows = t.coded_tokens = t.max_steps = 0;
+  for (const BlockDesc &d : bd) {
+    t.coded_tokens += (uint64_t)d.L * m.d.bs;
+    if (m.d.model_on && d.L > (uint32_t)m.d.t) t.model_rows += (uint64_t)(d.L - m.d.t) * m.d.bs;
+    t.max_steps = std::max<uint64_t>(t.max_steps, d.L);
+  }
+}
+
 pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
-                      hipStream_t st) {
+                      hipStream_t st, StepTimer *tm = nullptr) {
   StepArgs a;
   memset(&a, 0, sizeof a);
   a.d = m.d;
@@ -431,6 +451,12 @@ pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector
   HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.snap_flag, 0, bd.size() * sizeof(int), st));
   if (bd.empty()) return PMKLC_OK;
+  if (tm) {
+    HIP_TRY(hipEventCreate(&tm->a));
+    HIP_TRY(hipEventCreate(&tm->b));
+    HIP_TRY(hipEventRecord(tm->a, st));
+  }
+  g_last.launches = schedule == PMKLC_PLAIN ? (uint32_t)bd.size() : 1;
   if (schedule == PMKLC_PLAIN) {
     // one block per launch, in block order (the per-block baseline)
     for (size_t b = 0; b < bd.size(); b++) {
@@ -455,7 +481,15 @@ pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector
     int grid = (int)std::min<uint64_t>(bd.size(), (uint64_t)std::max(ncu, 1));
     HIP_TRY(launch_step(a, grid, m.nt, st));
   }
+  if (tm) HIP_TRY(hipEventRecord(tm->b, st));
   return PMKLC_OK;
+}
+
+// after the stream has been synchronised
+void finish_timing(StepTimer &tm, std::chrono::steady_clock::time_point t0) {
+  float ms = 0.0f;
+  if (tm.a && tm.b && hipEventElapsedTime(&ms, tm.a, tm.b) == hipSuccess) g_last.step_ms = ms;
+  g_last.call_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 }  // namespace
@@ -539,6 +573,9 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t 
 pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
                             uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
                             void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  g_last = pmklc_timing{};
+  StepTimer tm;
   pmklc_status rc = check_cfg(cfg);
   if (rc) return rc;
   if (!out_len || (n && !in_dev) || !ws_dev) return PMKLC_ERR_INVALID_ARG;
@@ -635,7 +672,8 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
       HIP_TRY(hipMemcpyAsync(w.stat, cfg->static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
     }
   }
-  rc = run_step(m, w, 0, bd, cfg->schedule, st);
+  count_work(m, bd, g_last);
+  rc = run_step(m, w, 0, bd, cfg->schedule, st, &tm);
   if (rc) return rc;
   std::vector<uint32_t> seg_bits, run_start, run_len;
   std::vector<uint8_t> extras;
@@ -694,6 +732,7 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
     HIP_TRY(hipStreamSynchronize(st));
   }
   *out_len = total;
+  finish_timing(tm, t0);
   return PMKLC_OK;
 }
 
@@ -851,6 +890,9 @@ pmklc_status pmklc_decompress_info(const uint8_t *cbf_host, uint64_t len, uint64
 pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float *static_host, uint64_t static_len,
                               void *ws_dev, uint64_t ws_bytes, uint8_t *out_dev, uint64_t out_cap, uint64_t *out_len,
                               void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  g_last = pmklc_timing{};
+  StepTimer tm;
   if (!out_len || !ws_dev) return PMKLC_ERR_INVALID_ARG;
   Parsed o;
   pmklc_status rc = parse(cbf_host, len, o, true);
@@ -921,7 +963,8 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
     HIP_TRY(launch_init_params(m.d, o.c.seed, w.init, st));
     if (m.d.static_on) HIP_TRY(hipMemcpyAsync(w.stat, static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
   }
-  rc = run_step(m, w, 1, bd, PMKLC_BATCHED, st);
+  count_work(m, bd, g_last);
+  rc = run_step(m, w, 1, bd, PMKLC_BATCHED, st, &tm);
   if (rc) return rc;
   uint64_t max_raw = 0;
   for (const SeqBlock &q : o.sb) max_raw = std::max(max_raw, q.raw_len);
@@ -932,6 +975,13 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   HIP_TRY(hipStreamSynchronize(st));
   if (ctr[1]) return PMKLC_ERR_DEVICE;
   *out_len = o.n;
+  finish_timing(tm, t0);
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_last_timing(pmklc_timing *t) {
+  if (!t) return PMKLC_ERR_INVALID_ARG;
+  *t = g_last;
   return PMKLC_OK;
 }
 
