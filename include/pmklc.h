@@ -48,7 +48,14 @@ typedef enum {
 } pmklc_status;
 
 enum { PMKLC_SGD = 0, PMKLC_ADAM = 1 };
-enum { PMKLC_FP32 = 0, PMKLC_BF16 = 1 };          /* arithmetic of the model GEMMs */
+/* Arithmetic of the model GEMMs. PMKLC_FP32 uses the FP32 matrix-core kernel
+ * when the model shape allows it (one hidden layer; bs, hidden and V multiples
+ * of 32, E of 8) and the per-thread FMA kernel otherwise; PMKLC_FP32_VALU
+ * always uses the per-thread FMA kernel; PMKLC_BF16 rounds GEMM inputs to
+ * BF16 on the matrix cores (FP32 accumulation; softmax, mixing weight,
+ * quantiser and optimiser state stay FP32). The container records which
+ * numeric path made it, and only that path decodes it. */
+enum { PMKLC_FP32 = 0, PMKLC_BF16 = 1, PMKLC_FP32_VALU = 2 };
 enum { PMKLC_BATCHED = 0, PMKLC_PLAIN = 1 };      /* all blocks in one launch | one block per launch */
 /* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. */
 enum {
@@ -68,7 +75,7 @@ typedef struct pmklc_config {
   uint32_t hidden[4];       /* hidden widths */
   uint32_t optimizer;       /* PMKLC_SGD | PMKLC_ADAM */
   float lr, beta1, beta2, eps;
-  uint32_t precision;       /* PMKLC_FP32 | PMKLC_BF16 */
+  uint32_t precision;       /* PMKLC_FP32 | PMKLC_BF16 | PMKLC_FP32_VALU */
   uint32_t schedule;        /* PMKLC_BATCHED | PMKLC_PLAIN */
   uint32_t selector;        /* PMKLC_SEL_* mask: 0, DM, or SPUM|DM */
   uint32_t smp_ppm;         /* step-wise model passing point in parts per million of a
@@ -163,8 +170,29 @@ typedef struct pmklc_timing {
   uint64_t coded_tokens;  /* tokens coded by the arithmetic coders: sum_b bs * L_b */
   uint64_t max_steps;     /* longest block's step count (the critical path) */
   uint32_t launches;      /* step-kernel launches */
+  uint32_t threads;       /* threads per workgroup the autotuner chose */
 } pmklc_timing;
 pmklc_status pmklc_last_timing(pmklc_timing *t);
+
+/* The dynamic model as a differentiable op (Sec. 4.2.4 with the MLP
+ * reading; Sec. 2 step (4)), for autograd use and gradient checks. Uses
+ * cfg's k, t, embed, n_hidden (0..2) and hidden; any widths.
+ *   params_dev: n_params FP32 (layout above, no mixing weight);
+ *   ctx_dev: rows x t token ids (u8, < 4^k; oldest first);
+ *   logits_dev: rows x V FP32 output.
+ * pmklc_dm_backward writes grad_dev (n_params FP32, same layout) = the
+ * gradient of sum(dlogits * logits) with respect to the parameters; the
+ * activations are recomputed from ctx_dev, not stored. The embedding
+ * gradient is summed in 64-bit fixed point (scale 2^44), so results do not
+ * depend on scheduling. ws_dev must hold pmklc_dm_workspace bytes. A token
+ * >= 4^k gives PMKLC_ERR_INVALID_ARG. */
+pmklc_status pmklc_dm_workspace(const pmklc_config *cfg, uint32_t rows, uint64_t *ws_bytes);
+pmklc_status pmklc_dm_forward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev,
+                              uint32_t rows, float *logits_dev, void *ws_dev, uint64_t ws_bytes,
+                              void *stream);
+pmklc_status pmklc_dm_backward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev,
+                               uint32_t rows, const float *dlogits_dev, float *grad_dev, void *ws_dev,
+                               uint64_t ws_bytes, void *stream);
 
 /* Number of model parameters (without the mixing weight) for cfg. */
 uint64_t pmklc_param_count(const pmklc_config *cfg);

@@ -45,7 +45,8 @@ class _Config(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_float), ("call_ms", ctypes.c_float), ("model_rows", ctypes.c_uint64),
-                ("coded_tokens", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("launches", ctypes.c_uint32)]
+                ("coded_tokens", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("launches", ctypes.c_uint32),
+                ("threads", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -74,6 +75,11 @@ def load():
     L.pmklc_wnc_encode.argtypes = [_vp, _vp, _u64, _vp, _u64, _u64p, _vp]
     L.pmklc_wnc_decode.argtypes = [_vp, _u64, _vp, _u32, _u64, _vp, _vp]
     L.pmklc_model_trace.argtypes = [cp, _vp, _u64, _vp, _vp, _u64, _u64p, _u32, _vp, _vp, _vp]
+    L.pmklc_dm_workspace.argtypes = [cp, _u32, _u64p]
+    L.pmklc_dm_forward.argtypes = [cp, _vp, _vp, _u32, _vp, _vp, _u64, _vp]
+    L.pmklc_dm_backward.argtypes = [cp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, _vp]
+    for f in ["pmklc_dm_workspace", "pmklc_dm_forward", "pmklc_dm_backward"]:
+        getattr(L, f).restype = ctypes.c_int
     L.pmklc_last_timing.argtypes = [ctypes.POINTER(Timing)]
     L.pmklc_last_timing.restype = ctypes.c_int
     L.pmklc_param_count.argtypes = [cp]
@@ -114,6 +120,7 @@ def _dev_tensor(x, dtype):
 
 
 SELECTORS = {"uniform": 0, "dm": 4, "spum_dm": 5}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp32_valu": 2}
 
 
 def make_config(cfg: dict, static=None):
@@ -128,7 +135,7 @@ def make_config(cfg: dict, static=None):
     c.optimizer = 1 if cfg.get("optimizer", "sgd") == "adam" else 0
     c.lr, c.beta1, c.beta2, c.eps = cfg.get("lr", 1e-3), cfg.get("beta1", 0.9), cfg.get("beta2", 0.999), \
         cfg.get("eps", 1e-8)
-    c.precision = 1 if cfg.get("precision", "fp32") == "bf16" else 0
+    c.precision = PRECISIONS[cfg.get("precision", "fp32")]
     c.schedule = 1 if cfg.get("schedule", "batched") == "plain" else 0
     c.selector = SELECTORS[cfg.get("selector", "dm")]
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
@@ -310,3 +317,40 @@ def model_trace(cfg: dict, tokens, steps=(), static=None, init=None, stop: int =
                                st.ctypes.data_as(_u64p) if len(st) else None, len(st), _dptr(P), _dptr(params),
                                _stream()), "pmklc_model_trace")
     return P[:len(st)], params
+
+
+# ------------------------------------------------- differentiable DM op
+def dm_forward(cfg: dict, params, ctx):
+    """Logits [rows, V] of the dynamic model for contexts ctx [rows, t]."""
+    torch = _torch()
+    L = load()
+    c, _ = make_config(cfg)
+    p = _dev_tensor(params, torch.float32)
+    x = _dev_tensor(ctx, torch.uint8)
+    rows = x.shape[0]
+    ws_b = ctypes.c_uint64(0)
+    _check(L.pmklc_dm_workspace(ctypes.byref(c), rows, ctypes.byref(ws_b)), "pmklc_dm_workspace")
+    ws = torch.empty(ws_b.value, dtype=torch.uint8, device="cuda")
+    out = torch.empty((rows, 4 ** cfg["k"]), dtype=torch.float32, device="cuda")
+    _check(L.pmklc_dm_forward(ctypes.byref(c), _dptr(p), _dptr(x), rows, _dptr(out), _dptr(ws), ws.numel(),
+                              _stream()), "pmklc_dm_forward")
+    return out
+
+
+def dm_backward(cfg: dict, params, ctx, dlogits):
+    """Gradient of sum(dlogits * logits) with respect to the flat parameters
+    (activations recomputed by the kernel)."""
+    torch = _torch()
+    L = load()
+    c, _ = make_config(cfg)
+    p = _dev_tensor(params, torch.float32)
+    x = _dev_tensor(ctx, torch.uint8)
+    g = _dev_tensor(dlogits, torch.float32)
+    rows = x.shape[0]
+    ws_b = ctypes.c_uint64(0)
+    _check(L.pmklc_dm_workspace(ctypes.byref(c), rows, ctypes.byref(ws_b)), "pmklc_dm_workspace")
+    ws = torch.empty(ws_b.value, dtype=torch.uint8, device="cuda")
+    grad = torch.zeros_like(p)
+    _check(L.pmklc_dm_backward(ctypes.byref(c), _dptr(p), _dptr(x), rows, _dptr(g), _dptr(grad), _dptr(ws),
+                               ws.numel(), _stream()), "pmklc_dm_backward")
+    return grad

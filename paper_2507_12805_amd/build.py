@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmklc.so")
-SOURCES = ["step_kernel.hip", "seq_kernels.hip", "api.cpp"]
+SOURCES = ["step_kernel.hip", "step_mfma.hip", "seq_kernels.hip", "dm_op.hip", "api.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     # packed FP32 instructions are kept out of every kernel

@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/pmklc.h"
@@ -16,7 +18,9 @@ using namespace pmklc;
 
 namespace {
 
-constexpr uint8_t kPathFP32 = 1, kPathBF16 = 2, kPathUniform = 255;
+// numeric path of a container: which kernel computed its probabilities
+constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathUniform = 255;
+enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2 };
 constexpr int kHeaderBytes = 80;
 
 #define HIP_TRY(x)                                     \
@@ -115,6 +119,7 @@ struct Model {
   Dims d;
   LdsLayout lay;
   int nt;
+  int kind;
 };
 
 pmklc_status check_cfg(const pmklc_config *c) {
@@ -125,7 +130,7 @@ pmklc_status check_cfg(const pmklc_config *c) {
   if (c->n_hidden > 4) return PMKLC_ERR_INVALID_ARG;
   for (uint32_t l = 0; l < c->n_hidden; l++)
     if (c->hidden[l] < 1 || c->hidden[l] > 65535) return PMKLC_ERR_INVALID_ARG;
-  if (c->optimizer > 1 || c->precision > 1 || c->schedule > 1) return PMKLC_ERR_INVALID_ARG;
+  if (c->optimizer > 1 || c->precision > 2 || c->schedule > 1) return PMKLC_ERR_INVALID_ARG;
   if (c->selector != PMKLC_SEL_UNIFORM && c->selector != PMKLC_SEL_DM &&
       c->selector != (PMKLC_SEL_SPUM | PMKLC_SEL_DM)) {
     return (c->selector & PMKLC_SEL_SPRM) ? PMKLC_ERR_UNSUPPORTED : PMKLC_ERR_INVALID_ARG;
@@ -145,12 +150,11 @@ uint64_t param_count(uint32_t k, uint32_t t, uint32_t E, uint32_t nh, const uint
 
 // Shape + LDS plan of the step kernel; UNSUPPORTED when this build's kernel
 // cannot hold it (see the design notes: tile and LDS limits).
-pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh,
-                        const uint32_t *hidden, uint32_t selector, uint32_t opt, float lr, float b1, float b2,
-                        float eps, Model &m) {
-  (void)s;
-  Dims &d = m.d;
+// Shape and parameter offsets of the model (no kernel-support checks).
+pmklc_status fill_dims(uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh, const uint32_t *hidden,
+                       uint32_t selector, uint32_t opt, float lr, float b1, float b2, float eps, Dims &d) {
   memset(&d, 0, sizeof d);
+  if (nh > 2) return PMKLC_ERR_UNSUPPORTED;
   d.V = 1 << (2 * k);
   d.E = (int)E;
   d.t = (int)t;
@@ -161,16 +165,8 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
   d.static_on = (selector & PMKLC_SEL_SPUM) ? 1 : 0;
   d.optimizer = (int)opt;
   d.lr = lr; d.b1 = b1; d.b2 = b2; d.eps = eps;
-  if (!d.model_on) {
-    // uniform coding needs no model; keep a minimal valid shape
-    d.nh = 0;
-  }
-  if (d.model_on) {
-    if (nh > 2) return PMKLC_ERR_UNSUPPORTED;
-    if (E % 4 || bs % 4 || d.V % 4) return PMKLC_ERR_UNSUPPORTED;
-    for (uint32_t l = 0; l < nh; l++) if (hidden[l] % 4) return PMKLC_ERR_UNSUPPORTED;
-    if ((uint64_t)t * E > (1u << 20)) return PMKLC_ERR_UNSUPPORTED;
-  }
+  if (!d.model_on) d.nh = 0;   // uniform coding needs no model
+  if ((uint64_t)t * E > (1u << 20)) return PMKLC_ERR_UNSUPPORTED;
   d.dim[0] = d.D;
   for (int l = 0; l < d.nh; l++) { d.H[l] = (int)hidden[l]; d.dim[l + 1] = (int)hidden[l]; }
   d.dim[d.nh + 1] = d.V;
@@ -186,6 +182,24 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
   if (off > (1ull << 30)) return PMKLC_ERR_UNSUPPORTED;
   d.P = (int)off;
   d.stride = (int)align_up(off + 1, 64);
+  return PMKLC_OK;
+}
+
+// Shape + LDS plan of the step kernel; UNSUPPORTED when this build's kernels
+// cannot hold it (tile multiples of 4, LDS <= 160 KB, at most two hidden
+// layers).
+pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh,
+                        const uint32_t *hidden, uint32_t selector, uint32_t opt, float lr, float b1, float b2,
+                        float eps, uint32_t precision, Model &m) {
+  (void)s;
+  Dims &d = m.d;
+  pmklc_status rc = fill_dims(k, t, bs, E, nh, hidden, selector, opt, lr, b1, b2, eps, d);
+  if (rc) return rc;
+  if (d.model_on) {
+    if (E % 4 || bs % 4 || d.V % 4) return PMKLC_ERR_UNSUPPORTED;
+    for (uint32_t l = 0; l < nh; l++) if (hidden[l] % 4) return PMKLC_ERR_UNSUPPORTED;
+  }
+
   d.CH = 32;
   int rs = 1;
   while (rs < d.t + d.CH) rs <<= 1;
@@ -214,12 +228,23 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
   if (o > 160 * 1024) return PMKLC_ERR_UNSUPPORTED;
   m.nt = bs <= 256 ? 256 : 512;
   if (bs > 512) return PMKLC_ERR_UNSUPPORTED;
+  // matrix-core kernel: one hidden layer, tile-friendly shapes
+  const bool mfma_ok = d.model_on && d.nh == 1 && bs % 32 == 0 && bs <= 128 && d.H[0] % 32 == 0 && d.V % 32 == 0 &&
+                       E % 8 == 0 && d.D % 32 == 0;
+  m.kind = kGeneric;
+  if (precision == PMKLC_BF16) {
+    if (d.model_on && !mfma_ok) return PMKLC_ERR_UNSUPPORTED;
+    m.kind = kMfmaBf16;
+  } else if (precision == PMKLC_FP32 && mfma_ok) {
+    m.kind = kMfmaF32;
+  }
+  if (m.kind != kGeneric) m.nt = 512;
   return PMKLC_OK;
 }
 
 pmklc_status make_model(const pmklc_config *c, Model &m) {
   return make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, c->selector, c->optimizer, c->lr,
-                    c->beta1, c->beta2, c->eps, m);
+                    c->beta1, c->beta2, c->eps, c->precision, m);
 }
 
 // -------------------------------------------------------------- planning
@@ -287,6 +312,7 @@ struct Work {
   uint64_t *seg_src, *seg_dst;
   uint32_t *seg_bytes;
   uint8_t *staging;
+  StepArgs *args;         // device copies of the step-kernel arguments (one per launch)
 };
 
 struct Sizes {
@@ -321,6 +347,70 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   w.seg_dst = A.take<uint64_t>((uint64_t)n_blocks * m.d.bs);
   w.seg_bytes = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
   w.staging = A.take<uint8_t>(z.staging + 16);
+  w.args = A.take<StepArgs>((uint64_t)n_blocks + 1);
+}
+
+// One synthetic block of t + 64 steps (constant tokens) in encode mode,
+// best of two runs, with the candidate width.
+hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms) {
+  m.nt = nt;
+  const uint32_t L = (uint32_t)m.d.t + 64;
+  Sizes z{};
+  z.tokens = (uint64_t)L * m.d.bs;
+  z.slot_words = (uint64_t)slot_words_for(L) * m.d.bs;
+  Arena A{nullptr, ~0ull};
+  Work w;
+  layout(A, m, 1, z, m.d.optimizer == 1, false, w);
+  uint8_t *base = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&base), A.used + 256);
+  if (e != hipSuccess) return e;
+  Arena B{base, A.used + 256};
+  layout(B, m, 1, z, m.d.optimizer == 1, false, w);
+  BlockDesc bd{0, 0, L, slot_words_for(L), 0, -1, 0, 0};
+  StepArgs a;
+  memset(&a, 0, sizeof a);
+  a.d = m.d;
+  a.lay = m.lay;
+  a.n_blocks = 1;
+  a.blocks = w.desc;
+  a.tokens = w.tok;
+  a.params = w.params;
+  a.adam_m = w.adam_m;
+  a.adam_v = w.adam_v;
+  a.init = w.init;
+  a.stat = m.d.static_on ? w.init : nullptr;
+  a.snap_flag = w.snap_flag;
+  a.queue = w.ctr;
+  a.err = w.ctr + 1;
+  a.slots = w.slots;
+  a.seg_bits = w.seg_bits;
+  a.seg_words = w.seg_words;
+  a.spin_limit = 1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float best = 1e30f;
+  if (e == hipSuccess) e = hipMemcpyAsync(w.desc, &bd, sizeof bd, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(w.tok, 1, z.tokens, st);
+  if (e == hipSuccess) e = launch_init_params(m.d, 1, w.init, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(w.args, &a, sizeof a, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int rep = 0; rep < 2 && e == hipSuccess; rep++) {
+    e = hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess)
+      e = m.kind == kGeneric ? launch_step(a, 1, nt, st) : launch_step_mfma(a, w.args, 1, m.kind == kMfmaBf16, nt, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e == hipSuccess) best = std::min(best, t);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(base);
+  *ms = best;
+  return e;
 }
 
 template <class T>
@@ -335,9 +425,9 @@ hipError_t d2h(std::vector<T> &v, const T *src, uint64_t count, hipStream_t st) 
   return hipMemcpyAsync(v.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, st);
 }
 
-uint8_t path_of(uint32_t selector, uint32_t precision) {
+uint8_t path_of(uint32_t selector, int kind) {
   if (!(selector & PMKLC_SEL_DM)) return kPathUniform;
-  return precision == PMKLC_BF16 ? kPathBF16 : kPathFP32;
+  return kind == kMfmaBf16 ? kPathBF16 : kind == kMfmaF32 ? kPathFP32Mfma : kPathFP32Valu;
 }
 
 void write_header(Writer &o, const pmklc_config *c, uint8_t path, uint32_t scrc, uint64_t n, uint32_t n_files) {
@@ -408,6 +498,54 @@ void fill_blockdesc(const Model &m, const std::vector<SeqBlock> &sb, const Plan 
 
 thread_local pmklc_timing g_last = {};
 
+// ------------------------------------------------------------- autotuner
+// Picks the threads per workgroup of the step kernel (4 or 8 waves) for a
+// model shape by timing a short synthetic block with each candidate, and
+// caches the choice for the process. The choice never changes a value:
+// every output element is computed by one thread or wave in a fixed order
+// whatever the workgroup size. PMKLC_NT=256|512 forces a width.
+struct TuneEntry {
+  int kind, bs, H0, H1, V, E, t, nh, stat, opt;
+  int nt;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+
+hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms);
+
+int choose_nt(Model &m, hipStream_t st) {
+  const char *env = getenv("PMKLC_NT");
+  std::vector<int> cands;
+  if (m.kind == kGeneric) {
+    cands = {256};
+    if (m.d.bs <= 512) cands.push_back(512);
+  } else {
+    cands = {256, 512};
+  }
+  if (m.d.bs > 256) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
+  if (env) {
+    int f = atoi(env);
+    if (std::find(cands.begin(), cands.end(), f) != cands.end()) return f;
+  }
+  if (cands.size() == 1 || !m.d.model_on) return cands[0];
+  TuneEntry key{m.kind, m.d.bs, m.d.H[0], m.d.H[1], m.d.V, m.d.E, m.d.t, m.d.nh, m.d.static_on, m.d.optimizer, 0};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneEntry &e : g_tune)
+    if (e.kind == key.kind && e.bs == key.bs && e.H0 == key.H0 && e.H1 == key.H1 && e.V == key.V && e.E == key.E &&
+        e.t == key.t && e.nh == key.nh && e.stat == key.stat && e.opt == key.opt)
+      return e.nt;
+  int best = cands.back();
+  float best_ms = 1e30f;
+  for (int nt : cands) {
+    float ms = 0.0f;
+    if (time_candidate(m, nt, st, &ms) != hipSuccess) continue;
+    if (ms < best_ms) { best_ms = ms; best = nt; }
+  }
+  key.nt = best;
+  g_tune.push_back(key);
+  return best;
+}
+
 struct StepTimer {
   hipEvent_t a = nullptr, b = nullptr;
   ~StepTimer() {
@@ -425,8 +563,10 @@ void count_work(const Model &m, const std::vector<BlockDesc> &bd, pmklc_timing &
   }
 }
 
-pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
+pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
                       hipStream_t st, StepTimer *tm = nullptr) {
+  m.nt = choose_nt(m, st);
+  g_last.threads = (uint32_t)m.nt;
   StepArgs a;
   memset(&a, 0, sizeof a);
   a.d = m.d;
@@ -457,10 +597,14 @@ pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector
     HIP_TRY(hipEventRecord(tm->a, st));
   }
   g_last.launches = schedule == PMKLC_PLAIN ? (uint32_t)bd.size() : 1;
+  // host copies of the kernel arguments stay alive until the stream has
+  // consumed them (synchronised before returning)
+  std::vector<StepArgs> hold(schedule == PMKLC_PLAIN ? bd.size() : 1);
   if (schedule == PMKLC_PLAIN) {
     // one block per launch, in block order (the per-block baseline)
     for (size_t b = 0; b < bd.size(); b++) {
-      StepArgs one = a;
+      StepArgs &one = hold[b];
+      one = a;
       one.n_blocks = 1;
       one.blocks = w.desc + b;
       // parameters/slots/bits are indexed by the block number: offset them
@@ -472,16 +616,22 @@ pmklc_status run_step(const Model &m, const Work &w, int mode, const std::vector
       one.queue = w.ctr + 2 + (int)(b % 60);
       if (bd[b].pred >= 0 || bd[b].has_snap) return PMKLC_ERR_UNSUPPORTED;
       HIP_TRY(hipMemsetAsync(one.queue, 0, sizeof(int), st));
-      HIP_TRY(launch_step(one, 1, m.nt, st));
+      HIP_TRY(hipMemcpyAsync(w.args + b, &one, sizeof(StepArgs), hipMemcpyHostToDevice, st));
+      if (m.kind == kGeneric) HIP_TRY(launch_step(one, 1, m.nt, st));
+      else HIP_TRY(launch_step_mfma(one, w.args + b, 1, m.kind == kMfmaBf16, m.nt, st));
     }
   } else {
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     int grid = (int)std::min<uint64_t>(bd.size(), (uint64_t)std::max(ncu, 1));
-    HIP_TRY(launch_step(a, grid, m.nt, st));
+    hold[0] = a;
+    HIP_TRY(hipMemcpyAsync(w.args, &hold[0], sizeof(StepArgs), hipMemcpyHostToDevice, st));
+    if (m.kind == kGeneric) HIP_TRY(launch_step(a, grid, m.nt, st));
+    else HIP_TRY(launch_step_mfma(a, w.args, grid, m.kind == kMfmaBf16, m.nt, st));
   }
   if (tm) HIP_TRY(hipEventRecord(tm->b, st));
+  HIP_TRY(hipStreamSynchronize(st));
   return PMKLC_OK;
 }
 
@@ -585,7 +735,6 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
   if ((cfg->selector & PMKLC_SEL_SPUM) &&
       (!cfg->static_host || cfg->static_len != (uint64_t)m.d.P))
     return PMKLC_ERR_MODEL_MISMATCH;
-  if (cfg->precision != PMKLC_FP32 && (cfg->selector & PMKLC_SEL_DM)) return PMKLC_ERR_UNSUPPORTED;
   const bool smp = cfg->smp_ppm > 0 && (cfg->selector & PMKLC_SEL_DM);
   Plan p;
   rc = plan_blocks(n, cfg->n_blocks, cfg->block_len_host, cfg->n_files, cfg->file_blocks_host, smp, p);
@@ -688,7 +837,7 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
 
   // ---- A12: container
   Writer meta{out_host, out_cap};
-  write_header(meta, cfg, path_of(cfg->selector, cfg->precision), scrc, n, (uint32_t)p.file_blocks.size());
+  write_header(meta, cfg, path_of(cfg->selector, m.kind), scrc, n, (uint32_t)p.file_blocks.size());
   for (uint64_t fb : p.file_blocks) meta.varint(fb);
   std::vector<uint64_t> seg_src, seg_dst;
   std::vector<uint32_t> seg_bytes;
@@ -783,9 +932,10 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.n_blocks = (uint32_t)r.le(4);
   uint32_t nf = (uint32_t)r.le(4);
   if (r.bad) return PMKLC_ERR_CORRUPT;
-  c.precision = o.path == kPathBF16 ? PMKLC_BF16 : PMKLC_FP32;
+  c.precision = o.path == kPathBF16 ? PMKLC_BF16 : o.path == kPathFP32Valu ? PMKLC_FP32_VALU : PMKLC_FP32;
   if (check_cfg(&c)) return PMKLC_ERR_CORRUPT;
-  if (o.path != path_of(c.selector, c.precision)) return PMKLC_ERR_MODEL_MISMATCH;
+  if (o.path != kPathUniform && o.path != kPathBF16 && o.path != kPathFP32Valu && o.path != kPathFP32Mfma)
+    return PMKLC_ERR_MODEL_MISMATCH;
   if (nf < 1 || (uint64_t)nf > len || (uint64_t)c.n_blocks * 2 > len) return PMKLC_ERR_CORRUPT;
   o.file_blocks.resize(nf);
   uint64_t tot = 0;
@@ -900,11 +1050,11 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   Model m;
   rc = make_model(&o.c, m);
   if (rc) return rc;
+  if (path_of(o.c.selector, m.kind) != o.path) return PMKLC_ERR_MODEL_MISMATCH;
   if (m.d.static_on) {
     if (!static_host || static_len != (uint64_t)m.d.P || crc32(static_host, 4ull * m.d.P) != o.scrc)
       return PMKLC_ERR_MODEL_MISMATCH;
   }
-  if (o.c.precision != PMKLC_FP32 && m.d.model_on) return PMKLC_ERR_UNSUPPORTED;
   if (o.n > out_cap) { *out_len = o.n; return PMKLC_ERR_BUFFER_TOO_SMALL; }
   if (o.n && !out_dev) return PMKLC_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -979,6 +1129,50 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   return PMKLC_OK;
 }
 
+// ------------------------------------------------ differentiable DM op
+static pmklc_status dm_dims(const pmklc_config *cfg, Dims &d) {
+  pmklc_status rc = check_cfg(cfg);
+  if (rc) return rc;
+  return fill_dims(cfg->k, cfg->t, cfg->bs, cfg->embed, cfg->n_hidden, cfg->hidden, PMKLC_SEL_DM, cfg->optimizer,
+                   cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, d);
+}
+
+pmklc_status pmklc_dm_workspace(const pmklc_config *cfg, uint32_t rows, uint64_t *ws_bytes) {
+  Dims d;
+  pmklc_status rc = dm_dims(cfg, d);
+  if (rc) return rc;
+  if (!ws_bytes) return PMKLC_ERR_INVALID_ARG;
+  *ws_bytes = dm_op_workspace(d, (int)rows);
+  return PMKLC_OK;
+}
+
+pmklc_status pmklc_dm_forward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev, uint32_t rows,
+                              float *logits_dev, void *ws_dev, uint64_t ws_bytes, void *stream) {
+  Dims d;
+  pmklc_status rc = dm_dims(cfg, d);
+  if (rc) return rc;
+  if (rows == 0) return PMKLC_OK;
+  if (!params_dev || !ctx_dev || !logits_dev || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+  if (ws_bytes < dm_op_workspace(d, (int)rows)) return PMKLC_ERR_BUFFER_TOO_SMALL;
+  int err = 0;
+  HIP_TRY(dm_forward(d, params_dev, ctx_dev, (int)rows, logits_dev, ws_dev, &err, static_cast<hipStream_t>(stream)));
+  return err ? PMKLC_ERR_INVALID_ARG : PMKLC_OK;
+}
+
+pmklc_status pmklc_dm_backward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev, uint32_t rows,
+                               const float *dlogits_dev, float *grad_dev, void *ws_dev, uint64_t ws_bytes,
+                               void *stream) {
+  Dims d;
+  pmklc_status rc = dm_dims(cfg, d);
+  if (rc) return rc;
+  if (!params_dev || !ctx_dev || !dlogits_dev || !grad_dev || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+  if (ws_bytes < dm_op_workspace(d, (int)rows)) return PMKLC_ERR_BUFFER_TOO_SMALL;
+  int err = 0;
+  HIP_TRY(dm_backward(d, params_dev, ctx_dev, (int)rows, dlogits_dev, grad_dev, ws_dev, &err,
+                      static_cast<hipStream_t>(stream)));
+  return err ? PMKLC_ERR_INVALID_ARG : PMKLC_OK;
+}
+
 pmklc_status pmklc_last_timing(pmklc_timing *t) {
   if (!t) return PMKLC_ERR_INVALID_ARG;
   *t = g_last;
@@ -1039,11 +1233,11 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   pmklc_status rc = check_cfg(cfg);
   if (rc) return rc;
   if (!(cfg->selector & PMKLC_SEL_DM) || !tokens_dev) return PMKLC_ERR_INVALID_ARG;
-  if (cfg->precision != PMKLC_FP32) return PMKLC_ERR_UNSUPPORTED;
   Model m;
   rc = make_model(cfg, m);
   if (rc) return rc;
   if (m.d.static_on && !static_dev) return PMKLC_ERR_MODEL_MISMATCH;
+  m.nt = choose_nt(m, static_cast<hipStream_t>(stream));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t bs = cfg->bs;
   uint64_t L = l / bs;
@@ -1097,7 +1291,11 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   a.probe_P = probs_dev;
   a.params_out = params_dev;
   a.spin_limit = 1ll << 30;
-  if (e == hipSuccess) chk(launch_step(a, 1, m.nt, st));
+  chk(hipMemcpyAsync(w.args, &a, sizeof(StepArgs), hipMemcpyHostToDevice, st));
+  if (e == hipSuccess) {
+    if (m.kind == kGeneric) chk(launch_step(a, 1, m.nt, st));
+    else chk(launch_step_mfma(a, w.args, 1, m.kind == kMfmaBf16, m.nt, st));
+  }
   int herr[2] = {0, 0};
   chk(hipMemcpyAsync(herr, w.ctr, 8, hipMemcpyDeviceToHost, st));
   chk(hipStreamSynchronize(st));

@@ -72,12 +72,20 @@ struct StepArgs {
 };
 
 hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);
+hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, hipStream_t st);
 hipError_t launch_init_params(const Dims &d, uint64_t seed, float *out, hipStream_t st);
 hipError_t launch_quantise(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf, hipStream_t st);
 hipError_t launch_wnc_encode(const uint32_t *lo, const uint32_t *hi, uint64_t m, uint32_t *out_words,
                              uint32_t cap_words, uint64_t *nbits_dev, int *err, hipStream_t st);
 hipError_t launch_wnc_decode(const uint32_t *words, uint32_t nwords, const uint32_t *cdfs, uint32_t V,
                              uint64_t m, uint32_t *sym, hipStream_t st);
+
+// ---- the dynamic model as a stand-alone differentiable op ----
+uint64_t dm_op_workspace(const Dims &d, int rows);
+hipError_t dm_forward(const Dims &d, const float *W, const uint8_t *ctx, int rows, float *logits, void *ws,
+                      int *err_host, hipStream_t st);
+hipError_t dm_backward(const Dims &d, const float *W, const uint8_t *ctx, int rows, const float *dlogits,
+                       float *grad, void *ws, int *err_host, hipStream_t st);
 
 // ---- sequence kernels (tokeniser, scan, inverse) ----
 struct SeqBlock {              // per block, shared by the scan / tokenise / inverse kernels

@@ -1,0 +1,473 @@
+// Device code shared by the step kernels (library-private).
+#pragma once
+#include "pmklc_internal.h"
+
+namespace pmklc {
+namespace detail {
+
+
+constexpr uint32_t kHalf = 0x80000000u;
+constexpr uint32_t kQuarter = 0x40000000u;
+
+__device__ __forceinline__ float wave_max(float x) {
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ __forceinline__ float wave_sum(float x) {
+  for (int o = 32; o > 0; o >>= 1) x = x + __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ int wave_sum_i(int x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ void wave_argmax(float &v, int &i) {
+  for (int o = 32; o > 0; o >>= 1) {
+    float ov = __shfl_xor(v, o);
+    int oi = __shfl_xor(i, o);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+  }
+}
+// inclusive scan of ints over the 64 lanes (lane order)
+__device__ __forceinline__ int wave_scan_incl(int x, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------- coder
+struct Enc {
+  uint32_t low, high, pending, widx;
+  uint64_t buf, nbits;
+  int nbuf;
+};
+__device__ __forceinline__ void enc_init(Enc &e) {
+  e.low = 0; e.high = 0xFFFFFFFFu; e.pending = 0; e.widx = 0; e.buf = 0; e.nbits = 0; e.nbuf = 0;
+}
+__device__ __forceinline__ void enc_emit(Enc &e, uint32_t *slot, uint32_t cap, uint32_t bits, int n, int &ovf) {
+  e.buf = (e.buf << n) | (uint64_t)bits;
+  e.nbuf += n;
+  e.nbits += (uint64_t)n;
+  if (e.nbuf >= 32) {
+    e.nbuf -= 32;
+    uint32_t w = (uint32_t)(e.buf >> e.nbuf);
+    if (e.widx < cap) slot[e.widx] = __builtin_bswap32(w);
+    else ovf = 1;
+    e.widx++;
+    e.buf &= (1ull << e.nbuf) - 1ull;
+  }
+}
+__device__ __forceinline__ void enc_run(Enc &e, uint32_t *slot, uint32_t cap, int bit, uint32_t count, int &ovf) {
+  while (count) {
+    int n = count > 32u ? 32 : (int)count;
+    uint32_t bits = bit ? (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) : 0u;
+    enc_emit(e, slot, cap, bits, n, ovf);
+    count -= (uint32_t)n;
+  }
+}
+__device__ __forceinline__ void enc_symbol(Enc &e, uint32_t *slot, uint32_t cap, uint32_t lo, uint32_t hi, int &ovf) {
+  uint64_t r = (uint64_t)e.high - e.low + 1u;
+  uint32_t l0 = e.low;
+  e.high = l0 + (uint32_t)((r * hi) >> kTotalBits) - 1u;
+  e.low = l0 + (uint32_t)((r * lo) >> kTotalBits);
+  for (;;) {
+    if (e.high < kHalf) {
+      enc_emit(e, slot, cap, 0u, 1, ovf);
+      enc_run(e, slot, cap, 1, e.pending, ovf);
+      e.pending = 0;
+    } else if (e.low >= kHalf) {
+      enc_emit(e, slot, cap, 1u, 1, ovf);
+      enc_run(e, slot, cap, 0, e.pending, ovf);
+      e.pending = 0;
+      e.low -= kHalf;
+      e.high -= kHalf;
+    } else if (e.low >= kQuarter && e.high < 3u * kQuarter) {
+      e.pending++;
+      e.low -= kQuarter;
+      e.high -= kQuarter;
+    } else {
+      break;
+    }
+    e.low <<= 1;
+    e.high = (e.high << 1) | 1u;
+  }
+}
+__device__ __forceinline__ void enc_finish(Enc &e, uint32_t *slot, uint32_t cap, int &ovf) {
+  e.pending++;
+  int bit = e.low < kQuarter ? 0 : 1;
+  enc_emit(e, slot, cap, (uint32_t)bit, 1, ovf);
+  enc_run(e, slot, cap, !bit, e.pending, ovf);
+  e.pending = 0;
+  if (e.nbuf > 0) {
+    uint32_t w = (uint32_t)(e.buf << (32 - e.nbuf));
+    if (e.widx < cap) slot[e.widx] = __builtin_bswap32(w);
+    else ovf = 1;
+    e.widx++;
+    e.nbuf = 0;
+    e.buf = 0;
+  }
+}
+
+struct Dec {
+  uint32_t low, high, value, widx;
+  uint32_t buf;
+  int nbuf;
+};
+__device__ __forceinline__ int dec_bit(Dec &d, const uint32_t *w, uint32_t nw) {
+  if (d.nbuf == 0) {
+    d.buf = d.widx < nw ? __builtin_bswap32(w[d.widx]) : 0u;
+    d.widx++;
+    d.nbuf = 32;
+  }
+  d.nbuf--;
+  return (int)((d.buf >> d.nbuf) & 1u);
+}
+__device__ __forceinline__ void dec_init(Dec &d, const uint32_t *w, uint32_t nw) {
+  d.low = 0; d.high = 0xFFFFFFFFu; d.value = 0; d.widx = 0; d.buf = 0; d.nbuf = 0;
+  for (int i = 0; i < 32; i++) d.value = (d.value << 1) | (uint32_t)dec_bit(d, w, nw);
+}
+// cum(s) is the cumulative count below symbol s (cum(0) = 0, cum(V) = 2^16).
+template <class Cum>
+__device__ __forceinline__ int dec_symbol(Dec &d, const uint32_t *w, uint32_t nw, int V, Cum cum) {
+  uint64_t r = (uint64_t)d.high - d.low + 1u;
+  uint32_t target = d.value - d.low;
+  int a = 0, b = V;
+  while (b - a > 1) {
+    int m = (a + b) >> 1;
+    if ((uint32_t)((r * cum(m)) >> kTotalBits) <= target) a = m;
+    else b = m;
+  }
+  uint32_t l0 = d.low;
+  d.high = l0 + (uint32_t)((r * cum(a + 1)) >> kTotalBits) - 1u;
+  d.low = l0 + (uint32_t)((r * cum(a)) >> kTotalBits);
+  for (;;) {
+    if (d.high < kHalf) {
+    } else if (d.low >= kHalf) {
+      d.low -= kHalf; d.high -= kHalf; d.value -= kHalf;
+    } else if (d.low >= kQuarter && d.high < 3u * kQuarter) {
+      d.low -= kQuarter; d.high -= kQuarter; d.value -= kQuarter;
+    } else {
+      break;
+    }
+    d.low <<= 1;
+    d.high = (d.high << 1) | 1u;
+    d.value = (d.value << 1) | (uint32_t)dec_bit(d, w, nw);
+  }
+  return a;
+}
+
+// -------------------------------------------------- softmax + quantiser
+// One wave turns the V logits of a row into probabilities and an integer
+// CDF.  Lane l holds symbols l, l+64, ... (V <= 256).
+__device__ __forceinline__ void row_quantise(const float *p_in, int V, int lane, uint32_t *cdf) {
+  int f[4];
+  float pq[4];
+  int fsum = 0;
+  float best = -1.0f;
+  int besti = 0x7fffffff;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    int v = lane + 64 * q;
+    f[q] = 0;
+    pq[q] = 0.0f;
+    if (v < V) {
+      float p = p_in[q];
+      p = (p >= 0.0f && p <= 1.0f) ? p : 0.0f;
+      pq[q] = p;
+      // exact: a 24-bit mantissa times a 16-bit integer fits FP64
+      f[q] = 1 + (int)floor((double)p * (double)(kTotal - (uint32_t)V));
+      fsum += f[q];
+      if (p > best) { best = p; besti = v; }
+    }
+  }
+  fsum = wave_sum_i(fsum);
+  wave_argmax(best, besti);
+  besti = __builtin_amdgcn_readfirstlane(besti);
+  int resid = (int)kTotal - fsum;
+  int run = 0;
+#pragma unroll
+  for (int q = 0; q < 4; q++) {
+    if (64 * q >= V) break;
+    int v = lane + 64 * q;
+    int fv = (v < V) ? f[q] + (v == besti ? resid : 0) : 0;
+    int incl = wave_scan_incl(fv, lane);
+    if (v < V) cdf[v] = (uint32_t)(run + incl - fv);
+    run += __shfl(incl, 63);
+  }
+  if (lane == 0) cdf[V] = kTotal;
+  (void)pq;
+}
+
+__device__ __forceinline__ long long to_fixed(float x) {
+  double y = (double)x * (double)(1ull << kFixShift);
+  y = fmin(fmax(y, -4.0e18), 4.0e18);
+  return (long long)rint(y);
+}
+
+struct Opt {
+  int kind;
+  float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^tau, c2 = 1 - b2^tau
+};
+__device__ __forceinline__ float opt_delta(const Opt &o, float g, float *m, float *v) {
+  if (o.kind == 0) return o.lr * g;
+  float mm = o.b1 * (*m) + (1.0f - o.b1) * g;
+  float vv = o.b2 * (*v) + (1.0f - o.b2) * (g * g);
+  *m = mm;
+  *v = vv;
+  float mh = mm / o.c1, vh = vv / o.c2;
+  return o.lr * mh / (sqrtf(vh) + o.eps);
+}
+
+
+}  // namespace detail
+
+using namespace detail;
+
+// The per-block loop shared by every step kernel: block queue, model
+// passing, token staging, mixer + softmax + quantiser, coders, loss
+// gradient, embedding and mixing-weight updates.  `Net` supplies the
+// forward (logits into lm, and lu when the static model is on) and the
+// backward of the MLP layers (weight updates and the embedding-gradient
+// scatter); both end with a workgroup barrier.
+template <int NT, class Net>
+__device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds, Net &net) {
+  __shared__ int sh_b;
+  __shared__ float sh_ga;
+  const Dims &d = a.d;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int bs = d.bs, V = d.V, E = d.E, t = d.t, RS = d.RS, mask = d.RS - 1;
+  float *emb = reinterpret_cast<float *>(lds + a.lay.emb);
+  float *embs = reinterpret_cast<float *>(lds + a.lay.embs);
+  uint8_t *ring = lds + a.lay.ring;
+  float *lm = reinterpret_cast<float *>(lds + a.lay.lm);
+  float *lu = reinterpret_cast<float *>(lds + a.lay.lu);
+  uint32_t *cdf = reinterpret_cast<uint32_t *>(lds + a.lay.cdf);
+  uint8_t *tgt = lds + a.lay.tgt;
+  long long *demb = reinterpret_cast<long long *>(lds + a.lay.demb);
+  float *misc = reinterpret_cast<float *>(lds + a.lay.misc);   // [bs] row sums for the alpha gradient
+  const int stride = d.stride;
+  const float inv_bs = 1.0f / (float)bs;
+
+  for (;;) {
+    if (tid == 0) sh_b = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int b = sh_b;
+    __syncthreads();
+    if (b >= a.n_blocks) break;
+    const BlockDesc bd = a.blocks[b];
+    float *W = a.params + (size_t)b * stride;
+    float *M = a.adam_m ? a.adam_m + (size_t)b * stride : nullptr;
+    float *Vs = a.adam_v ? a.adam_v + (size_t)b * stride : nullptr;
+    uint64_t Lrun = bd.L;
+    if (a.stop && a.stop < Lrun) Lrun = a.stop;
+
+    // ---- initial parameters: seeded, or the predecessor's snapshot (Sec. 4.3)
+    const float *src = a.init;
+    if (bd.pred >= 0) {
+      if (tid == 0) {
+        long long spins = 0;
+        while (__hip_atomic_load(a.snap_flag + bd.pred, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+          __builtin_amdgcn_s_sleep(8);
+          if (++spins > a.spin_limit) { atomicOr(a.err, 4); break; }
+        }
+      }
+      __syncthreads();
+      src = a.snap + (size_t)bd.pred * stride;
+    }
+    for (int q = tid; q < stride; q += NT) {
+      W[q] = __builtin_nontemporal_load(src + q);
+      if (M) { M[q] = 0.0f; Vs[q] = 0.0f; }
+    }
+    __syncthreads();
+    for (int q = tid; q < V * E; q += NT) {
+      emb[q] = W[d.off_emb + q];
+      if (d.static_on) embs[q] = a.stat[d.off_emb + q];
+      demb[q] = 0;
+    }
+    __syncthreads();
+
+    auto snapshot = [&]() {
+      float *dst = a.snap + (size_t)b * stride;
+      for (int q = tid; q < stride; q += NT) dst[q] = (q >= d.off_emb && q < d.off_emb + V * E) ? emb[q - d.off_emb] : W[q];
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(a.snap_flag + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    if (bd.has_snap && bd.S == 0) snapshot();
+
+    // ---- coders: lane j < bs owns segment j
+    Enc enc;
+    Dec dec;
+    int ovf = 0;
+    uint32_t *slot = a.slots + bd.slot_off + (size_t)tid * bd.slot_words;
+    uint32_t nwords = 0;
+    if (tid < bs) {
+      if (a.mode == 0) enc_init(enc);
+      else {
+        nwords = a.seg_words[(size_t)b * bs + tid];
+        if (nwords > bd.slot_words) nwords = bd.slot_words;
+        dec_init(dec, slot, nwords);
+      }
+    }
+    Opt opt;
+    opt.kind = d.optimizer;
+    opt.lr = d.lr; opt.b1 = d.b1; opt.b2 = d.b2; opt.eps = d.eps;
+    float b1t = 1.0f, b2t = 1.0f;
+    int probe_i = 0;
+    const size_t tok0 = bd.tok_off;
+
+    for (uint64_t i = 0; i < Lrun; i++) {
+      const bool uniform = !d.model_on || i < (uint64_t)t;
+      // stage the true tokens of the next CH steps (encode)
+      if (a.mode == 0 && (i % (uint64_t)d.CH) == 0) {
+        const int CH = d.CH;
+        for (int q = tid; q < bs * CH; q += NT) {
+          int j = q / CH, c = q % CH;
+          uint64_t pos = i + (uint64_t)c;
+          if (pos < bd.L) ring[j * RS + (int)(pos & (uint64_t)mask)] = a.tokens[tok0 + (size_t)j * bd.L + pos];
+        }
+        __syncthreads();
+      }
+      float alpha = 0.0f;
+      if (!uniform) {
+        if (d.static_on) alpha = 1.0f / (1.0f + expf(-W[d.P]));
+        net.forward(W, i, alpha);
+        // mixer (Eq. 1) + softmax + quantiser, one wave per row
+        for (int j = wave; j < bs; j += NT / 64) {
+          float z[4], p[4];
+          float mx = -INFINITY;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            int v = lane + 64 * q;
+            z[q] = -INFINITY;
+            if (v < V) {
+              float m = lm[j * V + v];
+              z[q] = d.static_on ? (alpha * lu[j * V + v] + (1.0f - alpha) * m) : m;
+              mx = fmaxf(mx, z[q]);
+            }
+          }
+          mx = wave_max(mx);
+          float se = 0.0f;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            int v = lane + 64 * q;
+            p[q] = (v < V) ? expf(z[q] - mx) : 0.0f;
+            se += p[q];
+          }
+          se = wave_sum(se);
+          float srow = 0.0f;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            int v = lane + 64 * q;
+            if (v < V) {
+              p[q] = p[q] / se;
+              if (d.static_on) {
+                float diff = lu[j * V + v] - lm[j * V + v];
+                lu[j * V + v] = diff;
+                srow = fmaf(p[q], diff, srow);
+              }
+              lm[j * V + v] = p[q];
+            }
+          }
+          if (d.static_on) {
+            srow = wave_sum(srow);
+            if (lane == 0) misc[j] = srow;
+          }
+          row_quantise(p, V, lane, cdf + j * (V + 1));
+          if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+              int v = lane + 64 * q;
+              if (v < V) a.probe_P[((size_t)probe_i * bs + j) * V + v] = p[q];
+            }
+          }
+        }
+        __syncthreads();
+      } else if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) {
+        for (int q = tid; q < bs * V; q += NT) a.probe_P[(size_t)probe_i * bs * V + q] = 1.0f / (float)V;
+      }
+      if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) probe_i++;
+
+      // ---- coding: lane j codes token i of segment j
+      if (tid < bs) {
+        const int j = tid;
+        const int rp = j * RS + (int)(i & (uint64_t)mask);
+        const uint32_t unit = kTotal / (uint32_t)V;
+        if (a.mode == 0) {
+          int e = ring[rp];
+          uint32_t lo, hi;
+          if (uniform) { lo = (uint32_t)e * unit; hi = lo + unit; }
+          else { lo = cdf[j * (V + 1) + e]; hi = cdf[j * (V + 1) + e + 1]; }
+          enc_symbol(enc, slot, bd.slot_words, lo, hi, ovf);
+          tgt[j] = (uint8_t)e;
+        } else {
+          int e;
+          if (uniform) e = dec_symbol(dec, slot, nwords, V, [&](int s) { return (uint32_t)s * unit; });
+          else {
+            const uint32_t *c = cdf + j * (V + 1);
+            e = dec_symbol(dec, slot, nwords, V, [&](int s) { return c[s]; });
+          }
+          ring[rp] = (uint8_t)e;
+          tgt[j] = (uint8_t)e;
+          a.tokens[tok0 + (size_t)j * bd.L + i] = (uint8_t)e;
+        }
+      }
+      __syncthreads();
+
+      if (!uniform) {
+        // dz = (P - onehot)/bs (mean loss over the step's rows); dL^m = (1-alpha) dz
+        for (int q = tid; q < bs * V; q += NT) {
+          int j = q / V, v = q % V;
+          float dz = (lm[q] - (v == tgt[j] ? 1.0f : 0.0f)) * inv_bs;
+          lm[q] = d.static_on ? dz * (1.0f - alpha) : dz;
+        }
+        if (d.static_on && tid == 0) {
+          float acc = 0.0f;
+          for (int j = 0; j < bs; j++) acc += misc[j] - lu[j * V + tgt[j]];
+          sh_ga = acc * inv_bs * (alpha * (1.0f - alpha));
+        }
+        __syncthreads();
+        opt.c1 = 1.0f;
+        opt.c2 = 1.0f;
+        if (opt.kind == 1) {
+          b1t *= d.b1;
+          b2t *= d.b2;
+          opt.c1 = 1.0f - b1t;
+          opt.c2 = 1.0f - b2t;
+        }
+        net.backward(W, M, Vs, i, opt);
+        // embedding update from the fixed-point sums
+        for (int q = tid; q < V * E; q += NT) {
+          float gq = (float)((double)demb[q] * (1.0 / (double)(1ull << kFixShift)));
+          demb[q] = 0;
+          const int pi = d.off_emb + q;
+          emb[q] = emb[q] - opt_delta(opt, gq, M ? M + pi : nullptr, Vs ? Vs + pi : nullptr);
+        }
+        if (d.static_on && tid == 0) {
+          W[d.P] = W[d.P] - opt_delta(opt, sh_ga, M ? M + d.P : nullptr, Vs ? Vs + d.P : nullptr);
+        }
+        __syncthreads();
+      }
+      if (bd.has_snap && i + 1 == (uint64_t)bd.S) snapshot();
+    }
+
+    if (tid < bs) {
+      if (a.mode == 0) {
+        enc_finish(enc, slot, bd.slot_words, ovf);
+        a.seg_bits[(size_t)b * bs + tid] = (uint32_t)enc.nbits;
+      }
+      if (ovf) atomicOr(a.err, 2);
+    }
+    // final parameters (embedding lives in LDS during the loop)
+    for (int q = tid; q < V * E; q += NT) W[d.off_emb + q] = emb[q];
+    __syncthreads();
+    if (a.params_out && b == 0)
+      for (int q = tid; q < d.P + 1; q += NT) a.params_out[q] = W[q];
+    __syncthreads();
+  }
+}
+
+
+}  // namespace pmklc

@@ -172,6 +172,22 @@ def test_plain_and_batched_schedules_give_identical_bytes(gpu):
     assert b1 == b2
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp32_valu"])
+def test_autotuner_choices_give_identical_bytes(gpu, precision, monkeypatch):
+    """Every workgroup width the autotuner may pick yields the same container."""
+    a = _dna(60000, seed=21, n_rate=0.001)
+    cfg = model_small(n_blocks=3, precision=precision)
+    blobs = []
+    for nt in ["256", "512"]:
+        monkeypatch.setenv("PMKLC_NT", nt)
+        blobs.append(gpu.compress(cfg, _cuda(a)))
+        assert gpu.last_timing()["threads"] == int(nt)
+    monkeypatch.delenv("PMKLC_NT")
+    blobs.append(gpu.compress(cfg, _cuda(a)))
+    assert blobs[0] == blobs[1] == blobs[2]
+    assert np.array_equal(gpu.decompress(blobs[0]).cpu().numpy(), a)
+
+
 def test_smp_chain_roundtrip_and_snapshot(gpu, orc):
     a = _dna(30000, seed=10, n_rate=0.001)
     cfg = _tiny(block_len=[5000, 7000, 3000, 9000, 6000], file_blocks=[3, 2], smp_ppm=50000)
@@ -219,10 +235,12 @@ def test_errors(gpu):
 
 
 # ------------------------------------------------- probability parity
-def test_teacher_forced_probabilities_and_gradient(gpu, orc):
-    """At identical weights the GPU's FP32 step gives P within 1e-4 of the
-    FP64 oracle, and its SGD update matches w - lr * grad_oracle."""
-    rec, cfg = synth.recipe_cfg1(), model_small()
+@pytest.mark.parametrize("precision", ["fp32", "fp32_valu"])
+def test_teacher_forced_probabilities_and_gradient(gpu, orc, precision):
+    """At identical weights the GPU's FP32 step (matrix-core and per-thread
+    FMA kernels) gives P within 1e-4 of the FP64 oracle, and its SGD update
+    matches w - lr * grad_oracle."""
+    rec, cfg = synth.recipe_cfg1(), model_small(precision=precision)
     a = synth.generate(rec)
     tok = orc.encode_skmer(a, 3, 3)
     L = len(tok) // cfg["bs"]
@@ -239,10 +257,11 @@ def test_teacher_forced_probabilities_and_gradient(gpu, orc):
         assert np.max(np.abs(w_i1.cpu().numpy()[:n] - expect)) <= 1e-6
 
 
-def test_trajectory_probabilities_cfg1(gpu, orc):
+@pytest.mark.parametrize("precision", ["fp32", "fp32_valu"])
+def test_trajectory_probabilities_cfg1(gpu, orc, precision):
     """Whole-block trajectory of the first workload (256 KiB, one block):
     sampled steps' P within 1e-4 of the FP64 oracle, code ratio within 0.5%."""
-    rec, cfg = synth.recipe_cfg1(), model_small()
+    rec, cfg = synth.recipe_cfg1(), model_small(precision=precision)
     a = synth.generate(rec)
     tok = orc.encode_skmer(a, 3, 3)
     L = len(tok) // cfg["bs"]
@@ -255,6 +274,38 @@ def test_trajectory_probabilities_cfg1(gpu, orc):
     blob_g = gpu.compress(cfg, _cuda(a))
     blob_o = orc.compress(cfg, a)
     assert abs(len(blob_g) - len(blob_o)) <= 0.005 * len(blob_o)
+
+
+@pytest.mark.parametrize("precision,path", [("fp32", 3), ("fp32_valu", 1), ("bf16", 2)])
+def test_numeric_paths_roundtrip_and_ratio(gpu, orc, precision, path):
+    """Every numeric path: bit-exact GPU round trip, identical bytes from
+    both launch schedules, ratio within 0.5% of the FP64 oracle on the first
+    workload and on a 1 MiB sample of the static + dynamic workload. BF16
+    probabilities are reported (|dp| statistics), not held to 1e-4."""
+    from synth.workloads import cfg2
+    static = np.fromfile(os.path.join(GOLD, "static_cfg2.f32"), dtype=np.float32)
+    rec2, c2 = cfg2(n=1 << 20, n_blocks=16)
+    cases = [(synth.generate(synth.recipe_cfg1()), model_small(), None),
+             (synth.generate(rec2), c2, static)]
+    for a, cfg, st in cases:
+        cfg = dict(cfg, precision=precision)
+        blob = gpu.compress(cfg, _cuda(a), static=st)
+        assert blob[5] == path
+        assert np.array_equal(gpu.decompress(blob, static=st).cpu().numpy(), a)
+        assert gpu.compress(dict(cfg, schedule="plain"), _cuda(a), static=st) == blob
+        blob_o = orc.compress(cfg, a, static=st)
+        rel = len(blob) / len(blob_o) - 1
+        print(f"{precision}: {len(blob)} vs oracle {len(blob_o)} bytes, rel {rel:+.5f}")
+        assert abs(rel) <= 0.005
+    rec, cfg = synth.recipe_cfg1(), model_small(precision=precision)
+    tok = orc.encode_skmer(synth.generate(rec), 3, 3)
+    L = len(tok) // cfg["bs"]
+    steps = [cfg["t"], 200, L - 1]
+    Pg, _ = gpu.model_trace(cfg, tok, steps=steps)
+    Po, _, _ = orc.trace_block(cfg, tok, steps=steps)
+    dp = np.abs(Pg.cpu().numpy() - Po)
+    print(f"{precision}: |dp| max {dp.max():.3g} mean {dp.mean():.3g}")
+    assert dp.max() <= (1e-4 if precision != "bf16" else 0.05)
 
 
 def test_static_mixer_probabilities(gpu, orc):
