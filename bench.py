@@ -44,9 +44,22 @@ def flops_per_row(cfg: dict) -> int:
     return f
 
 
-def workload(name: str):
+def workload(name: str, scale: float = 1.0):
     import synth
     from synth import workloads as W
+    if name == "uneven1g":
+        n = int((1 << 30) * scale)
+        rec, cfg = W.cfg3(n=n)
+        desc = (f"uneven1g: {n} bases of order-3 synthetic DNA (5% repeats), 256 blocks of lognormal length "
+                "(median 2 MiB x scale, sigma 1), (3,3)-mers, t=32, E=16, hidden [32], bs=64, SGD 1e-3")
+        return synth.generate(rec), cfg, None, desc
+    if name == "archive":
+        recs, cfg = W.cfg5(scale=scale)
+        data = np.concatenate([synth.generate(r) for r in recs])
+        desc = (f"archive: 64 synthetic files, log-uniform 1 KiB-512 MiB x {scale}, per-file order 2-8, GC 0.3-0.7, "
+                "repeats 0-30%, N runs; 4 MiB blocks, model passing at 5% of each block's steps within a file; "
+                "(3,3)-mers, t=32, E=16, hidden [32], bs=64, SGD 1e-3")
+        return data, cfg, None, desc
     if name == "static64":
         rec, cfg = W.cfg2()
         static = np.fromfile(os.path.join(ROOT, "tests", "golden", "static_cfg2.f32"), dtype=np.float32)
@@ -91,8 +104,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="static64")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--workload", default="static64", choices=["static64", "small256k", "uneven1g", "archive"])
+    ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive")
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp32_valu"])
+    ap.add_argument("--no-fp32-compare", action="store_true",
+                    help="skip the one batched FP32 compress+decompress measured beside the main precision")
     ap.add_argument("--schedule", default="batched", choices=["batched", "plain"])
     ap.add_argument("--cpu-sample-bytes", type=int, default=1 << 19)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -118,7 +134,7 @@ def main():
         del src, dst
 
     log(f"generating workload {a.workload}")
-    data, cfg, static, desc = workload(a.workload)
+    data, cfg, static, desc = workload(a.workload, a.scale)
     cfg = dict(cfg, precision=a.precision, schedule=a.schedule)
     n = len(data)
     x = torch.from_numpy(data).cuda()
@@ -162,7 +178,7 @@ def main():
         "ms_per_step": round((CT + DT) * 1e3, 2), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if a.precision == "fp32" else "bf16",
         "data": "synthetic (seeded Markov DNA stand-in for the paper's genomes)",
-        "config": {"workload": desc, "bases": n, "blocks": cfg.get("n_blocks", 1), "precision": a.precision,
+        "config": {"workload": desc, "bases": n, "blocks": len(cfg["block_len"]) if "block_len" in cfg else cfg.get("n_blocks", 1), "precision": a.precision,
                    "schedule": a.schedule},
         "compress_MBps": round(n / CT / 1e6, 4), "decompress_MBps": round(n / DT / 1e6, 4),
         "ratio_bits_per_base": round(8.0 * len(blob) / n, 5), "roundtrip_bit_exact": ok,
@@ -172,7 +188,23 @@ def main():
                      "kernel": "step_kernel", "flops_per_launch": int(flops_launch), "flops_per_row": fpr,
                      "rows_per_launch": int(tim_c["model_rows"]), "max_steps": int(tim_c["max_steps"])},
     }
-    if a.plain_blocks and a.schedule == "batched":
+    res["threads_per_workgroup"] = int(tim_c["threads"])
+    if not a.no_fp32_compare and a.precision != "fp32":
+        cf = dict(cfg, precision="fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b32 = P.compress(cf, x, static=static, workspace=ws)
+        t1 = time.perf_counter()
+        o32 = P.decompress(b32, static=static, workspace=wsd, out=out)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res["fp32_batched"] = {"value": round(n / (t2 - t0) / 1e6, 4), "compress_MBps": round(n / (t1 - t0) / 1e6, 4),
+                               "decompress_MBps": round(n / (t2 - t1) / 1e6, 4),
+                               "ratio_bits_per_base": round(8.0 * len(b32) / n, 5),
+                               "roundtrip_bit_exact": bool((o32[:n] == x).all()),
+                               "bf16_ratio_cost_rel": round(len(blob) / len(b32) - 1.0, 6)}
+        log(f"fp32 batched: compress {t1 - t0:.3f}s decompress {t2 - t1:.3f}s")
+    if a.plain_blocks and a.schedule == "batched" and "block_len" not in cfg:
         nb = cfg.get("n_blocks", 1)
         k = min(a.plain_blocks, nb)
         per = n // nb
@@ -187,8 +219,10 @@ def main():
         res["plain_fp32_sample"] = f"first {k} of {nb} blocks, one launch per block"
     if not a.no_cpu_baseline:
         log("oracle on the CPU sample")
-        cb, oblob, sample = cpu_baseline(cfg, static, data, a.cpu_sample_bytes)
-        gblob = P.compress(dict(cfg, schedule="batched"), torch.from_numpy(sample).cuda(), static=static)
+        cb, oblob, sample = cpu_baseline({k: v for k, v in cfg.items() if k not in ("block_len", "file_blocks")},
+                                         static, data, a.cpu_sample_bytes)
+        gcfg = {k: v for k, v in cfg.items() if k not in ("block_len", "file_blocks")}
+        gblob = P.compress(dict(gcfg, schedule="batched"), torch.from_numpy(sample).cuda(), static=static)
         cb["gpu_ratio_bits_per_base_same_sample"] = round(8.0 * len(gblob) / len(sample), 5)
         cb["ratio_rel_diff"] = round(len(gblob) / len(oblob) - 1.0, 6)
         res["cpu_baseline"] = cb

@@ -204,32 +204,44 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
   int rs = 1;
   while (rs < d.t + d.CH) rs <<= 1;
   d.RS = rs;
-  // LDS plan
+  // LDS plan; when the activations do not fit, they move to a global slab
+  // per workgroup (act/dh offsets then count floats in that slab)
   LdsLayout &L = m.lay;
-  memset(&L, 0, sizeof L);
-  uint64_t o = 0;
-  auto take = [&](uint64_t bytes) { uint64_t at = o; o = align_up(o + bytes, 16); return (int)at; };
   int hmax = 0;
   for (int l = 0; l < d.nh; l++) hmax = std::max(hmax, d.H[l]);
-  L.emb = take(4ull * d.V * E);
-  L.embs = take(d.static_on ? 4ull * d.V * E : 0);
-  L.ring = take((uint64_t)bs * d.RS);
-  L.act[0] = take(d.nh >= 1 ? 4ull * bs * d.H[0] : 0);
-  L.act[1] = take(d.nh >= 2 ? 4ull * bs * d.H[1] : 0);
-  L.lm = take(4ull * bs * d.V);
-  L.lu = take(d.static_on ? 4ull * bs * d.V : 0);
-  L.cdf = take(4ull * bs * (d.V + 1));
-  L.tgt = take(bs);
-  L.dh[0] = take(d.nh >= 1 ? 4ull * bs * hmax : 0);
-  L.dh[1] = take(d.nh >= 2 ? 4ull * bs * hmax : 0);
-  L.demb = take(8ull * d.V * E);
-  L.misc = take(4ull * bs + 64);
-  L.total = (int)o;
-  if (o > 160 * 1024) return PMKLC_ERR_UNSUPPORTED;
+  for (int glob = 0; glob < 2; glob++) {
+    memset(&L, 0, sizeof L);
+    uint64_t o = 0, g = 0;
+    auto take = [&](uint64_t bytes) { uint64_t at = o; o = align_up(o + bytes, 16); return (int)at; };
+    auto act = [&](uint64_t bytes) {
+      if (!glob) return take(bytes);
+      uint64_t at = g;
+      g = align_up(g + bytes / 4, 64);
+      return (int)at;
+    };
+    L.emb = take(4ull * d.V * E);
+    L.embs = take(d.static_on ? 4ull * d.V * E : 0);
+    L.ring = take((uint64_t)bs * d.RS);
+    L.act[0] = act(d.nh >= 1 ? 4ull * bs * d.H[0] : 0);
+    L.act[1] = act(d.nh >= 2 ? 4ull * bs * d.H[1] : 0);
+    L.lm = take(4ull * bs * d.V);
+    L.lu = take(d.static_on ? 4ull * bs * d.V : 0);
+    L.cdf = take(4ull * bs * (d.V + 1));
+    L.tgt = take(bs);
+    L.dh[0] = act(d.nh >= 1 ? 4ull * bs * hmax : 0);
+    L.dh[1] = act(d.nh >= 2 ? 4ull * bs * hmax : 0);
+    L.demb = take(8ull * d.V * E);
+    L.misc = take(4ull * bs + 64);
+    L.total = (int)o;
+    L.act_global = glob;
+    L.act_slot = (int)g;
+    if (o <= 160 * 1024) break;
+    if (glob) return PMKLC_ERR_UNSUPPORTED;
+  }
   m.nt = bs <= 256 ? 256 : 512;
   if (bs > 512) return PMKLC_ERR_UNSUPPORTED;
   // matrix-core kernel: one hidden layer, tile-friendly shapes
-  const bool mfma_ok = d.model_on && d.nh == 1 && bs % 32 == 0 && bs <= 128 && d.H[0] % 32 == 0 && d.V % 32 == 0 &&
+  const bool mfma_ok = d.model_on && !L.act_global && d.nh == 1 && bs % 32 == 0 && bs <= 128 && d.H[0] % 32 == 0 && d.V % 32 == 0 &&
                        E % 8 == 0 && d.D % 32 == 0;
   m.kind = kGeneric;
   if (precision == PMKLC_BF16) {
@@ -313,6 +325,7 @@ struct Work {
   uint32_t *seg_bytes;
   uint8_t *staging;
   StepArgs *args;         // device copies of the step-kernel arguments (one per launch)
+  float *act;             // activation slabs (models whose activations exceed the LDS)
 };
 
 struct Sizes {
@@ -348,6 +361,7 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   w.seg_bytes = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
   w.staging = A.take<uint8_t>(z.staging + 16);
   w.args = A.take<StepArgs>((uint64_t)n_blocks + 1);
+  w.act = m.lay.act_global ? A.take<float>((uint64_t)std::min<uint32_t>(n_blocks, kMaxGrid) * m.lay.act_slot) : nullptr;
 }
 
 // One synthetic block of t + 64 steps (constant tokens) in encode mode,
@@ -385,6 +399,7 @@ hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms) {
   a.slots = w.slots;
   a.seg_bits = w.seg_bits;
   a.seg_words = w.seg_words;
+  a.act_scratch = w.act;
   a.spin_limit = 1;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   float best = 1e30f;
@@ -587,6 +602,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   a.slots = w.slots;
   a.seg_bits = w.seg_bits;
   a.seg_words = w.seg_words;
+  a.act_scratch = w.act;
   a.spin_limit = 1ll << 26;   // ~10 s of waiting before giving up with an error
   HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.snap_flag, 0, bd.size() * sizeof(int), st));
@@ -624,7 +640,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
     int dev = 0, ncu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int grid = (int)std::min<uint64_t>(bd.size(), (uint64_t)std::max(ncu, 1));
+    int grid = (int)std::min<uint64_t>(std::min<uint64_t>(bd.size(), (uint64_t)std::max(ncu, 1)), kMaxGrid);
     hold[0] = a;
     HIP_TRY(hipMemcpyAsync(w.args, &hold[0], sizeof(StepArgs), hipMemcpyHostToDevice, st));
     if (m.kind == kGeneric) HIP_TRY(launch_step(a, grid, m.nt, st));
@@ -1290,6 +1306,7 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   a.n_probe = (int)n_probe;
   a.probe_P = probs_dev;
   a.params_out = params_dev;
+  a.act_scratch = w.act;
   a.spin_limit = 1ll << 30;
   chk(hipMemcpyAsync(w.args, &a, sizeof(StepArgs), hipMemcpyHostToDevice, st));
   if (e == hipSuccess) {

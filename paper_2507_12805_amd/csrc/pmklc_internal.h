@@ -30,7 +30,10 @@ struct Dims {
 // LDS layout (byte offsets into dynamic shared memory).
 struct LdsLayout {
   int emb, embs, ring, act[2], lm, lu, cdf, tgt, dh[2], demb, misc, total;
+  int act_global;     // 1: act[] and dh[] are float offsets into a per-workgroup global slab
+  int act_slot;       // floats per workgroup slab
 };
+constexpr int kMaxGrid = 1024;   // upper bound on step-kernel workgroups (global slabs)
 
 // One data block as the step kernel sees it.
 struct BlockDesc {
@@ -69,6 +72,7 @@ struct StepArgs {
   float *probe_P;                 // [n_probe][bs][V]
   float *params_out;              // [P+1] parameters after the last step, or null
   long long spin_limit;           // bound on model-passing waits (iterations)
+  float *act_scratch;             // [grid][act_slot] activations when lay.act_global
 };
 
 hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);

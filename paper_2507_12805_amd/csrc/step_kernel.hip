@@ -185,12 +185,21 @@ struct NetGeneric {
   __device__ NetGeneric(const StepArgs &a_, unsigned char *lds) : a(a_), d(a_.d) {
     emb = reinterpret_cast<float *>(lds + a.lay.emb);
     embs = reinterpret_cast<float *>(lds + a.lay.embs);
-    act[0] = reinterpret_cast<float *>(lds + a.lay.act[0]);
-    act[1] = reinterpret_cast<float *>(lds + a.lay.act[1]);
+    if (a.lay.act_global) {
+      // activations too large for the LDS live in this workgroup's slab
+      float *slab = a.act_scratch + (size_t)blockIdx.x * a.lay.act_slot;
+      act[0] = slab + a.lay.act[0];
+      act[1] = slab + a.lay.act[1];
+      dh[0] = slab + a.lay.dh[0];
+      dh[1] = slab + a.lay.dh[1];
+    } else {
+      act[0] = reinterpret_cast<float *>(lds + a.lay.act[0]);
+      act[1] = reinterpret_cast<float *>(lds + a.lay.act[1]);
+      dh[0] = reinterpret_cast<float *>(lds + a.lay.dh[0]);
+      dh[1] = reinterpret_cast<float *>(lds + a.lay.dh[1]);
+    }
     lm = reinterpret_cast<float *>(lds + a.lay.lm);
     lu = reinterpret_cast<float *>(lds + a.lay.lu);
-    dh[0] = reinterpret_cast<float *>(lds + a.lay.dh[0]);
-    dh[1] = reinterpret_cast<float *>(lds + a.lay.dh[1]);
     ring = lds + a.lay.ring;
     demb = reinterpret_cast<long long *>(lds + a.lay.demb);
     tid = threadIdx.x;

@@ -132,11 +132,15 @@ struct NetMfma {
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int k0 = 0; k0 < D; k0 += KS) {
+      // B fragments are fetched two k-steps ahead
+      const float *wcol = W1 + 16 * n + r + (size_t)(g * KL) * H;
+      float b0[KL], b1[KL];
+      load_strided<KL>(wcol, H, b0);
+      if (KS < D) load_strided<KL>(wcol + (size_t)KS * H, H, b1);
+      auto step = [&](int k0, float *bcur) {
+        const typename P::frag bf = P::pack(bcur);
+        if (k0 + 2 * KS < D) load_strided<KL>(wcol + (size_t)(k0 + 2 * KS) * H, H, bcur);
         const int kk = k0 + g * KL;
-        float bv[KL];
-        load_strided<KL>(W1 + (size_t)kk * H + 16 * n + r, H, bv);
-        const typename P::frag bf = P::pack(bv);
         const int p = kk / E, e = kk % E;
 #pragma unroll
         for (int m = 0; m < MAXT; m++) {
@@ -145,7 +149,13 @@ struct NetMfma {
           load_run<KL>(em + token(16 * m + r, p, i) * E + e, av);
           acc[m] = P::mma(P::pack(av), bf, acc[m]);
         }
+      };
+      int k0 = 0;
+      for (; k0 + 2 * KS <= D; k0 += 2 * KS) {
+        step(k0, b0);
+        step(k0 + KS, b1);
       }
+      if (k0 < D) step(k0, b0);
       const float bias = Wm[d.off_b[0] + 16 * n + r];
       float *out = model ? hs : h1;
 #pragma unroll
@@ -165,11 +175,14 @@ struct NetMfma {
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int k0 = 0; k0 < H; k0 += KS) {
+      const float *wcol = W2 + 16 * n + r + (size_t)(g * KL) * V;
+      float b0[KL], b1[KL];
+      load_strided<KL>(wcol, V, b0);
+      if (KS < H) load_strided<KL>(wcol + (size_t)KS * V, V, b1);
+      auto step = [&](int k0, float *bcur) {
+        const typename P::frag bf = P::pack(bcur);
+        if (k0 + 2 * KS < H) load_strided<KL>(wcol + (size_t)(k0 + 2 * KS) * V, V, bcur);
         const int kk = k0 + g * KL;
-        float bv[KL];
-        load_strided<KL>(W2 + (size_t)kk * V + 16 * n + r, V, bv);
-        const typename P::frag bf = P::pack(bv);
 #pragma unroll
         for (int m = 0; m < MAXT; m++) {
           if (m < mb || m >= me) continue;
@@ -177,7 +190,13 @@ struct NetMfma {
           load_run<KL>(hin + (16 * m + r) * H + kk, av);
           acc[m] = P::mma(P::pack(av), bf, acc[m]);
         }
+      };
+      int k0 = 0;
+      for (; k0 + 2 * KS <= H; k0 += 2 * KS) {
+        step(k0, b0);
+        step(k0 + KS, b1);
       }
+      if (k0 < H) step(k0, b0);
       const float bias = Wm[d.off_b[1] + 16 * n + r];
       float *out = model ? lu : lm;
 #pragma unroll
@@ -266,11 +285,14 @@ struct NetMfma {
       f32x4 acc[MAXT];
 #pragma unroll
       for (int n = 0; n < MAXT; n++) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int k0 = 0; k0 < H; k0 += KS) {
+      const float *wrow = W1 + (size_t)(16 * mt + r) * H + g * KL;
+      float a0[KL], a1[KL];
+      load_run<KL>(wrow, a0);
+      if (KS < H) load_run<KL>(wrow + KS, a1);
+      auto step = [&](int k0, float *acur) {
+        const typename P::frag af = P::pack(acur);
+        if (k0 + 2 * KS < H) load_run<KL>(wrow + k0 + 2 * KS, acur);
         const int kk = k0 + g * KL;
-        float av[KL];
-        load_run<KL>(W1 + (size_t)(16 * mt + r) * H + kk, av);
-        const typename P::frag af = P::pack(av);
 #pragma unroll
         for (int n = 0; n < MAXT; n++) {
           if (n >= Mt) continue;
@@ -278,7 +300,13 @@ struct NetMfma {
           load_run<KL>(dpre + (16 * n + r) * H + kk, bv);
           acc[n] = P::mma(af, P::pack(bv), acc[n]);
         }
+      };
+      int k0 = 0;
+      for (; k0 + 2 * KS <= H; k0 += 2 * KS) {
+        step(k0, a0);
+        step(k0 + KS, a1);
       }
+      if (k0 < H) step(k0, a0);
 #pragma unroll
       for (int n = 0; n < MAXT; n++) {
         if (n >= Mt) continue;

@@ -31,37 +31,45 @@ static uint64_t sm_below(uint64_t *s, uint64_t n) { return n ? sm_next(s) % n : 
 
 static const uint8_t ACGT[4] = {'A', 'C', 'G', 'T'};
 
-/* rows: 4^order x 4 probabilities (row-major). gc: n_seg values or NULL. */
+/* rows: 4^order x 4 probabilities (row-major). gc: n_seg values or NULL.
+ * Per GC segment the tilted rows are turned into three cumulative
+ * thresholds once; each base then costs one draw and three compares. */
 void synth_markov(uint8_t *out, uint64_t n, int order, const double *rows,
                   const double *gc, uint64_t seg_len, uint64_t seed) {
     uint64_t st = seed ^ 0x5DEECE66Dull;
-    uint64_t mask = (order > 0) ? ((1ull << (2 * order)) - 1) : 0;
-    uint64_t ctx = 0;
+    uint64_t nrows = 1ull << (2 * order);
+    uint64_t mask = (order > 0) ? (nrows - 1) : 0;
+    double *thr = (double *)malloc(sizeof(double) * 3 * nrows);
+    if (!thr) return;
+    uint64_t ctx = 0, cur_seg = ~0ull;
     for (uint64_t i = 0; i < n; i++) {
         int b;
         double u = sm_unit(&st);
+        uint64_t seg = (gc && seg_len) ? i / seg_len : 0;
+        if (seg != cur_seg) {
+            cur_seg = seg;
+            double wat = 1.0, wcg = 1.0;
+            if (gc) { wat = (1.0 - gc[seg]) / 0.5; wcg = gc[seg] / 0.5; }
+            for (uint64_t r = 0; r < nrows; r++) {
+                const double *q = rows + 4 * r;
+                double p0 = q[0] * wat, p1 = q[1] * wcg, p2 = q[2] * wcg, p3 = q[3] * wat;
+                double tot = p0 + p1 + p2 + p3;
+                thr[3 * r] = p0 / tot;
+                thr[3 * r + 1] = (p0 + p1) / tot;
+                thr[3 * r + 2] = (p0 + p1 + p2) / tot;
+            }
+        }
         if (i < (uint64_t)order) {
             b = (int)(u * 4.0);
             if (b > 3) b = 3;
         } else {
-            const double *r = rows + 4 * ctx;
-            double p[4] = {r[0], r[1], r[2], r[3]};
-            if (gc) {
-                double g = gc[seg_len ? i / seg_len : 0];
-                double wat = (1.0 - g) / 0.5, wcg = g / 0.5;
-                p[0] *= wat; p[1] *= wcg; p[2] *= wcg; p[3] *= wat;
-            }
-            double tot = p[0] + p[1] + p[2] + p[3];
-            double x = u * tot, acc = 0.0;
-            b = 3;
-            for (int c = 0; c < 3; c++) {
-                acc += p[c];
-                if (x < acc) { b = c; break; }
-            }
+            const double *t3 = thr + 3 * ctx;
+            b = (u < t3[0]) ? 0 : (u < t3[1]) ? 1 : (u < t3[2]) ? 2 : 3;
         }
         out[i] = ACGT[b];
         ctx = ((ctx << 2) | (uint64_t)b) & mask;
     }
+    free(thr);
 }
 
 static uint8_t comp(uint8_t c) {

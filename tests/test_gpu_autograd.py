@@ -59,7 +59,10 @@ def test_autograd_function_matches_oracle_gradient(gpu, orc):
 
 def test_gradient_against_finite_differences(gpu, orc):
     """FP64 central differences of the oracle's mean cross-entropy on sampled
-    coordinates of every tensor (4 KB slice), against the HIP backward."""
+    coordinates of every tensor (4 KB slice), against the HIP backward.
+    A central difference is invalid where the step crosses a ReLU kink; such
+    coordinates show up as FD disagreeing with the oracle's own analytic
+    gradient and are counted, not compared (at most a few may occur)."""
     import torch
     from paper_2507_12805_amd.autograd import DynamicModel
     cfg, ctx, tgt, w = _slice_case(orc, rows=32)
@@ -67,9 +70,10 @@ def test_gradient_against_finite_differences(gpu, orc):
     logits = DynamicModel.apply(params, torch.from_numpy(ctx).cuda(), cfg)
     torch.nn.functional.cross_entropy(logits, torch.from_numpy(tgt.astype(np.int64)).cuda()).backward()
     g = params.grad.cpu().numpy().astype(np.float64)
+    _, go, _, _ = orc.step(cfg, w, ctx, tgt)
     rng = np.random.default_rng(0)
-    h = 1e-4
-    checked = 0
+    h = 1e-6
+    checked = kinks = 0
     for name, (off, shp) in orc.param_slices(cfg).items():
         n = int(np.prod(shp))
         seg = g[off:off + n]
@@ -80,9 +84,12 @@ def test_gradient_against_finite_differences(gpu, orc):
             wp[i] += h
             wm[i] -= h
             fd = (orc.step(cfg, wp, ctx, tgt, grad=False)[3] - orc.step(cfg, wm, ctx, tgt, grad=False)[3]) / (2 * h)
+            if abs(go[i] - fd) > 1e-3 * abs(fd) + 1e-8:
+                kinks += 1
+                continue
             assert abs(g[i] - fd) <= 1e-3 * abs(fd) + 1e-7, (name, i, g[i], fd)
             checked += 1
-    assert checked >= 30
+    assert checked >= 30 and kinks <= 2, (checked, kinks)
 
 
 def test_backward_is_deterministic_and_matches_small_shapes(gpu, orc):
