@@ -171,6 +171,13 @@ typedef struct pmklc_timing {
   uint64_t max_steps;     /* longest block's step count (the critical path) */
   uint32_t launches;      /* step-kernel launches */
   uint32_t threads;       /* threads per workgroup the autotuner chose */
+  uint32_t wall_khz;      /* device wall-clock rate for phase_ticks */
+  /* With PMKLC_PHASES=1 in the environment: wall-clock ticks block 0 spent
+   * per phase of its loop (0 staging, 1 forward, 2 softmax + quantiser,
+   * 3 coder, 4 loss gradient, 5 backward, 6 embedding update; matrix-core
+   * backward split into 8 input gradient, 9 output-layer update + embedding
+   * scatter, 10 first-layer update). Zero otherwise. */
+  uint64_t phase_ticks[12];
 } pmklc_timing;
 pmklc_status pmklc_last_timing(pmklc_timing *t);
 

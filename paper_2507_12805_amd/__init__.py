@@ -46,7 +46,7 @@ class _Config(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_float), ("call_ms", ctypes.c_float), ("model_rows", ctypes.c_uint64),
                 ("coded_tokens", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("launches", ctypes.c_uint32),
-                ("threads", ctypes.c_uint32)]
+                ("threads", ctypes.c_uint32), ("wall_khz", ctypes.c_uint32), ("phase_ticks", ctypes.c_uint64 * 12)]
 
 
 _vp = ctypes.c_void_p
@@ -170,7 +170,9 @@ def last_timing() -> dict:
     call on this thread, and the work it did."""
     t = Timing()
     _check(load().pmklc_last_timing(ctypes.byref(t)), "pmklc_last_timing")
-    return {f: getattr(t, f) for f, _ in Timing._fields_}
+    out = {f: getattr(t, f) for f, _ in Timing._fields_}
+    out["phase_ticks"] = list(t.phase_ticks)
+    return out
 
 
 def param_count(cfg: dict) -> int:

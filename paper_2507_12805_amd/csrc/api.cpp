@@ -200,6 +200,8 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
     for (uint32_t l = 0; l < nh; l++) if (hidden[l] % 4) return PMKLC_ERR_UNSUPPORTED;
   }
 
+  d.VS = d.V + 4;
+  d.ES = d.E + 1;
   d.CH = 32;
   int rs = 1;
   while (rs < d.t + d.CH) rs <<= 1;
@@ -224,13 +226,13 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
     L.ring = take((uint64_t)bs * d.RS);
     L.act[0] = act(d.nh >= 1 ? 4ull * bs * d.H[0] : 0);
     L.act[1] = act(d.nh >= 2 ? 4ull * bs * d.H[1] : 0);
-    L.lm = take(4ull * bs * d.V);
-    L.lu = take(d.static_on ? 4ull * bs * d.V : 0);
+    L.lm = take(4ull * bs * d.VS);
+    L.lu = take(d.static_on ? 4ull * bs * d.VS : 0);
     L.cdf = take(4ull * bs * (d.V + 1));
     L.tgt = take(bs);
     L.dh[0] = act(d.nh >= 1 ? 4ull * bs * hmax : 0);
     L.dh[1] = act(d.nh >= 2 ? 4ull * bs * hmax : 0);
-    L.demb = take(8ull * d.V * E);
+    L.demb = take(8ull * d.V * d.ES);
     L.misc = take(4ull * bs + 64);
     L.total = (int)o;
     L.act_global = glob;
@@ -326,6 +328,7 @@ struct Work {
   uint8_t *staging;
   StepArgs *args;         // device copies of the step-kernel arguments (one per launch)
   float *act;             // activation slabs (models whose activations exceed the LDS)
+  unsigned long long *phase;   // [16] phase clock of block 0
 };
 
 struct Sizes {
@@ -362,6 +365,7 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   w.staging = A.take<uint8_t>(z.staging + 16);
   w.args = A.take<StepArgs>((uint64_t)n_blocks + 1);
   w.act = m.lay.act_global ? A.take<float>((uint64_t)std::min<uint32_t>(n_blocks, kMaxGrid) * m.lay.act_slot) : nullptr;
+  w.phase = A.take<unsigned long long>(16);
 }
 
 // One synthetic block of t + 64 steps (constant tokens) in encode mode,
@@ -604,6 +608,9 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   a.seg_words = w.seg_words;
   a.act_scratch = w.act;
   a.spin_limit = 1ll << 26;   // ~10 s of waiting before giving up with an error
+  const char *ph = getenv("PMKLC_PHASES");
+  a.phase_clk = (ph && ph[0] == '1') ? w.phase : nullptr;
+  if (a.phase_clk) HIP_TRY(hipMemsetAsync(w.phase, 0, 16 * sizeof(unsigned long long), st));
   HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.snap_flag, 0, bd.size() * sizeof(int), st));
   if (bd.empty()) return PMKLC_OK;
@@ -648,6 +655,13 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   }
   if (tm) HIP_TRY(hipEventRecord(tm->b, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (a.phase_clk) {
+    HIP_TRY(hipMemcpy(g_last.phase_ticks, w.phase, 12 * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    g_last.wall_khz = (uint32_t)khz;
+  }
   return PMKLC_OK;
 }
 

@@ -19,6 +19,8 @@ struct Dims {
   int off_W[kMaxLayers], off_b[kMaxLayers];
   int P;                        // parameters without the mixing weight
   int stride;                   // floats per block parameter slab (>= P+1, multiple of 64)
+  int VS;                       // row stride (floats) of the logits / probability rows in LDS (V + 4)
+  int ES;                       // row stride (entries) of the fixed-point embedding gradient (E + 1)
   int RS;                       // context ring length (power of two >= t + CH)
   int CH;                       // tokens staged per row at a time (encode)
   int static_on;                // frozen static model mixed in (Eq. 1)
@@ -73,6 +75,7 @@ struct StepArgs {
   float *params_out;              // [P+1] parameters after the last step, or null
   long long spin_limit;           // bound on model-passing waits (iterations)
   float *act_scratch;             // [grid][act_slot] activations when lay.act_global
+  unsigned long long *phase_clk;  // [12] per-phase wall-clock ticks of block 0, or null
 };
 
 hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);

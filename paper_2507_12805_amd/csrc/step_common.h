@@ -21,21 +21,6 @@ __device__ __forceinline__ int wave_sum_i(int x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
   return x;
 }
-__device__ __forceinline__ void wave_argmax(float &v, int &i) {
-  for (int o = 32; o > 0; o >>= 1) {
-    float ov = __shfl_xor(v, o);
-    int oi = __shfl_xor(i, o);
-    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
-  }
-}
-// inclusive scan of ints over the 64 lanes (lane order)
-__device__ __forceinline__ int wave_scan_incl(int x, int lane) {
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  return x;
-}
 
 // ---------------------------------------------------------------- coder
 struct Enc {
@@ -158,46 +143,30 @@ __device__ __forceinline__ int dec_symbol(Dec &d, const uint32_t *w, uint32_t nw
   return a;
 }
 
-// -------------------------------------------------- softmax + quantiser
-// One wave turns the V logits of a row into probabilities and an integer
-// CDF.  Lane l holds symbols l, l+64, ... (V <= 256).
-__device__ __forceinline__ void row_quantise(const float *p_in, int V, int lane, uint32_t *cdf) {
-  int f[4];
-  float pq[4];
-  int fsum = 0;
+// ------------------------------------------------------------ quantiser
+// Frequency quantisation of one row held by one lane: f_v = 1 +
+// floor(p_v * (2^16 - V)) with the product taken exactly in FP64, the
+// residual 2^16 - sum f added to the most probable symbol (lowest index on
+// ties); writes the V+1 cumulative counts.
+__device__ __forceinline__ void row_quantise_lane(const float *p, int V, uint32_t *cdf) {
+  int fsum = 0, besti = 0;
   float best = -1.0f;
-  int besti = 0x7fffffff;
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    int v = lane + 64 * q;
-    f[q] = 0;
-    pq[q] = 0.0f;
-    if (v < V) {
-      float p = p_in[q];
-      p = (p >= 0.0f && p <= 1.0f) ? p : 0.0f;
-      pq[q] = p;
-      // exact: a 24-bit mantissa times a 16-bit integer fits FP64
-      f[q] = 1 + (int)floor((double)p * (double)(kTotal - (uint32_t)V));
-      fsum += f[q];
-      if (p > best) { best = p; besti = v; }
-    }
+  for (int v = 0; v < V; v++) {
+    float pv = p[v];
+    pv = (pv >= 0.0f && pv <= 1.0f) ? pv : 0.0f;
+    fsum += 1 + (int)floor((double)pv * (double)(kTotal - (uint32_t)V));
+    if (pv > best) { best = pv; besti = v; }
   }
-  fsum = wave_sum_i(fsum);
-  wave_argmax(best, besti);
-  besti = __builtin_amdgcn_readfirstlane(besti);
-  int resid = (int)kTotal - fsum;
-  int run = 0;
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    if (64 * q >= V) break;
-    int v = lane + 64 * q;
-    int fv = (v < V) ? f[q] + (v == besti ? resid : 0) : 0;
-    int incl = wave_scan_incl(fv, lane);
-    if (v < V) cdf[v] = (uint32_t)(run + incl - fv);
-    run += __shfl(incl, 63);
+  const int resid = (int)kTotal - fsum;
+  uint32_t run = 0;
+  for (int v = 0; v < V; v++) {
+    float pv = p[v];
+    pv = (pv >= 0.0f && pv <= 1.0f) ? pv : 0.0f;
+    const int f = 1 + (int)floor((double)pv * (double)(kTotal - (uint32_t)V)) + (v == besti ? resid : 0);
+    cdf[v] = run;
+    run += (uint32_t)f;
   }
-  if (lane == 0) cdf[V] = kTotal;
-  (void)pq;
+  cdf[V] = kTotal;
 }
 
 __device__ __forceinline__ long long to_fixed(float x) {
@@ -221,6 +190,33 @@ __device__ __forceinline__ float opt_delta(const Opt &o, float g, float *m, floa
 }
 
 
+// Per-phase wall-clock accounting of one block's loop (block 0, thread 0):
+// phases 0 staging, 1 forward, 2 softmax+quantiser, 3 coder, 4 loss
+// gradient, 5 network backward, 6 embedding update; the network may split
+// its backward into 8.. (B1, B2+B3, B4). Enabled when a sink is given.
+struct PhaseClock {
+  unsigned long long *sink;
+  unsigned long long acc[12];
+  unsigned long long t0;
+  bool on;
+  __device__ void init(unsigned long long *s, bool active) {
+    sink = s;
+    on = s && active;
+    for (int q = 0; q < 12; q++) acc[q] = 0;
+    t0 = on ? wall_clock64() : 0;
+  }
+  __device__ __forceinline__ void mark(int phase) {
+    if (!on) return;
+    unsigned long long t = wall_clock64();
+    acc[phase] += t - t0;
+    t0 = t;
+  }
+  __device__ void flush() {
+    if (!on) return;
+    for (int q = 0; q < 12; q++) sink[q] = acc[q];
+  }
+};
+
 }  // namespace detail
 
 using namespace detail;
@@ -237,7 +233,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
   __shared__ float sh_ga;
   const Dims &d = a.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bs = d.bs, V = d.V, E = d.E, t = d.t, RS = d.RS, mask = d.RS - 1;
+  const int bs = d.bs, V = d.V, E = d.E, t = d.t, RS = d.RS, mask = d.RS - 1, VS = d.VS;
   float *emb = reinterpret_cast<float *>(lds + a.lay.emb);
   float *embs = reinterpret_cast<float *>(lds + a.lay.embs);
   uint8_t *ring = lds + a.lay.ring;
@@ -284,8 +280,8 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     for (int q = tid; q < V * E; q += NT) {
       emb[q] = W[d.off_emb + q];
       if (d.static_on) embs[q] = a.stat[d.off_emb + q];
-      demb[q] = 0;
     }
+    for (int q = tid; q < V * d.ES; q += NT) demb[q] = 0;
     __syncthreads();
 
     auto snapshot = [&]() {
@@ -317,6 +313,9 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     float b1t = 1.0f, b2t = 1.0f;
     int probe_i = 0;
     const size_t tok0 = bd.tok_off;
+    PhaseClock pc;
+    pc.init(a.phase_clk, b == 0 && tid == 0);
+    net.pc = &pc;
 
     for (uint64_t i = 0; i < Lrun; i++) {
       const bool uniform = !d.model_on || i < (uint64_t)t;
@@ -330,59 +329,66 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         }
         __syncthreads();
       }
+      pc.mark(0);
       float alpha = 0.0f;
       if (!uniform) {
         if (d.static_on) alpha = 1.0f / (1.0f + expf(-W[d.P]));
         net.forward(W, i, alpha);
-        // mixer (Eq. 1) + softmax + quantiser, one wave per row
-        for (int j = wave; j < bs; j += NT / 64) {
-          float z[4], p[4];
+        pc.mark(1);
+        // mixer (Eq. 1) + softmax + quantiser: lane j owns row j (no cross-lane
+        // traffic; rows are VS = V + 4 floats apart, so b128 reads are
+        // conflict-free)
+        if (tid < bs) {
+          const int j = tid;
+          float *lr = lm + j * VS;
+          float *ur = lu + j * VS;
           float mx = -INFINITY;
-#pragma unroll
-          for (int q = 0; q < 4; q++) {
-            int v = lane + 64 * q;
-            z[q] = -INFINITY;
-            if (v < V) {
-              float m = lm[j * V + v];
-              z[q] = d.static_on ? (alpha * lu[j * V + v] + (1.0f - alpha) * m) : m;
-              mx = fmaxf(mx, z[q]);
+          for (int v = 0; v < V; v += 4) {
+            float4 m4 = *reinterpret_cast<float4 *>(lr + v);
+            float4 z4 = m4;
+            if (d.static_on) {
+              const float4 u4 = *reinterpret_cast<const float4 *>(ur + v);
+              z4.x = alpha * u4.x + (1.0f - alpha) * m4.x;
+              z4.y = alpha * u4.y + (1.0f - alpha) * m4.y;
+              z4.z = alpha * u4.z + (1.0f - alpha) * m4.z;
+              z4.w = alpha * u4.w + (1.0f - alpha) * m4.w;
+              // keep L^u - L^m for the mixing-weight gradient
+              *reinterpret_cast<float4 *>(ur + v) =
+                  make_float4(u4.x - m4.x, u4.y - m4.y, u4.z - m4.z, u4.w - m4.w);
             }
+            *reinterpret_cast<float4 *>(lr + v) = z4;
+            mx = fmaxf(mx, fmaxf(fmaxf(z4.x, z4.y), fmaxf(z4.z, z4.w)));
           }
-          mx = wave_max(mx);
           float se = 0.0f;
-#pragma unroll
-          for (int q = 0; q < 4; q++) {
-            int v = lane + 64 * q;
-            p[q] = (v < V) ? expf(z[q] - mx) : 0.0f;
-            se += p[q];
+          for (int v = 0; v < V; v += 4) {
+            float4 z4 = *reinterpret_cast<float4 *>(lr + v);
+            z4.x = expf(z4.x - mx);
+            z4.y = expf(z4.y - mx);
+            z4.z = expf(z4.z - mx);
+            z4.w = expf(z4.w - mx);
+            se = se + z4.x + z4.y + z4.z + z4.w;
+            *reinterpret_cast<float4 *>(lr + v) = z4;
           }
-          se = wave_sum(se);
           float srow = 0.0f;
-#pragma unroll
-          for (int q = 0; q < 4; q++) {
-            int v = lane + 64 * q;
-            if (v < V) {
-              p[q] = p[q] / se;
-              if (d.static_on) {
-                float diff = lu[j * V + v] - lm[j * V + v];
-                lu[j * V + v] = diff;
-                srow = fmaf(p[q], diff, srow);
-              }
-              lm[j * V + v] = p[q];
+          for (int v = 0; v < V; v += 4) {
+            float4 e4 = *reinterpret_cast<float4 *>(lr + v);
+            e4.x = e4.x / se;
+            e4.y = e4.y / se;
+            e4.z = e4.z / se;
+            e4.w = e4.w / se;
+            *reinterpret_cast<float4 *>(lr + v) = e4;
+            if (d.static_on) {
+              const float4 df = *reinterpret_cast<const float4 *>(ur + v);
+              srow = fmaf(e4.x, df.x, srow);
+              srow = fmaf(e4.y, df.y, srow);
+              srow = fmaf(e4.z, df.z, srow);
+              srow = fmaf(e4.w, df.w, srow);
             }
           }
-          if (d.static_on) {
-            srow = wave_sum(srow);
-            if (lane == 0) misc[j] = srow;
-          }
-          row_quantise(p, V, lane, cdf + j * (V + 1));
-          if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) {
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-              int v = lane + 64 * q;
-              if (v < V) a.probe_P[((size_t)probe_i * bs + j) * V + v] = p[q];
-            }
-          }
+          if (d.static_on) misc[j] = srow;
+          row_quantise_lane(lr, V, cdf + j * (V + 1));
+          if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i)
+            for (int v = 0; v < V; v++) a.probe_P[((size_t)probe_i * bs + j) * V + v] = lr[v];
         }
         __syncthreads();
       } else if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) {
@@ -390,6 +396,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       }
       if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) probe_i++;
 
+      pc.mark(2);
       // ---- coding: lane j codes token i of segment j
       if (tid < bs) {
         const int j = tid;
@@ -414,18 +421,27 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
           a.tokens[tok0 + (size_t)j * bd.L + i] = (uint8_t)e;
         }
       }
+      // mixing-weight gradient: per-row terms summed by a wave butterfly,
+      // then the wave partials in order by thread 0
+      if (d.static_on && !uniform && wave < (bs + 63) / 64) {
+        float gt = 0.0f;
+        if (tid < bs) gt = misc[tid] - lu[tid * VS + tgt[tid]];
+        gt = wave_sum(gt);
+        if (lane == 0) misc[bs + wave] = gt;
+      }
       __syncthreads();
 
       if (!uniform) {
+        pc.mark(3);
         // dz = (P - onehot)/bs (mean loss over the step's rows); dL^m = (1-alpha) dz
         for (int q = tid; q < bs * V; q += NT) {
-          int j = q / V, v = q % V;
-          float dz = (lm[q] - (v == tgt[j] ? 1.0f : 0.0f)) * inv_bs;
-          lm[q] = d.static_on ? dz * (1.0f - alpha) : dz;
+          const int j = q / V, v = q % V, idx = j * VS + v;
+          float dz = (lm[idx] - (v == tgt[j] ? 1.0f : 0.0f)) * inv_bs;
+          lm[idx] = d.static_on ? dz * (1.0f - alpha) : dz;
         }
         if (d.static_on && tid == 0) {
           float acc = 0.0f;
-          for (int j = 0; j < bs; j++) acc += misc[j] - lu[j * V + tgt[j]];
+          for (int w = 0; w < (bs + 63) / 64; w++) acc += misc[bs + w];
           sh_ga = acc * inv_bs * (alpha * (1.0f - alpha));
         }
         __syncthreads();
@@ -437,11 +453,14 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
           opt.c1 = 1.0f - b1t;
           opt.c2 = 1.0f - b2t;
         }
+        pc.mark(4);
         net.backward(W, M, Vs, i, opt);
+        pc.mark(5);
         // embedding update from the fixed-point sums
         for (int q = tid; q < V * E; q += NT) {
-          float gq = (float)((double)demb[q] * (1.0 / (double)(1ull << kFixShift)));
-          demb[q] = 0;
+          const int qi = (q / E) * d.ES + q % E;
+          float gq = (float)((double)demb[qi] * (1.0 / (double)(1ull << kFixShift)));
+          demb[qi] = 0;
           const int pi = d.off_emb + q;
           emb[q] = emb[q] - opt_delta(opt, gq, M ? M + pi : nullptr, Vs ? Vs + pi : nullptr);
         }
@@ -450,9 +469,11 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         }
         __syncthreads();
       }
+      pc.mark(6);
       if (bd.has_snap && i + 1 == (uint64_t)bd.S) snapshot();
     }
 
+    pc.flush();
     if (tid < bs) {
       if (a.mode == 0) {
         enc_finish(enc, slot, bd.slot_words, ovf);

@@ -45,7 +45,7 @@ struct Ctx {   // context-window gather for the first layer
 // layer 0 gathers in[j][p*E+e] = emb[ring[j][(base+p)&mask]][e]
 __device__ __forceinline__ void fwd_tile(int r0, int c0, int Din, int Dout, const float *__restrict__ W,
                                          const float *__restrict__ b, const float *in, const Ctx *g, float *out,
-                                         bool relu) {
+                                         int ldo, bool relu) {
   float acc[4][4];
   float4 bb = *reinterpret_cast<const float4 *>(b + c0);
 #pragma unroll
@@ -102,13 +102,13 @@ __device__ __forceinline__ void fwd_tile(int r0, int c0, int Din, int Dout, cons
     o.y = relu ? fmaxf(acc[r][1], 0.0f) : acc[r][1];
     o.z = relu ? fmaxf(acc[r][2], 0.0f) : acc[r][2];
     o.w = relu ? fmaxf(acc[r][3], 0.0f) : acc[r][3];
-    *reinterpret_cast<float4 *>(out + (r0 + r) * Dout + c0) = o;
+    *reinterpret_cast<float4 *>(out + (r0 + r) * ldo + c0) = o;
   }
 }
 
 // dIn[j][d] = sum_o dOut[j][o] W[d][o]; rows j0..j0+3, columns d0..d0+3
 __device__ __forceinline__ void bwd_in_tile(int r0, int d0, int Dout, const float *__restrict__ W,
-                                            const float *dOut, float acc[4][4]) {
+                                            const float *dOut, int ldo, float acc[4][4]) {
 #pragma unroll
   for (int r = 0; r < 4; r++)
 #pragma unroll
@@ -116,7 +116,7 @@ __device__ __forceinline__ void bwd_in_tile(int r0, int d0, int Dout, const floa
   for (int o = 0; o < Dout; o += 4) {
     float4 a[4], w[4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) a[r] = *reinterpret_cast<const float4 *>(dOut + (r0 + r) * Dout + o);
+    for (int r = 0; r < 4; r++) a[r] = *reinterpret_cast<const float4 *>(dOut + (r0 + r) * ldo + o);
 #pragma unroll
     for (int q = 0; q < 4; q++) w[q] = *reinterpret_cast<const float4 *>(W + (size_t)(d0 + q) * Dout + o);
 #pragma unroll
@@ -133,7 +133,7 @@ __device__ __forceinline__ void bwd_in_tile(int r0, int d0, int Dout, const floa
 
 // dW[d][o] = sum_j In[j][d] dOut[j][o], then the optimiser update of W.
 __device__ __forceinline__ void bwd_w_tile(int d0, int o0, int rows, int Dout, float *W, float *M, float *Vv,
-                                           const float *in, int Din, const Ctx *g, const float *dOut,
+                                           const float *in, int Din, const Ctx *g, const float *dOut, int ldo,
                                            const Opt &opt) {
   float acc[4][4];
 #pragma unroll
@@ -150,7 +150,7 @@ __device__ __forceinline__ void bwd_w_tile(int d0, int o0, int rows, int Dout, f
     } else {
       a = *reinterpret_cast<const float4 *>(in + j * Din + d0);
     }
-    float4 bv = *reinterpret_cast<const float4 *>(dOut + j * Dout + o0);
+    float4 bv = *reinterpret_cast<const float4 *>(dOut + j * ldo + o0);
     const float av[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
     for (int q = 0; q < 4; q++) {
@@ -182,6 +182,7 @@ struct NetGeneric {
   uint8_t *ring;
   long long *demb;
   int tid;
+  PhaseClock *pc = nullptr;
   __device__ NetGeneric(const StepArgs &a_, unsigned char *lds) : a(a_), d(a_.d) {
     emb = reinterpret_cast<float *>(lds + a.lay.emb);
     embs = reinterpret_cast<float *>(lds + a.lay.embs);
@@ -224,7 +225,7 @@ struct NetGeneric {
         const float *in = l == 0 ? nullptr : (st ? dh[(l - 1) & 1] : act[l - 1]);
         float *out = last ? (st ? lu : lm) : (st ? dh[l & 1] : act[l]);
         fwd_tile(r0, c0, Din, Dout, Wp + d.off_W[l], Wp + d.off_b[l], in, l == 0 ? (st ? &gs : &g) : nullptr, out,
-                 !last);
+                 last ? d.VS : Dout, !last);
       }
       __syncthreads();
     }
@@ -236,6 +237,7 @@ struct NetGeneric {
     const int bs = d.bs, nh = d.nh, RS = d.RS, mask = d.RS - 1, t = d.t, E = d.E;
     const Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E};
     const float *dout = lm;
+    int ldo = d.VS;
     for (int l = nh; l >= 0; l--) {
       const int Din = d.dim[l], Dout = d.dim[l + 1];
       float *Wl = W + d.off_W[l];
@@ -245,7 +247,7 @@ struct NetGeneric {
       for (int tile = tid; tile < tiles_a; tile += NT) {
         const int r0 = (tile / (Din / 4)) * 4, c0 = (tile % (Din / 4)) * 4;
         float acc[4][4];
-        bwd_in_tile(r0, c0, Dout, Wl, dout, acc);
+        bwd_in_tile(r0, c0, Dout, Wl, dout, ldo, acc);
         if (l > 0) {
           const float *ain = act[l - 1];
 #pragma unroll
@@ -266,7 +268,7 @@ struct NetGeneric {
             for (int q = 0; q < 4; q++) {
               const int dd = c0 + q, p = dd / E, e = dd % E;
               const int tk = ring[j * RS + (((int)(i - (uint64_t)t) + p) & mask)];
-              atomicAdd(reinterpret_cast<unsigned long long *>(demb + tk * E + e),
+              atomicAdd(reinterpret_cast<unsigned long long *>(demb + tk * d.ES + e),
                         (unsigned long long)to_fixed(acc[r][q]));
             }
           }
@@ -279,15 +281,17 @@ struct NetGeneric {
       float *Vl = Vs ? Vs + d.off_W[l] : nullptr;
       for (int tile = tid; tile < tiles_b; tile += NT) {
         const int d0 = (tile / (Dout / 4)) * 4, o0 = (tile % (Dout / 4)) * 4;
-        bwd_w_tile(d0, o0, bs, Dout, Wl, Ml, Vl, l == 0 ? nullptr : act[l - 1], Din, l == 0 ? &g : nullptr, dout, opt);
+        bwd_w_tile(d0, o0, bs, Dout, Wl, Ml, Vl, l == 0 ? nullptr : act[l - 1], Din, l == 0 ? &g : nullptr, dout, ldo,
+                   opt);
       }
       for (int o = tid; o < Dout; o += NT) {
         float gsum = 0.0f;
-        for (int j = 0; j < bs; j++) gsum += dout[j * Dout + o];
+        for (int j = 0; j < bs; j++) gsum += dout[j * ldo + o];
         const int bi = d.off_b[l] + o;
         W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
       }
       dout = dIn;
+      ldo = Din;
     }
     __syncthreads();
   }
@@ -362,22 +366,16 @@ hipError_t launch_init_params(const Dims &d, uint64_t seed, float *out, hipStrea
 }
 
 // ------------------------------------------------------- test exports
+// the step kernels' quantiser, one row per thread
 __global__ void quantise_kernel(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf) {
-  const int lane = threadIdx.x & 63;
-  const uint32_t row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= rows) return;
-  float p[4];
-#pragma unroll
-  for (int q = 0; q < 4; q++) {
-    int v = lane + 64 * q;
-    p[q] = v < (int)V ? P[(size_t)row * V + v] : 0.0f;
-  }
-  row_quantise(p, (int)V, lane, cdf + (size_t)row * (V + 1));
+  row_quantise_lane(P + (size_t)row * V, (int)V, cdf + (size_t)row * (V + 1));
 }
 
 hipError_t launch_quantise(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf, hipStream_t st) {
   if (rows == 0) return hipSuccess;
-  hipLaunchKernelGGL(quantise_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, P, rows, V, cdf);
+  hipLaunchKernelGGL(quantise_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, P, rows, V, cdf);
   return hipGetLastError();
 }
 

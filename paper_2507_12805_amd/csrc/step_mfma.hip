@@ -98,6 +98,7 @@ struct NetMfma {
   uint8_t *ring;
   long long *demb;
   int tid, lane, wave, r, g;
+  PhaseClock *pc = nullptr;
   __device__ NetMfma(const StepArgs &a_, unsigned char *lds) : a(a_), d(a_.d) {
     emb = reinterpret_cast<float *>(lds + a.lay.emb);
     embs = reinterpret_cast<float *>(lds + a.lay.embs);
@@ -203,7 +204,7 @@ struct NetMfma {
       for (int m = 0; m < MAXT; m++) {
         if (m < mb || m >= me) continue;
 #pragma unroll
-        for (int q = 0; q < 4; q++) out[(16 * m + 4 * g + q) * V + 16 * n + r] = acc[m][q] + bias;
+        for (int q = 0; q < 4; q++) out[(16 * m + 4 * g + q) * d.VS + 16 * n + r] = acc[m][q] + bias;
       }
     });
     __syncthreads();
@@ -228,7 +229,7 @@ struct NetMfma {
         for (int m = 0; m < MAXT; m++) {
           if (m < mb || m >= me) continue;
           float av[KL];
-          load_run<KL>(lm + (16 * m + r) * V + kk, av);
+          load_run<KL>(lm + (16 * m + r) * d.VS + kk, av);
           acc[m] = P::mma(P::pack(av), bf, acc[m]);
         }
       }
@@ -243,6 +244,7 @@ struct NetMfma {
       }
     });
     __syncthreads();
+    pc->mark(8);
     // B2: dW2^T = dL^T H1 -> W2 update; db2.   B3: dX^T = W1 dpre^T -> embedding scatter.
     float *M2 = M ? M + d.off_W[1] : nullptr, *V2 = Vs ? Vs + d.off_W[1] : nullptr;
     split_groups<NW>(H / 16, V / 16, wave, [&](int n, int mb, int me) {
@@ -258,7 +260,7 @@ struct NetMfma {
         for (int m = 0; m < MAXT; m++) {
           if (m < mb || m >= me) continue;
           float av[KL];
-          load_strided<KL>(lm + kk * V + 16 * m + r, V, av);
+          load_strided<KL>(lm + kk * d.VS + 16 * m + r, d.VS, av);
           acc[m] = P::mma(P::pack(av), bf, acc[m]);
         }
       }
@@ -276,7 +278,7 @@ struct NetMfma {
     });
     for (int v = tid; v < V; v += NT) {
       float gsum = 0.0f;
-      for (int j = 0; j < bs; j++) gsum += lm[j * V + v];
+      for (int j = 0; j < bs; j++) gsum += lm[j * d.VS + v];
       const int bi = d.off_b[1] + v;
       W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
     }
@@ -314,12 +316,13 @@ struct NetMfma {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           const int dd = 16 * mt + 4 * g + q, p = dd / E, e = dd % E;
-          atomicAdd(reinterpret_cast<unsigned long long *>(demb + token(j, p, i) * E + e),
+          atomicAdd(reinterpret_cast<unsigned long long *>(demb + token(j, p, i) * d.ES + e),
                     (unsigned long long)to_fixed(acc[n][q]));
         }
       }
     }
     __syncthreads();
+    pc->mark(9);
     // B4: dW1^T = dpre^T X -> W1 update (a wave owns column tiles over d); db1
     float *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
     const int Ht = H / 16;
@@ -363,6 +366,7 @@ struct NetMfma {
       W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
     }
     __syncthreads();
+    pc->mark(10);
   }
 };
 
