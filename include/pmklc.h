@@ -131,7 +131,8 @@ const char *pmklc_status_string(pmklc_status s);
 /* Frequency quantisation of probabilities: for each of `rows` rows of V
  * FP32 probabilities, f_v = 1 + floor(p_v * (2^16 - V)) with the product
  * taken exactly, the residual 2^16 - sum(f) added to the largest p (lowest
- * index on ties); cdf_dev receives rows x (V+1) cumulative counts (u32). */
+ * index on ties); cdf_dev receives rows x (V+1) cumulative counts (u32).
+ * V is a vocabulary size 4^k: 4, 16, 64 or 256 (else ERR_INVALID_ARG). */
 pmklc_status pmklc_quantise(const float *probs_dev, uint32_t rows, uint32_t V, uint32_t *cdf_dev,
                             void *stream);
 

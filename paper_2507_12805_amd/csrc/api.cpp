@@ -166,8 +166,9 @@ pmklc_status fill_dims(uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t
   d.optimizer = (int)opt;
   d.lr = lr; d.b1 = b1; d.b2 = b2; d.eps = eps;
   if (!d.model_on) d.nh = 0;   // uniform coding needs no model
-  if ((uint64_t)t * E > (1u << 20)) return PMKLC_ERR_UNSUPPORTED;
+  if ((uint64_t)t * E > (1u << 20) || E >= 4096) return PMKLC_ERR_UNSUPPORTED;
   d.dim[0] = d.D;
+  d.Emag = E ? (uint32_t)(((1ull << 32) + E - 1) / E) : 0;
   for (int l = 0; l < d.nh; l++) { d.H[l] = (int)hidden[l]; d.dim[l + 1] = (int)hidden[l]; }
   d.dim[d.nh + 1] = d.V;
   uint64_t off = 0;
@@ -202,6 +203,8 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
 
   d.VS = d.V + 4;
   d.ES = d.E + 1;
+  d.EP = d.E + 4;
+  d.HP = d.H[0] + 4;
   d.CH = 32;
   int rs = 1;
   while (rs < d.t + d.CH) rs <<= 1;
@@ -221,16 +224,16 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
       g = align_up(g + bytes / 4, 64);
       return (int)at;
     };
-    L.emb = take(4ull * d.V * E);
-    L.embs = take(d.static_on ? 4ull * d.V * E : 0);
+    L.emb = take(4ull * d.V * d.EP);
+    L.embs = take(d.static_on ? 4ull * d.V * d.EP : 0);
     L.ring = take((uint64_t)bs * d.RS);
-    L.act[0] = act(d.nh >= 1 ? 4ull * bs * d.H[0] : 0);
+    L.act[0] = act(d.nh >= 1 ? 4ull * bs * d.HP : 0);
     L.act[1] = act(d.nh >= 2 ? 4ull * bs * d.H[1] : 0);
     L.lm = take(4ull * bs * d.VS);
     L.lu = take(d.static_on ? 4ull * bs * d.VS : 0);
     L.cdf = take(4ull * bs * (d.V + 1));
     L.tgt = take(bs);
-    L.dh[0] = act(d.nh >= 1 ? 4ull * bs * hmax : 0);
+    L.dh[0] = act(d.nh >= 1 ? 4ull * bs * (hmax + 4) : 0);
     L.dh[1] = act(d.nh >= 2 ? 4ull * bs * hmax : 0);
     L.demb = take(8ull * d.V * d.ES);
     L.misc = take(4ull * bs + 64);
@@ -244,7 +247,7 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
   if (bs > 512) return PMKLC_ERR_UNSUPPORTED;
   // matrix-core kernel: one hidden layer, tile-friendly shapes
   const bool mfma_ok = d.model_on && !L.act_global && d.nh == 1 && bs % 32 == 0 && bs <= 128 && d.H[0] % 32 == 0 && d.V % 32 == 0 &&
-                       E % 8 == 0 && d.D % 32 == 0;
+                       E % 8 == 0 && E < 4096 && d.D % 32 == 0;
   m.kind = kGeneric;
   if (precision == PMKLC_BF16) {
     if (d.model_on && !mfma_ok) return PMKLC_ERR_UNSUPPORTED;
@@ -1211,7 +1214,7 @@ pmklc_status pmklc_last_timing(pmklc_timing *t) {
 
 // ------------------------------------------------------------ test exports
 pmklc_status pmklc_quantise(const float *probs_dev, uint32_t rows, uint32_t V, uint32_t *cdf_dev, void *stream) {
-  if (V < 2 || V > 256 || (rows && (!probs_dev || !cdf_dev))) return PMKLC_ERR_INVALID_ARG;
+  if ((V != 4 && V != 16 && V != 64 && V != 256) || (rows && (!probs_dev || !cdf_dev))) return PMKLC_ERR_INVALID_ARG;
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIP_TRY(launch_quantise(probs_dev, rows, V, cdf_dev, st));
   HIP_TRY(hipStreamSynchronize(st));

@@ -21,8 +21,13 @@ struct Dims {
   int stride;                   // floats per block parameter slab (>= P+1, multiple of 64)
   int VS;                       // row stride (floats) of the logits / probability rows in LDS (V + 4)
   int ES;                       // row stride (entries) of the fixed-point embedding gradient (E + 1)
+  int EP;                       // row pitch (floats) of the embedding tables in LDS (E + 4: rows of
+                                // 16 tokens fall in distinct banks, float4 runs stay aligned)
+  int HP;                       // row pitch (floats) of the hidden activations of the matrix-core
+                                // kernel in LDS (H[0] + 4, same reason)
   int RS;                       // context ring length (power of two >= t + CH)
   int CH;                       // tokens staged per row at a time (encode)
+  uint32_t Emag;                // ceil(2^32 / E): k / E = umulhi(k, Emag) for k < 2^20, E < 4096
   int static_on;                // frozen static model mixed in (Eq. 1)
   int model_on;                 // dynamic model present (else every token is uniform)
   int optimizer;                // 0 SGD, 1 Adam

@@ -5,6 +5,19 @@
 namespace pmklc {
 namespace detail {
 
+// Global-memory views.  Pointers read out of the argument block are generic
+// (flat) to the compiler, and a flat load also counts as LDS traffic: every
+// wait for an LDS read would then wait for the outstanding weight loads too.
+// Hot loops address weights through these address-space-1 views instead.
+typedef __attribute__((address_space(1))) float gfloat;
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) fvec4 gfvec4;
+__device__ __forceinline__ gfloat *glb(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *glb(const float *p) { return (const gfloat *)p; }
+// four consecutive floats, 16-byte aligned
+__device__ __forceinline__ fvec4 ld4(const gfloat *p) { return *(const gfvec4 *)p; }
+__device__ __forceinline__ void st4(gfloat *p, fvec4 v) { *(gfvec4 *)p = v; }
+
 
 constexpr uint32_t kHalf = 0x80000000u;
 constexpr uint32_t kQuarter = 0x40000000u;
@@ -144,29 +157,64 @@ __device__ __forceinline__ int dec_symbol(Dec &d, const uint32_t *w, uint32_t nw
 }
 
 // ------------------------------------------------------------ quantiser
-// Frequency quantisation of one row held by one lane: f_v = 1 +
-// floor(p_v * (2^16 - V)) with the product taken exactly in FP64, the
-// residual 2^16 - sum f added to the most probable symbol (lowest index on
-// ties); writes the V+1 cumulative counts.
-__device__ __forceinline__ void row_quantise_lane(const float *p, int V, uint32_t *cdf) {
-  int fsum = 0, besti = 0;
+// floor(p * c) of the exact real product, for 0 <= p <= 1 and an integer
+// 0 < c < 2^24, in FP32: y = fl(p c) and the FMA residual p c - y (exact for
+// a product) decide the only ambiguous case, y integral with p c < y.  If y
+// is not an integer, no integer lies between p c and y (integers below 2^24
+// are representable and rounding is monotone), so floor(y) is exact.
+__device__ __forceinline__ int floor_mul_exact(float p, float c) {
+  const float y = p * c;
+  const float err = fmaf(p, c, -y);
+  float fy = floorf(y);
+  if (fy == y && err < 0.0f) fy -= 1.0f;
+  return (int)fy;
+}
+
+// Lanes per row of the mixer/softmax/quantiser and symbols per lane: V/8
+// symbols per lane (at least 4, a float4 run); G = V/spl divides 64 for
+// every V = 4^k, so a row's lanes sit in one wave, aligned.
+__device__ __forceinline__ int row_spl(int V) { return V >= 32 ? V >> 3 : 4; }
+
+// Frequency quantisation of one row by its G lanes (lane gl owns symbols
+// [gl*spl, gl*spl + spl)): f_v = 1 + floor(p_v * (2^16 - V)) with the
+// product exact, the residual 2^16 - sum f added to the most probable
+// symbol (lowest index on ties), and the V+1 cumulative counts written.
+// Integer sums and a fixed-order scan: the result does not depend on G.
+// Invalid probabilities (NaN, outside [0, 1]) count as 0.
+__device__ __forceinline__ void row_quantise_group(const float *p, int V, int spl, int G, int gl, uint32_t *cdf) {
+  const float qc = (float)(kTotal - (uint32_t)V);
+  const int v0 = gl * spl;
+  int fs = 0, bi = v0;
   float best = -1.0f;
-  for (int v = 0; v < V; v++) {
+  for (int v = v0; v < v0 + spl; v++) {
     float pv = p[v];
     pv = (pv >= 0.0f && pv <= 1.0f) ? pv : 0.0f;
-    fsum += 1 + (int)floor((double)pv * (double)(kTotal - (uint32_t)V));
-    if (pv > best) { best = pv; besti = v; }
+    fs += 1 + floor_mul_exact(pv, qc);
+    if (pv > best) { best = pv; bi = v; }
   }
-  const int resid = (int)kTotal - fsum;
-  uint32_t run = 0;
-  for (int v = 0; v < V; v++) {
+  int tot = fs;
+  for (int o = G >> 1; o > 0; o >>= 1) {
+    tot += __shfl_xor(tot, o);
+    const float ob = __shfl_xor(best, o);
+    const int oi = __shfl_xor(bi, o);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int resid = (int)kTotal - tot;
+  const int mine = fs + ((bi >= v0 && bi < v0 + spl) ? resid : 0);
+  int incl = mine;
+  for (int o = 1; o < G; o <<= 1) {
+    const int y = __shfl_up(incl, o, G);
+    if (gl >= o) incl += y;
+  }
+  uint32_t run = (uint32_t)(incl - mine);
+  for (int v = v0; v < v0 + spl; v++) {
     float pv = p[v];
     pv = (pv >= 0.0f && pv <= 1.0f) ? pv : 0.0f;
-    const int f = 1 + (int)floor((double)pv * (double)(kTotal - (uint32_t)V)) + (v == besti ? resid : 0);
+    const int f = 1 + floor_mul_exact(pv, qc) + (v == bi ? resid : 0);
     cdf[v] = run;
     run += (uint32_t)f;
   }
-  cdf[V] = kTotal;
+  if (gl == G - 1) cdf[V] = kTotal;
 }
 
 __device__ __forceinline__ long long to_fixed(float x) {
@@ -179,7 +227,10 @@ struct Opt {
   int kind;
   float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^tau, c2 = 1 - b2^tau
 };
-__device__ __forceinline__ float opt_delta(const Opt &o, float g, float *m, float *v) {
+// m, v: optimiser state in LDS/registers (float) or global memory (gfloat);
+// untouched by SGD
+template <class F>
+__device__ __forceinline__ float opt_delta(const Opt &o, float g, F *m, F *v) {
   if (o.kind == 0) return o.lr * g;
   float mm = o.b1 * (*m) + (1.0f - o.b1) * g;
   float vv = o.b2 * (*v) + (1.0f - o.b2) * (g * g);
@@ -278,15 +329,19 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     }
     __syncthreads();
     for (int q = tid; q < V * E; q += NT) {
-      emb[q] = W[d.off_emb + q];
-      if (d.static_on) embs[q] = a.stat[d.off_emb + q];
+      const int v = (int)__umulhi((uint32_t)q, d.Emag), qp = q + v * (d.EP - E);   // row v, pitch EP
+      emb[qp] = W[d.off_emb + q];
+      if (d.static_on) embs[qp] = a.stat[d.off_emb + q];
     }
     for (int q = tid; q < V * d.ES; q += NT) demb[q] = 0;
     __syncthreads();
 
     auto snapshot = [&]() {
       float *dst = a.snap + (size_t)b * stride;
-      for (int q = tid; q < stride; q += NT) dst[q] = (q >= d.off_emb && q < d.off_emb + V * E) ? emb[q - d.off_emb] : W[q];
+      for (int q = tid; q < stride; q += NT) {
+        const int qe = q - d.off_emb;
+        dst[q] = (qe >= 0 && qe < V * E) ? emb[qe + (int)__umulhi((uint32_t)qe, d.Emag) * (d.EP - E)] : W[q];
+      }
       __threadfence();
       __syncthreads();
       if (tid == 0) __hip_atomic_store(a.snap_flag + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -332,18 +387,22 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       pc.mark(0);
       float alpha = 0.0f;
       if (!uniform) {
-        if (d.static_on) alpha = 1.0f / (1.0f + expf(-W[d.P]));
+        if (d.static_on) alpha = 1.0f / (1.0f + expf(-glb(W)[d.P]));
         net.forward(W, i, alpha);
         pc.mark(1);
-        // mixer (Eq. 1) + softmax + quantiser: lane j owns row j (no cross-lane
-        // traffic; rows are VS = V + 4 floats apart, so b128 reads are
-        // conflict-free)
-        if (tid < bs) {
-          const int j = tid;
+        // mixer (Eq. 1) + softmax + quantiser: G aligned lanes of one wave per
+        // row, spl symbols each (float4 runs); row reductions are xor
+        // butterflies over the G lanes after a sequential per-lane sum, so
+        // the order is fixed.  Rows are VS = V + 4 floats apart.
+        const int spl = row_spl(V), G = V / spl;
+        for (int j0 = 0; j0 < bs; j0 += NT / G) {
+          const int j = j0 + tid / G, gl = tid % G;
+          if (j >= bs) continue;   // a row's lanes are all in or all out
           float *lr = lm + j * VS;
           float *ur = lu + j * VS;
+          const int v0 = gl * spl;
           float mx = -INFINITY;
-          for (int v = 0; v < V; v += 4) {
+          for (int v = v0; v < v0 + spl; v += 4) {
             float4 m4 = *reinterpret_cast<float4 *>(lr + v);
             float4 z4 = m4;
             if (d.static_on) {
@@ -359,8 +418,9 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
             *reinterpret_cast<float4 *>(lr + v) = z4;
             mx = fmaxf(mx, fmaxf(fmaxf(z4.x, z4.y), fmaxf(z4.z, z4.w)));
           }
+          for (int o = G >> 1; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
           float se = 0.0f;
-          for (int v = 0; v < V; v += 4) {
+          for (int v = v0; v < v0 + spl; v += 4) {
             float4 z4 = *reinterpret_cast<float4 *>(lr + v);
             z4.x = expf(z4.x - mx);
             z4.y = expf(z4.y - mx);
@@ -369,8 +429,9 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
             se = se + z4.x + z4.y + z4.z + z4.w;
             *reinterpret_cast<float4 *>(lr + v) = z4;
           }
+          for (int o = G >> 1; o > 0; o >>= 1) se = se + __shfl_xor(se, o);
           float srow = 0.0f;
-          for (int v = 0; v < V; v += 4) {
+          for (int v = v0; v < v0 + spl; v += 4) {
             float4 e4 = *reinterpret_cast<float4 *>(lr + v);
             e4.x = e4.x / se;
             e4.y = e4.y / se;
@@ -385,10 +446,13 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
               srow = fmaf(e4.w, df.w, srow);
             }
           }
-          if (d.static_on) misc[j] = srow;
-          row_quantise_lane(lr, V, cdf + j * (V + 1));
+          if (d.static_on) {
+            for (int o = G >> 1; o > 0; o >>= 1) srow = srow + __shfl_xor(srow, o);
+            if (gl == 0) misc[j] = srow;
+          }
+          row_quantise_group(lr, V, spl, G, gl, cdf + j * (V + 1));
           if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i)
-            for (int v = 0; v < V; v++) a.probe_P[((size_t)probe_i * bs + j) * V + v] = lr[v];
+            for (int v = v0; v < v0 + spl; v++) a.probe_P[((size_t)probe_i * bs + j) * V + v] = lr[v];
         }
         __syncthreads();
       } else if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) {
@@ -458,14 +522,16 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         pc.mark(5);
         // embedding update from the fixed-point sums
         for (int q = tid; q < V * E; q += NT) {
-          const int qi = (q / E) * d.ES + q % E;
+          const int v = (int)__umulhi((uint32_t)q, d.Emag);
+          const int qi = q + v * (d.ES - E), qp = q + v * (d.EP - E);
           float gq = (float)((double)demb[qi] * (1.0 / (double)(1ull << kFixShift)));
           demb[qi] = 0;
           const int pi = d.off_emb + q;
-          emb[q] = emb[q] - opt_delta(opt, gq, M ? M + pi : nullptr, Vs ? Vs + pi : nullptr);
+          emb[qp] = emb[qp] - opt_delta(opt, gq, M ? glb(M) + pi : nullptr, Vs ? glb(Vs) + pi : nullptr);
         }
         if (d.static_on && tid == 0) {
-          W[d.P] = W[d.P] - opt_delta(opt, sh_ga, M ? M + d.P : nullptr, Vs ? Vs + d.P : nullptr);
+          gfloat *Wg = glb(W);
+          Wg[d.P] = Wg[d.P] - opt_delta(opt, sh_ga, M ? glb(M) + d.P : nullptr, Vs ? glb(Vs) + d.P : nullptr);
         }
         __syncthreads();
       }
@@ -482,7 +548,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       if (ovf) atomicOr(a.err, 2);
     }
     // final parameters (embedding lives in LDS during the loop)
-    for (int q = tid; q < V * E; q += NT) W[d.off_emb + q] = emb[q];
+    for (int q = tid; q < V * E; q += NT) W[d.off_emb + q] = emb[q + (int)__umulhi((uint32_t)q, d.Emag) * (d.EP - E)];
     __syncthreads();
     if (a.params_out && b == 0)
       for (int q = tid; q < d.P + 1; q += NT) a.params_out[q] = W[q];

@@ -38,7 +38,7 @@ struct Ctx {   // context-window gather for the first layer
   const uint8_t *ring;
   int RS, mask, base;   // ring row length, RS-1, (i - t)
   const float *emb;
-  int E;
+  int E, EP;            // embedding width, LDS row pitch
 };
 
 // out[j][o] = b[o] + sum_d in[j][d] W[d][o]   (optionally ReLU)
@@ -59,7 +59,7 @@ __device__ __forceinline__ void fwd_tile(int r0, int c0, int Din, int Dout, cons
       for (int e = 0; e < g->E; e += 4) {
         float4 a[4], w[4];
 #pragma unroll
-        for (int r = 0; r < 4; r++) a[r] = *reinterpret_cast<const float4 *>(g->emb + tk[r] * g->E + e);
+        for (int r = 0; r < 4; r++) a[r] = *reinterpret_cast<const float4 *>(g->emb + tk[r] * g->EP + e);
 #pragma unroll
         for (int q = 0; q < 4; q++) w[q] = *reinterpret_cast<const float4 *>(W + (size_t)(p * g->E + e + q) * Dout + c0);
 #pragma unroll
@@ -146,7 +146,7 @@ __device__ __forceinline__ void bwd_w_tile(int d0, int o0, int rows, int Dout, f
     float4 a;
     if (g) {
       int tk = g->ring[j * g->RS + ((g->base + p) & g->mask)];
-      a = *reinterpret_cast<const float4 *>(g->emb + tk * g->E + e);
+      a = *reinterpret_cast<const float4 *>(g->emb + tk * g->EP + e);
     } else {
       a = *reinterpret_cast<const float4 *>(in + j * Din + d0);
     }
@@ -210,8 +210,8 @@ struct NetGeneric {
   __device__ void forward(float *W, uint64_t i, float alpha) {
     (void)alpha;
     const int bs = d.bs, nh = d.nh, RS = d.RS, mask = d.RS - 1, t = d.t, E = d.E;
-    Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E};
-    Ctx gs{ring, RS, mask, (int)(i - (uint64_t)t), embs, E};
+    Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E, d.EP};
+    Ctx gs{ring, RS, mask, (int)(i - (uint64_t)t), embs, E, d.EP};
     for (int l = 0; l <= nh; l++) {
       const int Din = d.dim[l], Dout = d.dim[l + 1];
       const bool last = (l == nh);
@@ -235,7 +235,7 @@ struct NetGeneric {
   // the optimiser update, layer by layer from the output down
   __device__ void backward(float *W, float *M, float *Vs, uint64_t i, const Opt &opt) {
     const int bs = d.bs, nh = d.nh, RS = d.RS, mask = d.RS - 1, t = d.t, E = d.E;
-    const Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E};
+    const Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E, d.EP};
     const float *dout = lm;
     int ldo = d.VS;
     for (int l = nh; l >= 0; l--) {
@@ -366,16 +366,20 @@ hipError_t launch_init_params(const Dims &d, uint64_t seed, float *out, hipStrea
 }
 
 // ------------------------------------------------------- test exports
-// the step kernels' quantiser, one row per thread
+// the step kernels' quantiser (G lanes per row, as in the step loop)
 __global__ void quantise_kernel(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf) {
-  const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= rows) return;
-  row_quantise_lane(P + (size_t)row * V, (int)V, cdf + (size_t)row * (V + 1));
+  const int spl = row_spl((int)V), G = (int)V / spl;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t row = gid / (uint64_t)G;
+  if (row >= rows) return;   // whole groups leave together (G divides the block)
+  row_quantise_group(P + row * V, (int)V, spl, G, (int)(gid % (uint64_t)G), cdf + row * (V + 1));
 }
 
 hipError_t launch_quantise(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf, hipStream_t st) {
   if (rows == 0) return hipSuccess;
-  hipLaunchKernelGGL(quantise_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, P, rows, V, cdf);
+  const uint64_t G = V / (uint64_t)(V >= 32 ? V / 8 : 4);
+  const uint64_t threads = (uint64_t)rows * G;
+  hipLaunchKernelGGL(quantise_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, P, rows, V, cdf);
   return hipGetLastError();
 }
 

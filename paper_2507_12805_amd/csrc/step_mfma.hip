@@ -49,13 +49,18 @@ struct MmaBf16 {
   }
 };
 
-// KL consecutive floats (16-byte aligned when KL >= 4)
-template <int KL>
-__device__ __forceinline__ void load_run(const float *p, float *v) {
+// four consecutive floats (16-byte aligned) from LDS or global memory
+__device__ __forceinline__ fvec4 vec4_at(const float *p) { return *reinterpret_cast<const fvec4 *>(p); }
+__device__ __forceinline__ fvec4 vec4_at(const gfloat *p) { return ld4(p); }
+
+// KL consecutive floats (16-byte aligned when KL >= 4) from LDS (F = float)
+// or global memory (F = gfloat)
+template <int KL, class F>
+__device__ __forceinline__ void load_run(const F *p, float *v) {
   if constexpr (KL >= 4) {
 #pragma unroll
     for (int q = 0; q < KL; q += 4) {
-      float4 x = *reinterpret_cast<const float4 *>(p + q);
+      const fvec4 x = vec4_at(p + q);
       v[q] = x.x; v[q + 1] = x.y; v[q + 2] = x.z; v[q + 3] = x.w;
     }
   } else {
@@ -64,26 +69,10 @@ __device__ __forceinline__ void load_run(const float *p, float *v) {
   }
 }
 // KL floats with a stride
-template <int KL>
-__device__ __forceinline__ void load_strided(const float *p, int stride, float *v) {
+template <int KL, class F>
+__device__ __forceinline__ void load_strided(const F *p, int stride, float *v) {
 #pragma unroll
   for (int q = 0; q < KL; q++) v[q] = p[q * stride];
-}
-
-// Distributes `groups` groups of Mt tiles over NW waves: a wave gets whole
-// groups when there are enough, else a contiguous part of one group.
-template <int NW, class F>
-__device__ __forceinline__ void split_groups(int groups, int Mt, int wave, F &&f) {
-  if (groups >= NW) {
-    for (int g = wave; g < groups; g += NW) f(g, 0, Mt);
-  } else {
-    const int per = NW / groups;
-    const int g = wave / per, part = wave % per;
-    if (g < groups) {
-      const int mb = Mt * part / per, me = Mt * (part + 1) / per;
-      if (mb < me) f(g, mb, me);
-    }
-  }
 }
 
 }  // namespace
@@ -92,14 +81,20 @@ template <int NT, class P, int MAXT>
 struct NetMfma {
   static constexpr int NW = NT / 64;
   static constexpr int KS = P::KS, KL = P::KL;   // MAXT = bs / 16 row tiles
+  static constexpr int KC = 16 / KL;             // k-steps per streamed chunk (16 raw floats per lane)
+  static constexpr int KB = 16 * MAXT / KS;      // k-steps over the bs rows
+  // hidden tiles whose dpre^T fragments B4 keeps in registers (about 32 VGPRs)
+  static constexpr int HB = (32 / (KB * (KL == 8 ? 4 : 1))) > 0 ? (32 / (KB * (KL == 8 ? 4 : 1))) : 1;
+  typedef typename P::frag frag;
   const StepArgs &a;
   const Dims &d;
+  unsigned char *lds;
   float *emb, *embs, *h1, *hs, *lm, *lu;
   uint8_t *ring;
   long long *demb;
   int tid, lane, wave, r, g;
   PhaseClock *pc = nullptr;
-  __device__ NetMfma(const StepArgs &a_, unsigned char *lds) : a(a_), d(a_.d) {
+  __device__ NetMfma(const StepArgs &a_, unsigned char *lds_) : a(a_), d(a_.d), lds(lds_) {
     emb = reinterpret_cast<float *>(lds + a.lay.emb);
     embs = reinterpret_cast<float *>(lds + a.lay.embs);
     h1 = reinterpret_cast<float *>(lds + a.lay.act[0]);
@@ -110,212 +105,238 @@ struct NetMfma {
     demb = reinterpret_cast<long long *>(lds + a.lay.demb);
     tid = threadIdx.x;
     lane = tid & 63;
-    wave = tid >> 6;
+    wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: branches on it stay scalar
     r = lane & 15;
     g = lane >> 4;
   }
 
+  __device__ __forceinline__ frag zero_frag() const {
+    float z[KL];
+#pragma unroll
+    for (int q = 0; q < KL; q++) z[q] = 0.0f;
+    return P::pack(z);
+  }
+
+  // acc[m] += A_m(ks) B(ks) over k-steps 0..ksteps-1 with the streamed
+  // operand (B, or A when SA) fetched from global memory in chunks of KC
+  // k-steps, the next chunk in flight while the current one is used.
+  // load(ks, raw) issues the KL loads of k-step ks; reg(m, ks) gives the
+  // other operand of tile m (gathered for the whole chunk before its MFMAs,
+  // so the LDS round trips overlap).  Every fetch is issued unconditionally
+  // (addresses clamped to the last k-step), which keeps the in-order
+  // memory counter exact (a scheduling barrier pins each chunk's loads
+  // ahead of the previous chunk's MFMAs); chunks go in pairs, and k-steps
+  // past the end multiply a zero fragment, leaving acc exact.
+  template <int NM, bool SA, class LD, class RG>
+  __device__ __forceinline__ void stream(int ksteps, f32x4 *acc, LD &&load, RG &&reg) const {
+    float bufA[KC][KL], bufB[KC][KL];
+    const int nch = (ksteps + KC - 1) / KC;
+    // chunks are used in pairs; the k-steps of a padded pair past the end are zero
+    const bool ragged = (ksteps % (2 * KC)) != 0;
+    auto fetch = [&](int ch, float (&buf)[KC][KL]) {
+#pragma unroll
+      for (int c = 0; c < KC; c++) load(min(ch * KC + c, ksteps - 1), buf[c]);
+      // keep the scheduler from sinking the loads below the MFMAs they are
+      // meant to overlap
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    auto use = [&](int ch, float (&buf)[KC][KL]) {
+      frag o[KC][NM];
+#pragma unroll
+      for (int c = 0; c < KC; c++)
+#pragma unroll
+        for (int m = 0; m < NM; m++) o[c][m] = reg(m, min(ch * KC + c, ksteps - 1));
+#pragma unroll
+      for (int c = 0; c < KC; c++) {
+        frag sf = P::pack(buf[c]);
+        if (ragged && ch * KC + c >= ksteps) sf = zero_frag();
+#pragma unroll
+        for (int m = 0; m < NM; m++) acc[m] = SA ? P::mma(sf, o[c][m], acc[m]) : P::mma(o[c][m], sf, acc[m]);
+      }
+    };
+    fetch(0, bufA);
+    for (int ch = 0; ch < nch; ch += 2) {
+      fetch(ch + 1, bufB);
+      use(ch, bufA);
+      fetch(ch + 2, bufA);
+      use(ch + 1, bufB);
+    }
+  }
+
+  // an LDS array by byte offset (selecting offsets, not pointers, keeps the
+  // compiler from building a pointer table in scratch)
+  __device__ __forceinline__ float *lds_f(int off) const { return reinterpret_cast<float *>(lds + off); }
+
+  // token of context position p (0..t-1) of row j at step i
   __device__ __forceinline__ int token(int j, int p, uint64_t i) const {
     return ring[j * d.RS + (((int)(i - (uint64_t)d.t) + p) & (d.RS - 1))];
+  }
+  __device__ __forceinline__ void split_k(int kk, int &p, int &e) const {
+    p = (int)__umulhi((uint32_t)kk, d.Emag);
+    e = kk - p * d.E;
   }
 
   __device__ void forward(float *W, uint64_t i, float alpha) {
     (void)alpha;
-    const int bs = d.bs, H = d.H[0], V = d.V, E = d.E, D = d.D;
+    const int H = d.H[0], HP = d.HP, V = d.V, D = d.D;
     const int nmod = d.static_on ? 2 : 1;
-    const int Mt = bs / 16;
-    // F1: X W1 + b1, ReLU; a wave owns a column tile n and all its rows
-    split_groups<NW>(nmod * (H / 16), Mt, wave, [&](int grp, int mb, int me) {
+    // F1: X W1 + b1, ReLU; a wave owns a column tile n of one model and all row tiles
+    for (int grp = wave; grp < nmod * (H / 16); grp += NW) {
       const int model = grp / (H / 16), n = grp % (H / 16);
-      const float *Wm = model ? a.stat : W;
-      const float *W1 = Wm + d.off_W[0];
-      const float *em = model ? embs : emb;
+      const gfloat *Wm = glb(model ? a.stat : W);
+      const gfloat *wcol = Wm + d.off_W[0] + 16 * n + r + (size_t)(g * KL) * H;
+      const float *em = lds_f(model ? a.lay.embs : a.lay.emb);
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      // B fragments are fetched two k-steps ahead
-      const float *wcol = W1 + 16 * n + r + (size_t)(g * KL) * H;
-      float b0[KL], b1[KL];
-      load_strided<KL>(wcol, H, b0);
-      if (KS < D) load_strided<KL>(wcol + (size_t)KS * H, H, b1);
-      auto step = [&](int k0, float *bcur) {
-        const typename P::frag bf = P::pack(bcur);
-        if (k0 + 2 * KS < D) load_strided<KL>(wcol + (size_t)(k0 + 2 * KS) * H, H, bcur);
-        const int kk = k0 + g * KL;
-        const int p = kk / E, e = kk % E;
-#pragma unroll
-        for (int m = 0; m < MAXT; m++) {
-          if (m < mb || m >= me) continue;
-          float av[KL];
-          load_run<KL>(em + token(16 * m + r, p, i) * E + e, av);
-          acc[m] = P::mma(P::pack(av), bf, acc[m]);
-        }
-      };
-      int k0 = 0;
-      for (; k0 + 2 * KS <= D; k0 += 2 * KS) {
-        step(k0, b0);
-        step(k0 + KS, b1);
-      }
-      if (k0 < D) step(k0, b0);
+      stream<MAXT, false>(D / KS, acc,
+          [&](int ks, float *v) { load_strided<KL>(wcol + (size_t)ks * KS * H, H, v); },
+          [&](int m, int ks) {
+            int p, e;
+            split_k(ks * KS + g * KL, p, e);
+            float av[KL];
+            load_run<KL>(em + token(16 * m + r, p, i) * d.EP + e, av);
+            return P::pack(av);
+          });
       const float bias = Wm[d.off_b[0] + 16 * n + r];
-      float *out = model ? hs : h1;
+      float *out = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
 #pragma unroll
-      for (int m = 0; m < MAXT; m++) {
-        if (m < mb || m >= me) continue;
+      for (int m = 0; m < MAXT; m++)
 #pragma unroll
-        for (int q = 0; q < 4; q++) out[(16 * m + 4 * g + q) * H + 16 * n + r] = fmaxf(acc[m][q] + bias, 0.0f);
-      }
-    });
+        for (int q = 0; q < 4; q++) out[(16 * m + 4 * g + q) * HP + 16 * n + r] = fmaxf(acc[m][q] + bias, 0.0f);
+    }
     __syncthreads();
     // F2: H1 W2 + b2 -> logits
-    split_groups<NW>(nmod * (V / 16), Mt, wave, [&](int grp, int mb, int me) {
+    for (int grp = wave; grp < nmod * (V / 16); grp += NW) {
       const int model = grp / (V / 16), n = grp % (V / 16);
-      const float *Wm = model ? a.stat : W;
-      const float *W2 = Wm + d.off_W[1];
-      const float *hin = model ? hs : h1;
+      const gfloat *Wm = glb(model ? a.stat : W);
+      const gfloat *wcol = Wm + d.off_W[1] + 16 * n + r + (size_t)(g * KL) * V;
+      const float *hin = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      const float *wcol = W2 + 16 * n + r + (size_t)(g * KL) * V;
-      float b0[KL], b1[KL];
-      load_strided<KL>(wcol, V, b0);
-      if (KS < H) load_strided<KL>(wcol + (size_t)KS * V, V, b1);
-      auto step = [&](int k0, float *bcur) {
-        const typename P::frag bf = P::pack(bcur);
-        if (k0 + 2 * KS < H) load_strided<KL>(wcol + (size_t)(k0 + 2 * KS) * V, V, bcur);
-        const int kk = k0 + g * KL;
-#pragma unroll
-        for (int m = 0; m < MAXT; m++) {
-          if (m < mb || m >= me) continue;
-          float av[KL];
-          load_run<KL>(hin + (16 * m + r) * H + kk, av);
-          acc[m] = P::mma(P::pack(av), bf, acc[m]);
-        }
-      };
-      int k0 = 0;
-      for (; k0 + 2 * KS <= H; k0 += 2 * KS) {
-        step(k0, b0);
-        step(k0 + KS, b1);
-      }
-      if (k0 < H) step(k0, b0);
+      stream<MAXT, false>(H / KS, acc,
+          [&](int ks, float *v) { load_strided<KL>(wcol + (size_t)ks * KS * V, V, v); },
+          [&](int m, int ks) {
+            float av[KL];
+            load_run<KL>(hin + (16 * m + r) * HP + ks * KS + g * KL, av);
+            return P::pack(av);
+          });
       const float bias = Wm[d.off_b[1] + 16 * n + r];
-      float *out = model ? lu : lm;
+      float *out = lds_f(model ? a.lay.lu : a.lay.lm);
 #pragma unroll
-      for (int m = 0; m < MAXT; m++) {
-        if (m < mb || m >= me) continue;
+      for (int m = 0; m < MAXT; m++)
 #pragma unroll
         for (int q = 0; q < 4; q++) out[(16 * m + 4 * g + q) * d.VS + 16 * n + r] = acc[m][q] + bias;
-      }
-    });
+    }
     __syncthreads();
   }
 
-  __device__ void backward(float *W, float *M, float *Vs, uint64_t i, const Opt &opt) {
-    const int bs = d.bs, H = d.H[0], V = d.V, E = d.E, D = d.D;
-    const int Mt = bs / 16;
-    float *W1 = W + d.off_W[0], *W2 = W + d.off_W[1];
+  __device__ void backward(float *Wf, float *Mf, float *Vf, uint64_t i, const Opt &opt) {
+    const int bs = d.bs, H = d.H[0], HP = d.HP, V = d.V, D = d.D;
+    gfloat *W = glb(Wf), *M = Mf ? glb(Mf) : nullptr, *Vs = Vf ? glb(Vf) : nullptr;
+    gfloat *W1 = W + d.off_W[0], *W2 = W + d.off_W[1];
     float *dpre = hs;
-    // B1: dpre = (dL W2^T) * [H1 > 0]
-    split_groups<NW>(H / 16, Mt, wave, [&](int n, int mb, int me) {
+    const bool adam = opt.kind == 1;
+    // B1: dpre = (dL W2^T) * [H1 > 0]; B operand = rows of W2 (contiguous over v)
+    for (int n = wave; n < H / 16; n += NW) {
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int k0 = 0; k0 < V; k0 += KS) {
-        const int kk = k0 + g * KL;
-        float bv[KL];
-        load_run<KL>(W2 + (size_t)(16 * n + r) * V + kk, bv);
-        const typename P::frag bf = P::pack(bv);
+      const gfloat *wrow = W2 + (size_t)(16 * n + r) * V + g * KL;
+      stream<MAXT, false>(V / KS, acc,
+          [&](int ks, float *v) { load_run<KL>(wrow + ks * KS, v); },
+          [&](int m, int ks) {
+            float av[KL];
+            load_run<KL>(lm + (16 * m + r) * d.VS + ks * KS + g * KL, av);
+            return P::pack(av);
+          });
 #pragma unroll
-        for (int m = 0; m < MAXT; m++) {
-          if (m < mb || m >= me) continue;
-          float av[KL];
-          load_run<KL>(lm + (16 * m + r) * d.VS + kk, av);
-          acc[m] = P::mma(P::pack(av), bf, acc[m]);
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < MAXT; m++) {
-        if (m < mb || m >= me) continue;
+      for (int m = 0; m < MAXT; m++)
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-          const int idx = (16 * m + 4 * g + q) * H + 16 * n + r;
+          const int idx = (16 * m + 4 * g + q) * HP + 16 * n + r;
           dpre[idx] = h1[idx] > 0.0f ? acc[m][q] : 0.0f;
         }
-      }
-    });
+    }
     __syncthreads();
     pc->mark(8);
-    // B2: dW2^T = dL^T H1 -> W2 update; db2.   B3: dX^T = W1 dpre^T -> embedding scatter.
-    float *M2 = M ? M + d.off_W[1] : nullptr, *V2 = Vs ? Vs + d.off_W[1] : nullptr;
-    split_groups<NW>(H / 16, V / 16, wave, [&](int n, int mb, int me) {
+    // B2: dW2^T = dL^T H1 -> W2 update (4 consecutive v per lane); a group is
+    // a hidden tile n and MAXT symbol tiles from v-tile m0 (clamped past the end)
+    gfloat *M2 = M ? M + d.off_W[1] : nullptr, *V2 = Vs ? Vs + d.off_W[1] : nullptr;
+    const int VT = V / 16, VC = (VT + MAXT - 1) / MAXT;
+    for (int grp = wave; grp < (H / 16) * VC; grp += NW) {
+      const int n = grp / VC, m0 = (grp % VC) * MAXT;
+      fvec4 w[MAXT];
+#pragma unroll
+      for (int m = 0; m < MAXT; m++)   // W2[h][v .. v+3]
+        w[m] = ld4(W2 + (size_t)(16 * n + r) * V + 16 * min(m0 + m, VT - 1) + 4 * g);
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      for (int k0 = 0; k0 < bs; k0 += KS) {
-        const int kk = k0 + g * KL;
+#pragma unroll
+      for (int kb = 0; kb < KB; kb++) {
+        const int kk = kb * KS + g * KL;
         float bv[KL];
-        load_strided<KL>(h1 + kk * H + 16 * n + r, H, bv);
-        const typename P::frag bf = P::pack(bv);
+        load_strided<KL>(h1 + kk * HP + 16 * n + r, HP, bv);
+        const frag bf = P::pack(bv);
 #pragma unroll
         for (int m = 0; m < MAXT; m++) {
-          if (m < mb || m >= me) continue;
           float av[KL];
-          load_strided<KL>(lm + kk * d.VS + 16 * m + r, d.VS, av);
+          load_strided<KL>(lm + kk * d.VS + 16 * min(m0 + m, VT - 1) + r, d.VS, av);
           acc[m] = P::mma(P::pack(av), bf, acc[m]);
         }
       }
 #pragma unroll
       for (int m = 0; m < MAXT; m++) {
-        if (m < mb || m >= me) continue;
-        const size_t idx = (size_t)(16 * n + r) * V + 16 * m + 4 * g;   // W2[h][v .. v+3]
-        float4 w = *reinterpret_cast<float4 *>(W2 + idx);
-        float wv[4] = {w.x, w.y, w.z, w.w};
+        if (m0 + m >= VT) break;
+        const size_t idx = (size_t)(16 * n + r) * V + 16 * (m0 + m) + 4 * g;
+        float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
+        fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
+        if (adam) {
+          mo = ld4(M2 + idx);
+          vo = ld4(V2 + idx);
+        }
+        float mv[4] = {mo.x, mo.y, mo.z, mo.w};
+        float vv[4] = {vo.x, vo.y, vo.z, vo.w};
 #pragma unroll
-        for (int q = 0; q < 4; q++)
-          wv[q] = wv[q] - opt_delta(opt, acc[m][q], M2 ? M2 + idx + q : nullptr, V2 ? V2 + idx + q : nullptr);
-        *reinterpret_cast<float4 *>(W2 + idx) = make_float4(wv[0], wv[1], wv[2], wv[3]);
+        for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta(opt, acc[m][q], &mv[q], &vv[q]);
+        st4(W2 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
+        if (adam) {
+          st4(M2 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
+          st4(V2 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
+        }
       }
-    });
+    }
     for (int v = tid; v < V; v += NT) {
       float gsum = 0.0f;
       for (int j = 0; j < bs; j++) gsum += lm[j * d.VS + v];
       const int bi = d.off_b[1] + v;
       W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
     }
-    // B3: rows d of W1 (A operand, contiguous h), columns j from dpre
+    pc->mark(11);
+    // B3: dX^T = W1 dpre^T; rows d of W1 are the streamed A operand
+    // (contiguous over h), dpre the B operand; then the embedding-gradient
+    // scatter in 64-bit fixed point
     for (int mt = wave; mt < D / 16; mt += NW) {
       f32x4 acc[MAXT];
 #pragma unroll
       for (int n = 0; n < MAXT; n++) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      const float *wrow = W1 + (size_t)(16 * mt + r) * H + g * KL;
-      float a0[KL], a1[KL];
-      load_run<KL>(wrow, a0);
-      if (KS < H) load_run<KL>(wrow + KS, a1);
-      auto step = [&](int k0, float *acur) {
-        const typename P::frag af = P::pack(acur);
-        if (k0 + 2 * KS < H) load_run<KL>(wrow + k0 + 2 * KS, acur);
-        const int kk = k0 + g * KL;
-#pragma unroll
-        for (int n = 0; n < MAXT; n++) {
-          if (n >= Mt) continue;
-          float bv[KL];
-          load_run<KL>(dpre + (16 * n + r) * H + kk, bv);
-          acc[n] = P::mma(af, P::pack(bv), acc[n]);
-        }
-      };
-      int k0 = 0;
-      for (; k0 + 2 * KS <= H; k0 += 2 * KS) {
-        step(k0, a0);
-        step(k0 + KS, a1);
-      }
-      if (k0 < H) step(k0, a0);
+      const gfloat *wrow = W1 + (size_t)(16 * mt + r) * H + g * KL;
+      stream<MAXT, true>(H / KS, acc,
+          [&](int ks, float *v) { load_run<KL>(wrow + ks * KS, v); },
+          [&](int n, int ks) {
+            float bv[KL];
+            load_run<KL>(dpre + (16 * n + r) * HP + ks * KS + g * KL, bv);
+            return P::pack(bv);
+          });
 #pragma unroll
       for (int n = 0; n < MAXT; n++) {
-        if (n >= Mt) continue;
         const int j = 16 * n + r;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-          const int dd = 16 * mt + 4 * g + q, p = dd / E, e = dd % E;
+          int p, e;
+          split_k(16 * mt + 4 * g + q, p, e);
           atomicAdd(reinterpret_cast<unsigned long long *>(demb + token(j, p, i) * d.ES + e),
                     (unsigned long long)to_fixed(acc[n][q]));
         }
@@ -323,45 +344,73 @@ struct NetMfma {
     }
     __syncthreads();
     pc->mark(9);
-    // B4: dW1^T = dpre^T X -> W1 update (a wave owns column tiles over d); db1
-    float *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
-    const int Ht = H / 16;
-    for (int nt = wave; nt < D / 16; nt += NW) {
-      const int dd = 16 * nt + r, p = dd / E, e = dd % E;
-      for (int m0 = 0; m0 < Ht; m0 += MAXT) {
-        f32x4 acc[MAXT];
+    // B4: dW1^T = dpre^T X -> W1 update.  A wave keeps the dpre^T fragments
+    // of HB hidden tiles in registers and sweeps the d tiles; the W1 values a
+    // tile updates are loaded before its MFMAs.
+    gfloat *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
+    const int Ht = H / 16, DT = D / 16, HC = (Ht + HB - 1) / HB;
+    const int units = HC * DT;
+    for (int u = wave; u < units;) {
+      const int hc = u / DT;
+      frag af[HB][KB];
 #pragma unroll
-        for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        for (int k0 = 0; k0 < bs; k0 += KS) {
-          const int kk = k0 + g * KL;
+      for (int m = 0; m < HB; m++)
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+          float av[KL];
+          load_strided<KL>(dpre + (kb * KS + g * KL) * HP + 16 * min(hc * HB + m, Ht - 1) + r, HP, av);
+          af[m][kb] = P::pack(av);
+        }
+      // the d tiles of this hidden band that belong to the wave
+      for (; u < units && u / DT == hc; u += NW) {
+        const int nt = u % DT;
+        const int dd = 16 * nt + r;
+        int p, e;
+        split_k(dd, p, e);
+        fvec4 w[HB];
+#pragma unroll
+        for (int m = 0; m < HB; m++)   // W1[d][h .. h+3]
+          w[m] = ld4(W1 + (size_t)dd * H + 16 * min(hc * HB + m, Ht - 1) + 4 * g);
+        frag bf[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
           float bv[KL];
 #pragma unroll
-          for (int q = 0; q < KL; q++) bv[q] = emb[token(kk + q, p, i) * E + e];
-          const typename P::frag bf = P::pack(bv);
+          for (int q = 0; q < KL; q++) bv[q] = emb[token(kb * KS + g * KL + q, p, i) * d.EP + e];
+          bf[kb] = P::pack(bv);
+        }
+        f32x4 acc[HB];
 #pragma unroll
-          for (int m = 0; m < MAXT; m++) {
-            if (m0 + m >= Ht) continue;
-            float av[KL];
-            load_strided<KL>(dpre + kk * H + 16 * (m0 + m) + r, H, av);
-            acc[m] = P::mma(P::pack(av), bf, acc[m]);
-          }
+        for (int m = 0; m < HB; m++) {
+          acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int kb = 0; kb < KB; kb++) acc[m] = P::mma(af[m][kb], bf[kb], acc[m]);
         }
 #pragma unroll
-        for (int m = 0; m < MAXT; m++) {
-          if (m0 + m >= Ht) continue;
-          const size_t idx = (size_t)dd * H + 16 * (m0 + m) + 4 * g;   // W1[d][h .. h+3]
-          float4 w = *reinterpret_cast<float4 *>(W1 + idx);
-          float wv[4] = {w.x, w.y, w.z, w.w};
+        for (int m = 0; m < HB; m++) {
+          if (hc * HB + m >= Ht) break;
+          const size_t idx = (size_t)dd * H + 16 * (hc * HB + m) + 4 * g;
+          float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
+          fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
+          if (adam) {
+            mo = ld4(M1 + idx);
+            vo = ld4(V1 + idx);
+          }
+          float mv[4] = {mo.x, mo.y, mo.z, mo.w};
+          float vv[4] = {vo.x, vo.y, vo.z, vo.w};
 #pragma unroll
-          for (int q = 0; q < 4; q++)
-            wv[q] = wv[q] - opt_delta(opt, acc[m][q], M1 ? M1 + idx + q : nullptr, V1 ? V1 + idx + q : nullptr);
-          *reinterpret_cast<float4 *>(W1 + idx) = make_float4(wv[0], wv[1], wv[2], wv[3]);
+          for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta(opt, acc[m][q], &mv[q], &vv[q]);
+          st4(W1 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
+          if (adam) {
+            st4(M1 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
+            st4(V1 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
+          }
         }
       }
     }
     for (int h = tid; h < H; h += NT) {
       float gsum = 0.0f;
-      for (int j = 0; j < bs; j++) gsum += dpre[j * H + h];
+      for (int j = 0; j < bs; j++) gsum += dpre[j * HP + h];
       const int bi = d.off_b[0] + h;
       W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
     }

@@ -97,6 +97,15 @@ def test_quantiser_bit_exact(gpu, orc, V):
     P[0] = 0.0
     P[0, 5 % V] = 1.0
     P[1] = np.float32(1.0 / V)
+    # products p * (2^16 - V) at and next to integers: the FP32 floor's
+    # residual test decides these (row sums stay <= 1, so the residual is >= 0)
+    c = 65536 - V
+    n = rng.integers(0, c // V, size=(200, V))
+    near = (n / c).astype(np.float32)
+    P[2:202] = near
+    P[202:402] = np.nextafter(near, np.float32(0))
+    P[402:602] = np.nextafter(near, np.float32(1))
+    P[602:702] = np.float32(0.9 / V)                    # all ties: lowest index takes the residual
     got = gpu.quantise(_cuda(P)).cpu().numpy().astype(np.uint32)
     want = orc.quantise(P.astype(np.float64))
     assert np.array_equal(got, want)
