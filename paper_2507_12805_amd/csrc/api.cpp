@@ -331,6 +331,7 @@ struct Work {
   uint8_t *staging;
   StepArgs *args;         // device copies of the step-kernel arguments (one per launch)
   float *act;             // activation slabs (models whose activations exceed the LDS)
+  uint16_t *w1f, *s1f;
   unsigned long long *phase;   // [16] phase clock of block 0
 };
 
@@ -369,6 +370,9 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   w.args = A.take<StepArgs>((uint64_t)n_blocks + 1);
   w.act = m.lay.act_global ? A.take<float>((uint64_t)std::min<uint32_t>(n_blocks, kMaxGrid) * m.lay.act_slot) : nullptr;
   w.phase = A.take<unsigned long long>(16);
+  const uint64_t w1n = m.kind == kMfmaBf16 ? (uint64_t)m.d.D * m.d.H[0] : 0;
+  w.w1f = w1n ? A.take<uint16_t>((uint64_t)std::min<uint32_t>(n_blocks, kMaxGrid) * w1n) : nullptr;
+  w.s1f = (w1n && m.d.static_on) ? A.take<uint16_t>(w1n) : nullptr;
 }
 
 // One synthetic block of t + 64 steps (constant tokens) in encode mode,
@@ -408,11 +412,14 @@ hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms) {
   a.seg_words = w.seg_words;
   a.act_scratch = w.act;
   a.spin_limit = 1;
+  a.w1f = w.w1f;
+  a.s1f = w.s1f;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   float best = 1e30f;
   if (e == hipSuccess) e = hipMemcpyAsync(w.desc, &bd, sizeof bd, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemsetAsync(w.tok, 1, z.tokens, st);
   if (e == hipSuccess) e = launch_init_params(m.d, 1, w.init, st);
+  if (e == hipSuccess && w.s1f) e = launch_w1_frag(w.init + m.d.off_W[0], m.d.D, m.d.H[0], w.s1f, st);
   if (e == hipSuccess) e = hipMemcpyAsync(w.args, &a, sizeof a, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -610,6 +617,8 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   a.seg_bits = w.seg_bits;
   a.seg_words = w.seg_words;
   a.act_scratch = w.act;
+  a.w1f = w.w1f;
+  a.s1f = w.s1f;
   a.spin_limit = 1ll << 26;   // ~10 s of waiting before giving up with an error
   const char *ph = getenv("PMKLC_PHASES");
   a.phase_clk = (ph && ph[0] == '1') ? w.phase : nullptr;
@@ -617,6 +626,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.snap_flag, 0, bd.size() * sizeof(int), st));
   if (bd.empty()) return PMKLC_OK;
+  if (w.s1f) HIP_TRY(launch_w1_frag(w.stat + m.d.off_W[0], m.d.D, m.d.H[0], w.s1f, st));
   if (tm) {
     HIP_TRY(hipEventCreate(&tm->a));
     HIP_TRY(hipEventCreate(&tm->b));
@@ -1324,7 +1334,10 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   a.probe_P = probs_dev;
   a.params_out = params_dev;
   a.act_scratch = w.act;
+  a.w1f = w.w1f;
+  a.s1f = w.s1f;
   a.spin_limit = 1ll << 30;
+  if (w.s1f && static_dev) chk(launch_w1_frag(static_dev + m.d.off_W[0], m.d.D, m.d.H[0], w.s1f, st));
   chk(hipMemcpyAsync(w.args, &a, sizeof(StepArgs), hipMemcpyHostToDevice, st));
   if (e == hipSuccess) {
     if (m.kind == kGeneric) chk(launch_step(a, 1, m.nt, st));

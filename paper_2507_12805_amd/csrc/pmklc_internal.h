@@ -81,7 +81,24 @@ struct StepArgs {
   long long spin_limit;           // bound on model-passing waits (iterations)
   float *act_scratch;             // [grid][act_slot] activations when lay.act_global
   unsigned long long *phase_clk;  // [12] per-phase wall-clock ticks of block 0, or null
+  // BF16 matrix-core kernel: W1 rounded to BF16 in the first layer's
+  // B-fragment order (see w1_frag_index), one slab per workgroup for the
+  // dynamic model (kept in step with the FP32 master by the update) and one
+  // for the static model; null otherwise
+  uint16_t *w1f;
+  const uint16_t *s1f;
 };
+
+// Offset of W1[d][h] (D x H) in the fragment-ordered BF16 copy: 16-column
+// tiles n of h, 32-row k-steps ks of d, then the 64 lanes (r = h % 16,
+// g = (d % 32) / 8) and 8 consecutive d per lane, so a wave reads one k-step
+// of a column tile as 1 KB of contiguous memory.
+__host__ __device__ inline uint32_t w1_frag_index(int d, int h, int D) {
+  const uint32_t n = (uint32_t)h >> 4, ks = (uint32_t)d >> 5;
+  const uint32_t lane = ((uint32_t)h & 15u) + 16u * (((uint32_t)d & 31u) >> 3);
+  return ((n * ((uint32_t)D >> 5) + ks) * 64u + lane) * 8u + ((uint32_t)d & 7u);
+}
+hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStream_t st);
 
 hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);
 hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, hipStream_t st);

@@ -327,6 +327,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       W[q] = __builtin_nontemporal_load(src + q);
       if (M) { M[q] = 0.0f; Vs[q] = 0.0f; }
     }
+    net.begin_block(src);
     __syncthreads();
     for (int q = tid; q < V * E; q += NT) {
       const int v = (int)__umulhi((uint32_t)q, d.Emag), qp = q + v * (d.EP - E);   // row v, pitch EP

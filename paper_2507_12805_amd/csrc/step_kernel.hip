@@ -206,6 +206,8 @@ struct NetGeneric {
     tid = threadIdx.x;
   }
 
+  __device__ void begin_block(const float *) {}
+
   // forward, layer by layer; DM and static tiles share one pass
   __device__ void forward(float *W, uint64_t i, float alpha) {
     (void)alpha;

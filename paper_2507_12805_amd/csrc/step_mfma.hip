@@ -83,15 +83,20 @@ struct NetMfma {
   static constexpr int KS = P::KS, KL = P::KL;   // MAXT = bs / 16 row tiles
   static constexpr int KC = 16 / KL;             // k-steps per streamed chunk (16 raw floats per lane)
   static constexpr int KB = 16 * MAXT / KS;      // k-steps over the bs rows
-  // hidden tiles whose dpre^T fragments B4 keeps in registers (about 32 VGPRs)
-  static constexpr int HB = (32 / (KB * (KL == 8 ? 4 : 1))) > 0 ? (32 / (KB * (KL == 8 ? 4 : 1))) : 1;
+  // hidden tiles whose dpre^T fragments B4 keeps in registers (at most 4
+  // tiles and about 32 VGPRs, next to two 4-tile W1 prefetch buffers)
+  static constexpr int HB0 = 32 / (KB * (KL == 8 ? 4 : 1));
+  static constexpr int HB = HB0 < 1 ? 1 : HB0 > 4 ? 4 : HB0;
   typedef typename P::frag frag;
+  typedef __attribute__((address_space(1))) frag gfrag;
+  typedef __attribute__((address_space(1))) __bf16 gbf16;
   const StepArgs &a;
   const Dims &d;
   unsigned char *lds;
   float *emb, *embs, *h1, *hs, *lm, *lu;
   uint8_t *ring;
   long long *demb;
+  uint16_t *w1f;   // this workgroup's BF16 copy of W1 (fragment order), BF16 only
   int tid, lane, wave, r, g;
   PhaseClock *pc = nullptr;
   __device__ NetMfma(const StepArgs &a_, unsigned char *lds_) : a(a_), d(a_.d), lds(lds_) {
@@ -108,6 +113,21 @@ struct NetMfma {
     wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: branches on it stay scalar
     r = lane & 15;
     g = lane >> 4;
+    w1f = a.w1f ? a.w1f + (size_t)blockIdx.x * d.D * d.H[0] : nullptr;
+  }
+
+  // a block starts from the parameters at src: fill the BF16 W1 copy (the
+  // caller's barrier orders it before the first forward)
+  __device__ void begin_block(const float *src) {
+    if constexpr (KL == 8) {
+      const int D = d.D, H = d.H[0];
+      const gfloat *W1 = glb(src) + d.off_W[0];
+      gbf16 *out = (gbf16 *)w1f;
+      for (int q = tid; q < D * H; q += NT) {
+        const int dd = q / H, h = q - dd * H;
+        out[w1_frag_index(dd, h, D)] = (__bf16)W1[q];
+      }
+    }
   }
 
   __device__ __forceinline__ frag zero_frag() const {
@@ -117,41 +137,50 @@ struct NetMfma {
     return P::pack(z);
   }
 
+  // a k-step of the streamed operand as loaded: KL raw floats (packed at
+  // use) or a ready fragment (the BF16 W1 copy)
+  struct RawF { float v[KL]; };
+  __device__ static frag to_frag(const RawF &x) { return P::pack(x.v); }
+  __device__ static frag to_frag(const frag &x) { return x; }
+
   // acc[m] += A_m(ks) B(ks) over k-steps 0..ksteps-1 with the streamed
-  // operand (B, or A when SA) fetched from global memory in chunks of KC
+  // operand (B, or A when SA) fetched from global memory in chunks of KCX
   // k-steps, the next chunk in flight while the current one is used.
-  // load(ks, raw) issues the KL loads of k-step ks; reg(m, ks) gives the
-  // other operand of tile m (gathered for the whole chunk before its MFMAs,
-  // so the LDS round trips overlap).  Every fetch is issued unconditionally
-  // (addresses clamped to the last k-step), which keeps the in-order
-  // memory counter exact (a scheduling barrier pins each chunk's loads
-  // ahead of the previous chunk's MFMAs); chunks go in pairs, and k-steps
-  // past the end multiply a zero fragment, leaving acc exact.
-  template <int NM, bool SA, class LD, class RG>
+  // load(ks, buf) issues the loads of k-step ks; reg(m, ks) gives the other
+  // operand of tile m (gathered for the whole chunk before its MFMAs, so the
+  // LDS round trips overlap).  Every fetch is issued unconditionally
+  // (addresses clamped to the last k-step), which keeps the in-order memory
+  // counter exact (a scheduling barrier pins each chunk's loads ahead of the
+  // previous chunk's MFMAs); chunks go in pairs, and k-steps past the end
+  // multiply a zero fragment, leaving acc exact.
+  template <int NM, bool SA, int KCX, class Buf, class LD, class RG>
   __device__ __forceinline__ void stream(int ksteps, f32x4 *acc, LD &&load, RG &&reg) const {
-    float bufA[KC][KL], bufB[KC][KL];
-    const int nch = (ksteps + KC - 1) / KC;
-    // chunks are used in pairs; the k-steps of a padded pair past the end are zero
-    const bool ragged = (ksteps % (2 * KC)) != 0;
-    auto fetch = [&](int ch, float (&buf)[KC][KL]) {
+    Buf bufA[KCX], bufB[KCX];
+    const int nch = (ksteps + KCX - 1) / KCX;
+    const bool ragged = (ksteps % (2 * KCX)) != 0;
+    auto fetch = [&](int ch, Buf (&buf)[KCX]) {
 #pragma unroll
-      for (int c = 0; c < KC; c++) load(min(ch * KC + c, ksteps - 1), buf[c]);
-      // keep the scheduler from sinking the loads below the MFMAs they are
-      // meant to overlap
+      for (int c = 0; c < KCX; c++) load(min(ch * KCX + c, ksteps - 1), buf[c]);
       __builtin_amdgcn_sched_barrier(0);
     };
-    auto use = [&](int ch, float (&buf)[KC][KL]) {
-      frag o[KC][NM];
+    // register operands are gathered GC k-steps at a time (about 8 fragments)
+    constexpr int GC0 = NM >= 8 ? 1 : 8 / NM, GC = GC0 < KCX ? GC0 : KCX;
+    static_assert(KCX % GC == 0, "gather groups must tile the chunk");
+    auto use = [&](int ch, Buf (&buf)[KCX]) {
 #pragma unroll
-      for (int c = 0; c < KC; c++)
+      for (int c0 = 0; c0 < KCX; c0 += GC) {
+        frag o[GC][NM];
 #pragma unroll
-        for (int m = 0; m < NM; m++) o[c][m] = reg(m, min(ch * KC + c, ksteps - 1));
+        for (int c = 0; c < GC; c++)
 #pragma unroll
-      for (int c = 0; c < KC; c++) {
-        frag sf = P::pack(buf[c]);
-        if (ragged && ch * KC + c >= ksteps) sf = zero_frag();
+          for (int m = 0; m < NM; m++) o[c][m] = reg(m, min(ch * KCX + c0 + c, ksteps - 1));
 #pragma unroll
-        for (int m = 0; m < NM; m++) acc[m] = SA ? P::mma(sf, o[c][m], acc[m]) : P::mma(o[c][m], sf, acc[m]);
+        for (int c = 0; c < GC; c++) {
+          frag sf = to_frag(buf[c0 + c]);
+          if (ragged && ch * KCX + c0 + c >= ksteps) sf = zero_frag();
+#pragma unroll
+          for (int m = 0; m < NM; m++) acc[m] = SA ? P::mma(sf, o[c][m], acc[m]) : P::mma(o[c][m], sf, acc[m]);
+        }
       }
     };
     fetch(0, bufA);
@@ -161,6 +190,11 @@ struct NetMfma {
       fetch(ch + 2, bufA);
       use(ch + 1, bufB);
     }
+  }
+  // the common case: KC k-steps of raw floats per chunk
+  template <int NM, bool SA, class LD, class RG>
+  __device__ __forceinline__ void stream(int ksteps, f32x4 *acc, LD &&load, RG &&reg) const {
+    stream<NM, SA, KC, RawF>(ksteps, acc, [&](int ks, RawF &b) { load(ks, b.v); }, reg);
   }
 
   // an LDS array by byte offset (selecting offsets, not pointers, keeps the
@@ -189,15 +223,21 @@ struct NetMfma {
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      stream<MAXT, false>(D / KS, acc,
-          [&](int ks, float *v) { load_strided<KL>(wcol + (size_t)ks * KS * H, H, v); },
-          [&](int m, int ks) {
-            int p, e;
-            split_k(ks * KS + g * KL, p, e);
-            float av[KL];
-            load_run<KL>(em + token(16 * m + r, p, i) * d.EP + e, av);
-            return P::pack(av);
-          });
+      auto xfrag = [&](int m, int ks) {
+        int p, e;
+        split_k(ks * KS + g * KL, p, e);
+        float av[KL];
+        load_run<KL>(em + token(16 * m + r, p, i) * d.EP + e, av);
+        return P::pack(av);
+      };
+      if constexpr (KL == 8) {
+        // BF16: one 16-byte load per lane and k-step from the fragment-ordered copy
+        const gfrag *src = ((const gfrag *)(model ? a.s1f : w1f)) + (size_t)n * (D / KS) * 64 + lane;
+        stream<MAXT, false, 4, frag>(D / KS, acc, [&](int ks, frag &b) { b = src[(size_t)ks * 64]; }, xfrag);
+      } else {
+        stream<MAXT, false>(D / KS, acc,
+            [&](int ks, float *v) { load_strided<KL>(wcol + (size_t)ks * KS * H, H, v); }, xfrag);
+      }
       const float bias = Wm[d.off_b[0] + 16 * n + r];
       float *out = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
 #pragma unroll
@@ -345,13 +385,16 @@ struct NetMfma {
     __syncthreads();
     pc->mark(9);
     // B4: dW1^T = dpre^T X -> W1 update.  A wave keeps the dpre^T fragments
-    // of HB hidden tiles in registers and sweeps the d tiles; the W1 values a
-    // tile updates are loaded before its MFMAs.
+    // of a band of HB hidden tiles in registers and sweeps its d tiles in
+    // pairs: the W1 values of the next tile are in flight while the current
+    // one computes (loads unconditional, clamped; an unpaired last tile is
+    // recomputed as a dummy whose stores are skipped).
     gfloat *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
     const int Ht = H / 16, DT = D / 16, HC = (Ht + HB - 1) / HB;
-    const int units = HC * DT;
-    for (int u = wave; u < units;) {
-      const int hc = u / DT;
+    for (int hc = 0; hc < HC; hc++) {
+      const int nt0 = ((wave - hc * DT) % NW + NW) % NW;   // the wave's first d tile in this band
+      if (nt0 >= DT) continue;
+      const int ntc = (DT - nt0 + NW - 1) / NW;
       frag af[HB][KB];
 #pragma unroll
       for (int m = 0; m < HB; m++)
@@ -361,16 +404,18 @@ struct NetMfma {
           load_strided<KL>(dpre + (kb * KS + g * KL) * HP + 16 * min(hc * HB + m, Ht - 1) + r, HP, av);
           af[m][kb] = P::pack(av);
         }
-      // the d tiles of this hidden band that belong to the wave
-      for (; u < units && u / DT == hc; u += NW) {
-        const int nt = u % DT;
-        const int dd = 16 * nt + r;
-        int p, e;
-        split_k(dd, p, e);
-        fvec4 w[HB];
+      auto loadw = [&](int k, fvec4 (&w)[HB]) {
+        const int dd = 16 * (nt0 + min(k, ntc - 1) * NW) + r;
 #pragma unroll
         for (int m = 0; m < HB; m++)   // W1[d][h .. h+3]
           w[m] = ld4(W1 + (size_t)dd * H + 16 * min(hc * HB + m, Ht - 1) + 4 * g);
+        __builtin_amdgcn_sched_barrier(0);
+      };
+      auto tile = [&](int k, const fvec4 (&w)[HB]) {
+        const bool real = k < ntc;
+        const int dd = 16 * (nt0 + min(k, ntc - 1) * NW) + r;
+        int p, e;
+        split_k(dd, p, e);
         frag bf[KB];
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
@@ -386,6 +431,7 @@ struct NetMfma {
 #pragma unroll
           for (int kb = 0; kb < KB; kb++) acc[m] = P::mma(af[m][kb], bf[kb], acc[m]);
         }
+        if (!real) return;
 #pragma unroll
         for (int m = 0; m < HB; m++) {
           if (hc * HB + m >= Ht) break;
@@ -401,11 +447,24 @@ struct NetMfma {
 #pragma unroll
           for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta(opt, acc[m][q], &mv[q], &vv[q]);
           st4(W1 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
+          if constexpr (KL == 8) {
+            gbf16 *cp = (gbf16 *)w1f;
+#pragma unroll
+            for (int q = 0; q < 4; q++) cp[w1_frag_index(dd, 16 * (hc * HB + m) + 4 * g + q, D)] = (__bf16)wv[q];
+          }
           if (adam) {
             st4(M1 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
             st4(V1 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
           }
         }
+      };
+      fvec4 wA[HB], wB[HB];
+      loadw(0, wA);
+      for (int k = 0; k < ntc; k += 2) {
+        loadw(k + 1, wB);
+        tile(k, wA);
+        loadw(k + 2, wA);
+        tile(k + 1, wB);
       }
     }
     for (int h = tid; h < H; h += NT) {
@@ -418,6 +477,22 @@ struct NetMfma {
     pc->mark(10);
   }
 };
+
+// W1 (D x H, FP32) -> BF16 in the first layer's fragment order
+__global__ void w1_frag_kernel(const float *__restrict__ W1, int D, int H, uint16_t *__restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= D * H) return;
+  const int dd = q / H, h = q - dd * H;
+  __bf16 v = (__bf16)W1[q];
+  out[w1_frag_index(dd, h, D)] = __builtin_bit_cast(uint16_t, v);
+}
+
+hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStream_t st) {
+  const int n = D * H;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(w1_frag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, W1, D, H, out);
+  return hipGetLastError();
+}
 
 template <int NT, class P, int MT>
 __global__ __launch_bounds__(NT) void step_mfma_kernel(const StepArgs *__restrict__ args) {
@@ -448,6 +523,9 @@ hipError_t launch_nt(const StepArgs *a_dev, int grid, bool bf16, int mt, size_t 
 // a_dev: a device copy of `a` (kernel arguments are read through it).
 // nt: 256 or 512 threads per workgroup; the choice never changes a value.
 hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, hipStream_t st) {
+  // the BF16 kernel reads and writes W1 through its BF16 copies: refuse to
+  // launch without them
+  if (bf16 && (!a.w1f || (a.d.static_on && (!a.s1f || !a.stat)))) return hipErrorInvalidValue;
   const size_t lds = (size_t)a.lay.total;
   const int mt = a.d.bs / 16;
   if (nt == 256) return launch_nt<256>(a_dev, grid, bf16, mt, lds, st);
