@@ -12,6 +12,12 @@ namespace detail {
 typedef __attribute__((address_space(1))) float gfloat;
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) fvec4 gfvec4;
+// Waits until this wave's outstanding global loads and stores are done.
+// Loads and stores share one counter, and with stores outstanding the
+// compiler can only wait for everything; draining the stores of an earlier
+// phase once (they are long done) lets the loads of the next phase be waited
+// for one chunk at a time.  (gfx9 encoding: vmcnt 0, expcnt 7, lgkmcnt 15.)
+__device__ __forceinline__ void drain_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 __device__ __forceinline__ gfloat *glb(float *p) { return (gfloat *)p; }
 __device__ __forceinline__ const gfloat *glb(const float *p) { return (const gfloat *)p; }
 // four consecutive floats, 16-byte aligned
@@ -228,16 +234,24 @@ struct Opt {
   float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^tau, c2 = 1 - b2^tau
 };
 // m, v: optimiser state in LDS/registers (float) or global memory (gfloat);
-// untouched by SGD
+// untouched by SGD.  opt_delta_c fixes the optimiser at compile time (no
+// branch in the caller's loop); opt_delta picks it at run time.
+template <bool ADAM, class F>
+__device__ __forceinline__ float opt_delta_c(const Opt &o, float g, F *m, F *v) {
+  if constexpr (!ADAM) {
+    return o.lr * g;
+  } else {
+    float mm = o.b1 * (*m) + (1.0f - o.b1) * g;
+    float vv = o.b2 * (*v) + (1.0f - o.b2) * (g * g);
+    *m = mm;
+    *v = vv;
+    float mh = mm / o.c1, vh = vv / o.c2;
+    return o.lr * mh / (sqrtf(vh) + o.eps);
+  }
+}
 template <class F>
 __device__ __forceinline__ float opt_delta(const Opt &o, float g, F *m, F *v) {
-  if (o.kind == 0) return o.lr * g;
-  float mm = o.b1 * (*m) + (1.0f - o.b1) * g;
-  float vv = o.b2 * (*v) + (1.0f - o.b2) * (g * g);
-  *m = mm;
-  *v = vv;
-  float mh = mm / o.c1, vh = vv / o.c2;
-  return o.lr * mh / (sqrtf(vh) + o.eps);
+  return o.kind == 1 ? opt_delta_c<true>(o, g, m, v) : opt_delta_c<false>(o, g, m, v);
 }
 
 
@@ -282,6 +296,7 @@ template <int NT, class Net>
 __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds, Net &net) {
   __shared__ int sh_b;
   __shared__ float sh_ga;
+  __shared__ float sh_a;   // the mixing weight's raw parameter a (Eq. 1), kept beside its global copy
   const Dims &d = a.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bs = d.bs, V = d.V, E = d.E, t = d.t, RS = d.RS, mask = d.RS - 1, VS = d.VS;
@@ -328,6 +343,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       if (M) { M[q] = 0.0f; Vs[q] = 0.0f; }
     }
     net.begin_block(src);
+    if (tid == 0) sh_a = d.static_on ? src[d.P] : 0.0f;
     __syncthreads();
     for (int q = tid; q < V * E; q += NT) {
       const int v = (int)__umulhi((uint32_t)q, d.Emag), qp = q + v * (d.EP - E);   // row v, pitch EP
@@ -388,7 +404,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       pc.mark(0);
       float alpha = 0.0f;
       if (!uniform) {
-        if (d.static_on) alpha = 1.0f / (1.0f + expf(-glb(W)[d.P]));
+        if (d.static_on) alpha = 1.0f / (1.0f + expf(-sh_a));
         net.forward(W, i, alpha);
         pc.mark(1);
         // mixer (Eq. 1) + softmax + quantiser: G aligned lanes of one wave per
@@ -531,8 +547,9 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
           emb[qp] = emb[qp] - opt_delta(opt, gq, M ? glb(M) + pi : nullptr, Vs ? glb(Vs) + pi : nullptr);
         }
         if (d.static_on && tid == 0) {
-          gfloat *Wg = glb(W);
-          Wg[d.P] = Wg[d.P] - opt_delta(opt, sh_ga, M ? glb(M) + d.P : nullptr, Vs ? glb(Vs) + d.P : nullptr);
+          const float an = sh_a - opt_delta(opt, sh_ga, M ? glb(M) + d.P : nullptr, Vs ? glb(Vs) + d.P : nullptr);
+          sh_a = an;
+          glb(W)[d.P] = an;
         }
         __syncthreads();
       }

@@ -77,7 +77,7 @@ __device__ __forceinline__ void load_strided(const F *p, int stride, float *v) {
 
 }  // namespace
 
-template <int NT, class P, int MAXT>
+template <int NT, class P, int MAXT, bool ADAM>
 struct NetMfma {
   static constexpr int NW = NT / 64;
   static constexpr int KS = P::KS, KL = P::KL;   // MAXT = bs / 16 row tiles
@@ -87,6 +87,9 @@ struct NetMfma {
   // tiles and about 32 VGPRs, next to two 4-tile W1 prefetch buffers)
   static constexpr int HB0 = 32 / (KB * (KL == 8 ? 4 : 1));
   static constexpr int HB = HB0 < 1 ? 1 : HB0 > 4 ? 4 : HB0;
+  static constexpr int TB = NT >= 512 ? 2 : 4;   // B4 d tiles whose W1 values are loaded together
+  static constexpr int NC1 = 4;                  // F1 column tiles per unit
+  static constexpr int MR1 = MAXT % 2 == 0 ? 2 : 1;   // F1 row tiles per unit
   typedef typename P::frag frag;
   typedef __attribute__((address_space(1))) frag gfrag;
   typedef __attribute__((address_space(1))) __bf16 gbf16;
@@ -143,30 +146,33 @@ struct NetMfma {
   __device__ static frag to_frag(const RawF &x) { return P::pack(x.v); }
   __device__ static frag to_frag(const frag &x) { return x; }
 
-  // acc[m] += A_m(ks) B(ks) over k-steps 0..ksteps-1 with the streamed
-  // operand (B, or A when SA) fetched from global memory in chunks of KCX
-  // k-steps, the next chunk in flight while the current one is used.
-  // load(ks, buf) issues the loads of k-step ks; reg(m, ks) gives the other
-  // operand of tile m (gathered for the whole chunk before its MFMAs, so the
-  // LDS round trips overlap).  Every fetch is issued unconditionally
-  // (addresses clamped to the last k-step), which keeps the in-order memory
-  // counter exact (a scheduling barrier pins each chunk's loads ahead of the
+  // acc[m][n] += A_m(ks) B_n(ks) over k-steps 0..ksteps-1, with the NN
+  // streamed operands (B_n, or A_n when SA) fetched from global memory in
+  // chunks of KCX k-steps, the next chunk in flight while the current one is
+  // used.  load(ks, n, buf) issues the loads of k-step ks of operand n;
+  // reg(m, ks) gives the register operand of tile m (gathered a few k-steps
+  // at a time before their MFMAs, so the LDS round trips overlap, and each
+  // used for NN MFMAs).  Every fetch is issued unconditionally (addresses
+  // clamped to the last k-step), which keeps the in-order memory counter
+  // exact (a scheduling barrier pins each chunk's loads ahead of the
   // previous chunk's MFMAs); chunks go in pairs, and k-steps past the end
   // multiply a zero fragment, leaving acc exact.
-  template <int NM, bool SA, int KCX, class Buf, class LD, class RG>
-  __device__ __forceinline__ void stream(int ksteps, f32x4 *acc, LD &&load, RG &&reg) const {
-    Buf bufA[KCX], bufB[KCX];
+  template <int NM, int NN, bool SA, int KCX, class Buf, class LD, class RG>
+  __device__ __forceinline__ void stream2(int ksteps, f32x4 (*acc)[NN], LD &&load, RG &&reg) const {
+    Buf bufA[KCX][NN], bufB[KCX][NN];
     const int nch = (ksteps + KCX - 1) / KCX;
     const bool ragged = (ksteps % (2 * KCX)) != 0;
-    auto fetch = [&](int ch, Buf (&buf)[KCX]) {
+    auto fetch = [&](int ch, Buf (&buf)[KCX][NN]) {
 #pragma unroll
-      for (int c = 0; c < KCX; c++) load(min(ch * KCX + c, ksteps - 1), buf[c]);
+      for (int c = 0; c < KCX; c++)
+#pragma unroll
+        for (int n = 0; n < NN; n++) load(min(ch * KCX + c, ksteps - 1), n, buf[c][n]);
       __builtin_amdgcn_sched_barrier(0);
     };
     // register operands are gathered GC k-steps at a time (about 8 fragments)
     constexpr int GC0 = NM >= 8 ? 1 : 8 / NM, GC = GC0 < KCX ? GC0 : KCX;
     static_assert(KCX % GC == 0, "gather groups must tile the chunk");
-    auto use = [&](int ch, Buf (&buf)[KCX]) {
+    auto use = [&](int ch, Buf (&buf)[KCX][NN]) {
 #pragma unroll
       for (int c0 = 0; c0 < KCX; c0 += GC) {
         frag o[GC][NM];
@@ -176,10 +182,15 @@ struct NetMfma {
           for (int m = 0; m < NM; m++) o[c][m] = reg(m, min(ch * KCX + c0 + c, ksteps - 1));
 #pragma unroll
         for (int c = 0; c < GC; c++) {
-          frag sf = to_frag(buf[c0 + c]);
-          if (ragged && ch * KCX + c0 + c >= ksteps) sf = zero_frag();
+          const bool past = ragged && ch * KCX + c0 + c >= ksteps;
 #pragma unroll
-          for (int m = 0; m < NM; m++) acc[m] = SA ? P::mma(sf, o[c][m], acc[m]) : P::mma(o[c][m], sf, acc[m]);
+          for (int n = 0; n < NN; n++) {
+            frag sf = to_frag(buf[c0 + c][n]);
+            if (past) sf = zero_frag();
+#pragma unroll
+            for (int m = 0; m < NM; m++)
+              acc[m][n] = SA ? P::mma(sf, o[c][m], acc[m][n]) : P::mma(o[c][m], sf, acc[m][n]);
+          }
         }
       }
     };
@@ -190,6 +201,12 @@ struct NetMfma {
       fetch(ch + 2, bufA);
       use(ch + 1, bufB);
     }
+  }
+  // one streamed operand
+  template <int NM, bool SA, int KCX, class Buf, class LD, class RG>
+  __device__ __forceinline__ void stream(int ksteps, f32x4 *acc, LD &&load, RG &&reg) const {
+    stream2<NM, 1, SA, KCX, Buf>(ksteps, reinterpret_cast<f32x4 (*)[1]>(acc),
+                                 [&](int ks, int, Buf &b) { load(ks, b); }, reg);
   }
   // the common case: KC k-steps of raw floats per chunk
   template <int NM, bool SA, class LD, class RG>
@@ -214,36 +231,59 @@ struct NetMfma {
     (void)alpha;
     const int H = d.H[0], HP = d.HP, V = d.V, D = d.D;
     const int nmod = d.static_on ? 2 : 1;
-    // F1: X W1 + b1, ReLU; a wave owns a column tile n of one model and all row tiles
-    for (int grp = wave; grp < nmod * (H / 16); grp += NW) {
-      const int model = grp / (H / 16), n = grp % (H / 16);
-      const gfloat *Wm = glb(model ? a.stat : W);
-      const gfloat *wcol = Wm + d.off_W[0] + 16 * n + r + (size_t)(g * KL) * H;
-      const float *em = lds_f(model ? a.lay.embs : a.lay.emb);
-      f32x4 acc[MAXT];
+    drain_stores();
+    // F1: X W1 + b1, ReLU.  A unit is NC1 column tiles x MR1 row tiles of one
+    // model: each gathered X fragment feeds NC1 MFMAs, so X is gathered
+    // H/(16 NC1) times per model.  Column tiles past the end repeat the last
+    // one and are not stored.
+    {
+      const int HT = H / 16, CG = (HT + NC1 - 1) / NC1, RG = MAXT / MR1;
+      const int units = nmod * CG * RG;
+      for (int u = wave; u < units; u += NW) {
+        const int model = u / (CG * RG), rem = u - model * (CG * RG), cg = rem / RG, rg = rem - cg * RG;
+        const gfloat *Wm = glb(model ? a.stat : W);
+        const float *em = lds_f(model ? a.lay.embs : a.lay.emb);
+        int ncol[NC1];
+        float bias[NC1];
 #pragma unroll
-      for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      auto xfrag = [&](int m, int ks) {
-        int p, e;
-        split_k(ks * KS + g * KL, p, e);
-        float av[KL];
-        load_run<KL>(em + token(16 * m + r, p, i) * d.EP + e, av);
-        return P::pack(av);
-      };
-      if constexpr (KL == 8) {
-        // BF16: one 16-byte load per lane and k-step from the fragment-ordered copy
-        const gfrag *src = ((const gfrag *)(model ? a.s1f : w1f)) + (size_t)n * (D / KS) * 64 + lane;
-        stream<MAXT, false, 4, frag>(D / KS, acc, [&](int ks, frag &b) { b = src[(size_t)ks * 64]; }, xfrag);
-      } else {
-        stream<MAXT, false>(D / KS, acc,
-            [&](int ks, float *v) { load_strided<KL>(wcol + (size_t)ks * KS * H, H, v); }, xfrag);
+        for (int c = 0; c < NC1; c++) {
+          ncol[c] = min(cg * NC1 + c, HT - 1);
+          bias[c] = Wm[d.off_b[0] + 16 * ncol[c] + r];
+        }
+        f32x4 acc[MR1][NC1];
+#pragma unroll
+        for (int mm = 0; mm < MR1; mm++)
+#pragma unroll
+          for (int c = 0; c < NC1; c++) acc[mm][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        auto xfrag = [&](int mm, int ks) {
+          int p, e;
+          split_k(ks * KS + g * KL, p, e);
+          float av[KL];
+          load_run<KL>(em + token(16 * (rg * MR1 + mm) + r, p, i) * d.EP + e, av);
+          return P::pack(av);
+        };
+        if constexpr (KL == 8) {
+          // BF16: one 16-byte load per lane, k-step and column tile from the fragment-ordered copy
+          const gfrag *src = ((const gfrag *)(model ? a.s1f : w1f)) + lane;
+          const int kst = D / KS;
+          stream2<MR1, NC1, false, 2, frag>(kst, acc,
+              [&](int ks, int c, frag &b) { b = src[((size_t)ncol[c] * kst + ks) * 64]; }, xfrag);
+        } else {
+          const gfloat *W1 = Wm + d.off_W[0] + r + (size_t)(g * KL) * H;
+          stream2<MR1, NC1, false, 4, RawF>(D / KS, acc,
+              [&](int ks, int c, RawF &b) { load_strided<KL>(W1 + 16 * ncol[c] + (size_t)ks * KS * H, H, b.v); }, xfrag);
+        }
+        float *out = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
+#pragma unroll
+        for (int c = 0; c < NC1; c++) {
+          if (cg * NC1 + c >= HT) break;
+#pragma unroll
+          for (int mm = 0; mm < MR1; mm++)
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+              out[(16 * (rg * MR1 + mm) + 4 * g + q) * HP + 16 * ncol[c] + r] = fmaxf(acc[mm][c][q] + bias[c], 0.0f);
+        }
       }
-      const float bias = Wm[d.off_b[0] + 16 * n + r];
-      float *out = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
-#pragma unroll
-      for (int m = 0; m < MAXT; m++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) out[(16 * m + 4 * g + q) * HP + 16 * n + r] = fmaxf(acc[m][q] + bias, 0.0f);
     }
     __syncthreads();
     // F2: H1 W2 + b2 -> logits
@@ -252,6 +292,7 @@ struct NetMfma {
       const gfloat *Wm = glb(model ? a.stat : W);
       const gfloat *wcol = Wm + d.off_W[1] + 16 * n + r + (size_t)(g * KL) * V;
       const float *hin = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
+      const float bias = Wm[d.off_b[1] + 16 * n + r];   // issued before the k-loop
       f32x4 acc[MAXT];
 #pragma unroll
       for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -262,7 +303,6 @@ struct NetMfma {
             load_run<KL>(hin + (16 * m + r) * HP + ks * KS + g * KL, av);
             return P::pack(av);
           });
-      const float bias = Wm[d.off_b[1] + 16 * n + r];
       float *out = lds_f(model ? a.lay.lu : a.lay.lm);
 #pragma unroll
       for (int m = 0; m < MAXT; m++)
@@ -277,7 +317,8 @@ struct NetMfma {
     gfloat *W = glb(Wf), *M = Mf ? glb(Mf) : nullptr, *Vs = Vf ? glb(Vf) : nullptr;
     gfloat *W1 = W + d.off_W[0], *W2 = W + d.off_W[1];
     float *dpre = hs;
-    const bool adam = opt.kind == 1;
+    constexpr bool adam = ADAM;   // fixed per kernel: no optimiser branch in the update loops
+    drain_stores();
     // B1: dpre = (dL W2^T) * [H1 > 0]; B operand = rows of W2 (contiguous over v)
     for (int n = wave; n < H / 16; n += NW) {
       f32x4 acc[MAXT];
@@ -333,16 +374,16 @@ struct NetMfma {
         const size_t idx = (size_t)(16 * n + r) * V + 16 * (m0 + m) + 4 * g;
         float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
         fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
-        if (adam) {
+        if constexpr (adam) {
           mo = ld4(M2 + idx);
           vo = ld4(V2 + idx);
         }
         float mv[4] = {mo.x, mo.y, mo.z, mo.w};
         float vv[4] = {vo.x, vo.y, vo.z, vo.w};
 #pragma unroll
-        for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta(opt, acc[m][q], &mv[q], &vv[q]);
+        for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc[m][q], &mv[q], &vv[q]);
         st4(W2 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
-        if (adam) {
+        if constexpr (adam) {
           st4(M2 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
           st4(V2 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
         }
@@ -352,9 +393,10 @@ struct NetMfma {
       float gsum = 0.0f;
       for (int j = 0; j < bs; j++) gsum += lm[j * d.VS + v];
       const int bi = d.off_b[1] + v;
-      W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+      W[bi] = W[bi] - opt_delta_c<ADAM>(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
     }
     pc->mark(11);
+    drain_stores();   // the W2 update's stores
     // B3: dX^T = W1 dpre^T; rows d of W1 are the streamed A operand
     // (contiguous over h), dpre the B operand; then the embedding-gradient
     // scatter in 64-bit fixed point
@@ -385,10 +427,12 @@ struct NetMfma {
     __syncthreads();
     pc->mark(9);
     // B4: dW1^T = dpre^T X -> W1 update.  A wave keeps the dpre^T fragments
-    // of a band of HB hidden tiles in registers and sweeps its d tiles in
-    // pairs: the W1 values of the next tile are in flight while the current
-    // one computes (loads unconditional, clamped; an unpaired last tile is
-    // recomputed as a dummy whose stores are skipped).
+    // of a band of HB hidden tiles in registers and takes its d tiles of the
+    // band TB at a time: all their W1 loads first, then the MFMAs (LDS
+    // operands only), then one wait and the updates, so no load waits behind
+    // a store.  Tile slots past the wave's last tile recompute its last tile
+    // and store nothing.
+    drain_stores();
     gfloat *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
     const int Ht = H / 16, DT = D / 16, HC = (Ht + HB - 1) / HB;
     for (int hc = 0; hc < HC; hc++) {
@@ -404,74 +448,73 @@ struct NetMfma {
           load_strided<KL>(dpre + (kb * KS + g * KL) * HP + 16 * min(hc * HB + m, Ht - 1) + r, HP, av);
           af[m][kb] = P::pack(av);
         }
-      auto loadw = [&](int k, fvec4 (&w)[HB]) {
-        const int dd = 16 * (nt0 + min(k, ntc - 1) * NW) + r;
+      for (int k0 = 0; k0 < ntc; k0 += TB) {
+        int ddt[TB];
+        fvec4 w[TB][HB];
 #pragma unroll
-        for (int m = 0; m < HB; m++)   // W1[d][h .. h+3]
-          w[m] = ld4(W1 + (size_t)dd * H + 16 * min(hc * HB + m, Ht - 1) + 4 * g);
-        __builtin_amdgcn_sched_barrier(0);
-      };
-      auto tile = [&](int k, const fvec4 (&w)[HB]) {
-        const bool real = k < ntc;
-        const int dd = 16 * (nt0 + min(k, ntc - 1) * NW) + r;
-        int p, e;
-        split_k(dd, p, e);
-        frag bf[KB];
+        for (int t = 0; t < TB; t++) {
+          ddt[t] = 16 * (nt0 + min(k0 + t, ntc - 1) * NW) + r;
 #pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-          float bv[KL];
-#pragma unroll
-          for (int q = 0; q < KL; q++) bv[q] = emb[token(kb * KS + g * KL + q, p, i) * d.EP + e];
-          bf[kb] = P::pack(bv);
+          for (int m = 0; m < HB; m++)   // W1[d][h .. h+3]
+            w[t][m] = ld4(W1 + (size_t)ddt[t] * H + 16 * min(hc * HB + m, Ht - 1) + 4 * g);
         }
-        f32x4 acc[HB];
+        f32x4 acc[TB][HB];
 #pragma unroll
-        for (int m = 0; m < HB; m++) {
-          acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < TB; t++) {
+          int p, e;
+          split_k(ddt[t], p, e);
+          frag bf[KB];
 #pragma unroll
-          for (int kb = 0; kb < KB; kb++) acc[m] = P::mma(af[m][kb], bf[kb], acc[m]);
-        }
-        if (!real) return;
+          for (int kb = 0; kb < KB; kb++) {
+            float bv[KL];
 #pragma unroll
-        for (int m = 0; m < HB; m++) {
-          if (hc * HB + m >= Ht) break;
-          const size_t idx = (size_t)dd * H + 16 * (hc * HB + m) + 4 * g;
-          float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
-          fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
-          if (adam) {
-            mo = ld4(M1 + idx);
-            vo = ld4(V1 + idx);
+            for (int q = 0; q < KL; q++) bv[q] = emb[token(kb * KS + g * KL + q, p, i) * d.EP + e];
+            bf[kb] = P::pack(bv);
           }
-          float mv[4] = {mo.x, mo.y, mo.z, mo.w};
-          float vv[4] = {vo.x, vo.y, vo.z, vo.w};
 #pragma unroll
-          for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta(opt, acc[m][q], &mv[q], &vv[q]);
-          st4(W1 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
-          if constexpr (KL == 8) {
-            gbf16 *cp = (gbf16 *)w1f;
+          for (int m = 0; m < HB; m++) {
+            acc[t][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int q = 0; q < 4; q++) cp[w1_frag_index(dd, 16 * (hc * HB + m) + 4 * g + q, D)] = (__bf16)wv[q];
-          }
-          if (adam) {
-            st4(M1 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
-            st4(V1 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
+            for (int kb = 0; kb < KB; kb++) acc[t][m] = P::mma(af[m][kb], bf[kb], acc[t][m]);
           }
         }
-      };
-      fvec4 wA[HB], wB[HB];
-      loadw(0, wA);
-      for (int k = 0; k < ntc; k += 2) {
-        loadw(k + 1, wB);
-        tile(k, wA);
-        loadw(k + 2, wA);
-        tile(k + 1, wB);
+#pragma unroll
+        for (int t = 0; t < TB; t++) {
+          if (k0 + t >= ntc) break;
+          const int dd = ddt[t];
+#pragma unroll
+          for (int m = 0; m < HB; m++) {
+            if (hc * HB + m >= Ht) break;
+            const size_t idx = (size_t)dd * H + 16 * (hc * HB + m) + 4 * g;
+            float wv[4] = {w[t][m].x, w[t][m].y, w[t][m].z, w[t][m].w};
+            fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
+            if constexpr (adam) {
+              mo = ld4(M1 + idx);
+              vo = ld4(V1 + idx);
+            }
+            float mv[4] = {mo.x, mo.y, mo.z, mo.w};
+            float vv[4] = {vo.x, vo.y, vo.z, vo.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc[t][m][q], &mv[q], &vv[q]);
+            st4(W1 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
+            if constexpr (KL == 8) {
+              gbf16 *cp = (gbf16 *)w1f;
+#pragma unroll
+              for (int q = 0; q < 4; q++) cp[w1_frag_index(dd, 16 * (hc * HB + m) + 4 * g + q, D)] = (__bf16)wv[q];
+            }
+            if constexpr (adam) {
+              st4(M1 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
+              st4(V1 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
+            }
+          }
+        }
       }
     }
     for (int h = tid; h < H; h += NT) {
       float gsum = 0.0f;
       for (int j = 0; j < bs; j++) gsum += dpre[j * HP + h];
       const int bi = d.off_b[0] + h;
-      W[bi] = W[bi] - opt_delta(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+      W[bi] = W[bi] - opt_delta_c<ADAM>(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
     }
     __syncthreads();
     pc->mark(10);
@@ -494,30 +537,36 @@ hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStrea
   return hipGetLastError();
 }
 
-template <int NT, class P, int MT>
+template <int NT, class P, int MT, bool ADAM>
 __global__ __launch_bounds__(NT) void step_mfma_kernel(const StepArgs *__restrict__ args) {
   extern __shared__ __align__(16) unsigned char lds[];
   const StepArgs &a = *args;
-  NetMfma<NT, P, MT> net(a, lds);
+  NetMfma<NT, P, MT, ADAM> net(a, lds);
   run_blocks<NT>(a, lds, net);
 }
 
-template <int NT, class P, int MT>
+template <int NT, class P, int MT, bool ADAM>
 hipError_t launch_one(const StepArgs *a_dev, int grid, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_mfma_kernel<NT, P, MT>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_mfma_kernel<NT, P, MT, ADAM>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((step_mfma_kernel<NT, P, MT>), dim3(grid), dim3(NT), lds, st, a_dev);
+  hipLaunchKernelGGL((step_mfma_kernel<NT, P, MT, ADAM>), dim3(grid), dim3(NT), lds, st, a_dev);
   return hipGetLastError();
 }
 
-template <int NT>
-hipError_t launch_nt(const StepArgs *a_dev, int grid, bool bf16, int mt, size_t lds, hipStream_t st) {
-  if (mt == 2) return bf16 ? launch_one<NT, MmaBf16, 2>(a_dev, grid, lds, st) : launch_one<NT, MmaF32, 2>(a_dev, grid, lds, st);
-  if (mt == 4) return bf16 ? launch_one<NT, MmaBf16, 4>(a_dev, grid, lds, st) : launch_one<NT, MmaF32, 4>(a_dev, grid, lds, st);
-  if (mt == 6) return bf16 ? launch_one<NT, MmaBf16, 6>(a_dev, grid, lds, st) : launch_one<NT, MmaF32, 6>(a_dev, grid, lds, st);
-  if (mt == 8) return bf16 ? launch_one<NT, MmaBf16, 8>(a_dev, grid, lds, st) : launch_one<NT, MmaF32, 8>(a_dev, grid, lds, st);
+template <int NT, class P, bool ADAM>
+hipError_t launch_mt(const StepArgs *a_dev, int grid, int mt, size_t lds, hipStream_t st) {
+  if (mt == 2) return launch_one<NT, P, 2, ADAM>(a_dev, grid, lds, st);
+  if (mt == 4) return launch_one<NT, P, 4, ADAM>(a_dev, grid, lds, st);
+  if (mt == 6) return launch_one<NT, P, 6, ADAM>(a_dev, grid, lds, st);
+  if (mt == 8) return launch_one<NT, P, 8, ADAM>(a_dev, grid, lds, st);
   return hipErrorInvalidValue;
+}
+
+template <int NT>
+hipError_t launch_nt(const StepArgs *a_dev, int grid, bool bf16, bool adam, int mt, size_t lds, hipStream_t st) {
+  if (bf16) return adam ? launch_mt<NT, MmaBf16, true>(a_dev, grid, mt, lds, st) : launch_mt<NT, MmaBf16, false>(a_dev, grid, mt, lds, st);
+  return adam ? launch_mt<NT, MmaF32, true>(a_dev, grid, mt, lds, st) : launch_mt<NT, MmaF32, false>(a_dev, grid, mt, lds, st);
 }
 
 // a_dev: a device copy of `a` (kernel arguments are read through it).
@@ -528,8 +577,9 @@ hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, 
   if (bf16 && (!a.w1f || (a.d.static_on && (!a.s1f || !a.stat)))) return hipErrorInvalidValue;
   const size_t lds = (size_t)a.lay.total;
   const int mt = a.d.bs / 16;
-  if (nt == 256) return launch_nt<256>(a_dev, grid, bf16, mt, lds, st);
-  if (nt == 512) return launch_nt<512>(a_dev, grid, bf16, mt, lds, st);
+  const bool adam = a.d.optimizer == 1;
+  if (nt == 256) return launch_nt<256>(a_dev, grid, bf16, adam, mt, lds, st);
+  if (nt == 512) return launch_nt<512>(a_dev, grid, bf16, adam, mt, lds, st);
   return hipErrorInvalidValue;
 }
 
