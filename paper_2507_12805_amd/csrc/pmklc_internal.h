@@ -37,6 +37,7 @@ struct Dims {
 // LDS layout (byte offsets into dynamic shared memory).
 struct LdsLayout {
   int emb, embs, ring, act[2], lm, lu, cdf, tgt, dh[2], demb, misc, total;
+  int dpt;            // matrix-core kernel: BF16 dpre^T fragments (aliases cdf, dead in the backward, when it fits)
   int act_global;     // 1: act[] and dh[] are float offsets into a per-workgroup global slab
   int act_slot;       // floats per workgroup slab
 };

@@ -27,6 +27,7 @@ namespace pmklc {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct MmaF32 {
@@ -89,6 +90,7 @@ struct NetMfma {
   static constexpr int HB = HB0 < 1 ? 1 : HB0 > 4 ? 4 : HB0;
   static constexpr int TB = NT >= 512 ? 2 : 4;   // B4 d tiles whose W1 values are loaded together
   static constexpr int NC1 = 4;                  // F1 column tiles per unit
+  static constexpr int HCH = NT >= 512 ? 4 : 8;  // hidden tiles per chunk of the fused B3/B4
   static constexpr int MR1 = MAXT % 2 == 0 ? 2 : 1;   // F1 row tiles per unit
   typedef typename P::frag frag;
   typedef __attribute__((address_space(1))) frag gfrag;
@@ -99,6 +101,7 @@ struct NetMfma {
   float *emb, *embs, *h1, *hs, *lm, *lu;
   uint8_t *ring;
   long long *demb;
+  __bf16 *dpt;     // BF16 dpre^T in B4's A-fragment order (LDS), BF16 only
   uint16_t *w1f;   // this workgroup's BF16 copy of W1 (fragment order), BF16 only
   int tid, lane, wave, r, g;
   PhaseClock *pc = nullptr;
@@ -111,6 +114,7 @@ struct NetMfma {
     lu = reinterpret_cast<float *>(lds + a.lay.lu);
     ring = lds + a.lay.ring;
     demb = reinterpret_cast<long long *>(lds + a.lay.demb);
+    dpt = reinterpret_cast<__bf16 *>(lds + a.lay.dpt);
     tid = threadIdx.x;
     lane = tid & 63;
     wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: branches on it stay scalar
@@ -333,12 +337,24 @@ struct NetMfma {
             return P::pack(av);
           });
 #pragma unroll
-      for (int m = 0; m < MAXT; m++)
+      for (int m = 0; m < MAXT; m++) {
+        float dv[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
           const int idx = (16 * m + 4 * g + q) * HP + 16 * n + r;
-          dpre[idx] = h1[idx] > 0.0f ? acc[m][q] : 0.0f;
+          dv[q] = h1[idx] > 0.0f ? acc[m][q] : 0.0f;
+          dpre[idx] = dv[q];
         }
+        if constexpr (KL == 8) {
+          // BF16 dpre^T as B4's A fragments: tile n of h, k-step m/2 of j;
+          // this lane's 4 rows j are 4 consecutive slots of lane r + 16 (2 (m%2) + g/2)
+          bf16x4 pk;
+#pragma unroll
+          for (int q = 0; q < 4; q++) pk[q] = (__bf16)dv[q];
+          const int slot = r + 16 * (2 * (m & 1) + (g >> 1));
+          *reinterpret_cast<bf16x4 *>(dpt + (((size_t)n * KB + (m >> 1)) * 64 + slot) * 8 + 4 * (g & 1)) = pk;
+        }
+      }
     }
     __syncthreads();
     pc->mark(8);
@@ -397,96 +413,95 @@ struct NetMfma {
     }
     pc->mark(11);
     drain_stores();   // the W2 update's stores
-    // B3: dX^T = W1 dpre^T; rows d of W1 are the streamed A operand
-    // (contiguous over h), dpre the B operand; then the embedding-gradient
-    // scatter in 64-bit fixed point
-    for (int mt = wave; mt < D / 16; mt += NW) {
-      f32x4 acc[MAXT];
-#pragma unroll
-      for (int n = 0; n < MAXT; n++) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      const gfloat *wrow = W1 + (size_t)(16 * mt + r) * H + g * KL;
-      stream<MAXT, true>(H / KS, acc,
-          [&](int ks, float *v) { load_run<KL>(wrow + ks * KS, v); },
-          [&](int n, int ks) {
-            float bv[KL];
-            load_run<KL>(dpre + (16 * n + r) * HP + ks * KS + g * KL, bv);
-            return P::pack(bv);
-          });
-#pragma unroll
-      for (int n = 0; n < MAXT; n++) {
-        const int j = 16 * n + r;
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          int p, e;
-          split_k(16 * mt + 4 * g + q, p, e);
-          atomicAdd(reinterpret_cast<unsigned long long *>(demb + token(j, p, i) * d.ES + e),
-                    (unsigned long long)to_fixed(acc[n][q]));
-        }
-      }
-    }
-    __syncthreads();
-    pc->mark(9);
-    // B4: dW1^T = dpre^T X -> W1 update.  A wave keeps the dpre^T fragments
-    // of a band of HB hidden tiles in registers and takes its d tiles of the
-    // band TB at a time: all their W1 loads first, then the MFMAs (LDS
-    // operands only), then one wait and the updates, so no load waits behind
-    // a store.  Tile slots past the wave's last tile recompute its last tile
-    // and store nothing.
-    drain_stores();
-    gfloat *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
-    const int Ht = H / 16, DT = D / 16, HC = (Ht + HB - 1) / HB;
-    for (int hc = 0; hc < HC; hc++) {
-      const int nt0 = ((wave - hc * DT) % NW + NW) % NW;   // the wave's first d tile in this band
-      if (nt0 >= DT) continue;
-      const int ntc = (DT - nt0 + NW - 1) / NW;
-      frag af[HB][KB];
-#pragma unroll
-      for (int m = 0; m < HB; m++)
+    // B3 + B4, fused per tile of 16 rows d of W1 (a wave takes d tiles
+    // wave, wave + NW, ...).  Lane (r, g) loads W1[d][16m + 4g .. +3] for the
+    // hidden tiles m of a chunk of HCH: these are the values its B4 output tile
+    // updates, and, with the contraction index h of B3 permuted to match
+    // (k-slot q of a BF16 k-step: h = 32k + 4g + q for q < 4, 32k + 16 + 4g +
+    // q - 4 otherwise; FP32 k-step 4m + i: h = 16m + 4g + i, gathered the same
+    // way from dpre), also B3's A operand, so W1 is read once.  B4's MFMAs
+    // need only LDS operands and run while the loads are in flight.
+    //   B3: dX^T[d][j] = sum_h W1[d][h] dpre[j][h] -> embedding-gradient scatter
+    //   B4: dW1^T[h][d] = sum_j dpre^T[h][j] X[j][d] -> W1 update
+    {
+      gfloat *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
+      const int HT = H / 16, DT = D / 16, NHC = (HT + HCH - 1) / HCH;
+      for (int mt = wave; mt < DT; mt += NW) {
+        const int dd = 16 * mt + r;
+        int p, e;
+        split_k(dd, p, e);
+        // X^T fragments of this d tile (B4's B operand)
+        frag bf[KB];
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-          float av[KL];
-          load_strided<KL>(dpre + (kb * KS + g * KL) * HP + 16 * min(hc * HB + m, Ht - 1) + r, HP, av);
-          af[m][kb] = P::pack(av);
+          float bv[KL];
+#pragma unroll
+          for (int q = 0; q < KL; q++) bv[q] = emb[token(kb * KS + g * KL + q, p, i) * d.EP + e];
+          bf[kb] = P::pack(bv);
         }
-      for (int k0 = 0; k0 < ntc; k0 += TB) {
-        int ddt[TB];
-        fvec4 w[TB][HB];
+        f32x4 acc3[MAXT];
 #pragma unroll
-        for (int t = 0; t < TB; t++) {
-          ddt[t] = 16 * (nt0 + min(k0 + t, ntc - 1) * NW) + r;
+        for (int n = 0; n < MAXT; n++) acc3[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int hc = 0; hc < NHC; hc++) {
+          fvec4 w[HCH];
 #pragma unroll
-          for (int m = 0; m < HB; m++)   // W1[d][h .. h+3]
-            w[t][m] = ld4(W1 + (size_t)ddt[t] * H + 16 * min(hc * HB + m, Ht - 1) + 4 * g);
-        }
-        f32x4 acc[TB][HB];
+          for (int m = 0; m < HCH; m++)
+            w[m] = ld4(W1 + (size_t)dd * H + 16 * min(HCH * hc + m, HT - 1) + 4 * g);
+          __builtin_amdgcn_sched_barrier(0);
+          // B4 (LDS operands only)
+          f32x4 acc4[HCH];
 #pragma unroll
-        for (int t = 0; t < TB; t++) {
-          int p, e;
-          split_k(ddt[t], p, e);
-          frag bf[KB];
+          for (int m = 0; m < HCH; m++) {
+            const int ht = min(HCH * hc + m, HT - 1);
+            acc4[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-          for (int kb = 0; kb < KB; kb++) {
-            float bv[KL];
-#pragma unroll
-            for (int q = 0; q < KL; q++) bv[q] = emb[token(kb * KS + g * KL + q, p, i) * d.EP + e];
-            bf[kb] = P::pack(bv);
+            for (int kb = 0; kb < KB; kb++) {
+              frag af;
+              if constexpr (KL == 8) {
+                af = *reinterpret_cast<const bf16x8 *>(dpt + (((size_t)ht * KB + kb) * 64 + lane) * 8);
+              } else {
+                af = dpre[(kb * KS + g) * HP + 16 * ht + r];
+              }
+              acc4[m] = P::mma(af, bf[kb], acc4[m]);
+            }
           }
+          // B3 over this chunk's hidden units (tiles past the end contribute zero)
+          if constexpr (KL == 8) {
 #pragma unroll
-          for (int m = 0; m < HB; m++) {
-            acc[t][m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            for (int k = 0; k < HCH / 2; k++) {
+              const bool v0 = HCH * hc + 2 * k < HT, v1 = HCH * hc + 2 * k + 1 < HT;
+              float av[8] = {v0 ? w[2 * k].x : 0.0f, v0 ? w[2 * k].y : 0.0f, v0 ? w[2 * k].z : 0.0f,
+                             v0 ? w[2 * k].w : 0.0f, v1 ? w[2 * k + 1].x : 0.0f, v1 ? w[2 * k + 1].y : 0.0f,
+                             v1 ? w[2 * k + 1].z : 0.0f, v1 ? w[2 * k + 1].w : 0.0f};
+              const frag a3 = P::pack(av);
+              const int h0 = 16 * min(HCH * hc + 2 * k, HT - 1) + 4 * g, h1c = 16 * min(HCH * hc + 2 * k + 1, HT - 1) + 4 * g;
 #pragma unroll
-            for (int kb = 0; kb < KB; kb++) acc[t][m] = P::mma(af[m][kb], bf[kb], acc[t][m]);
+              for (int n = 0; n < MAXT; n++) {
+                float bv[8];
+                load_run<4>(dpre + (16 * n + r) * HP + h0, bv);
+                load_run<4>(dpre + (16 * n + r) * HP + h1c, bv + 4);
+                acc3[n] = P::mma(a3, P::pack(bv), acc3[n]);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int m = 0; m < HCH; m++) {
+              const bool vm = HCH * hc + m < HT;
+              const int hb = 16 * min(HCH * hc + m, HT - 1) + 4 * g;
+#pragma unroll
+              for (int q = 0; q < 4; q++) {
+                const float av = vm ? w[m][q] : 0.0f;
+#pragma unroll
+                for (int n = 0; n < MAXT; n++) acc3[n] = P::mma(av, dpre[(16 * n + r) * HP + hb + q], acc3[n]);
+              }
+            }
           }
-        }
+          // B4 update of this chunk
 #pragma unroll
-        for (int t = 0; t < TB; t++) {
-          if (k0 + t >= ntc) break;
-          const int dd = ddt[t];
-#pragma unroll
-          for (int m = 0; m < HB; m++) {
-            if (hc * HB + m >= Ht) break;
-            const size_t idx = (size_t)dd * H + 16 * (hc * HB + m) + 4 * g;
-            float wv[4] = {w[t][m].x, w[t][m].y, w[t][m].z, w[t][m].w};
+          for (int m = 0; m < HCH; m++) {
+            if (HCH * hc + m >= HT) break;
+            const size_t idx = (size_t)dd * H + 16 * (HCH * hc + m) + 4 * g;
+            float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
             fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
             if constexpr (adam) {
               mo = ld4(M1 + idx);
@@ -495,17 +510,29 @@ struct NetMfma {
             float mv[4] = {mo.x, mo.y, mo.z, mo.w};
             float vv[4] = {vo.x, vo.y, vo.z, vo.w};
 #pragma unroll
-            for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc[t][m][q], &mv[q], &vv[q]);
+            for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc4[m][q], &mv[q], &vv[q]);
             st4(W1 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
             if constexpr (KL == 8) {
               gbf16 *cp = (gbf16 *)w1f;
 #pragma unroll
-              for (int q = 0; q < 4; q++) cp[w1_frag_index(dd, 16 * (hc * HB + m) + 4 * g + q, D)] = (__bf16)wv[q];
+              for (int q = 0; q < 4; q++) cp[w1_frag_index(dd, 16 * (HCH * hc + m) + 4 * g + q, D)] = (__bf16)wv[q];
             }
             if constexpr (adam) {
               st4(M1 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
               st4(V1 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
             }
+          }
+        }
+        // embedding-gradient scatter of dX^T[d][j] in 64-bit fixed point
+#pragma unroll
+        for (int n = 0; n < MAXT; n++) {
+          const int j = 16 * n + r;
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            int pq, eq;
+            split_k(16 * mt + 4 * g + q, pq, eq);
+            atomicAdd(reinterpret_cast<unsigned long long *>(demb + token(j, pq, i) * d.ES + eq),
+                      (unsigned long long)to_fixed(acc3[n][q]));
           }
         }
       }
