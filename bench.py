@@ -30,6 +30,34 @@ if ROOT not in sys.path:
 # MI355X published peaks
 PEAK = {"fp32_alu_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0}
 
+# Sources that define the step kernel; a stored HBM-traffic measurement is
+# reported only while their hash matches the one it was taken with.
+KERNEL_SOURCES = ["paper_2507_12805_amd/csrc/step_mfma.hip", "paper_2507_12805_amd/csrc/step_common.h",
+                  "paper_2507_12805_amd/csrc/pmklc_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(name: str):
+    """HBM bytes per step-kernel launch from the counter runs summarised in
+    profiles/<name>.json (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    factor a copy of known size gives), or None when absent or stale."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return int(t["hbm_bytes_per_launch"])
+
 
 def flops_per_row(cfg: dict) -> int:
     """Algorithmic FLOPs of one model row (one token of one segment): dynamic
@@ -184,7 +212,9 @@ def main():
         "ratio_bits_per_base": round(8.0 * len(blob) / n, 5), "roundtrip_bit_exact": ok,
         "step_kernel_ms": {"compress": round(float(np.mean(ks_c)), 3), "decompress": round(float(np.mean(ks_d)), 3)},
         "roofline": {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 6), "traffic": None,
+                     "frac": round(achieved / peak, 6),
+                     "traffic": stored_traffic(f"traffic_step_kernel_{a.workload}_{a.precision}")
+                     if a.schedule == "batched" and a.scale == 1.0 else None,
                      "kernel": "step_kernel", "flops_per_launch": int(flops_launch), "flops_per_row": fpr,
                      "rows_per_launch": int(tim_c["model_rows"]), "max_steps": int(tim_c["max_steps"])},
     }
