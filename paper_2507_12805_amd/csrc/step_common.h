@@ -436,24 +436,27 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
             mx = fmaxf(mx, fmaxf(fmaxf(z4.x, z4.y), fmaxf(z4.z, z4.w)));
           }
           for (int o = G >> 1; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+          // hardware exp2-based exponential and one reciprocal per row: both
+          // deterministic, within a few ulp of the correctly rounded values
           float se = 0.0f;
           for (int v = v0; v < v0 + spl; v += 4) {
             float4 z4 = *reinterpret_cast<float4 *>(lr + v);
-            z4.x = expf(z4.x - mx);
-            z4.y = expf(z4.y - mx);
-            z4.z = expf(z4.z - mx);
-            z4.w = expf(z4.w - mx);
+            z4.x = __expf(z4.x - mx);
+            z4.y = __expf(z4.y - mx);
+            z4.z = __expf(z4.z - mx);
+            z4.w = __expf(z4.w - mx);
             se = se + z4.x + z4.y + z4.z + z4.w;
             *reinterpret_cast<float4 *>(lr + v) = z4;
           }
           for (int o = G >> 1; o > 0; o >>= 1) se = se + __shfl_xor(se, o);
+          const float rse = 1.0f / se;
           float srow = 0.0f;
           for (int v = v0; v < v0 + spl; v += 4) {
             float4 e4 = *reinterpret_cast<float4 *>(lr + v);
-            e4.x = e4.x / se;
-            e4.y = e4.y / se;
-            e4.z = e4.z / se;
-            e4.w = e4.w / se;
+            e4.x = e4.x * rse;
+            e4.y = e4.y * rse;
+            e4.z = e4.z * rse;
+            e4.w = e4.w * rse;
             *reinterpret_cast<float4 *>(lr + v) = e4;
             if (d.static_on) {
               const float4 df = *reinterpret_cast<const float4 *>(ur + v);

@@ -317,6 +317,74 @@ def test_numeric_paths_roundtrip_and_ratio(gpu, orc, precision, path):
     assert dp.max() <= (1e-4 if precision != "bf16" else 0.05)
 
 
+# matrix-core shapes beyond the two workloads: 256 symbols with E 8 and 32 rows
+# (B2 takes more symbol tiles than row tiles; a 16-wide tile of inputs spans two
+# context positions), E 24 with 96 rows and H 96 (partial 4-tile F1 units and
+# hidden chunks), 128 rows with Adam
+MFMA_SHAPES = {
+    "k4_E8_bs32_H64": dict(s=2, k=4, t=32, E=8, hidden=[64], bs=32),
+    "E24_bs96_H96_t16": dict(s=3, k=3, t=16, E=24, hidden=[96], bs=96),
+    "bs128_adam": dict(s=3, k=3, t=32, E=16, hidden=[32], bs=128, optimizer="adam", lr=3e-3),
+}
+
+
+@pytest.mark.parametrize("precision,path", [("bf16", 2), ("fp32", 3)])
+@pytest.mark.parametrize("name", sorted(MFMA_SHAPES))
+def test_mfma_shapes_roundtrip_ratio_probabilities(gpu, orc, name, precision, path):
+    """Bit-exact round trip on the matrix-core path (container path id) and
+    ratio within 0.5% of the FP64 oracle.  On the FP32 matrix-core path:
+    with SGD, probabilities within 1e-4 of the oracle along the whole
+    trajectory; with Adam, whose update lr m/(sqrt(v)+eps) turns a rounding-
+    level gradient into a full lr step, the trajectory is compared over its
+    first steps, probabilities at the GPU's own late weights against the
+    oracle's at the same weights, and the first Adam update against the
+    oracle's optimiser step wherever the gradient is not rounding-level."""
+    cfg = model_small(**MFMA_SHAPES[name], precision=precision)
+    rec = synth.recipe_cfg1(seed=31, n=1 << 16)
+    a = synth.generate(rec)
+    blob = gpu.compress(cfg, _cuda(a))
+    assert blob[5] == path
+    assert np.array_equal(gpu.decompress(blob).cpu().numpy(), a)
+    blob_o = orc.compress(cfg, a)
+    rel = len(blob) / len(blob_o) - 1
+    print(f"{name} {precision}: {len(blob)} vs oracle {len(blob_o)} bytes, rel {rel:+.5f}")
+    assert abs(rel) <= 0.005
+    if precision != "fp32":
+        return
+    tok = orc.encode_skmer(a, cfg["s"], cfg["k"])
+    L, t, bs = len(tok) // cfg["bs"], cfg["t"], cfg["bs"]
+    adam = cfg.get("optimizer") == "adam"
+    steps = [t, t + 3] if adam else [t, (t + L) // 2, L - 1]
+    Pg, _ = gpu.model_trace(cfg, tok, steps=steps)
+    Po, _, _ = orc.trace_block(cfg, tok, steps=steps)
+    print(f"trajectory |dp| max {np.abs(Pg.cpu().numpy() - Po).max():.3g}")
+    assert np.abs(Pg.cpu().numpy() - Po).max() <= 1e-4
+    if not adam:
+        return
+
+    def oracle_at(i, w64):
+        rows = np.arange(bs) * L + i
+        ctx = np.stack([tok[r - t:r] for r in rows])
+        return orc.step(cfg, w64, ctx, tok[rows])
+
+    n = orc.param_count(cfg)
+    for i in [(t + L) // 2, L - 1]:                    # teacher-forced, late
+        _, w_i = gpu.model_trace(cfg, tok, stop=i)
+        P_i, _ = gpu.model_trace(cfg, tok, steps=[i], stop=i + 1)
+        Po_i = oracle_at(i, w_i.cpu().numpy().astype(np.float64)[:n])[0]
+        assert np.abs(P_i[0].cpu().numpy() - Po_i).max() <= 1e-4
+    _, w0 = gpu.model_trace(cfg, tok, stop=t)         # first Adam update from zero moments
+    _, w1 = gpu.model_trace(cfg, tok, stop=t + 1)
+    w0 = w0.cpu().numpy().astype(np.float64)[:n]
+    _, g, _, _ = oracle_at(t, w0)
+    want = w0.copy()
+    orc.opt_step(1, cfg["lr"], cfg["beta1"], cfg["beta2"], cfg["eps"], want, g, np.zeros(n), np.zeros(n), 1)
+    big = np.abs(g) > 1e-4 * np.abs(g).max()
+    err = np.abs(w1.cpu().numpy()[:n] - want)
+    print(f"first Adam step: {big.sum()} of {n} coordinates compared, max err {err[big].max():.3g}")
+    assert big.sum() > n // 4 and err[big].max() <= 1e-6
+
+
 def test_static_mixer_probabilities(gpu, orc):
     """Eq. 1 with the frozen static model (the second workload's model
     shape) on a short sequence: P within 1e-4 along the trajectory."""
