@@ -137,6 +137,20 @@ struct NetMfma {
     }
   }
 
+  // B4's A fragment of dpre^T: hidden tile ht, k-step kb of the rows j
+  __device__ __forceinline__ frag dpre_frag(int ht, int kb) const {
+    if constexpr (KL == 8) {
+      return *reinterpret_cast<const bf16x8 *>(dpt + (((size_t)ht * KB + kb) * 64 + lane) * 8);
+    } else {
+      return hs[(kb * KS + g) * d.HP + 16 * ht + r];
+    }
+  }
+  __device__ __forceinline__ frag ones_frag() const {
+    float o[KL];
+#pragma unroll
+    for (int q = 0; q < KL; q++) o[q] = 1.0f;
+    return P::pack(o);
+  }
   __device__ __forceinline__ frag zero_frag() const {
     float z[KL];
 #pragma unroll
@@ -323,96 +337,148 @@ struct NetMfma {
     float *dpre = hs;
     constexpr bool adam = ADAM;   // fixed per kernel: no optimiser branch in the update loops
     drain_stores();
-    // B1: dpre = (dL W2^T) * [H1 > 0]; B operand = rows of W2 (contiguous over v)
-    for (int n = wave; n < H / 16; n += NW) {
-      f32x4 acc[MAXT];
+    // B1 + B2, fused per hidden tile n (a wave per tile).  Lane (r, g) loads
+    // W2[16n + r][16m + 4g .. +3] for a chunk of 4 symbol tiles m: these are
+    // the values its B2 output tile updates, and, with the contraction index v
+    // of B1 permuted to match (BF16 k-slot q: v = 32k + 4g + q for q < 4,
+    // 32k + 16 + 4g + q - 4 otherwise; FP32 k-step 4m + i: v = 16m + 4g + i;
+    // dz gathered the same way), B1's B operand, so W2 is read once.
+    //   B1: dpre = (dz W2^T) * [H1 > 0]   (old W2; all chunks)
+    //   B2: dW2^T = dz^T H1 -> W2 update  (per chunk, after B1 has used it)
+    {
+      gfloat *M2 = M ? M + d.off_W[1] : nullptr, *V2 = Vs ? Vs + d.off_W[1] : nullptr;
+      const int VT = V / 16;
+      for (int n = wave; n < H / 16; n += NW) {
+        f32x4 acc1[MAXT];
 #pragma unroll
-      for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-      const gfloat *wrow = W2 + (size_t)(16 * n + r) * V + g * KL;
-      stream<MAXT, false>(V / KS, acc,
-          [&](int ks, float *v) { load_run<KL>(wrow + ks * KS, v); },
-          [&](int m, int ks) {
-            float av[KL];
-            load_run<KL>(lm + (16 * m + r) * d.VS + ks * KS + g * KL, av);
-            return P::pack(av);
-          });
+        for (int m = 0; m < MAXT; m++) acc1[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        // H1 columns of this tile as B2's B operand (k = rows j), all k-steps
+        frag hb[KB];
 #pragma unroll
-      for (int m = 0; m < MAXT; m++) {
-        float dv[4];
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-          const int idx = (16 * m + 4 * g + q) * HP + 16 * n + r;
-          dv[q] = h1[idx] > 0.0f ? acc[m][q] : 0.0f;
-          dpre[idx] = dv[q];
+        for (int kb = 0; kb < KB; kb++) {
+          float bv[KL];
+          load_strided<KL>(h1 + (kb * KS + g * KL) * HP + 16 * n + r, HP, bv);
+          hb[kb] = P::pack(bv);
         }
-        if constexpr (KL == 8) {
-          // BF16 dpre^T as B4's A fragments: tile n of h, k-step m/2 of j;
-          // this lane's 4 rows j are 4 consecutive slots of lane r + 16 (2 (m%2) + g/2)
-          bf16x4 pk;
+        for (int vc = 0; vc < VT; vc += 4) {
+          fvec4 w[4];
 #pragma unroll
-          for (int q = 0; q < 4; q++) pk[q] = (__bf16)dv[q];
-          const int slot = r + 16 * (2 * (m & 1) + (g >> 1));
-          *reinterpret_cast<bf16x4 *>(dpt + (((size_t)n * KB + (m >> 1)) * 64 + slot) * 8 + 4 * (g & 1)) = pk;
+          for (int m = 0; m < 4; m++)   // W2[h][v .. v+3]
+            w[m] = ld4(W2 + (size_t)(16 * n + r) * V + 16 * min(vc + m, VT - 1) + 4 * g);
+          // B2 (LDS operands only) while the loads are in flight
+          f32x4 acc2[4];
+#pragma unroll
+          for (int m = 0; m < 4; m++) {
+            acc2[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kb = 0; kb < KB; kb++) {
+              float av[KL];
+              load_strided<KL>(lm + (kb * KS + g * KL) * d.VS + 16 * min(vc + m, VT - 1) + r, d.VS, av);
+              acc2[m] = P::mma(P::pack(av), hb[kb], acc2[m]);
+            }
+          }
+          // B1 over this chunk's symbols (tiles past the end contribute zero)
+          if constexpr (KL == 8) {
+#pragma unroll
+            for (int k = 0; k < 2; k++) {
+              const bool v0 = vc + 2 * k < VT, v1 = vc + 2 * k + 1 < VT;
+              float bv[8] = {v0 ? w[2 * k].x : 0.0f, v0 ? w[2 * k].y : 0.0f, v0 ? w[2 * k].z : 0.0f,
+                             v0 ? w[2 * k].w : 0.0f, v1 ? w[2 * k + 1].x : 0.0f, v1 ? w[2 * k + 1].y : 0.0f,
+                             v1 ? w[2 * k + 1].z : 0.0f, v1 ? w[2 * k + 1].w : 0.0f};
+              const frag b1f = P::pack(bv);
+              const int c0 = 16 * min(vc + 2 * k, VT - 1) + 4 * g, c1 = 16 * min(vc + 2 * k + 1, VT - 1) + 4 * g;
+#pragma unroll
+              for (int m = 0; m < MAXT; m++) {
+                float av[8];
+                load_run<4>(lm + (16 * m + r) * d.VS + c0, av);
+                load_run<4>(lm + (16 * m + r) * d.VS + c1, av + 4);
+                acc1[m] = P::mma(P::pack(av), b1f, acc1[m]);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int mv = 0; mv < 4; mv++) {
+              const bool ok = vc + mv < VT;
+              const int cb = 16 * min(vc + mv, VT - 1) + 4 * g;
+#pragma unroll
+              for (int q = 0; q < 4; q++) {
+                const float bv = ok ? w[mv][q] : 0.0f;
+#pragma unroll
+                for (int m = 0; m < MAXT; m++) acc1[m] = P::mma(lm[(16 * m + r) * d.VS + cb + q], bv, acc1[m]);
+              }
+            }
+          }
+          // output-bias gradient sum_j dz[j][v] (BF16): the wave of tile 0
+          // multiplies the dz^T fragments by a ones fragment (column 0)
+          if (KL == 8 && n == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+              if (vc + m >= VT) break;
+              f32x4 accb = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+              for (int kb = 0; kb < KB; kb++) {
+                float av[KL];
+                load_strided<KL>(lm + (kb * KS + g * KL) * d.VS + 16 * (vc + m) + r, d.VS, av);
+                accb = P::mma(P::pack(av), ones_frag(), accb);
+              }
+              if (r == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                  const int bi = d.off_b[1] + 16 * (vc + m) + 4 * g + q;
+                  W[bi] = W[bi] - opt_delta_c<ADAM>(opt, accb[q], M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+                }
+              }
+            }
+          }
+          // W2 update of this chunk
+#pragma unroll
+          for (int m = 0; m < 4; m++) {
+            if (vc + m >= VT) break;
+            const size_t idx = (size_t)(16 * n + r) * V + 16 * (vc + m) + 4 * g;
+            float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
+            fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
+            if constexpr (adam) {
+              mo = ld4(M2 + idx);
+              vo = ld4(V2 + idx);
+            }
+            float mv[4] = {mo.x, mo.y, mo.z, mo.w};
+            float vv[4] = {vo.x, vo.y, vo.z, vo.w};
+#pragma unroll
+            for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc2[m][q], &mv[q], &vv[q]);
+            st4(W2 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
+            if constexpr (adam) {
+              st4(M2 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
+              st4(V2 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
+            }
+          }
+        }
+        // dpre = B1 * [H1 > 0] (and its BF16 transpose for B4)
+#pragma unroll
+        for (int m = 0; m < MAXT; m++) {
+          float dv[4];
+#pragma unroll
+          for (int q = 0; q < 4; q++) {
+            const int idx = (16 * m + 4 * g + q) * HP + 16 * n + r;
+            dv[q] = h1[idx] > 0.0f ? acc1[m][q] : 0.0f;
+            dpre[idx] = dv[q];
+          }
+          if constexpr (KL == 8) {
+            // BF16 dpre^T as B4's A fragments: tile n of h, k-step m/2 of j;
+            // this lane's 4 rows j are 4 consecutive slots of lane r + 16 (2 (m%2) + g/2)
+            bf16x4 pk;
+#pragma unroll
+            for (int q = 0; q < 4; q++) pk[q] = (__bf16)dv[q];
+            const int slot = r + 16 * (2 * (m & 1) + (g >> 1));
+            *reinterpret_cast<bf16x4 *>(dpt + (((size_t)n * KB + (m >> 1)) * 64 + slot) * 8 + 4 * (g & 1)) = pk;
+          }
         }
       }
     }
     __syncthreads();
     pc->mark(8);
-    // B2: dW2^T = dL^T H1 -> W2 update (4 consecutive v per lane); a group is
-    // a hidden tile n and MAXT symbol tiles from v-tile m0 (clamped past the end)
-    gfloat *M2 = M ? M + d.off_W[1] : nullptr, *V2 = Vs ? Vs + d.off_W[1] : nullptr;
-    const int VT = V / 16, VC = (VT + MAXT - 1) / MAXT;
-    for (int grp = wave; grp < (H / 16) * VC; grp += NW) {
-      const int n = grp / VC, m0 = (grp % VC) * MAXT;
-      fvec4 w[MAXT];
-#pragma unroll
-      for (int m = 0; m < MAXT; m++)   // W2[h][v .. v+3]
-        w[m] = ld4(W2 + (size_t)(16 * n + r) * V + 16 * min(m0 + m, VT - 1) + 4 * g);
-      f32x4 acc[MAXT];
-#pragma unroll
-      for (int m = 0; m < MAXT; m++) acc[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int kb = 0; kb < KB; kb++) {
-        const int kk = kb * KS + g * KL;
-        float bv[KL];
-        load_strided<KL>(h1 + kk * HP + 16 * n + r, HP, bv);
-        const frag bf = P::pack(bv);
-#pragma unroll
-        for (int m = 0; m < MAXT; m++) {
-          float av[KL];
-          load_strided<KL>(lm + kk * d.VS + 16 * min(m0 + m, VT - 1) + r, d.VS, av);
-          acc[m] = P::mma(P::pack(av), bf, acc[m]);
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < MAXT; m++) {
-        if (m0 + m >= VT) break;
-        const size_t idx = (size_t)(16 * n + r) * V + 16 * (m0 + m) + 4 * g;
-        float wv[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
-        fvec4 mo = fvec4{0.0f, 0.0f, 0.0f, 0.0f}, vo = mo;
-        if constexpr (adam) {
-          mo = ld4(M2 + idx);
-          vo = ld4(V2 + idx);
-        }
-        float mv[4] = {mo.x, mo.y, mo.z, mo.w};
-        float vv[4] = {vo.x, vo.y, vo.z, vo.w};
-#pragma unroll
-        for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc[m][q], &mv[q], &vv[q]);
-        st4(W2 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
-        if constexpr (adam) {
-          st4(M2 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
-          st4(V2 + idx, fvec4{vv[0], vv[1], vv[2], vv[3]});
-        }
-      }
-    }
-    for (int v = tid; v < V; v += NT) {
-      float gsum = 0.0f;
-      for (int j = 0; j < bs; j++) gsum += lm[j * d.VS + v];
-      const int bi = d.off_b[1] + v;
-      W[bi] = W[bi] - opt_delta_c<ADAM>(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
-    }
     pc->mark(11);
-    drain_stores();   // the W2 update's stores
+    // (no store drain here: the W2 update's stores complete behind the first
+    // chunk's B4 MFMAs, and every later wait of this phase follows W1 stores)
     // B3 + B4, fused per tile of 16 rows d of W1 (a wave takes d tiles
     // wave, wave + NW, ...).  Lane (r, g) loads W1[d][16m + 4g .. +3] for the
     // hidden tiles m of a chunk of HCH: these are the values its B4 output tile
@@ -455,14 +521,24 @@ struct NetMfma {
             const int ht = min(HCH * hc + m, HT - 1);
             acc4[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int kb = 0; kb < KB; kb++) {
-              frag af;
-              if constexpr (KL == 8) {
-                af = *reinterpret_cast<const bf16x8 *>(dpt + (((size_t)ht * KB + kb) * 64 + lane) * 8);
-              } else {
-                af = dpre[(kb * KS + g) * HP + 16 * ht + r];
+            for (int kb = 0; kb < KB; kb++) acc4[m] = P::mma(dpre_frag(ht, kb), bf[kb], acc4[m]);
+          }
+          // hidden-bias gradient sum_j dpre[j][h] (BF16): the wave of d tile 0
+          // multiplies the dpre^T fragments by a ones fragment (column 0)
+          if (KL == 8 && mt == 0) {
+#pragma unroll
+            for (int m = 0; m < HCH; m++) {
+              if (HCH * hc + m >= HT) break;
+              f32x4 accb = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+              for (int kb = 0; kb < KB; kb++) accb = P::mma(dpre_frag(HCH * hc + m, kb), ones_frag(), accb);
+              if (r == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                  const int bi = d.off_b[0] + 16 * (HCH * hc + m) + 4 * g + q;
+                  W[bi] = W[bi] - opt_delta_c<ADAM>(opt, accb[q], M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+                }
               }
-              acc4[m] = P::mma(af, bf[kb], acc4[m]);
             }
           }
           // B3 over this chunk's hidden units (tiles past the end contribute zero)
@@ -537,11 +613,17 @@ struct NetMfma {
         }
       }
     }
-    for (int h = tid; h < H; h += NT) {
-      float gsum = 0.0f;
-      for (int j = 0; j < bs; j++) gsum += dpre[j * HP + h];
-      const int bi = d.off_b[0] + h;
-      W[bi] = W[bi] - opt_delta_c<ADAM>(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+    if constexpr (KL != 8) {
+      // FP32: bias gradients as plain column sums of dz and dpre
+      for (int c = tid; c < V + H; c += NT) {
+        const bool out = c < V;
+        const float *src = out ? lm + c : dpre + (c - V);
+        const int pitch = out ? d.VS : HP;
+        float gsum = 0.0f;
+        for (int j = 0; j < bs; j++) gsum += src[j * pitch];
+        const int bi = out ? d.off_b[1] + c : d.off_b[0] + (c - V);
+        W[bi] = W[bi] - opt_delta_c<ADAM>(opt, gsum, M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+      }
     }
     __syncthreads();
     pc->mark(10);
