@@ -181,22 +181,26 @@ __device__ __forceinline__ int floor_mul_exact(float p, float c) {
 // every V = 4^k, so a row's lanes sit in one wave, aligned.
 __device__ __forceinline__ int row_spl(int V) { return V >= 32 ? V >> 3 : 4; }
 
-// Frequency quantisation of one row by its G lanes (lane gl owns symbols
-// [gl*spl, gl*spl + spl)): f_v = 1 + floor(p_v * (2^16 - V)) with the
-// product exact, the residual 2^16 - sum f added to the most probable
-// symbol (lowest index on ties), and the V+1 cumulative counts written.
-// Integer sums and a fixed-order scan: the result does not depend on G.
-// Invalid probabilities (NaN, outside [0, 1]) count as 0.
-__device__ __forceinline__ void row_quantise_group(const float *p, int V, int spl, int G, int gl, uint32_t *cdf) {
+// Frequency quantisation of one row by its G lanes (lane gl holds the SPL
+// probabilities of symbols [gl*SPL, gl*SPL + SPL) in registers):
+// f_v = 1 + floor(p_v * (2^16 - V)) with the product exact, the residual
+// 2^16 - sum f added to the most probable symbol (lowest index on ties), and
+// the V+1 cumulative counts written.  Integer sums and a fixed-order scan: the
+// result does not depend on G.  Invalid probabilities (NaN, outside [0, 1])
+// count as 0.
+template <int SPL>
+__device__ __forceinline__ void row_quantise_regs(const float (&p)[SPL], int V, int G, int gl, uint32_t *cdf) {
   const float qc = (float)(kTotal - (uint32_t)V);
-  const int v0 = gl * spl;
+  const int v0 = gl * SPL;
+  int f[SPL];
   int fs = 0, bi = v0;
   float best = -1.0f;
-  for (int v = v0; v < v0 + spl; v++) {
-    float pv = p[v];
-    pv = (pv >= 0.0f && pv <= 1.0f) ? pv : 0.0f;
-    fs += 1 + floor_mul_exact(pv, qc);
-    if (pv > best) { best = pv; bi = v; }
+#pragma unroll
+  for (int q = 0; q < SPL; q++) {
+    const float pv = (p[q] >= 0.0f && p[q] <= 1.0f) ? p[q] : 0.0f;
+    f[q] = 1 + floor_mul_exact(pv, qc);
+    fs += f[q];
+    if (pv > best) { best = pv; bi = v0 + q; }
   }
   int tot = fs;
   for (int o = G >> 1; o > 0; o >>= 1) {
@@ -206,21 +210,92 @@ __device__ __forceinline__ void row_quantise_group(const float *p, int V, int sp
     if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
   }
   const int resid = (int)kTotal - tot;
-  const int mine = fs + ((bi >= v0 && bi < v0 + spl) ? resid : 0);
+  const int mine = fs + ((bi >= v0 && bi < v0 + SPL) ? resid : 0);
   int incl = mine;
   for (int o = 1; o < G; o <<= 1) {
     const int y = __shfl_up(incl, o, G);
     if (gl >= o) incl += y;
   }
   uint32_t run = (uint32_t)(incl - mine);
-  for (int v = v0; v < v0 + spl; v++) {
-    float pv = p[v];
-    pv = (pv >= 0.0f && pv <= 1.0f) ? pv : 0.0f;
-    const int f = 1 + floor_mul_exact(pv, qc) + (v == bi ? resid : 0);
-    cdf[v] = run;
-    run += (uint32_t)f;
+#pragma unroll
+  for (int q = 0; q < SPL; q++) {
+    cdf[v0 + q] = run;
+    run += (uint32_t)(f[q] + (v0 + q == bi ? resid : 0));
   }
   if (gl == G - 1) cdf[V] = kTotal;
+}
+
+// the same from a row in memory (symbols per lane: 4, 8 or 32 for V = 4^k)
+template <int SPL>
+__device__ __forceinline__ void row_quantise_mem(const float *p, int V, int G, int gl, uint32_t *cdf) {
+  float r[SPL];
+#pragma unroll
+  for (int q = 0; q < SPL; q++) r[q] = p[gl * SPL + q];
+  row_quantise_regs<SPL>(r, V, G, gl, cdf);
+}
+__device__ __forceinline__ void row_quantise_group(const float *p, int V, int spl, int G, int gl, uint32_t *cdf) {
+  if (spl == 4) row_quantise_mem<4>(p, V, G, gl, cdf);
+  else if (spl == 8) row_quantise_mem<8>(p, V, G, gl, cdf);
+  else row_quantise_mem<32>(p, V, G, gl, cdf);
+}
+
+// Mixer (Eq. 1), softmax and quantiser of one row by its G lanes, SPL
+// symbols per lane held in registers.  lr: the dynamic logits, replaced by
+// the probabilities; ur: the static logits, replaced by L^u - L^m (for the
+// mixing-weight gradient).  Returns this row's sum_v p_v (L^u_v - L^m_v)
+// (static model on) in every lane of the row.
+template <int SPL>
+__device__ __forceinline__ float row_softmax_regs(float *lr, float *ur, bool mix, float alpha, int V, int G, int gl,
+                                                  uint32_t *cdf, float (&pr)[SPL]) {
+  const int v0 = gl * SPL;
+  float z[SPL], df[SPL];
+  float mx = -INFINITY;
+#pragma unroll
+  for (int q = 0; q < SPL; q += 4) {
+    const float4 m4 = *reinterpret_cast<const float4 *>(lr + v0 + q);
+    const float mm[4] = {m4.x, m4.y, m4.z, m4.w};
+    if (mix) {
+      const float4 u4 = *reinterpret_cast<const float4 *>(ur + v0 + q);
+      const float uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        z[q + c] = alpha * uu[c] + (1.0f - alpha) * mm[c];
+        df[q + c] = uu[c] - mm[c];
+      }
+      *reinterpret_cast<float4 *>(ur + v0 + q) = make_float4(df[q], df[q + 1], df[q + 2], df[q + 3]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; c++) z[q + c] = mm[c];
+    }
+    mx = fmaxf(mx, fmaxf(fmaxf(z[q], z[q + 1]), fmaxf(z[q + 2], z[q + 3])));
+  }
+  for (int o = G >> 1; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  // hardware exp2-based exponential and one reciprocal per row: both
+  // deterministic, within a few ulp of the correctly rounded values
+  float se = 0.0f;
+#pragma unroll
+  for (int q = 0; q < SPL; q += 4) {
+#pragma unroll
+    for (int c = 0; c < 4; c++) z[q + c] = __expf(z[q + c] - mx);
+    se = se + z[q] + z[q + 1] + z[q + 2] + z[q + 3];
+  }
+  for (int o = G >> 1; o > 0; o >>= 1) se = se + __shfl_xor(se, o);
+  const float rse = 1.0f / se;
+  float srow = 0.0f;
+#pragma unroll
+  for (int q = 0; q < SPL; q += 4) {
+#pragma unroll
+    for (int c = 0; c < 4; c++) pr[q + c] = z[q + c] * rse;
+    *reinterpret_cast<float4 *>(lr + v0 + q) = make_float4(pr[q], pr[q + 1], pr[q + 2], pr[q + 3]);
+    if (mix) {
+#pragma unroll
+      for (int c = 0; c < 4; c++) srow = fmaf(pr[q + c], df[q + c], srow);
+    }
+  }
+  if (mix)
+    for (int o = G >> 1; o > 0; o >>= 1) srow = srow + __shfl_xor(srow, o);
+  row_quantise_regs<SPL>(pr, V, G, gl, cdf);
+  return srow;
 }
 
 __device__ __forceinline__ long long to_fixed(float x) {
@@ -417,62 +492,24 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
           if (j >= bs) continue;   // a row's lanes are all in or all out
           float *lr = lm + j * VS;
           float *ur = lu + j * VS;
-          const int v0 = gl * spl;
-          float mx = -INFINITY;
-          for (int v = v0; v < v0 + spl; v += 4) {
-            float4 m4 = *reinterpret_cast<float4 *>(lr + v);
-            float4 z4 = m4;
-            if (d.static_on) {
-              const float4 u4 = *reinterpret_cast<const float4 *>(ur + v);
-              z4.x = alpha * u4.x + (1.0f - alpha) * m4.x;
-              z4.y = alpha * u4.y + (1.0f - alpha) * m4.y;
-              z4.z = alpha * u4.z + (1.0f - alpha) * m4.z;
-              z4.w = alpha * u4.w + (1.0f - alpha) * m4.w;
-              // keep L^u - L^m for the mixing-weight gradient
-              *reinterpret_cast<float4 *>(ur + v) =
-                  make_float4(u4.x - m4.x, u4.y - m4.y, u4.z - m4.z, u4.w - m4.w);
-            }
-            *reinterpret_cast<float4 *>(lr + v) = z4;
-            mx = fmaxf(mx, fmaxf(fmaxf(z4.x, z4.y), fmaxf(z4.z, z4.w)));
+          uint32_t *crow = cdf + j * (V + 1);
+          float srow;
+          const bool probe = a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i;
+          float *pp = probe ? a.probe_P + ((size_t)probe_i * bs + j) * V + gl * spl : nullptr;
+          if (spl == 8) {
+            float pr[8];
+            srow = row_softmax_regs<8>(lr, ur, d.static_on, alpha, V, G, gl, crow, pr);
+            if (pp) for (int q = 0; q < 8; q++) pp[q] = pr[q];
+          } else if (spl == 4) {
+            float pr[4];
+            srow = row_softmax_regs<4>(lr, ur, d.static_on, alpha, V, G, gl, crow, pr);
+            if (pp) for (int q = 0; q < 4; q++) pp[q] = pr[q];
+          } else {
+            float pr[32];
+            srow = row_softmax_regs<32>(lr, ur, d.static_on, alpha, V, G, gl, crow, pr);
+            if (pp) for (int q = 0; q < 32; q++) pp[q] = pr[q];
           }
-          for (int o = G >> 1; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-          // hardware exp2-based exponential and one reciprocal per row: both
-          // deterministic, within a few ulp of the correctly rounded values
-          float se = 0.0f;
-          for (int v = v0; v < v0 + spl; v += 4) {
-            float4 z4 = *reinterpret_cast<float4 *>(lr + v);
-            z4.x = __expf(z4.x - mx);
-            z4.y = __expf(z4.y - mx);
-            z4.z = __expf(z4.z - mx);
-            z4.w = __expf(z4.w - mx);
-            se = se + z4.x + z4.y + z4.z + z4.w;
-            *reinterpret_cast<float4 *>(lr + v) = z4;
-          }
-          for (int o = G >> 1; o > 0; o >>= 1) se = se + __shfl_xor(se, o);
-          const float rse = 1.0f / se;
-          float srow = 0.0f;
-          for (int v = v0; v < v0 + spl; v += 4) {
-            float4 e4 = *reinterpret_cast<float4 *>(lr + v);
-            e4.x = e4.x * rse;
-            e4.y = e4.y * rse;
-            e4.z = e4.z * rse;
-            e4.w = e4.w * rse;
-            *reinterpret_cast<float4 *>(lr + v) = e4;
-            if (d.static_on) {
-              const float4 df = *reinterpret_cast<const float4 *>(ur + v);
-              srow = fmaf(e4.x, df.x, srow);
-              srow = fmaf(e4.y, df.y, srow);
-              srow = fmaf(e4.z, df.z, srow);
-              srow = fmaf(e4.w, df.w, srow);
-            }
-          }
-          if (d.static_on) {
-            for (int o = G >> 1; o > 0; o >>= 1) srow = srow + __shfl_xor(srow, o);
-            if (gl == 0) misc[j] = srow;
-          }
-          row_quantise_group(lr, V, spl, G, gl, cdf + j * (V + 1));
-          if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i)
-            for (int v = v0; v < v0 + spl; v++) a.probe_P[((size_t)probe_i * bs + j) * V + v] = lr[v];
+          if (d.static_on && gl == 0) misc[j] = srow;
         }
         __syncthreads();
       } else if (a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i) {
