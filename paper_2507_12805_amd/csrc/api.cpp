@@ -242,6 +242,14 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
       const uint64_t need = d.nh == 1 ? 2ull * bs * d.H[0] : 0;
       const uint64_t cdf_bytes = 4ull * bs * (d.V + 1);
       L.dpt = need <= cdf_bytes ? L.cdf : take(need);
+      // dpre in BF16 as B3's B fragments (BF16 kernel only): in the static
+      // logits when they are there and large enough, else its own region if
+      // the total still fits, else absent (-1: B3 reads the FP32 dpre)
+      const uint64_t lu_bytes = d.static_on ? 4ull * bs * d.VS : 0;
+      if (precision != PMKLC_BF16 || need == 0) L.dpb = -1;
+      else if (need <= lu_bytes) L.dpb = L.lu;
+      else if (o + need <= 160 * 1024) L.dpb = take(need);
+      else L.dpb = -1;
     }
     L.total = (int)o;
     L.act_global = glob;

@@ -38,6 +38,8 @@ struct Dims {
 struct LdsLayout {
   int emb, embs, ring, act[2], lm, lu, cdf, tgt, dh[2], demb, misc, total;
   int dpt;            // matrix-core kernel: BF16 dpre^T fragments (aliases cdf, dead in the backward, when it fits)
+  int dpb;            // BF16 matrix-core kernel: dpre as B3's B fragments (aliases lu, dead in the backward, when
+                      // it fits), or -1 when absent
   int act_global;     // 1: act[] and dh[] are float offsets into a per-workgroup global slab
   int act_slot;       // floats per workgroup slab
 };

@@ -102,6 +102,7 @@ struct NetMfma {
   uint8_t *ring;
   long long *demb;
   __bf16 *dpt;     // BF16 dpre^T in B4's A-fragment order (LDS), BF16 only
+  __bf16 *dpb;     // BF16 dpre in B3's B-fragment order (LDS), BF16 only
   uint16_t *w1f;   // this workgroup's BF16 copy of W1 (fragment order), BF16 only
   int tid, lane, wave, r, g;
   PhaseClock *pc = nullptr;
@@ -115,6 +116,7 @@ struct NetMfma {
     ring = lds + a.lay.ring;
     demb = reinterpret_cast<long long *>(lds + a.lay.demb);
     dpt = reinterpret_cast<__bf16 *>(lds + a.lay.dpt);
+    dpb = a.lay.dpb >= 0 ? reinterpret_cast<__bf16 *>(lds + a.lay.dpb) : nullptr;
     tid = threadIdx.x;
     lane = tid & 63;
     wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: branches on it stay scalar
@@ -470,6 +472,14 @@ struct NetMfma {
             for (int q = 0; q < 4; q++) pk[q] = (__bf16)dv[q];
             const int slot = r + 16 * (2 * (m & 1) + (g >> 1));
             *reinterpret_cast<bf16x4 *>(dpt + (((size_t)n * KB + (m >> 1)) * 64 + slot) * 8 + 4 * (g & 1)) = pk;
+            // and dpre as B3's B fragments: row tile m of j, k-step n/2 of h with
+            // B3's slot order (q < 4: h = 32k + 4g' + q; q >= 4: h = 32k + 16 + 4g' + q - 4),
+            // so h = 16n + r sits in lane (4g + i) + 16 (r/4), slot 4 (n%2) + r%4
+            if (dpb) {
+              __bf16 *pb = dpb + ((m * (H / 32) + (n >> 1)) * 64 + 4 * g + 16 * (r >> 2)) * 8 + 4 * (n & 1) + (r & 3);
+#pragma unroll
+              for (int q = 0; q < 4; q++) pb[8 * q] = pk[q];
+            }
           }
         }
       }
@@ -550,13 +560,23 @@ struct NetMfma {
                              v0 ? w[2 * k].w : 0.0f, v1 ? w[2 * k + 1].x : 0.0f, v1 ? w[2 * k + 1].y : 0.0f,
                              v1 ? w[2 * k + 1].z : 0.0f, v1 ? w[2 * k + 1].w : 0.0f};
               const frag a3 = P::pack(av);
-              const int h0 = 16 * min(HCH * hc + 2 * k, HT - 1) + 4 * g, h1c = 16 * min(HCH * hc + 2 * k + 1, HT - 1) + 4 * g;
+              if (dpb) {
+                // B3's B fragments from the BF16 copy of dpre (k-steps past the end
+                // clamped; their A operand is zero)
+                const int ks3 = min((HCH * hc) / 2 + k, H / 32 - 1);
 #pragma unroll
-              for (int n = 0; n < MAXT; n++) {
-                float bv[8];
-                load_run<4>(dpre + (16 * n + r) * HP + h0, bv);
-                load_run<4>(dpre + (16 * n + r) * HP + h1c, bv + 4);
-                acc3[n] = P::mma(a3, P::pack(bv), acc3[n]);
+                for (int n = 0; n < MAXT; n++)
+                  acc3[n] = P::mma(a3, *reinterpret_cast<const bf16x8 *>(dpb + ((n * (H / 32) + ks3) * 64 + lane) * 8),
+                                   acc3[n]);
+              } else {
+                const int h0 = 16 * min(HCH * hc + 2 * k, HT - 1) + 4 * g, h1c = 16 * min(HCH * hc + 2 * k + 1, HT - 1) + 4 * g;
+#pragma unroll
+                for (int n = 0; n < MAXT; n++) {
+                  float bv[8];
+                  load_run<4>(dpre + (16 * n + r) * HP + h0, bv);
+                  load_run<4>(dpre + (16 * n + r) * HP + h1c, bv + 4);
+                  acc3[n] = P::mma(a3, P::pack(bv), acc3[n]);
+                }
               }
             }
           } else {
