@@ -237,6 +237,7 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
     L.dh[1] = act(d.nh >= 2 ? 4ull * bs * hmax : 0);
     L.demb = take(8ull * d.V * d.ES);
     L.misc = take(4ull * bs + 64);
+    L.cst = take(48ull * bs);
     {
       // BF16 copy of dpre^T for the fused backward (one hidden layer)
       const uint64_t need = d.nh == 1 ? 2ull * bs * d.H[0] : 0;

@@ -37,6 +37,7 @@ struct Dims {
 // LDS layout (byte offsets into dynamic shared memory).
 struct LdsLayout {
   int emb, embs, ring, act[2], lm, lu, cdf, tgt, dh[2], demb, misc, total;
+  int cst;            // per-segment coder states (CoderState, one per row)
   int dpt;            // matrix-core kernel: BF16 dpre^T fragments (aliases cdf, dead in the backward, when it fits)
   int dpb;            // BF16 matrix-core kernel: dpre as B3's B fragments (aliases lu, dead in the backward, when
                       // it fits), or -1 when absent

@@ -10,6 +10,8 @@ namespace detail {
 // wait for an LDS read would then wait for the outstanding weight loads too.
 // Hot loops address weights through these address-space-1 views instead.
 typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) uint8_t gu8;
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) fvec4 gfvec4;
 // Waits until this wave's outstanding global loads and stores are done.
@@ -50,7 +52,7 @@ struct Enc {
 __device__ __forceinline__ void enc_init(Enc &e) {
   e.low = 0; e.high = 0xFFFFFFFFu; e.pending = 0; e.widx = 0; e.buf = 0; e.nbits = 0; e.nbuf = 0;
 }
-__device__ __forceinline__ void enc_emit(Enc &e, uint32_t *slot, uint32_t cap, uint32_t bits, int n, int &ovf) {
+__device__ __forceinline__ void enc_emit(Enc &e, gu32 *slot, uint32_t cap, uint32_t bits, int n, int &ovf) {
   e.buf = (e.buf << n) | (uint64_t)bits;
   e.nbuf += n;
   e.nbits += (uint64_t)n;
@@ -63,7 +65,7 @@ __device__ __forceinline__ void enc_emit(Enc &e, uint32_t *slot, uint32_t cap, u
     e.buf &= (1ull << e.nbuf) - 1ull;
   }
 }
-__device__ __forceinline__ void enc_run(Enc &e, uint32_t *slot, uint32_t cap, int bit, uint32_t count, int &ovf) {
+__device__ __forceinline__ void enc_run(Enc &e, gu32 *slot, uint32_t cap, int bit, uint32_t count, int &ovf) {
   while (count) {
     int n = count > 32u ? 32 : (int)count;
     uint32_t bits = bit ? (n == 32 ? 0xFFFFFFFFu : ((1u << n) - 1u)) : 0u;
@@ -71,34 +73,48 @@ __device__ __forceinline__ void enc_run(Enc &e, uint32_t *slot, uint32_t cap, in
     count -= (uint32_t)n;
   }
 }
-__device__ __forceinline__ void enc_symbol(Enc &e, uint32_t *slot, uint32_t cap, uint32_t lo, uint32_t hi, int &ovf) {
+// Renormalisation of the WNC coder (Witten, Neal and Cleary 1987) in two
+// bulk moves that give exactly what its one-bit loop gives.  While the top
+// bits of low and high agree the loop outputs that bit (E1 for 0, E2 for 1)
+// and shifts both left (high taking a 1): the k1 = clz(low ^ high) agreed
+// leading bits go out together, the first followed by the pending opposite
+// bits.  Then, while low has 1 and high has 0 in bit 30 (E3), the loop counts
+// a pending bit and maps x -> 2 (x - 2^30): over k3 such positions that is
+// x << k3 with bit 31 flipped, mod 2^32, high again taking 1s.  After E3 the
+// top bits still differ, so no E1/E2 follows.  With the coding range above
+// 2^30 before a symbol and every frequency at least 1, the new range exceeds
+// 2^14, so k1 and k3 stay far below 32 (k1 is clamped to 31 for an empty
+// interval, which only a caller's invalid table can give).
+__device__ __forceinline__ void enc_symbol(Enc &e, gu32 *slot, uint32_t cap, uint32_t lo, uint32_t hi, int &ovf) {
   uint64_t r = (uint64_t)e.high - e.low + 1u;
   uint32_t l0 = e.low;
-  e.high = l0 + (uint32_t)((r * hi) >> kTotalBits) - 1u;
-  e.low = l0 + (uint32_t)((r * lo) >> kTotalBits);
-  for (;;) {
-    if (e.high < kHalf) {
-      enc_emit(e, slot, cap, 0u, 1, ovf);
-      enc_run(e, slot, cap, 1, e.pending, ovf);
+  uint32_t high = l0 + (uint32_t)((r * hi) >> kTotalBits) - 1u;
+  uint32_t low = l0 + (uint32_t)((r * lo) >> kTotalBits);
+  const int k1 = min(__clz(low ^ high), 31);   // (31 only for an empty interval)
+  if (k1 > 0) {
+    const uint32_t top = low >> (32 - k1);   // the agreed bits, first one highest
+    if (e.pending) {
+      const uint32_t first = top >> (k1 - 1);
+      enc_emit(e, slot, cap, first, 1, ovf);
+      enc_run(e, slot, cap, first ^ 1u, e.pending, ovf);
       e.pending = 0;
-    } else if (e.low >= kHalf) {
-      enc_emit(e, slot, cap, 1u, 1, ovf);
-      enc_run(e, slot, cap, 0, e.pending, ovf);
-      e.pending = 0;
-      e.low -= kHalf;
-      e.high -= kHalf;
-    } else if (e.low >= kQuarter && e.high < 3u * kQuarter) {
-      e.pending++;
-      e.low -= kQuarter;
-      e.high -= kQuarter;
+      if (k1 > 1) enc_emit(e, slot, cap, top & ((1u << (k1 - 1)) - 1u), k1 - 1, ovf);
     } else {
-      break;
+      enc_emit(e, slot, cap, top, k1, ovf);
     }
-    e.low <<= 1;
-    e.high = (e.high << 1) | 1u;
+    low <<= k1;
+    high = (high << k1) | ((1u << k1) - 1u);
   }
+  const int k3 = __clz(~((low & ~high) << 1));
+  if (k3 > 0) {
+    e.pending += (uint32_t)k3;
+    low = (low << k3) ^ kHalf;
+    high = ((high << k3) ^ kHalf) | ((1u << k3) - 1u);
+  }
+  e.low = low;
+  e.high = high;
 }
-__device__ __forceinline__ void enc_finish(Enc &e, uint32_t *slot, uint32_t cap, int &ovf) {
+__device__ __forceinline__ void enc_finish(Enc &e, gu32 *slot, uint32_t cap, int &ovf) {
   e.pending++;
   int bit = e.low < kQuarter ? 0 : 1;
   enc_emit(e, slot, cap, (uint32_t)bit, 1, ovf);
@@ -116,25 +132,29 @@ __device__ __forceinline__ void enc_finish(Enc &e, uint32_t *slot, uint32_t cap,
 
 struct Dec {
   uint32_t low, high, value, widx;
-  uint32_t buf;
+  uint64_t buf;   // the low nbuf bits are the next stream bits, first one highest
   int nbuf;
 };
-__device__ __forceinline__ int dec_bit(Dec &d, const uint32_t *w, uint32_t nw) {
-  if (d.nbuf == 0) {
-    d.buf = d.widx < nw ? __builtin_bswap32(w[d.widx]) : 0u;
+// the next n stream bits (1 <= n <= 32) as an integer, first bit highest;
+// bits past the last word are 0
+__device__ __forceinline__ uint32_t dec_bits(Dec &d, const gu32 *w, uint32_t nw, int n) {
+  if (d.nbuf < n) {
+    const uint32_t x = d.widx < nw ? __builtin_bswap32(w[d.widx]) : 0u;
     d.widx++;
-    d.nbuf = 32;
+    d.buf = (d.buf << 32) | x;
+    d.nbuf += 32;
   }
-  d.nbuf--;
-  return (int)((d.buf >> d.nbuf) & 1u);
+  d.nbuf -= n;
+  return (uint32_t)(d.buf >> d.nbuf) & (uint32_t)((1ull << n) - 1ull);
 }
-__device__ __forceinline__ void dec_init(Dec &d, const uint32_t *w, uint32_t nw) {
-  d.low = 0; d.high = 0xFFFFFFFFu; d.value = 0; d.widx = 0; d.buf = 0; d.nbuf = 0;
-  for (int i = 0; i < 32; i++) d.value = (d.value << 1) | (uint32_t)dec_bit(d, w, nw);
+__device__ __forceinline__ void dec_init(Dec &d, const gu32 *w, uint32_t nw) {
+  d.low = 0; d.high = 0xFFFFFFFFu; d.widx = 0; d.buf = 0; d.nbuf = 0;
+  d.value = dec_bits(d, w, nw, 32);
 }
 // cum(s) is the cumulative count below symbol s (cum(0) = 0, cum(V) = 2^16).
+// The renormalisation mirrors enc_symbol's, value taking the stream bits.
 template <class Cum>
-__device__ __forceinline__ int dec_symbol(Dec &d, const uint32_t *w, uint32_t nw, int V, Cum cum) {
+__device__ __forceinline__ int dec_symbol(Dec &d, const gu32 *w, uint32_t nw, int V, Cum cum) {
   uint64_t r = (uint64_t)d.high - d.low + 1u;
   uint32_t target = d.value - d.low;
   int a = 0, b = V;
@@ -144,23 +164,39 @@ __device__ __forceinline__ int dec_symbol(Dec &d, const uint32_t *w, uint32_t nw
     else b = m;
   }
   uint32_t l0 = d.low;
-  d.high = l0 + (uint32_t)((r * cum(a + 1)) >> kTotalBits) - 1u;
-  d.low = l0 + (uint32_t)((r * cum(a)) >> kTotalBits);
-  for (;;) {
-    if (d.high < kHalf) {
-    } else if (d.low >= kHalf) {
-      d.low -= kHalf; d.high -= kHalf; d.value -= kHalf;
-    } else if (d.low >= kQuarter && d.high < 3u * kQuarter) {
-      d.low -= kQuarter; d.high -= kQuarter; d.value -= kQuarter;
-    } else {
-      break;
-    }
-    d.low <<= 1;
-    d.high = (d.high << 1) | 1u;
-    d.value = (d.value << 1) | (uint32_t)dec_bit(d, w, nw);
+  uint32_t high = l0 + (uint32_t)((r * cum(a + 1)) >> kTotalBits) - 1u;
+  uint32_t low = l0 + (uint32_t)((r * cum(a)) >> kTotalBits);
+  uint32_t value = d.value;
+  const int k1 = min(__clz(low ^ high), 31);   // (31 only for an empty interval)
+  if (k1 > 0) {
+    low <<= k1;
+    high = (high << k1) | ((1u << k1) - 1u);
+    value = (value << k1) | dec_bits(d, w, nw, k1);
   }
+  const int k3 = __clz(~((low & ~high) << 1));
+  if (k3 > 0) {
+    low = (low << k3) ^ kHalf;
+    high = ((high << k3) ^ kHalf) | ((1u << k3) - 1u);
+    value = ((value << k3) ^ kHalf) | dec_bits(d, w, nw, k3);
+  }
+  d.low = low;
+  d.high = high;
+  d.value = value;
   return a;
 }
+
+// One segment's coder between steps.  It is kept in LDS and loaded and
+// stored around each use, so that none of it is live (and spilled) across
+// the rest of the step.
+struct CoderState {
+  union {
+    Enc enc;
+    Dec dec;
+  };
+  uint32_t nwords;   // decode: words in the segment's stream
+  int ovf;           // encode: the slot overflowed
+};
+static_assert(sizeof(CoderState) == 48, "the LDS plan reserves 48 bytes per segment");
 
 // ------------------------------------------------------------ quantiser
 // floor(p * c) of the exact real product, for 0 <= p <= 1 and an integer
@@ -440,19 +476,22 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     };
     if (bd.has_snap && bd.S == 0) snapshot();
 
-    // ---- coders: lane j < bs owns segment j
-    Enc enc;
-    Dec dec;
-    int ovf = 0;
-    uint32_t *slot = a.slots + bd.slot_off + (size_t)tid * bd.slot_words;
-    uint32_t nwords = 0;
+    // ---- coders: lane j < bs owns segment j; its state lives in cst[j].
+    // (global-space views: a generic access would also hold up every LDS wait)
+    CoderState *cst = reinterpret_cast<CoderState *>(lds + a.lay.cst);
+    auto slot_of = [&](int j) { return (gu32 *)(a.slots + bd.slot_off + (size_t)j * bd.slot_words); };
+    gu8 *toks = (gu8 *)a.tokens;
     if (tid < bs) {
-      if (a.mode == 0) enc_init(enc);
+      CoderState c;
+      c.ovf = 0;
+      c.nwords = 0;
+      if (a.mode == 0) enc_init(c.enc);
       else {
-        nwords = a.seg_words[(size_t)b * bs + tid];
-        if (nwords > bd.slot_words) nwords = bd.slot_words;
-        dec_init(dec, slot, nwords);
+        c.nwords = a.seg_words[(size_t)b * bs + tid];
+        if (c.nwords > bd.slot_words) c.nwords = bd.slot_words;
+        dec_init(c.dec, slot_of(tid), c.nwords);
       }
+      cst[tid] = c;
     }
     Opt opt;
     opt.kind = d.optimizer;
@@ -472,7 +511,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         for (int q = tid; q < bs * CH; q += NT) {
           int j = q / CH, c = q % CH;
           uint64_t pos = i + (uint64_t)c;
-          if (pos < bd.L) ring[j * RS + (int)(pos & (uint64_t)mask)] = a.tokens[tok0 + (size_t)j * bd.L + pos];
+          if (pos < bd.L) ring[j * RS + (int)(pos & (uint64_t)mask)] = toks[tok0 + (size_t)j * bd.L + pos];
         }
         __syncthreads();
       }
@@ -523,24 +562,27 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         const int j = tid;
         const int rp = j * RS + (int)(i & (uint64_t)mask);
         const uint32_t unit = kTotal / (uint32_t)V;
+        CoderState cs = cst[j];
+        gu32 *slot = slot_of(j);
         if (a.mode == 0) {
           int e = ring[rp];
           uint32_t lo, hi;
           if (uniform) { lo = (uint32_t)e * unit; hi = lo + unit; }
           else { lo = cdf[j * (V + 1) + e]; hi = cdf[j * (V + 1) + e + 1]; }
-          enc_symbol(enc, slot, bd.slot_words, lo, hi, ovf);
+          enc_symbol(cs.enc, slot, bd.slot_words, lo, hi, cs.ovf);
           tgt[j] = (uint8_t)e;
         } else {
           int e;
-          if (uniform) e = dec_symbol(dec, slot, nwords, V, [&](int s) { return (uint32_t)s * unit; });
+          if (uniform) e = dec_symbol(cs.dec, slot, cs.nwords, V, [&](int s) { return (uint32_t)s * unit; });
           else {
             const uint32_t *c = cdf + j * (V + 1);
-            e = dec_symbol(dec, slot, nwords, V, [&](int s) { return c[s]; });
+            e = dec_symbol(cs.dec, slot, cs.nwords, V, [&](int s) { return c[s]; });
           }
           ring[rp] = (uint8_t)e;
           tgt[j] = (uint8_t)e;
-          a.tokens[tok0 + (size_t)j * bd.L + i] = (uint8_t)e;
+          toks[tok0 + (size_t)j * bd.L + i] = (uint8_t)e;
         }
+        cst[j] = cs;
       }
       // mixing-weight gradient: per-row terms summed by a wave butterfly,
       // then the wave partials in order by thread 0
@@ -599,11 +641,12 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
 
     pc.flush();
     if (tid < bs) {
+      CoderState cs = cst[tid];
       if (a.mode == 0) {
-        enc_finish(enc, slot, bd.slot_words, ovf);
-        a.seg_bits[(size_t)b * bs + tid] = (uint32_t)enc.nbits;
+        enc_finish(cs.enc, slot_of(tid), bd.slot_words, cs.ovf);
+        a.seg_bits[(size_t)b * bs + tid] = (uint32_t)cs.enc.nbits;
       }
-      if (ovf) atomicOr(a.err, 2);
+      if (cs.ovf) atomicOr(a.err, 2);
     }
     // final parameters (embedding lives in LDS during the loop)
     for (int q = tid; q < V * E; q += NT) W[d.off_emb + q] = emb[q + (int)__umulhi((uint32_t)q, d.Emag) * (d.EP - E)];

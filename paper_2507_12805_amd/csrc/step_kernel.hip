@@ -391,8 +391,9 @@ __global__ void wnc_encode_kernel(const uint32_t *lo, const uint32_t *hi, uint64
   Enc e;
   enc_init(e);
   int ovf = 0;
-  for (uint64_t i = 0; i < m; i++) enc_symbol(e, out, cap, lo[i], hi[i], ovf);
-  enc_finish(e, out, cap, ovf);
+  gu32 *o = (gu32 *)out;
+  for (uint64_t i = 0; i < m; i++) enc_symbol(e, o, cap, lo[i], hi[i], ovf);
+  enc_finish(e, o, cap, ovf);
   *nbits = e.nbits;
   if (ovf) *err = 2;
 }
@@ -407,10 +408,11 @@ __global__ void wnc_decode_kernel(const uint32_t *words, uint32_t nwords, const 
                                   uint64_t m, uint32_t *sym) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   Dec d;
-  dec_init(d, words, nwords);
+  const gu32 *w = (const gu32 *)words;
+  dec_init(d, w, nwords);
   for (uint64_t i = 0; i < m; i++) {
     const uint32_t *c = cdfs + i * (V + 1);
-    sym[i] = (uint32_t)dec_symbol(d, words, nwords, (int)V, [&](int s) { return c[s]; });
+    sym[i] = (uint32_t)dec_symbol(d, w, nwords, (int)V, [&](int s) { return c[s]; });
   }
 }
 

@@ -22,6 +22,8 @@
 // never changes its value.
 #include "step_common.h"
 
+#include <type_traits>
+
 namespace pmklc {
 
 namespace {
@@ -29,6 +31,21 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) u32x2 gu32x2;
+
+// the bits of the BF16 rounding (nearest even) of v
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v);
+}
+
+// x taken from the lane of this lane's quad that the DPP quad_perm pattern
+// PAT (four 2-bit source indices, lowest first) names
+template <int PAT>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, PAT, 0xF, 0xF, true);
+}
 
 struct MmaF32 {
   static constexpr int KS = 4, KL = 1;
@@ -192,7 +209,10 @@ struct NetMfma {
     // register operands are gathered GC k-steps at a time (about 8 fragments)
     constexpr int GC0 = NM >= 8 ? 1 : 8 / NM, GC = GC0 < KCX ? GC0 : KCX;
     static_assert(KCX % GC == 0, "gather groups must tile the chunk");
-    auto use = [&](int ch, Buf (&buf)[KCX][NN]) {
+    // CHK: this chunk may hold k-steps past the end (only the last pair of a
+    // ragged stream), whose streamed fragments are zeroed
+    auto use = [&](auto chk, int ch, Buf (&buf)[KCX][NN]) {
+      constexpr bool CHK = decltype(chk)::value;
 #pragma unroll
       for (int c0 = 0; c0 < KCX; c0 += GC) {
         frag o[GC][NM];
@@ -202,7 +222,7 @@ struct NetMfma {
           for (int m = 0; m < NM; m++) o[c][m] = reg(m, min(ch * KCX + c0 + c, ksteps - 1));
 #pragma unroll
         for (int c = 0; c < GC; c++) {
-          const bool past = ragged && ch * KCX + c0 + c >= ksteps;
+          const bool past = CHK && ch * KCX + c0 + c >= ksteps;
 #pragma unroll
           for (int n = 0; n < NN; n++) {
             frag sf = to_frag(buf[c0 + c][n]);
@@ -216,10 +236,13 @@ struct NetMfma {
     };
     fetch(0, bufA);
     for (int ch = 0; ch < nch; ch += 2) {
+      const bool tail = ragged && ch + 2 >= nch;   // uniform
       fetch(ch + 1, bufB);
-      use(ch, bufA);
+      if (tail) use(std::true_type{}, ch, bufA);
+      else use(std::false_type{}, ch, bufA);
       fetch(ch + 2, bufA);
-      use(ch + 1, bufB);
+      if (tail) use(std::true_type{}, ch + 1, bufB);
+      else use(std::false_type{}, ch + 1, bufB);
     }
   }
   // one streamed operand
@@ -306,6 +329,7 @@ struct NetMfma {
       }
     }
     __syncthreads();
+    pc->mark(7);
     // F2: H1 W2 + b2 -> logits
     for (int grp = wave; grp < nmod * (V / 16); grp += NW) {
       const int model = grp / (V / 16), n = grp % (V / 16);
@@ -339,6 +363,12 @@ struct NetMfma {
     float *dpre = hs;
     constexpr bool adam = ADAM;   // fixed per kernel: no optimiser branch in the update loops
     drain_stores();
+    // BF16: the biases are updated after the backward from gradients gathered
+    // in LDS (gb below, hidden first); each thread's first one is loaded now
+    // so that its latency hides behind the backward
+    auto bias_at = [&](int c) { return c < H ? d.off_b[0] + c : d.off_b[1] + (c - H); };
+    float b_old = 0.0f;
+    if (KL == 8 && tid < V + H) b_old = W[bias_at(tid)];
     // B1 + B2, fused per hidden tile n (a wave per tile).  Lane (r, g) loads
     // W2[16n + r][16m + 4g .. +3] for a chunk of 4 symbol tiles m: these are
     // the values its B2 output tile updates, and, with the contraction index v
@@ -410,28 +440,6 @@ struct NetMfma {
               }
             }
           }
-          // output-bias gradient sum_j dz[j][v] (BF16): the wave of tile 0
-          // multiplies the dz^T fragments by a ones fragment (column 0)
-          if (KL == 8 && n == 0) {
-#pragma unroll
-            for (int m = 0; m < 4; m++) {
-              if (vc + m >= VT) break;
-              f32x4 accb = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-              for (int kb = 0; kb < KB; kb++) {
-                float av[KL];
-                load_strided<KL>(lm + (kb * KS + g * KL) * d.VS + 16 * (vc + m) + r, d.VS, av);
-                accb = P::mma(P::pack(av), ones_frag(), accb);
-              }
-              if (r == 0) {
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                  const int bi = d.off_b[1] + 16 * (vc + m) + 4 * g + q;
-                  W[bi] = W[bi] - opt_delta_c<ADAM>(opt, accb[q], M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
-                }
-              }
-            }
-          }
           // W2 update of this chunk
 #pragma unroll
           for (int m = 0; m < 4; m++) {
@@ -489,6 +497,8 @@ struct NetMfma {
     pc->mark(11);
     // (no store drain here: the W2 update's stores complete behind the first
     // chunk's B4 MFMAs, and every later wait of this phase follows W1 stores)
+    // bias gradients (BF16): H1 is dead from here to the next forward
+    float *gb = h1;
     // B3 + B4, fused per tile of 16 rows d of W1 (a wave takes d tiles
     // wave, wave + NW, ...).  Lane (r, g) loads W1[d][16m + 4g .. +3] for the
     // hidden tiles m of a chunk of HCH: these are the values its B4 output tile
@@ -502,6 +512,23 @@ struct NetMfma {
     {
       gfloat *M1 = M ? M + d.off_W[0] : nullptr, *V1 = Vs ? Vs + d.off_W[0] : nullptr;
       const int HT = H / 16, DT = D / 16, NHC = (HT + HCH - 1) / HCH;
+      // output-bias gradient sum_j dz[j][v] (BF16, as an MFMA against a ones
+      // fragment): symbol tiles from the last wave down
+      if constexpr (KL == 8) {
+        for (int vt = NW - 1 - wave; vt < V / 16; vt += NW) {
+          f32x4 accb = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+          for (int kb = 0; kb < KB; kb++) {
+            float av[KL];
+            load_strided<KL>(lm + (kb * KS + g * KL) * d.VS + 16 * vt + r, d.VS, av);
+            accb = P::mma(P::pack(av), ones_frag(), accb);
+          }
+          if (r == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) gb[H + 16 * vt + 4 * g + q] = accb[q];
+          }
+        }
+      }
       for (int mt = wave; mt < DT; mt += NW) {
         const int dd = 16 * mt + r;
         int p, e;
@@ -544,10 +571,7 @@ struct NetMfma {
               for (int kb = 0; kb < KB; kb++) accb = P::mma(dpre_frag(HCH * hc + m, kb), ones_frag(), accb);
               if (r == 0) {
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                  const int bi = d.off_b[0] + 16 * (HCH * hc + m) + 4 * g + q;
-                  W[bi] = W[bi] - opt_delta_c<ADAM>(opt, accb[q], M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
-                }
+                for (int q = 0; q < 4; q++) gb[16 * (HCH * hc + m) + 4 * g + q] = accb[q];
               }
             }
           }
@@ -609,9 +633,26 @@ struct NetMfma {
             for (int q = 0; q < 4; q++) wv[q] = wv[q] - opt_delta_c<ADAM>(opt, acc4[m][q], &mv[q], &vv[q]);
             st4(W1 + idx, fvec4{wv[0], wv[1], wv[2], wv[3]});
             if constexpr (KL == 8) {
-              gbf16 *cp = (gbf16 *)w1f;
-#pragma unroll
-              for (int q = 0; q < 4; q++) cp[w1_frag_index(dd, 16 * (HCH * hc + m) + 4 * g + q, D)] = (__bf16)wv[q];
+              // BF16 copy: the four lanes of a quad hold 4 consecutive d and
+              // each the same 4 consecutive h; a 4x4 transpose of the 16-bit
+              // values inside the quad leaves lane c with h = 4g + c at those
+              // 4 d, which are 8 contiguous bytes of the fragment-ordered copy
+              const uint32_t c = lane & 3u;
+              const uint32_t p01 = bf16_bits(wv[0]) | (bf16_bits(wv[1]) << 16);
+              const uint32_t p23 = bf16_bits(wv[2]) | (bf16_bits(wv[3]) << 16);
+              // lanes c and c ^ 2 swap a dword: afterwards lane c = 2s + t holds
+              // A = (x[t][2s], x[t][2s+1]) and B = (x[2+t][2s], x[2+t][2s+1]),
+              // x[c'][q] being value q of quad lane c'
+              const uint32_t x2 = quad_perm<0x4E>(c < 2 ? p23 : p01);
+              const uint32_t A = c < 2 ? p01 : x2, B = c < 2 ? x2 : p23;
+              // lanes c and c ^ 1 swap a half of each: E = (x[0][c], x[1][c]), F = (x[2][c], x[3][c])
+              const bool odd = c & 1u;
+              const uint32_t ya = quad_perm<0xB1>(odd ? (A & 0xFFFFu) : (A >> 16));
+              const uint32_t yb = quad_perm<0xB1>(odd ? (B & 0xFFFFu) : (B >> 16));
+              const uint32_t E = odd ? (ya | (A & 0xFFFF0000u)) : ((A & 0xFFFFu) | (ya << 16));
+              const uint32_t F = odd ? (yb | (B & 0xFFFF0000u)) : ((B & 0xFFFFu) | (yb << 16));
+              gu32x2 *cp = (gu32x2 *)(w1f + w1_frag_index(16 * mt + (r & ~3), 16 * (HCH * hc + m) + 4 * g + (int)c, D));
+              *cp = u32x2{E, F};
             }
             if constexpr (adam) {
               st4(M1 + idx, fvec4{mv[0], mv[1], mv[2], mv[3]});
@@ -646,6 +687,15 @@ struct NetMfma {
       }
     }
     __syncthreads();
+    if constexpr (KL == 8) {
+      // BF16 bias updates (nothing reads the biases or H1 before the next
+      // step's forward, so no barrier follows)
+      for (int c = tid; c < V + H; c += NT) {
+        const int bi = bias_at(c);
+        const float old = c == tid ? b_old : W[bi];
+        W[bi] = old - opt_delta_c<ADAM>(opt, gb[c], M ? M + bi : nullptr, Vs ? Vs + bi : nullptr);
+      }
+    }
     pc->mark(10);
   }
 };
