@@ -30,17 +30,48 @@ __device__ __forceinline__ void st4(gfloat *p, fvec4 v) { *(gfvec4 *)p = v; }
 constexpr uint32_t kHalf = 0x80000000u;
 constexpr uint32_t kQuarter = 0x40000000u;
 
-__device__ __forceinline__ float wave_max(float x) {
-  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+// Lane exchanges inside aligned groups of G lanes (G a power of two), the
+// first three levels by DPP lane permutations, which are register moves,
+// the wider ones through the LDS crossbar.  Level 1 pairs lane i with
+// i ^ 1, level 2 with i ^ 2 (quad permutations), level 3 with 7 - i inside
+// its 8 (row half-mirror); level o >= 8 pairs i with i ^ o.  Every level
+// pairs lanes symmetrically, so a reduction ends with the same value, in the
+// same order of operations, in every lane of the group.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(dpp_mov<CTRL>(__float_as_int(x)));
+}
+template <class T, class Op>
+__device__ __forceinline__ T group_reduce(T x, int G, Op op) {
+  if (G >= 2) x = op(x, dpp_mov<0xB1>(x));    // quad_perm [1, 0, 3, 2]
+  if (G >= 4) x = op(x, dpp_mov<0x4E>(x));    // quad_perm [2, 3, 0, 1]
+  if (G >= 8) x = op(x, dpp_mov<0x141>(x));   // row_half_mirror
+  for (int o = 8; o < G; o <<= 1) x = op(x, __shfl_xor(x, o));
+  return x;
+}
+// the partner's value at each level, for reductions over several values
+template <class F>
+__device__ __forceinline__ void group_levels(int G, F &&level) {
+  if (G >= 2) level([](auto v) { return dpp_mov<0xB1>(v); });
+  if (G >= 4) level([](auto v) { return dpp_mov<0x4E>(v); });
+  if (G >= 8) level([](auto v) { return dpp_mov<0x141>(v); });
+  for (int o = 8; o < G; o <<= 1) level([o](auto v) { return __shfl_xor(v, o); });
+}
+// inclusive prefix sum over the G lanes of a group (gl: index in the group);
+// a row shift brings lane i - o, taken only when it is in the same group
+__device__ __forceinline__ int group_scan(int x, int G, int gl) {
+  if (G >= 2) { const int y = dpp_mov<0x111>(x); if (gl >= 1) x += y; }   // row_shr:1
+  if (G >= 4) { const int y = dpp_mov<0x112>(x); if (gl >= 2) x += y; }   // row_shr:2
+  if (G >= 8) { const int y = dpp_mov<0x114>(x); if (gl >= 4) x += y; }   // row_shr:4
+  for (int o = 8; o < G; o <<= 1) { const int y = __shfl_up(x, o, G); if (gl >= o) x += y; }
   return x;
 }
 __device__ __forceinline__ float wave_sum(float x) {
-  for (int o = 32; o > 0; o >>= 1) x = x + __shfl_xor(x, o);
-  return x;
-}
-__device__ __forceinline__ int wave_sum_i(int x) {
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
+  return group_reduce(x, 64, [](float a, float b) { return a + b; });
 }
 
 // ---------------------------------------------------------------- coder
@@ -239,19 +270,15 @@ __device__ __forceinline__ void row_quantise_regs(const float (&p)[SPL], int V, 
     if (pv > best) { best = pv; bi = v0 + q; }
   }
   int tot = fs;
-  for (int o = G >> 1; o > 0; o >>= 1) {
-    tot += __shfl_xor(tot, o);
-    const float ob = __shfl_xor(best, o);
-    const int oi = __shfl_xor(bi, o);
+  group_levels(G, [&](auto other) {
+    tot += other(tot);
+    const float ob = other(best);
+    const int oi = other(bi);
     if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-  }
+  });
   const int resid = (int)kTotal - tot;
   const int mine = fs + ((bi >= v0 && bi < v0 + SPL) ? resid : 0);
-  int incl = mine;
-  for (int o = 1; o < G; o <<= 1) {
-    const int y = __shfl_up(incl, o, G);
-    if (gl >= o) incl += y;
-  }
+  const int incl = group_scan(mine, G, gl);
   uint32_t run = (uint32_t)(incl - mine);
 #pragma unroll
   for (int q = 0; q < SPL; q++) {
@@ -305,7 +332,7 @@ __device__ __forceinline__ float row_softmax_regs(float *lr, float *ur, bool mix
     }
     mx = fmaxf(mx, fmaxf(fmaxf(z[q], z[q + 1]), fmaxf(z[q + 2], z[q + 3])));
   }
-  for (int o = G >> 1; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  mx = group_reduce(mx, G, [](float a, float b) { return fmaxf(a, b); });
   // hardware exp2-based exponential and one reciprocal per row: both
   // deterministic, within a few ulp of the correctly rounded values
   float se = 0.0f;
@@ -315,7 +342,7 @@ __device__ __forceinline__ float row_softmax_regs(float *lr, float *ur, bool mix
     for (int c = 0; c < 4; c++) z[q + c] = __expf(z[q + c] - mx);
     se = se + z[q] + z[q + 1] + z[q + 2] + z[q + 3];
   }
-  for (int o = G >> 1; o > 0; o >>= 1) se = se + __shfl_xor(se, o);
+  se = group_reduce(se, G, [](float a, float b) { return a + b; });
   const float rse = 1.0f / se;
   float srow = 0.0f;
 #pragma unroll
@@ -328,8 +355,7 @@ __device__ __forceinline__ float row_softmax_regs(float *lr, float *ur, bool mix
       for (int c = 0; c < 4; c++) srow = fmaf(pr[q + c], df[q + c], srow);
     }
   }
-  if (mix)
-    for (int o = G >> 1; o > 0; o >>= 1) srow = srow + __shfl_xor(srow, o);
+  if (mix) srow = group_reduce(srow, G, [](float a, float b) { return a + b; });
   row_quantise_regs<SPL>(pr, V, G, gl, cdf);
   return srow;
 }
