@@ -623,10 +623,19 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       if (!uniform) {
         pc.mark(3);
         // dz = (P - onehot)/bs (mean loss over the step's rows); dL^m = (1-alpha) dz
-        for (int q = tid; q < bs * V; q += NT) {
-          const int j = q / V, v = q % V, idx = j * VS + v;
-          float dz = (lm[idx] - (v == tgt[j] ? 1.0f : 0.0f)) * inv_bs;
-          lm[idx] = d.static_on ? dz * (1.0f - alpha) : dz;
+        // (four symbols per item; V = 4^k, so rows hold a power-of-two count of items)
+        const int vq = V >> 2, vqs = __builtin_ctz((unsigned)vq);
+        for (int q = tid; q < bs * vq; q += NT) {
+          const int j = q >> vqs, v0 = (q & (vq - 1)) << 2, idx = j * VS + v0;
+          const int tj = tgt[j];
+          const float4 x4 = *reinterpret_cast<const float4 *>(lm + idx);
+          float x[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            const float dz = (x[c] - (v0 + c == tj ? 1.0f : 0.0f)) * inv_bs;
+            x[c] = d.static_on ? dz * (1.0f - alpha) : dz;
+          }
+          *reinterpret_cast<float4 *>(lm + idx) = make_float4(x[0], x[1], x[2], x[3]);
         }
         if (d.static_on && tid == 0) {
           float acc = 0.0f;
