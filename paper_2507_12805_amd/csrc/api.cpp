@@ -205,7 +205,7 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
   d.ES = d.E + 1;
   d.EP = d.E + 4;
   d.HP = d.H[0] + 4;
-  d.CH = 32;
+  d.CH = 32;   // staging width in steps (a power of two)
   int rs = 1;
   while (rs < d.t + d.CH) rs <<= 1;
   d.RS = rs;

@@ -532,10 +532,10 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     for (uint64_t i = 0; i < Lrun; i++) {
       const bool uniform = !d.model_on || i < (uint64_t)t;
       // stage the true tokens of the next CH steps (encode)
-      if (a.mode == 0 && (i % (uint64_t)d.CH) == 0) {
-        const int CH = d.CH;
+      if (a.mode == 0 && (i & (uint64_t)(d.CH - 1)) == 0) {   // (CH a power of two)
+        const int CH = d.CH, chs = __builtin_ctz((unsigned)CH);
         for (int q = tid; q < bs * CH; q += NT) {
-          int j = q / CH, c = q % CH;
+          const int j = q >> chs, c = q & (CH - 1);
           uint64_t pos = i + (uint64_t)c;
           if (pos < bd.L) ring[j * RS + (int)(pos & (uint64_t)mask)] = toks[tok0 + (size_t)j * bd.L + pos];
         }
@@ -548,12 +548,13 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         net.forward(W, i, alpha);
         pc.mark(1);
         // mixer (Eq. 1) + softmax + quantiser: G aligned lanes of one wave per
-        // row, spl symbols each (float4 runs); row reductions are xor
-        // butterflies over the G lanes after a sequential per-lane sum, so
-        // the order is fixed.  Rows are VS = V + 4 floats apart.
-        const int spl = row_spl(V), G = V / spl;
-        for (int j0 = 0; j0 < bs; j0 += NT / G) {
-          const int j = j0 + tid / G, gl = tid % G;
+        // row, spl symbols each (float4 runs); row reductions are symmetric
+        // lane exchanges over the G lanes after a sequential per-lane sum, so
+        // the order is fixed.  Rows are VS = V + 4 floats apart.  (spl and G
+        // are powers of two.)
+        const int spl = row_spl(V), G = V / spl, gs = __builtin_ctz((unsigned)G);
+        for (int j0 = 0; j0 < bs; j0 += NT >> gs) {
+          const int j = j0 + (tid >> gs), gl = tid & (G - 1);
           if (j >= bs) continue;   // a row's lanes are all in or all out
           float *lr = lm + j * VS;
           float *ur = lu + j * VS;
