@@ -531,6 +531,9 @@ struct NetMfma {
       }
       for (int mt = wave; mt < DT; mt += NW) {
         const int dd = 16 * mt + r;
+        // BF16 copy offset of this lane's quad-transposed store for hidden tile
+        // 0; tile ht adds 16 D (the copy's column tiles are D/32 k-steps of 512)
+        const uint32_t w1f_base = KL == 8 ? w1_frag_index(16 * mt + (r & ~3), 4 * g + (lane & 3), D) : 0u;
         int p, e;
         split_k(dd, p, e);
         // X^T fragments of this d tile (B4's B operand)
@@ -575,34 +578,40 @@ struct NetMfma {
               }
             }
           }
-          // B3 over this chunk's hidden units (tiles past the end contribute zero)
+          // B3 over this chunk's hidden units (tiles past the end contribute
+          // zero; a full chunk needs no test)
           if constexpr (KL == 8) {
+            auto b3_bf16 = [&](auto full_chunk) {
+              constexpr bool FULL = decltype(full_chunk)::value;
 #pragma unroll
-            for (int k = 0; k < HCH / 2; k++) {
-              const bool v0 = HCH * hc + 2 * k < HT, v1 = HCH * hc + 2 * k + 1 < HT;
-              float av[8] = {v0 ? w[2 * k].x : 0.0f, v0 ? w[2 * k].y : 0.0f, v0 ? w[2 * k].z : 0.0f,
-                             v0 ? w[2 * k].w : 0.0f, v1 ? w[2 * k + 1].x : 0.0f, v1 ? w[2 * k + 1].y : 0.0f,
-                             v1 ? w[2 * k + 1].z : 0.0f, v1 ? w[2 * k + 1].w : 0.0f};
-              const frag a3 = P::pack(av);
-              if (dpb) {
-                // B3's B fragments from the BF16 copy of dpre (k-steps past the end
-                // clamped; their A operand is zero)
-                const int ks3 = min((HCH * hc) / 2 + k, H / 32 - 1);
+              for (int k = 0; k < HCH / 2; k++) {
+                const bool v0 = FULL || HCH * hc + 2 * k < HT, v1 = FULL || HCH * hc + 2 * k + 1 < HT;
+                float av[8] = {v0 ? w[2 * k].x : 0.0f, v0 ? w[2 * k].y : 0.0f, v0 ? w[2 * k].z : 0.0f,
+                               v0 ? w[2 * k].w : 0.0f, v1 ? w[2 * k + 1].x : 0.0f, v1 ? w[2 * k + 1].y : 0.0f,
+                               v1 ? w[2 * k + 1].z : 0.0f, v1 ? w[2 * k + 1].w : 0.0f};
+                const frag a3 = P::pack(av);
+                if (dpb) {
+                  // B3's B fragments from the BF16 copy of dpre (k-steps past the end
+                  // clamped; their A operand is zero)
+                  const int ks3 = min((HCH * hc) / 2 + k, H / 32 - 1);
 #pragma unroll
-                for (int n = 0; n < MAXT; n++)
-                  acc3[n] = P::mma(a3, *reinterpret_cast<const bf16x8 *>(dpb + ((n * (H / 32) + ks3) * 64 + lane) * 8),
-                                   acc3[n]);
-              } else {
-                const int h0 = 16 * min(HCH * hc + 2 * k, HT - 1) + 4 * g, h1c = 16 * min(HCH * hc + 2 * k + 1, HT - 1) + 4 * g;
+                  for (int n = 0; n < MAXT; n++)
+                    acc3[n] = P::mma(a3, *reinterpret_cast<const bf16x8 *>(dpb + ((n * (H / 32) + ks3) * 64 + lane) * 8),
+                                     acc3[n]);
+                } else {
+                  const int h0 = 16 * min(HCH * hc + 2 * k, HT - 1) + 4 * g, h1c = 16 * min(HCH * hc + 2 * k + 1, HT - 1) + 4 * g;
 #pragma unroll
-                for (int n = 0; n < MAXT; n++) {
-                  float bv[8];
-                  load_run<4>(dpre + (16 * n + r) * HP + h0, bv);
-                  load_run<4>(dpre + (16 * n + r) * HP + h1c, bv + 4);
-                  acc3[n] = P::mma(a3, P::pack(bv), acc3[n]);
+                  for (int n = 0; n < MAXT; n++) {
+                    float bv[8];
+                    load_run<4>(dpre + (16 * n + r) * HP + h0, bv);
+                    load_run<4>(dpre + (16 * n + r) * HP + h1c, bv + 4);
+                    acc3[n] = P::mma(a3, P::pack(bv), acc3[n]);
+                  }
                 }
               }
-            }
+            };
+            if (HCH * (hc + 1) <= HT) b3_bf16(std::true_type{});
+            else b3_bf16(std::false_type{});
           } else {
 #pragma unroll
             for (int m = 0; m < HCH; m++) {
@@ -651,7 +660,7 @@ struct NetMfma {
               const uint32_t yb = quad_perm<0xB1>(odd ? (B & 0xFFFFu) : (B >> 16));
               const uint32_t E = odd ? (ya | (A & 0xFFFF0000u)) : ((A & 0xFFFFu) | (ya << 16));
               const uint32_t F = odd ? (yb | (B & 0xFFFF0000u)) : ((B & 0xFFFFu) | (yb << 16));
-              gu32x2 *cp = (gu32x2 *)(w1f + w1_frag_index(16 * mt + (r & ~3), 16 * (HCH * hc + m) + 4 * g + (int)c, D));
+              gu32x2 *cp = (gu32x2 *)(w1f + w1f_base + (uint32_t)(HCH * hc + m) * ((uint32_t)D << 4));
               *cp = u32x2{E, F};
             }
             if constexpr (adam) {
@@ -660,16 +669,18 @@ struct NetMfma {
             }
           }
         }
-        // embedding-gradient scatter of dX^T[d][j] in 64-bit fixed point
+        // embedding-gradient scatter of dX^T[d][j] in 64-bit fixed point; this
+        // lane's 4 consecutive d are 4 consecutive embedding columns of one
+        // context position (E is a multiple of 8), so one token per row
+        {
+          int p0, e0;
+          split_k(16 * mt + 4 * g, p0, e0);
 #pragma unroll
-        for (int n = 0; n < MAXT; n++) {
-          const int j = 16 * n + r;
+          for (int n = 0; n < MAXT; n++) {
+            unsigned long long *row =
+                reinterpret_cast<unsigned long long *>(demb + token(16 * n + r, p0, i) * d.ES + e0);
 #pragma unroll
-          for (int q = 0; q < 4; q++) {
-            int pq, eq;
-            split_k(16 * mt + 4 * g + q, pq, eq);
-            atomicAdd(reinterpret_cast<unsigned long long *>(demb + token(j, pq, i) * d.ES + eq),
-                      (unsigned long long)to_fixed(acc3[n][q]));
+            for (int q = 0; q < 4; q++) atomicAdd(row + q, (unsigned long long)to_fixed(acc3[n][q]));
           }
         }
       }
