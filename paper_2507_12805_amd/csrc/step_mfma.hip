@@ -95,7 +95,10 @@ __device__ __forceinline__ void load_strided(const F *p, int stride, float *v) {
 
 }  // namespace
 
-template <int NT, class P, int MAXT, bool ADAM>
+// F1N: the F1 unit shape, 4 column tiles x MR1 row tiles (F1N = 4, for hidden
+// widths in multiples of 64) or 2 x 1 (F1N = 2); one shape per kernel keeps
+// the other's registers out of its allocation
+template <int NT, class P, int MAXT, bool ADAM, int F1N>
 struct NetMfma {
   static constexpr int NW = NT / 64;
   static constexpr int KS = P::KS, KL = P::KL;   // MAXT = bs / 16 row tiles
@@ -275,59 +278,64 @@ struct NetMfma {
     const int H = d.H[0], HP = d.HP, V = d.V, D = d.D;
     const int nmod = d.static_on ? 2 : 1;
     drain_stores();
-    // F1: X W1 + b1, ReLU.  A unit is NC1 column tiles x MR1 row tiles of one
-    // model: each gathered X fragment feeds NC1 MFMAs, so X is gathered
-    // H/(16 NC1) times per model.  Column tiles past the end repeat the last
-    // one and are not stored.
-    {
-      const int HT = H / 16, CG = (HT + NC1 - 1) / NC1, RG = MAXT / MR1;
+    // F1: X W1 + b1, ReLU.  A unit is NC column tiles x MR row tiles of one
+    // model: each gathered X fragment feeds NC MFMAs, so X is gathered
+    // H/(16 NC) times per model.  NC = 4, MR = MR1 when the column tiles come
+    // in fours (F1N = 4), else NC = 2, MR = 1 (more units, no repeated columns); column
+    // tiles past the end repeat the last one and are not stored.  Each output
+    // tile is one chain over the k-steps in order, whatever the unit shape.
+    auto f1 = [&](auto nc_c, auto mr_c) {
+      constexpr int NC = decltype(nc_c)::value, MR = decltype(mr_c)::value;
+      const int HT = H / 16, CG = (HT + NC - 1) / NC, RG = MAXT / MR;
       const int units = nmod * CG * RG;
       for (int u = wave; u < units; u += NW) {
         const int model = u / (CG * RG), rem = u - model * (CG * RG), cg = rem / RG, rg = rem - cg * RG;
         const gfloat *Wm = glb(model ? a.stat : W);
         const float *em = lds_f(model ? a.lay.embs : a.lay.emb);
-        int ncol[NC1];
-        float bias[NC1];
+        int ncol[NC];
+        float bias[NC];
 #pragma unroll
-        for (int c = 0; c < NC1; c++) {
-          ncol[c] = min(cg * NC1 + c, HT - 1);
+        for (int c = 0; c < NC; c++) {
+          ncol[c] = min(cg * NC + c, HT - 1);
           bias[c] = Wm[d.off_b[0] + 16 * ncol[c] + r];
         }
-        f32x4 acc[MR1][NC1];
+        f32x4 acc[MR][NC];
 #pragma unroll
-        for (int mm = 0; mm < MR1; mm++)
+        for (int mm = 0; mm < MR; mm++)
 #pragma unroll
-          for (int c = 0; c < NC1; c++) acc[mm][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          for (int c = 0; c < NC; c++) acc[mm][c] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         auto xfrag = [&](int mm, int ks) {
           int p, e;
           split_k(ks * KS + g * KL, p, e);
           float av[KL];
-          load_run<KL>(em + token(16 * (rg * MR1 + mm) + r, p, i) * d.EP + e, av);
+          load_run<KL>(em + token(16 * (rg * MR + mm) + r, p, i) * d.EP + e, av);
           return P::pack(av);
         };
         if constexpr (KL == 8) {
           // BF16: one 16-byte load per lane, k-step and column tile from the fragment-ordered copy
           const gfrag *src = ((const gfrag *)(model ? a.s1f : w1f)) + lane;
           const int kst = D / KS;
-          stream2<MR1, NC1, false, 2, frag>(kst, acc,
+          stream2<MR, NC, false, 2, frag>(kst, acc,
               [&](int ks, int c, frag &b) { b = src[((size_t)ncol[c] * kst + ks) * 64]; }, xfrag);
         } else {
           const gfloat *W1 = Wm + d.off_W[0] + r + (size_t)(g * KL) * H;
-          stream2<MR1, NC1, false, 4, RawF>(D / KS, acc,
+          stream2<MR, NC, false, 4, RawF>(D / KS, acc,
               [&](int ks, int c, RawF &b) { load_strided<KL>(W1 + 16 * ncol[c] + (size_t)ks * KS * H, H, b.v); }, xfrag);
         }
         float *out = lds_f(model ? a.lay.dh[0] : a.lay.act[0]);
 #pragma unroll
-        for (int c = 0; c < NC1; c++) {
-          if (cg * NC1 + c >= HT) break;
+        for (int c = 0; c < NC; c++) {
+          if (cg * NC + c >= HT) break;
 #pragma unroll
-          for (int mm = 0; mm < MR1; mm++)
+          for (int mm = 0; mm < MR; mm++)
 #pragma unroll
             for (int q = 0; q < 4; q++)
-              out[(16 * (rg * MR1 + mm) + 4 * g + q) * HP + 16 * ncol[c] + r] = fmaxf(acc[mm][c][q] + bias[c], 0.0f);
+              out[(16 * (rg * MR + mm) + 4 * g + q) * HP + 16 * ncol[c] + r] = fmaxf(acc[mm][c][q] + bias[c], 0.0f);
         }
       }
-    }
+    };
+    if constexpr (F1N == 4) f1(std::integral_constant<int, NC1>{}, std::integral_constant<int, MR1>{});
+    else f1(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
     __syncthreads();
     pc->mark(7);
     // F2: H1 W2 + b2 -> logits
@@ -557,12 +565,19 @@ struct NetMfma {
           // B4 (LDS operands only)
           f32x4 acc4[HCH];
 #pragma unroll
-          for (int m = 0; m < HCH; m++) {
-            const int ht = min(HCH * hc + m, HT - 1);
-            acc4[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          for (int m = 0; m < HCH; m++) acc4[m] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          auto b4 = [&](auto full_chunk) {
+            constexpr bool FULL = decltype(full_chunk)::value;
 #pragma unroll
-            for (int kb = 0; kb < KB; kb++) acc4[m] = P::mma(dpre_frag(ht, kb), bf[kb], acc4[m]);
-          }
+            for (int m = 0; m < HCH; m++) {
+              if (!FULL && HCH * hc + m >= HT) break;   // (tiles past the end are neither used nor stored)
+              const int ht = HCH * hc + m;
+#pragma unroll
+              for (int kb = 0; kb < KB; kb++) acc4[m] = P::mma(dpre_frag(ht, kb), bf[kb], acc4[m]);
+            }
+          };
+          if (HCH * (hc + 1) <= HT) b4(std::true_type{});
+          else b4(std::false_type{});
           // hidden-bias gradient sum_j dpre[j][h] (BF16): the wave of d tile 0
           // multiplies the dpre^T fragments by a ones fragment (column 0)
           if (KL == 8 && mt == 0) {
@@ -586,6 +601,7 @@ struct NetMfma {
 #pragma unroll
               for (int k = 0; k < HCH / 2; k++) {
                 const bool v0 = FULL || HCH * hc + 2 * k < HT, v1 = FULL || HCH * hc + 2 * k + 1 < HT;
+                if (!v0) break;   // both tiles past the end
                 float av[8] = {v0 ? w[2 * k].x : 0.0f, v0 ? w[2 * k].y : 0.0f, v0 ? w[2 * k].z : 0.0f,
                                v0 ? w[2 * k].w : 0.0f, v1 ? w[2 * k + 1].x : 0.0f, v1 ? w[2 * k + 1].y : 0.0f,
                                v1 ? w[2 * k + 1].z : 0.0f, v1 ? w[2 * k + 1].w : 0.0f};
@@ -727,36 +743,45 @@ hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStrea
   return hipGetLastError();
 }
 
-template <int NT, class P, int MT, bool ADAM>
+template <int NT, class P, int MT, bool ADAM, int F1N>
 __global__ __launch_bounds__(NT) void step_mfma_kernel(const StepArgs *__restrict__ args) {
   extern __shared__ __align__(16) unsigned char lds[];
   const StepArgs &a = *args;
-  NetMfma<NT, P, MT, ADAM> net(a, lds);
+  NetMfma<NT, P, MT, ADAM, F1N> net(a, lds);
   run_blocks<NT>(a, lds, net);
 }
 
-template <int NT, class P, int MT, bool ADAM>
+template <int NT, class P, int MT, bool ADAM, int F1N>
 hipError_t launch_one(const StepArgs *a_dev, int grid, size_t lds, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_mfma_kernel<NT, P, MT, ADAM>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&step_mfma_kernel<NT, P, MT, ADAM, F1N>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((step_mfma_kernel<NT, P, MT, ADAM>), dim3(grid), dim3(NT), lds, st, a_dev);
+  hipLaunchKernelGGL((step_mfma_kernel<NT, P, MT, ADAM, F1N>), dim3(grid), dim3(NT), lds, st, a_dev);
   return hipGetLastError();
 }
 
-template <int NT, class P, bool ADAM>
+template <int NT, class P, bool ADAM, int F1N>
 hipError_t launch_mt(const StepArgs *a_dev, int grid, int mt, size_t lds, hipStream_t st) {
-  if (mt == 2) return launch_one<NT, P, 2, ADAM>(a_dev, grid, lds, st);
-  if (mt == 4) return launch_one<NT, P, 4, ADAM>(a_dev, grid, lds, st);
-  if (mt == 6) return launch_one<NT, P, 6, ADAM>(a_dev, grid, lds, st);
-  if (mt == 8) return launch_one<NT, P, 8, ADAM>(a_dev, grid, lds, st);
+  if (mt == 2) return launch_one<NT, P, 2, ADAM, F1N>(a_dev, grid, lds, st);
+  if (mt == 4) return launch_one<NT, P, 4, ADAM, F1N>(a_dev, grid, lds, st);
+  if (mt == 6) return launch_one<NT, P, 6, ADAM, F1N>(a_dev, grid, lds, st);
+  if (mt == 8) return launch_one<NT, P, 8, ADAM, F1N>(a_dev, grid, lds, st);
   return hipErrorInvalidValue;
 }
 
+template <int NT, class P, bool ADAM>
+hipError_t launch_f1(const StepArgs *a_dev, int grid, int mt, bool f1_fours, size_t lds, hipStream_t st) {
+  return f1_fours ? launch_mt<NT, P, ADAM, 4>(a_dev, grid, mt, lds, st) : launch_mt<NT, P, ADAM, 2>(a_dev, grid, mt, lds, st);
+}
+
 template <int NT>
-hipError_t launch_nt(const StepArgs *a_dev, int grid, bool bf16, bool adam, int mt, size_t lds, hipStream_t st) {
-  if (bf16) return adam ? launch_mt<NT, MmaBf16, true>(a_dev, grid, mt, lds, st) : launch_mt<NT, MmaBf16, false>(a_dev, grid, mt, lds, st);
-  return adam ? launch_mt<NT, MmaF32, true>(a_dev, grid, mt, lds, st) : launch_mt<NT, MmaF32, false>(a_dev, grid, mt, lds, st);
+hipError_t launch_nt(const StepArgs *a_dev, int grid, bool bf16, bool adam, int mt, bool f1_fours, size_t lds,
+                     hipStream_t st) {
+  if (bf16)
+    return adam ? launch_f1<NT, MmaBf16, true>(a_dev, grid, mt, f1_fours, lds, st)
+                : launch_f1<NT, MmaBf16, false>(a_dev, grid, mt, f1_fours, lds, st);
+  return adam ? launch_f1<NT, MmaF32, true>(a_dev, grid, mt, f1_fours, lds, st)
+              : launch_f1<NT, MmaF32, false>(a_dev, grid, mt, f1_fours, lds, st);
 }
 
 // a_dev: a device copy of `a` (kernel arguments are read through it).
@@ -768,8 +793,9 @@ hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, 
   const size_t lds = (size_t)a.lay.total;
   const int mt = a.d.bs / 16;
   const bool adam = a.d.optimizer == 1;
-  if (nt == 256) return launch_nt<256>(a_dev, grid, bf16, adam, mt, lds, st);
-  if (nt == 512) return launch_nt<512>(a_dev, grid, bf16, adam, mt, lds, st);
+  const bool f1_fours = (a.d.H[0] / 16) % 4 == 0;
+  if (nt == 256) return launch_nt<256>(a_dev, grid, bf16, adam, mt, f1_fours, lds, st);
+  if (nt == 512) return launch_nt<512>(a_dev, grid, bf16, adam, mt, f1_fours, lds, st);
   return hipErrorInvalidValue;
 }
 
