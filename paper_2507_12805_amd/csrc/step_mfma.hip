@@ -35,9 +35,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) u32x2 gu32x2;
 
-// the bits of the BF16 rounding (nearest even) of v
-__device__ __forceinline__ uint32_t bf16_bits(float v) {
-  return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)v);
+// the BF16 roundings (nearest even) of lo and hi as one 32-bit word, lo in
+// the low half (one packed conversion)
+__device__ __forceinline__ uint32_t bf16x2_bits(float lo, float hi) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 // x taken from the lane of this lane's quad that the DPP quad_perm pattern
@@ -663,19 +666,19 @@ struct NetMfma {
               // values inside the quad leaves lane c with h = 4g + c at those
               // 4 d, which are 8 contiguous bytes of the fragment-ordered copy
               const uint32_t c = lane & 3u;
-              const uint32_t p01 = bf16_bits(wv[0]) | (bf16_bits(wv[1]) << 16);
-              const uint32_t p23 = bf16_bits(wv[2]) | (bf16_bits(wv[3]) << 16);
+              const uint32_t p01 = bf16x2_bits(wv[0], wv[1]), p23 = bf16x2_bits(wv[2], wv[3]);
               // lanes c and c ^ 2 swap a dword: afterwards lane c = 2s + t holds
               // A = (x[t][2s], x[t][2s+1]) and B = (x[2+t][2s], x[2+t][2s+1]),
               // x[c'][q] being value q of quad lane c'
               const uint32_t x2 = quad_perm<0x4E>(c < 2 ? p23 : p01);
               const uint32_t A = c < 2 ? p01 : x2, B = c < 2 ? x2 : p23;
-              // lanes c and c ^ 1 swap a half of each: E = (x[0][c], x[1][c]), F = (x[2][c], x[3][c])
-              const bool odd = c & 1u;
-              const uint32_t ya = quad_perm<0xB1>(odd ? (A & 0xFFFFu) : (A >> 16));
-              const uint32_t yb = quad_perm<0xB1>(odd ? (B & 0xFFFFu) : (B >> 16));
-              const uint32_t E = odd ? (ya | (A & 0xFFFF0000u)) : ((A & 0xFFFFu) | (ya << 16));
-              const uint32_t F = odd ? (yb | (B & 0xFFFF0000u)) : ((B & 0xFFFFu) | (yb << 16));
+              // lanes c and c ^ 1 swap a half of each: an odd lane sends its low
+              // half and keeps its high one, an even lane the reverse; one byte
+              // permutation then joins kept and received halves into
+              // E = (x[0][c], x[1][c]), F = (x[2][c], x[3][c])
+              const uint32_t sh = (c & 1u) ? 0u : 16u, sel = (c & 1u) ? 0x03020504u : 0x05040100u;
+              const uint32_t ya = quad_perm<0xB1>(A >> sh), yb = quad_perm<0xB1>(B >> sh);
+              const uint32_t E = __builtin_amdgcn_perm(ya, A, sel), F = __builtin_amdgcn_perm(yb, B, sel);
               gu32x2 *cp = (gu32x2 *)(w1f + w1f_base + (uint32_t)(HCH * hc + m) * ((uint32_t)D << 4));
               *cp = u32x2{E, F};
             }
