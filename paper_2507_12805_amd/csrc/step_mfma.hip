@@ -315,11 +315,18 @@ struct NetMfma {
           return P::pack(av);
         };
         if constexpr (KL == 8) {
-          // BF16: one 16-byte load per lane, k-step and column tile from the fragment-ordered copy
-          const gfrag *src = ((const gfrag *)(model ? a.s1f : w1f)) + lane;
-          const int kst = D / KS;
+          // BF16: one 16-byte load per lane, k-step and column tile from the
+          // fragment-ordered copy, through a buffer descriptor over the copy
+          // (the lane's slot as the vector offset, the tile and k-step as a
+          // scalar one; a load past the copy would read 0)
+          const uint16_t *copy = model ? a.s1f : w1f;
+          const __amdgpu_buffer_rsrc_t rs =
+              __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(copy), (short)0, D * H * 2, 0x00020000);
+          const int kst = D / KS, voff = lane * 16;
           stream2<MR, NC, false, 2, frag>(kst, acc,
-              [&](int ks, int c, frag &b) { b = src[((size_t)ncol[c] * kst + ks) * 64]; }, xfrag);
+              [&](int ks, int c, frag &b) {
+                b = __builtin_bit_cast(frag, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, (ncol[c] * kst + ks) * 1024, 0));
+              }, xfrag);
         } else {
           const gfloat *W1 = Wm + d.off_W[0] + r + (size_t)(g * KL) * H;
           stream2<MR, NC, false, 4, RawF>(D / KS, acc,
