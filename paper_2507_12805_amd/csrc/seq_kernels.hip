@@ -16,79 +16,127 @@ namespace {
 __device__ __forceinline__ uint32_t code_of(uint32_t c) { return ((c >> 1) ^ (c >> 2)) & 3u; }
 __device__ __forceinline__ bool is_acgt(uint32_t c) { return c == 'A' || c == 'C' || c == 'G' || c == 'T'; }
 
-constexpr int kTokPerThread = 4;
+constexpr int kTokPerThread = 4;   // per-block tokeniser
 constexpr int kTokPerWG = 256 * kTokPerThread;
 
 }  // namespace
 
 // ---------------------------------------------------------------- GskE
-// Direct ASCII -> tokens (no N allowed).  Each workgroup stages the bytes of
-// its 1024 tokens in LDS with coalesced loads, validates them, then every
-// thread builds 4 tokens and writes them with one 32-bit store when the
-// destination is aligned.
-__global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__restrict__ in, uint64_t n, int s, int k,
+// Direct ASCII -> tokens (no N allowed), one instance per (S, K).  A
+// workgroup owns 4096 tokens: it stages their bytes in LDS with 16-byte
+// loads in a 16-byte aligned frame (bytes outside [0, n) are never read; a
+// word that crosses either end is read byte by byte), validates them, then
+// every thread builds 16 tokens from the dwords of its window and writes them
+// with one 16-byte store when the destination run is whole and aligned.
+// Validation of a whole word: the 2-bit codes of its 4 bytes mapped back to
+// ASCII by one byte permutation ('A' 'C' 'G' 'T' at selectors 0..3) must give
+// the word again.
+constexpr int kSkTokPerThread = 16;
+constexpr int kSkTokPerWG = 256 * kSkTokPerThread;
+constexpr int kSkBuf = kSkTokPerWG * 4 + 32;   // s <= 4, plus the k - s tail and the frame offset
+
+__device__ __forceinline__ uint32_t codes4(uint32_t w) { return ((w >> 1) ^ (w >> 2)) & 0x03030303u; }
+__device__ __forceinline__ bool acgt4(uint32_t w) { return __builtin_amdgcn_perm(0u, 0x54474341u, codes4(w)) == w; }
+
+template <int S, int K>
+__global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__restrict__ in, uint64_t n,
                                                            uint8_t *__restrict__ tok, uint64_t l, int *err) {
-  __shared__ uint8_t buf[kTokPerWG * 4 + 16];
-  const uint64_t j0 = (uint64_t)blockIdx.x * kTokPerWG;
-  const uint64_t b0 = j0 * (uint64_t)s;
-  uint64_t b1 = (j0 + kTokPerWG) * (uint64_t)s + (uint64_t)(k - s);
+  __shared__ __align__(16) uint8_t buf[kSkBuf + 16];
+  const uint64_t j0 = (uint64_t)blockIdx.x * kSkTokPerWG;
+  const uint64_t b0 = j0 * (uint64_t)S;
+  uint64_t b1 = (j0 + kSkTokPerWG) * (uint64_t)S + (uint64_t)(K - S);
   if (b1 > n || blockIdx.x == gridDim.x - 1) b1 = n;
-  const int nbytes = (int)(b1 - b0);
-  int bad = 0;
-  // 4-byte loads from a 4-byte aligned address; bytes outside [0, n) are
-  // read one by one and never touched past the end
-  const int pre = (int)(reinterpret_cast<uintptr_t>(in + b0) & 3u);
+  // frame: buf[i] holds input byte a0 + i, a0 = b0 rounded down to 16 bytes
+  // of the input address; bytes of the frame outside [b0, b1) are not used
+  const int pre = (int)(reinterpret_cast<uintptr_t>(in + b0) & 15u);
   const int64_t a0 = (int64_t)b0 - pre;   // may be < 0 only when pre > b0
-  const int nw = (pre + nbytes + 3) >> 2;
-  for (int w = threadIdx.x; w < nw; w += 256) {
-    int64_t addr = a0 + 4 * (int64_t)w;
-    uint32_t v;
-    if (addr >= 0 && (uint64_t)addr + 4 <= n) {
-      v = *reinterpret_cast<const uint32_t *>(in + addr);
+  const int span = pre + (int)(b1 - b0);
+  const int nq = (span + 15) >> 4;
+  int bad = 0;
+  for (int w = threadIdx.x; w < nq; w += 256) {
+    const int64_t addr = a0 + 16 * (int64_t)w;
+    uint32_t v[4];
+    const bool whole = addr >= 0 && (uint64_t)addr + 16 <= n;
+    if (whole) {
+      const uint4 x = *reinterpret_cast<const uint4 *>(in + addr);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
     } else {
-      v = 0;
-      for (int q = 0; q < 4; q++)
-        if (addr + q >= 0 && (uint64_t)(addr + q) < n) v |= (uint32_t)in[addr + q] << (8 * q);
+      for (int q = 0; q < 4; q++) {
+        v[q] = 0;
+        for (int c = 0; c < 4; c++) {
+          const int64_t ad = addr + 4 * q + c;
+          if (ad >= 0 && (uint64_t)ad < n) v[q] |= (uint32_t)in[ad] << (8 * c);
+        }
+      }
     }
+    *reinterpret_cast<uint4 *>(buf + 16 * w) = make_uint4(v[0], v[1], v[2], v[3]);
+    if (whole && 16 * w >= pre && 16 * w + 16 <= span) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      int pos = 4 * w + q - pre;   // byte index relative to b0
-      if (pos >= 0 && pos < nbytes) {
-        uint32_t c = (v >> (8 * q)) & 0xFFu;
-        bad |= !is_acgt(c);
-        buf[pos] = (uint8_t)c;
+      for (int q = 0; q < 4; q++) bad |= !acgt4(v[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; q++) {
+        const int pos = 16 * w + q;   // frame index
+        if (pos >= pre && pos < span) bad |= !is_acgt((v[q >> 2] >> (8 * (q & 3))) & 0xFFu);
       }
     }
   }
   if (bad) atomicOr(err, 1);
   __syncthreads();
-  const uint64_t jt = j0 + (uint64_t)threadIdx.x * kTokPerThread;
-  uint32_t packed = 0;
-  int cnt = 0;
+  // this thread's 16 tokens: bytes [first, first + 15 S + K) of the frame
+  const int t16 = threadIdx.x * kSkTokPerThread;
+  const uint64_t jt = j0 + (uint64_t)t16;
+  if (jt >= l) return;
+  const int cnt = (int)min((uint64_t)kSkTokPerThread, l - jt);
+  const int first = pre + t16 * S;
+  const int fw = first >> 2, sh0 = first & 3;
+  constexpr int NW = ((kSkTokPerThread - 1) * S + K + 3 + 3) / 4;   // dwords covering any sh0
+  uint32_t cw[NW];
+  const uint32_t *bw = reinterpret_cast<const uint32_t *>(buf);
 #pragma unroll
-  for (int q = 0; q < kTokPerThread; q++) {
-    uint64_t j = jt + (uint64_t)q;
-    if (j < l) {
-      int base = (int)((j - j0) * (uint64_t)s);
-      uint32_t e = 0;
-      for (int m = 0; m < k; m++) e = (e << 2) | code_of(buf[base + m]);
-      packed |= e << (8 * q);
-      cnt++;
-    }
+  for (int q = 0; q < NW; q++) cw[q] = codes4(bw[fw + q]);
+  auto code_at = [&](int i) {   // i relative to `first`
+    const int bi = sh0 + i;
+    return (cw[bi >> 2] >> (8 * (bi & 3))) & 3u;
+  };
+  uint32_t packed[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int q = 0; q < kSkTokPerThread; q++) {
+    uint32_t e = 0;
+#pragma unroll
+    for (int m = 0; m < K; m++) e = (e << 2) | code_at(q * S + m);
+    packed[q >> 2] |= e << (8 * (q & 3));
   }
-  if (cnt == kTokPerThread && ((reinterpret_cast<uintptr_t>(tok + jt) & 3u) == 0)) {
-    *reinterpret_cast<uint32_t *>(tok + jt) = packed;
+  if (cnt == kSkTokPerThread && ((reinterpret_cast<uintptr_t>(tok + jt) & 15u) == 0)) {
+    *reinterpret_cast<uint4 *>(tok + jt) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
   } else {
-    for (int q = 0; q < cnt; q++) tok[jt + q] = (uint8_t)(packed >> (8 * q));
+    for (int q = 0; q < cnt; q++) tok[jt + q] = (uint8_t)(packed[q >> 2] >> (8 * (q & 3)));
   }
+}
+
+template <int S, int K>
+hipError_t launch_sk(const uint8_t *in, uint64_t n, uint8_t *tok, uint64_t l, int *err, hipStream_t st) {
+  const uint64_t grid = l ? (l + kSkTokPerWG - 1) / kSkTokPerWG : 1;
+  hipLaunchKernelGGL((skmer_direct_kernel<S, K>), dim3((unsigned)grid), dim3(256), 0, st, in, n, tok, l, err);
+  return hipGetLastError();
 }
 
 hipError_t launch_skmer_direct(const uint8_t *in, uint64_t n, int s, int k, uint8_t *tok, uint64_t l, int *err,
                                hipStream_t st) {
   if (n == 0) return hipSuccess;
-  uint64_t grid = l ? (l + kTokPerWG - 1) / kTokPerWG : 1;
-  hipLaunchKernelGGL(skmer_direct_kernel, dim3((unsigned)grid), dim3(256), 0, st, in, n, s, k, tok, l, err);
-  return hipGetLastError();
+  switch (k * 8 + s) {
+    case 1 * 8 + 1: return launch_sk<1, 1>(in, n, tok, l, err, st);
+    case 2 * 8 + 1: return launch_sk<1, 2>(in, n, tok, l, err, st);
+    case 2 * 8 + 2: return launch_sk<2, 2>(in, n, tok, l, err, st);
+    case 3 * 8 + 1: return launch_sk<1, 3>(in, n, tok, l, err, st);
+    case 3 * 8 + 2: return launch_sk<2, 3>(in, n, tok, l, err, st);
+    case 3 * 8 + 3: return launch_sk<3, 3>(in, n, tok, l, err, st);
+    case 4 * 8 + 1: return launch_sk<1, 4>(in, n, tok, l, err, st);
+    case 4 * 8 + 2: return launch_sk<2, 4>(in, n, tok, l, err, st);
+    case 4 * 8 + 3: return launch_sk<3, 4>(in, n, tok, l, err, st);
+    case 4 * 8 + 4: return launch_sk<4, 4>(in, n, tok, l, err, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ------------------------------------------------------------- input scan
