@@ -90,7 +90,9 @@ __global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__rest
   const int cnt = (int)min((uint64_t)kSkTokPerThread, l - jt);
   const int first = pre + t16 * S;
   const int fw = first >> 2, sh0 = first & 3;
-  constexpr int NW = ((kSkTokPerThread - 1) * S + K + 3 + 3) / 4;   // dwords covering any sh0
+  // dwords covering any sh0 (at least 6 for S = 1: its realignment reads one past the last needed)
+  constexpr int NW0 = ((kSkTokPerThread - 1) * S + K + 3 + 3) / 4;
+  constexpr int NW = (S == 1 && NW0 < 6) ? 6 : NW0;
   uint32_t cw[NW];
   const uint32_t *bw = reinterpret_cast<const uint32_t *>(buf);
 #pragma unroll
@@ -100,12 +102,28 @@ __global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__rest
     return (cw[bi >> 2] >> (8 * (bi & 3))) & 3u;
   };
   uint32_t packed[4] = {0u, 0u, 0u, 0u};
+  if constexpr (S == 1) {
+    // consecutive tokens: realign the code bytes to the first base, then
+    // the 4 tokens of output dword i are sum_m (codes i*4 + m .. + 3) << 2 (K - 1 - m),
+    // each byte's token staying below 256 (no carries between bytes)
+    uint32_t al[5];
 #pragma unroll
-  for (int q = 0; q < kSkTokPerThread; q++) {
-    uint32_t e = 0;
+    for (int q = 0; q < 5; q++) al[q] = __builtin_amdgcn_alignbyte(cw[q + 1], cw[q], (uint32_t)sh0);
 #pragma unroll
-    for (int m = 0; m < K; m++) e = (e << 2) | code_at(q * S + m);
-    packed[q >> 2] |= e << (8 * (q & 3));
+    for (int i = 0; i < 4; i++) {
+      uint32_t v = 0;
+#pragma unroll
+      for (int m = 0; m < K; m++) v |= __builtin_amdgcn_alignbyte(al[i + 1], al[i], (uint32_t)m) << (2 * (K - 1 - m));
+      packed[i] = v;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kSkTokPerThread; q++) {
+      uint32_t e = 0;
+#pragma unroll
+      for (int m = 0; m < K; m++) e = (e << 2) | code_at(q * S + m);
+      packed[q >> 2] |= e << (8 * (q & 3));
+    }
   }
   if (cnt == kSkTokPerThread && ((reinterpret_cast<uintptr_t>(tok + jt) & 15u) == 0)) {
     *reinterpret_cast<uint4 *>(tok + jt) = make_uint4(packed[0], packed[1], packed[2], packed[3]);
