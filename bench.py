@@ -4,16 +4,19 @@ One step = compress + decompress of the whole workload through the C ABI
 (GskE tokens -> per-block online-learned probabilities -> arithmetic
 coder, and back), input already resident in HBM. Prints ONE JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload static64]
+    python bench.py [--steps K] [--warmup W] [--workload uneven1g]
                     [--precision fp32|bf16] [--schedule batched|plain]
 
-The default workload is the 64 MiB synthetic DNA of 16 equal blocks,
-(1,3)-mers, frozen static model mixed with the dynamic model (Eq. 1),
-hidden width 128. ``value`` is Eq. 4's throughput, input bases / (CT + DT),
-in MB/s with MB = 10^6 bases. ``roofline`` prices the step kernel (the
-learning + coding loop, >99% of the time) with HIP-event timings;
-``cpu_baseline`` is the FP64 oracle on a bounded sample of the same
-workload on the host cores.
+The default workload is 1 GiB of synthetic DNA in 256 blocks of lognormal
+length (median 2 MiB, sigma 1), (3,3)-mers, context 32, embedding 16, one
+hidden layer of 32, SGD 1e-3, all blocks in one persistent launch with the
+model GEMMs in BF16 on the matrix cores. ``value`` is Eq. 4's throughput,
+input bases / (CT + DT), in MB/s with MB = 10^6 bases.  Beside it: the
+plain per-block FP32 form (one launch per block) on a stated sample of
+blocks, the container size against the FP64 oracle's on the whole input
+(tests/golden), ``roofline`` for the step kernel (the learning + coding
+loop, >99% of the time) from HIP-event timings, and ``cpu_baseline``, the
+FP64 oracle on a bounded sample of the same workload on the host cores.
 """
 import argparse
 import json
@@ -32,8 +35,8 @@ PEAK = {"fp32_alu_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0}
 
 # Sources that define the step kernel; a stored HBM-traffic measurement is
 # reported only while their hash matches the one it was taken with.
-KERNEL_SOURCES = ["paper_2507_12805_amd/csrc/step_mfma.hip", "paper_2507_12805_amd/csrc/step_common.h",
-                  "paper_2507_12805_amd/csrc/pmklc_internal.h"]
+KERNEL_SOURCES = ["paper_2507_12805_amd/csrc/step_mfma.h", "paper_2507_12805_amd/csrc/step_mfma_inst.hip",
+                  "paper_2507_12805_amd/csrc/step_common.h", "paper_2507_12805_amd/csrc/pmklc_internal.h"]
 
 
 def kernel_source_hash() -> str:
@@ -70,6 +73,25 @@ def flops_per_row(cfg: dict) -> int:
     if cfg.get("selector") == "spum_dm":
         f += fwd
     return f
+
+
+def oracle_golden(name: str, data: np.ndarray):
+    """The FP64 oracle's container size for the whole workload input
+    (tests/golden/<name>_oracle.txt, written by the oracle alone), when the
+    input's SHA-256 matches."""
+    import hashlib
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                key, val = line.split(None, 1)
+                kv[key] = val.strip()
+    if kv.get("input_sha256") != hashlib.sha256(memoryview(data)).hexdigest():
+        return None
+    return int(kv["container_bytes"]), float(kv["bits_per_base"])
 
 
 def workload(name: str, scale: float = 1.0):
@@ -193,15 +215,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="static64", choices=["static64", "small256k", "uneven1g", "archive"])
+    ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive"])
     ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp32_valu"])
     ap.add_argument("--no-fp32-compare", action="store_true",
-                    help="skip the one batched FP32 compress+decompress measured beside the main precision")
+                    help="skip the batched FP32 compress+decompress measured beside the main precision")
     ap.add_argument("--schedule", default="batched", choices=["batched", "plain"])
-    ap.add_argument("--cpu-sample-bytes", type=int, default=1 << 19)
+    ap.add_argument("--cpu-sample-bytes", type=int, default=1 << 22)
+    ap.add_argument("--cpu-sample-blocks", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain-blocks", type=int, default=2,
+    ap.add_argument("--plain-blocks", type=int, default=4,
                     help="blocks compressed with one launch per block for the plain-FP32 comparison (0 = skip)")
     ap.add_argument("--encoder", action="store_true",
                     help="measure the standalone GskE encoder on a Table-8-sized sequence instead")
@@ -286,39 +309,61 @@ def main():
                      "rows_per_launch": int(tim_c["model_rows"]), "max_steps": int(tim_c["max_steps"])},
     }
     res["threads_per_workgroup"] = int(tim_c["threads"])
-    if not a.no_fp32_compare and a.precision != "fp32":
-        cf = dict(cfg, precision="fp32")
+    gold = oracle_golden(a.workload, data) if a.scale == 1.0 else None
+    if gold:
+        res["oracle_full"] = {"container_bytes": gold[0], "bits_per_base": gold[1],
+                              "gpu_container_bytes": len(blob), "ratio_rel_diff": round(len(blob) / gold[0] - 1.0, 6),
+                              "source": f"tests/golden/{a.workload}_oracle.txt (FP64 oracle on the whole input)"}
+    # the sample of blocks for the per-block comparisons: the first few blocks
+    if "block_len" in cfg:
+        lens = [int(v) for v in cfg["block_len"]]
+    else:
+        nb = cfg.get("n_blocks", 1)
+        lens = [n // nb] * (nb - 1) + [n - (n // nb) * (nb - 1)]
+    kb = min(a.plain_blocks, len(lens))
+    sub_n = sum(lens[:kb])
+    sub = x[:sub_n]
+    sub_cfg = {q: v for q, v in cfg.items() if q not in ("block_len", "file_blocks", "smp_ppm")}
+    sub_cfg.update(block_len=lens[:kb], n_blocks=kb)
+    sample_desc = f"blocks 0-{kb - 1} of {len(lens)} ({sub_n} bases), model passing off"
+    if kb and a.schedule == "batched":
+        cp = dict(sub_cfg, precision="fp32", schedule="plain")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b32 = P.compress(cf, x, static=static, workspace=ws)
+        bp = P.compress(cp, sub, static=static, workspace=ws)
         t1 = time.perf_counter()
-        o32 = P.decompress(b32, static=static, workspace=wsd, out=out)
+        op = P.decompress(bp, static=static, workspace=wsd)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        res["fp32_batched"] = {"value": round(n / (t2 - t0) / 1e6, 4), "compress_MBps": round(n / (t1 - t0) / 1e6, 4),
-                               "decompress_MBps": round(n / (t2 - t1) / 1e6, 4),
-                               "ratio_bits_per_base": round(8.0 * len(b32) / n, 5),
-                               "roundtrip_bit_exact": bool((o32[:n] == x).all()),
-                               "bf16_ratio_cost_rel": round(len(blob) / len(b32) - 1.0, 6)}
-        log(f"fp32 batched: compress {t1 - t0:.3f}s decompress {t2 - t1:.3f}s")
-    if a.plain_blocks and a.schedule == "batched" and "block_len" not in cfg:
-        nb = cfg.get("n_blocks", 1)
-        k = min(a.plain_blocks, nb)
-        per = n // nb
-        sub = x[:per * k]
-        cp = dict(cfg, precision="fp32", schedule="plain", n_blocks=k)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        P.compress(cp, sub, static=static, workspace=ws)
-        t1 = time.perf_counter()
-        res["plain_fp32_compress_MBps"] = round(per * k / (t1 - t0) / 1e6, 4)
-        log(f"plain fp32, {k} blocks: {t1 - t0:.3f}s")
-        res["plain_fp32_sample"] = f"first {k} of {nb} blocks, one launch per block"
+        res["plain_fp32"] = {"compress_MBps": round(sub_n / (t1 - t0) / 1e6, 4),
+                             "decompress_MBps": round(sub_n / (t2 - t1) / 1e6, 4),
+                             "value": round(sub_n / (t2 - t0) / 1e6, 4),
+                             "roundtrip_bit_exact": bool((op[:sub_n] == sub).all()),
+                             "sample": sample_desc + ", one FP32 launch per block"}
+        log(f"plain fp32, {kb} blocks: compress {t1 - t0:.3f}s decompress {t2 - t1:.3f}s")
+        if not a.no_fp32_compare and a.precision != "fp32":
+            cf = dict(sub_cfg, precision="fp32")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b32 = P.compress(cf, sub, static=static, workspace=ws)
+            t1 = time.perf_counter()
+            o32 = P.decompress(b32, static=static, workspace=wsd)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            bb = P.compress(dict(sub_cfg), sub, static=static, workspace=ws)
+            res["fp32_batched"] = {"compress_MBps": round(sub_n / (t1 - t0) / 1e6, 4),
+                                   "decompress_MBps": round(sub_n / (t2 - t1) / 1e6, 4),
+                                   "value": round(sub_n / (t2 - t0) / 1e6, 4),
+                                   "roundtrip_bit_exact": bool((o32[:sub_n] == sub).all()),
+                                   "bf16_ratio_cost_rel": round(len(bb) / len(b32) - 1.0, 6),
+                                   "sample": sample_desc + ", one batched FP32 launch"}
+            log(f"fp32 batched, {kb} blocks: compress {t1 - t0:.3f}s decompress {t2 - t1:.3f}s")
     if not a.no_cpu_baseline:
         log("oracle on the CPU sample")
-        cb, oblob, sample = cpu_baseline({k: v for k, v in cfg.items() if k not in ("block_len", "file_blocks")},
-                                         static, data, a.cpu_sample_bytes)
-        gcfg = {k: v for k, v in cfg.items() if k not in ("block_len", "file_blocks")}
+        ccfg = {k: v for k, v in cfg.items() if k not in ("block_len", "file_blocks", "smp_ppm")}
+        ccfg["n_blocks"] = a.cpu_sample_blocks
+        cb, oblob, sample = cpu_baseline(ccfg, static, data, a.cpu_sample_bytes)
+        gcfg = ccfg
         gblob = P.compress(dict(gcfg, schedule="batched"), torch.from_numpy(sample).cuda(), static=static)
         cb["gpu_ratio_bits_per_base_same_sample"] = round(8.0 * len(gblob) / len(sample), 5)
         cb["ratio_rel_diff"] = round(len(gblob) / len(oblob) - 1.0, 6)

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
+#include <condition_variable>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -16,7 +17,65 @@
 
 using namespace pmklc;
 
+// Status words of the calls that take no workspace (the encoder's error flag,
+// the coder export's bit count and error flag): a fixed pool in device memory
+// owned by the library, 32 bytes per call in flight on a device, so that no
+// call allocates.  Each device holds its own copy (its address is looked up
+// once per device).
+namespace pmklc {
+constexpr int kStatusSlots = 64;
+__device__ __align__(256) unsigned long long g_status_words[kStatusSlots * 4];
+}  // namespace pmklc
+
 namespace {
+
+struct StatusPool {
+  std::mutex mu;
+  std::condition_variable cv;
+  unsigned long long *base = nullptr;   // this device's g_status_words
+  uint64_t busy = 0;                    // bit i: slot i in use
+};
+constexpr int kMaxDevices = 64;
+StatusPool g_status_pool[kMaxDevices];
+
+// One slot of the pool on the current device for the length of a call; a
+// call waits while all slots are taken.  Released only after the call's
+// stream has drained, so no kernel can still write it.
+struct StatusSlot {
+  StatusPool *pool = nullptr;
+  hipStream_t st = nullptr;
+  int idx = -1;
+  unsigned long long *ptr = nullptr;   // 4 words of device memory
+  hipError_t acquire(hipStream_t stream) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    pool = &g_status_pool[dev];
+    std::unique_lock<std::mutex> lk(pool->mu);
+    if (!pool->base) {
+      void *p = nullptr;
+      e = hipGetSymbolAddress(&p, HIP_SYMBOL(pmklc::g_status_words));
+      if (e != hipSuccess) return e;
+      pool->base = static_cast<unsigned long long *>(p);
+    }
+    pool->cv.wait(lk, [&] { return pool->busy != ~0ull >> (64 - kStatusSlots); });
+    idx = __builtin_ctzll(~pool->busy);
+    pool->busy |= 1ull << idx;
+    ptr = pool->base + 4 * idx;
+    st = stream;
+    return hipSuccess;
+  }
+  ~StatusSlot() {
+    if (idx < 0) return;
+    (void)hipStreamSynchronize(st);
+    {
+      std::lock_guard<std::mutex> lk(pool->mu);
+      pool->busy &= ~(1ull << idx);
+    }
+    pool->cv.notify_one();
+  }
+};
 
 // numeric path of a container: which kernel computed its probabilities
 constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathUniform = 255;
@@ -340,6 +399,8 @@ struct Work {
   uint8_t *tok, *extras;
   float *params, *adam_m, *adam_v, *init, *stat, *snap;
   int *snap_flag, *ctr;   // ctr[0] queue, ctr[1] err
+  uint32_t *progress;     // steps done per block (model-passing waits)
+  int *order;             // queue order of the blocks
   uint32_t *slots, *seg_bits, *seg_words;
   uint64_t *seg_src, *seg_dst;
   uint32_t *seg_bytes;
@@ -348,13 +409,19 @@ struct Work {
   float *act;             // activation slabs (models whose activations exceed the LDS)
   uint16_t *w1f, *s1f;
   unsigned long long *phase;   // [16] phase clock of block 0
+  uint8_t *tune;          // the autotuner's trial block (inside the caller's workspace)
+  uint64_t tune_bytes;
 };
 
 struct Sizes {
   uint64_t n_chunks, runs, tokens, slot_words, staging;
 };
 
-void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool adam, bool smp, Work &w) {
+uint64_t trial_bytes(const Model &m);
+
+// trial: the autotuner's own one-block layout (which holds no trial region)
+void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool adam, bool smp, Work &w,
+            bool trial = false) {
   const uint64_t stride = (uint64_t)m.d.stride;
   w.ctr = A.take<int>(64);
   w.chunk_block = A.take<uint64_t>(z.n_chunks + 1);
@@ -375,6 +442,8 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   w.stat = m.d.static_on ? A.take<float>(stride) : nullptr;
   w.snap = smp ? A.take<float>((uint64_t)n_blocks * stride) : nullptr;
   w.snap_flag = A.take<int>(n_blocks);
+  w.progress = A.take<uint32_t>(n_blocks);
+  w.order = A.take<int>(n_blocks);
   w.slots = A.take<uint32_t>(z.slot_words + 1);
   w.seg_bits = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
   w.seg_words = A.take<uint32_t>((uint64_t)n_blocks * m.d.bs);
@@ -388,24 +457,38 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   const uint64_t w1n = m.kind == kMfmaBf16 ? (uint64_t)m.d.D * m.d.H[0] : 0;
   w.w1f = w1n ? A.take<uint16_t>((uint64_t)std::min<uint32_t>(n_blocks, kMaxGrid) * w1n) : nullptr;
   w.s1f = (w1n && m.d.static_on) ? A.take<uint16_t>(w1n) : nullptr;
+  w.tune_bytes = (!trial && m.d.model_on) ? trial_bytes(m) : 0;
+  w.tune = w.tune_bytes ? A.take<uint8_t>(w.tune_bytes) : nullptr;
 }
 
-// One synthetic block of t + 64 steps (constant tokens) in encode mode,
-// best of two runs, with the candidate width.
-hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms) {
-  m.nt = nt;
+// The autotuner's trial: one synthetic block of t + 64 steps.
+Sizes trial_sizes(const Model &m) {
   const uint32_t L = (uint32_t)m.d.t + 64;
   Sizes z{};
   z.tokens = (uint64_t)L * m.d.bs;
   z.slot_words = (uint64_t)slot_words_for(L) * m.d.bs;
+  return z;
+}
+uint64_t trial_bytes(const Model &m) {
   Arena A{nullptr, ~0ull};
   Work w;
-  layout(A, m, 1, z, m.d.optimizer == 1, false, w);
-  uint8_t *base = nullptr;
-  hipError_t e = hipMalloc(reinterpret_cast<void **>(&base), A.used + 256);
-  if (e != hipSuccess) return e;
-  Arena B{base, A.used + 256};
-  layout(B, m, 1, z, m.d.optimizer == 1, false, w);
+  layout(A, m, 1, trial_sizes(m), m.d.optimizer == 1, false, w, true);
+  return A.used + 256;
+}
+
+// One synthetic block of t + 64 steps (constant tokens) in encode mode,
+// best of two runs, with the candidate width, in the trial region of the
+// caller's workspace (region: trial_bytes(m) bytes).
+hipError_t time_candidate(Model m, int nt, uint8_t *region, uint64_t cap, hipStream_t st, float *ms) {
+  m.nt = nt;
+  const uint32_t L = (uint32_t)m.d.t + 64;
+  const Sizes z = trial_sizes(m);
+  Work w;
+  Arena B{reinterpret_cast<uint8_t *>(align_up(reinterpret_cast<uintptr_t>(region), 256)), cap - 256};
+  if (!region || cap < 256) return hipErrorInvalidValue;
+  layout(B, m, 1, z, m.d.optimizer == 1, false, w, true);
+  if (B.over) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
   BlockDesc bd{0, 0, L, slot_words_for(L), 0, -1, 0, 0};
   StepArgs a;
   memset(&a, 0, sizeof a);
@@ -420,6 +503,7 @@ hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms) {
   a.init = w.init;
   a.stat = m.d.static_on ? w.init : nullptr;
   a.snap_flag = w.snap_flag;
+  a.progress = w.progress;
   a.queue = w.ctr;
   a.err = w.ctr + 1;
   a.slots = w.slots;
@@ -452,7 +536,6 @@ hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms) {
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(st);
-  (void)hipFree(base);
   *ms = best;
   return e;
 }
@@ -555,9 +638,7 @@ struct TuneEntry {
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
 
-hipError_t time_candidate(Model m, int nt, hipStream_t st, float *ms);
-
-int choose_nt(Model &m, hipStream_t st) {
+int choose_nt(Model &m, const Work &w, hipStream_t st) {
   const char *env = getenv("PMKLC_NT");
   std::vector<int> cands;
   if (m.kind == kGeneric) {
@@ -582,7 +663,7 @@ int choose_nt(Model &m, hipStream_t st) {
   float best_ms = 1e30f;
   for (int nt : cands) {
     float ms = 0.0f;
-    if (time_candidate(m, nt, st, &ms) != hipSuccess) continue;
+    if (time_candidate(m, nt, w.tune, w.tune_bytes, st, &ms) != hipSuccess) continue;
     if (ms < best_ms) { best_ms = ms; best = nt; }
   }
   key.nt = best;
@@ -607,9 +688,28 @@ void count_work(const Model &m, const std::vector<BlockDesc> &bd, pmklc_timing &
   }
 }
 
+// Queue order of the persistent kernel: longest critical path first, where a
+// block's path is its own steps or, with a successor in its file, the steps
+// up to its snapshot plus the successor's path.  A predecessor's path is at
+// least its successor's, and ties keep block order, so a block is never
+// dequeued before the block it waits on.
+std::vector<int> queue_order(const std::vector<BlockDesc> &bd) {
+  const size_t n = bd.size();
+  std::vector<int> succ(n, -1), ord(n);
+  std::vector<uint64_t> key(n, 0);
+  for (size_t b = 0; b < n; b++) if (bd[b].pred >= 0) succ[bd[b].pred] = (int)b;
+  for (size_t q = n; q-- > 0;) {
+    key[q] = bd[q].L;
+    if (succ[q] >= 0) key[q] = std::max<uint64_t>(key[q], (uint64_t)bd[q].S + key[succ[q]]);
+  }
+  for (size_t b = 0; b < n; b++) ord[b] = (int)b;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key[x] > key[y]; });
+  return ord;
+}
+
 pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
                       hipStream_t st, StepTimer *tm = nullptr) {
-  m.nt = choose_nt(m, st);
+  m.nt = choose_nt(m, w, st);
   g_last.threads = (uint32_t)m.nt;
   StepArgs a;
   memset(&a, 0, sizeof a);
@@ -626,6 +726,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   a.stat = w.stat;
   a.snap = w.snap;
   a.snap_flag = w.snap_flag;
+  a.progress = w.progress;
   a.queue = w.ctr;
   a.err = w.ctr + 1;
   a.slots = w.slots;
@@ -634,13 +735,24 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   a.act_scratch = w.act;
   a.w1f = w.w1f;
   a.s1f = w.s1f;
-  a.spin_limit = 1ll << 26;   // ~10 s of waiting before giving up with an error
+  // a waiting block gives up only after ~10 s without a step of its running
+  // predecessor (a hardware fault, not a slow model); PMKLC_SPIN_LIMIT
+  // overrides the bound (tests of the give-up path)
+  a.spin_limit = 1ll << 26;
+  if (const char *sl = getenv("PMKLC_SPIN_LIMIT")) a.spin_limit = atoll(sl);
   const char *ph = getenv("PMKLC_PHASES");
   a.phase_clk = (ph && ph[0] == '1') ? w.phase : nullptr;
   if (a.phase_clk) HIP_TRY(hipMemsetAsync(w.phase, 0, 16 * sizeof(unsigned long long), st));
   HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
   HIP_TRY(hipMemsetAsync(w.snap_flag, 0, bd.size() * sizeof(int), st));
+  HIP_TRY(hipMemsetAsync(w.progress, 0, bd.size() * sizeof(uint32_t), st));
   if (bd.empty()) return PMKLC_OK;
+  std::vector<int> order;
+  if (schedule != PMKLC_PLAIN) {
+    order = queue_order(bd);
+    HIP_TRY(h2d(w.order, order, st));
+    a.order = w.order;
+  }
   if (w.s1f) HIP_TRY(launch_w1_frag(w.stat + m.d.off_W[0], m.d.D, m.d.H[0], w.s1f, st));
   if (tm) {
     HIP_TRY(hipEventCreate(&tm->a));
@@ -732,14 +844,14 @@ pmklc_status pmklc_encode_skmer(const uint8_t *bases_dev, uint64_t n, uint32_t s
   if (l > cap) { *n_tokens = l; return PMKLC_ERR_BUFFER_TOO_SMALL; }
   if (l && !tokens_dev) return PMKLC_ERR_INVALID_ARG;
   if (n == 0) { *n_tokens = 0; return PMKLC_OK; }
-  int *err = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&err), sizeof(int), st));
+  StatusSlot slot;
+  HIP_TRY(slot.acquire(st));
+  int *err = reinterpret_cast<int *>(slot.ptr);
   int herr = 0;
   hipError_t e = hipMemsetAsync(err, 0, sizeof(int), st);
   if (e == hipSuccess) e = launch_skmer_direct(bases_dev, n, (int)s, (int)k, tokens_dev, l, err, st);
   if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFreeAsync(err, st);
   if (e != hipSuccess) return PMKLC_ERR_DEVICE;
   if (herr) return PMKLC_ERR_INVALID_BASE;
   *n_tokens = l;
@@ -1254,8 +1366,9 @@ pmklc_status pmklc_wnc_encode(const uint32_t *cum_lo_dev, const uint32_t *cum_hi
   uint64_t need = (17 * m + 2 + 7) / 8;
   uint64_t need_words = (17 * m + 2 + 31) / 32;
   if (cap / 4 < need_words) { *nbits = 8 * need; return PMKLC_ERR_BUFFER_TOO_SMALL; }
-  uint64_t *nb_dev = nullptr;
-  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&nb_dev), 16, st));
+  StatusSlot slot;
+  HIP_TRY(slot.acquire(st));
+  uint64_t *nb_dev = reinterpret_cast<uint64_t *>(slot.ptr);
   int *err = reinterpret_cast<int *>(nb_dev + 1);
   uint64_t hb = 0;
   int herr = 0;
@@ -1266,7 +1379,6 @@ pmklc_status pmklc_wnc_encode(const uint32_t *cum_lo_dev, const uint32_t *cum_hi
   if (e == hipSuccess) e = hipMemcpyAsync(&hb, nb_dev, 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFreeAsync(nb_dev, st);
   if (e != hipSuccess) return PMKLC_ERR_DEVICE;
   if (herr) return PMKLC_ERR_DEVICE;
   *nbits = hb;
@@ -1295,7 +1407,6 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   rc = make_model(cfg, m);
   if (rc) return rc;
   if (m.d.static_on && !static_dev) return PMKLC_ERR_MODEL_MISMATCH;
-  m.nt = choose_nt(m, static_cast<hipStream_t>(stream));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const uint32_t bs = cfg->bs;
   uint64_t L = l / bs;
@@ -1310,6 +1421,7 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&base), A.used + 256, st));
   Arena B{base, A.used + 256};
   layout(B, m, 1, z, cfg->optimizer == PMKLC_ADAM, false, w);
+  m.nt = choose_nt(m, w, st);
   uint64_t *probe_dev = nullptr;
   StepArgs a;
   memset(&a, 0, sizeof a);
@@ -1338,6 +1450,7 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   a.init = w.init;
   a.stat = static_dev;
   a.snap_flag = w.snap_flag;
+  a.progress = w.progress;
   a.queue = w.ctr;
   a.err = w.ctr + 1;
   a.slots = w.slots;

@@ -98,12 +98,14 @@ __device__ __forceinline__ long long fixed(float x) {
   return (long long)rint(y);
 }
 
-__global__ void scatter_emb_kernel(const float *dX, const uint8_t *ctx, int rows, int t, int E, long long *acc) {
+// (a token >= V has no embedding row: the gather flagged it and it is skipped here)
+__global__ void scatter_emb_kernel(const float *dX, const uint8_t *ctx, int rows, int t, int E, int V, long long *acc) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t D = (size_t)t * E;
   if (i >= (size_t)rows * D) return;
   const size_t j = i / D, dd = i % D, p = dd / E, e = dd % E;
   const int tok = ctx[j * t + p];
+  if (tok >= V) return;
   atomicAdd(reinterpret_cast<unsigned long long *>(acc + (size_t)tok * E + e), (unsigned long long)fixed(dX[i]));
 }
 
@@ -210,7 +212,7 @@ hipError_t dm_backward(const Dims &d, const float *W, const uint8_t *ctx, int ro
   if (e == hipSuccess) {
     const size_t nx = (size_t)rows * d.D;
     hipLaunchKernelGGL(scatter_emb_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, dout, ctx, rows, d.t,
-                       d.E, b.eacc);
+                       d.E, d.V, b.eacc);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {

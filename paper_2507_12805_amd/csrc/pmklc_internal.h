@@ -70,7 +70,11 @@ struct StepArgs {
   const float *init;              // [stride] seeded initial parameters (+ a)
   const float *stat;              // [P] static parameters or null
   float *snap;                    // [n_blocks][stride] model-passing snapshots or null
-  int *snap_flag;                 // [n_blocks] 1 when the snapshot is written
+  int *snap_flag;                 // [n_blocks] 1 when the snapshot is written, 2 when the block gave up
+  uint32_t *progress;             // [n_blocks] steps done by a block whose successor may wait on it
+                                  // (0 before its first step; zeroed before launch)
+  const int *order;               // [n_blocks] queue position -> block, or null (block order); a block's
+                                  // model-passing predecessor always comes before it
   int *queue;                     // work counter (zeroed before launch)
   int *err;                       // error word (0 = ok)
   uint32_t *slots;                // encode: segment slots; decode: aligned streams
@@ -82,7 +86,8 @@ struct StepArgs {
   int n_probe;
   float *probe_P;                 // [n_probe][bs][V]
   float *params_out;              // [P+1] parameters after the last step, or null
-  long long spin_limit;           // bound on model-passing waits (iterations)
+  long long spin_limit;           // model-passing wait: sleeps without progress of a running predecessor
+                                  // before the waiting block gives up (error bit 4)
   float *act_scratch;             // [grid][act_slot] activations when lay.act_global
   unsigned long long *phase_clk;  // [12] per-phase wall-clock ticks of block 0, or null
   // BF16 matrix-core kernel: W1 rounded to BF16 in the first layer's

@@ -449,8 +449,12 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
   const int stride = d.stride;
   const float inv_bs = 1.0f / (float)bs;
 
+  __shared__ int sh_ok;
   for (;;) {
-    if (tid == 0) sh_b = atomicAdd(a.queue, 1);
+    if (tid == 0) {
+      const int q = atomicAdd(a.queue, 1);
+      sh_b = q < a.n_blocks && a.order ? a.order[q] : q;
+    }
     __syncthreads();
     const int b = sh_b;
     __syncthreads();
@@ -463,16 +467,37 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     if (a.stop && a.stop < Lrun) Lrun = a.stop;
 
     // ---- initial parameters: seeded, or the predecessor's snapshot (Sec. 4.3)
+    // The predecessor was dequeued before this block, so it is running or
+    // done.  The wait ends when its snapshot is published (flag 1).  It fails
+    // only if the predecessor gave up (flag 2) or, while running, made no
+    // step for spin_limit sleeps; a predecessor that is itself waiting
+    // (progress 0) keeps the wait alive.  A block that fails skips its work
+    // and passes the failure on to its own successor.
     const float *src = a.init;
     if (bd.pred >= 0) {
       if (tid == 0) {
-        long long spins = 0;
-        while (__hip_atomic_load(a.snap_flag + bd.pred, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        int ok = 1;
+        uint32_t last = 0;
+        long long idle = 0;
+        for (;;) {
+          const int f = __hip_atomic_load(a.snap_flag + bd.pred, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+          if (f == 1) break;
+          if (f != 0) { ok = 0; break; }
+          const uint32_t pg = __hip_atomic_load(a.progress + bd.pred, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (pg == 0 || pg != last) { last = pg; idle = 0; }
+          else if (++idle > a.spin_limit) { ok = 0; break; }
           __builtin_amdgcn_s_sleep(8);
-          if (++spins > a.spin_limit) { atomicOr(a.err, 4); break; }
         }
+        if (!ok) {
+          atomicOr(a.err, 4);
+          if (bd.has_snap) __hip_atomic_store(a.snap_flag + b, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        sh_ok = ok;
       }
       __syncthreads();
+      const int ok = sh_ok;
+      __syncthreads();
+      if (!ok) continue;
       src = a.snap + (size_t)bd.pred * stride;
     }
     for (int q = tid; q < stride; q += NT) {
@@ -673,6 +698,8 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       }
       pc.mark(6);
       if (bd.has_snap && i + 1 == (uint64_t)bd.S) snapshot();
+      if (bd.has_snap && tid == 0)
+        __hip_atomic_store(a.progress + b, (uint32_t)(i + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     pc.flush();
