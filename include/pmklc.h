@@ -149,17 +149,23 @@ pmklc_status pmklc_wnc_decode(const uint8_t *in_dev, uint64_t nbytes, const uint
                               uint64_t m, uint32_t *symbols_dev, void *stream);
 
 /* Runs the learning loop of one block over l tokens (tokens_dev), exactly
- * as pmklc_compress does for a block, coding into a discarded stream.
- * init_dev: initial parameters + a (n_params+1 floats) or NULL for the
- * seeded ones. static_dev: static parameters (device) or NULL. stop: run
- * only the first `stop` steps (0 = all). probe_steps_host: sorted step
- * indices whose FP32 probabilities [bs][V] are written to probs_dev
- * (n_probe x bs x V). params_dev receives the parameters + a after the
- * last step run (n_params+1 floats). */
+ * as pmklc_compress does for a block (Sec. 2 steps (2)-(4)), coding into
+ * its own streams. init_dev: initial parameters + a (n_params+1 floats) or
+ * NULL for the seeded ones. static_dev: static parameters (device) or NULL.
+ * stop: run only the first `stop` steps (0 = all). probe_steps_host:
+ * sorted step indices whose FP32 probabilities [bs][V] are written to
+ * probs_dev (n_probe x bs x V). params_dev receives the parameters + a
+ * after the last step run (n_params+1 floats). If streams_len is not NULL,
+ * *streams_len receives the byte length of the bs segment streams,
+ * byte-aligned and concatenated in segment order (the block's payload in
+ * a container), and streams_host (capacity streams_cap bytes) receives them
+ * (PMKLC_ERR_BUFFER_TOO_SMALL if it is smaller). Allocates its own
+ * temporary device memory (a test export). */
 pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_dev, uint64_t l,
                                const float *static_dev, const float *init_dev, uint64_t stop,
                                const uint64_t *probe_steps_host, uint32_t n_probe, float *probs_dev,
-                               float *params_dev, void *stream);
+                               float *params_dev, uint8_t *streams_host, uint64_t streams_cap,
+                               uint64_t *streams_len, void *stream);
 
 /* Timing of the last pmklc_compress / pmklc_decompress on this thread,
  * measured with HIP events on the call's stream around the step kernel

@@ -74,7 +74,7 @@ def load():
     L.pmklc_quantise.argtypes = [_vp, _u32, _u32, _vp, _vp]
     L.pmklc_wnc_encode.argtypes = [_vp, _vp, _u64, _vp, _u64, _u64p, _vp]
     L.pmklc_wnc_decode.argtypes = [_vp, _u64, _vp, _u32, _u64, _vp, _vp]
-    L.pmklc_model_trace.argtypes = [cp, _vp, _u64, _vp, _vp, _u64, _u64p, _u32, _vp, _vp, _vp]
+    L.pmklc_model_trace.argtypes = [cp, _vp, _u64, _vp, _vp, _u64, _u64p, _u32, _vp, _vp, _vp, _u64, _u64p, _vp]
     L.pmklc_dm_workspace.argtypes = [cp, _u32, _u64p]
     L.pmklc_dm_forward.argtypes = [cp, _vp, _vp, _u32, _vp, _vp, _u64, _vp]
     L.pmklc_dm_backward.argtypes = [cp, _vp, _vp, _u32, _vp, _vp, _vp, _u64, _vp]
@@ -301,9 +301,10 @@ def wnc_decode(data: bytes, cdfs):
     return out[:m]
 
 
-def model_trace(cfg: dict, tokens, steps=(), static=None, init=None, stop: int = 0):
+def model_trace(cfg: dict, tokens, steps=(), static=None, init=None, stop: int = 0, streams: bool = False):
     """Run one block's learning loop over ``tokens`` on the GPU; returns
-    (P[len(steps), bs, V] float32, params[n+1] float32) as device tensors."""
+    (P[len(steps), bs, V] float32, params[n+1] float32) as device tensors,
+    plus the block's concatenated segment streams (bytes) if ``streams``."""
     torch = _torch()
     L = load()
     tok = _dev_tensor(tokens, torch.uint8)
@@ -315,9 +316,14 @@ def model_trace(cfg: dict, tokens, steps=(), static=None, init=None, stop: int =
     params = torch.zeros(n + 1, dtype=torch.float32, device="cuda")
     sd = None if static is None else _dev_tensor(static, torch.float32)
     ini = None if init is None else _dev_tensor(init, torch.float32)
+    buf = np.empty(4 * ((17 * (tok.numel() // cfg["bs"]) + 2 + 31) // 32 + 1) * cfg["bs"] + 16, dtype=np.uint8)
+    slen = ctypes.c_uint64(0)
     _check(L.pmklc_model_trace(ctypes.byref(c), _dptr(tok), tok.numel(), _dptr(sd), _dptr(ini), stop,
                                st.ctypes.data_as(_u64p) if len(st) else None, len(st), _dptr(P), _dptr(params),
-                               _stream()), "pmklc_model_trace")
+                               buf.ctypes.data_as(ctypes.c_void_p) if streams else None, buf.size if streams else 0,
+                               ctypes.byref(slen) if streams else None, _stream()), "pmklc_model_trace")
+    if streams:
+        return P[:len(st)], params, buf[:slen.value].tobytes()
     return P[:len(st)], params
 
 

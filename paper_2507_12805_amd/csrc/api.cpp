@@ -25,6 +25,7 @@ using namespace pmklc;
 namespace pmklc {
 constexpr int kStatusSlots = 64;
 __device__ __align__(256) unsigned long long g_status_words[kStatusSlots * 4];
+
 }  // namespace pmklc
 
 namespace {
@@ -638,7 +639,9 @@ struct TuneEntry {
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
 
-int choose_nt(Model &m, const Work &w, hipStream_t st) {
+// tune = false (the no-allocation entry point): no trial runs, which would
+// create timing events; the cached choice, else the widest candidate.
+int choose_nt(Model &m, const Work &w, hipStream_t st, bool tune = true) {
   const char *env = getenv("PMKLC_NT");
   std::vector<int> cands;
   if (m.kind == kGeneric) {
@@ -659,6 +662,7 @@ int choose_nt(Model &m, const Work &w, hipStream_t st) {
     if (e.kind == key.kind && e.bs == key.bs && e.H0 == key.H0 && e.H1 == key.H1 && e.V == key.V && e.E == key.E &&
         e.t == key.t && e.nh == key.nh && e.stat == key.stat && e.opt == key.opt)
       return e.nt;
+  if (!tune) return cands.back();
   int best = cands.back();
   float best_ms = 1e30f;
   for (int nt : cands) {
@@ -708,8 +712,8 @@ std::vector<int> queue_order(const std::vector<BlockDesc> &bd) {
 }
 
 pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
-                      hipStream_t st, StepTimer *tm = nullptr) {
-  m.nt = choose_nt(m, w, st);
+                      hipStream_t st, StepTimer *tm = nullptr, bool tune = true) {
+  m.nt = choose_nt(m, w, st, tune);
   g_last.threads = (uint32_t)m.nt;
   StepArgs a;
   memset(&a, 0, sizeof a);
@@ -890,9 +894,14 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t 
   return PMKLC_OK;
 }
 
-pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
-                            uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
-                            void *stream) {
+}  // extern "C"
+
+namespace {
+// pmklc_compress on a given workspace. noalloc: the no-allocation entry
+// point's call (no timing events, no autotuner trial runs).
+pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
+                           uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
+                           void *stream, bool noalloc) {
   const auto t0 = std::chrono::steady_clock::now();
   g_last = pmklc_timing{};
   StepTimer tm;
@@ -992,7 +1001,7 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
     }
   }
   count_work(m, bd, g_last);
-  rc = run_step(m, w, 0, bd, cfg->schedule, st, &tm);
+  rc = run_step(m, w, 0, bd, cfg->schedule, st, noalloc ? nullptr : &tm, !noalloc);
   if (rc) return rc;
   std::vector<uint32_t> seg_bits, run_start, run_len;
   std::vector<uint8_t> extras;
@@ -1053,6 +1062,16 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
   *out_len = total;
   finish_timing(tm, t0);
   return PMKLC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
+                            uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
+                            void *stream) {
+  return compress_impl(cfg, in_dev, n, ws_dev, ws_bytes, out_host, out_cap, out_len, stream, false);
 }
 
 // --------------------------------------------------------------- decode
@@ -1399,7 +1418,8 @@ pmklc_status pmklc_wnc_decode(const uint8_t *in_dev, uint64_t nbytes, const uint
 
 pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_dev, uint64_t l, const float *static_dev,
                                const float *init_dev, uint64_t stop, const uint64_t *probe_steps_host, uint32_t n_probe,
-                               float *probs_dev, float *params_dev, void *stream) {
+                               float *probs_dev, float *params_dev, uint8_t *streams_host, uint64_t streams_cap,
+                               uint64_t *streams_len, void *stream) {
   pmklc_status rc = check_cfg(cfg);
   if (rc) return rc;
   if (!(cfg->selector & PMKLC_SEL_DM) || !tokens_dev) return PMKLC_ERR_INVALID_ARG;
@@ -1473,11 +1493,33 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   }
   int herr[2] = {0, 0};
   chk(hipMemcpyAsync(herr, w.ctr, 8, hipMemcpyDeviceToHost, st));
+  // the segment streams, byte-aligned and concatenated in segment order (a
+  // block's payload in the container)
+  std::vector<uint32_t> bits, slots;
+  if (streams_len && L > 0) {
+    chk(d2h(bits, w.seg_bits, bs, st));
+    chk(d2h(slots, w.slots, (uint64_t)slot_words_for(L) * bs, st));
+  }
   chk(hipStreamSynchronize(st));
+  uint64_t total = 0;
+  for (uint32_t b : bits) total += (b + 7) / 8;
+  if (e == hipSuccess && streams_len && total <= streams_cap && (streams_host || !total)) {
+    uint64_t at = 0;
+    for (uint32_t j = 0; j < bits.size(); j++) {
+      const uint64_t nb = (bits[j] + 7) / 8;
+      memcpy(streams_host + at, reinterpret_cast<const uint8_t *>(slots.data() + (uint64_t)j * slot_words_for(L)),
+             nb);
+      at += nb;
+    }
+  }
   (void)hipFreeAsync(base, st);
   if (probe_dev) (void)hipFreeAsync(probe_dev, st);
   (void)hipStreamSynchronize(st);
   if (e != hipSuccess || herr[1]) return PMKLC_ERR_DEVICE;
+  if (streams_len) {
+    *streams_len = total;
+    if (total > streams_cap) return PMKLC_ERR_BUFFER_TOO_SMALL;
+  }
   return PMKLC_OK;
 }
 

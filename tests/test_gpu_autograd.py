@@ -51,10 +51,16 @@ def test_autograd_function_matches_oracle_gradient(gpu, orc):
     assert abs(loss.item() - loss_o) <= 1e-4
     rel = np.linalg.norm(g - go) / np.linalg.norm(go)
     assert rel <= 1e-3, rel
+    # every coordinate: 1e-3 relative, with an absolute floor of 1e-5 of the
+    # tensor's largest gradient for coordinates that cancel to near zero
+    # (FP32 sums of up to 4096 terms)
     for name, (off, shp) in orc.param_slices(cfg).items():
         n = int(np.prod(shp))
-        r = np.linalg.norm(g[off:off + n] - go[off:off + n]) / max(np.linalg.norm(go[off:off + n]), 1e-30)
-        assert r <= 1e-3, (name, r)
+        gs, gos = g[off:off + n], go[off:off + n]
+        err = np.abs(gs - gos)
+        bound = 1e-3 * np.abs(gos) + 1e-5 * np.abs(gos).max()
+        print(f"{name}: max err {err.max():.3g}, max |g| {np.abs(gos).max():.3g}")
+        assert np.all(err <= bound), (name, int(np.argmax(err - bound)), float((err - bound).max()))
 
 
 def test_gradient_against_finite_differences(gpu, orc):

@@ -143,6 +143,18 @@ def test_uniform_container_bit_exact_with_oracle(gpu, orc, k):
     assert np.array_equal(gpu.decompress(blob_g).cpu().numpy(), a)
 
 
+@pytest.mark.parametrize("s,k", [(s, k) for (s, k) in PAIRS if s < k])
+def test_uniform_container_bit_exact_overlapping_kmers(gpu, orc, s, k):
+    """Overlapping (s,k)-mers (s < k) through pmklc_compress's own scan and
+    tokeniser: under the uniform model the container equals the oracle's
+    byte for byte (N runs, tails, remainder tokens and every stream)."""
+    a = _dna(40009 + s, seed=10 * k + s, n_rate=0.001)
+    cfg = _tiny(s=s, k=k, selector="uniform", n_blocks=3)
+    blob_g = gpu.compress(cfg, _cuda(a))
+    assert blob_g == orc.compress(cfg, a)
+    assert np.array_equal(gpu.decompress(blob_g).cpu().numpy(), a)
+
+
 ROUNDTRIP = {
     "cfg1": (dict(), 1 << 18, 1, 0.0),
     "tiny_multi_N": (dict(t=4, E=4, hidden=[8], bs=8, n_blocks=3), 30011, 1, 0.003),
@@ -205,6 +217,38 @@ def test_smp_chain_roundtrip_and_snapshot(gpu, orc):
     blob_o = orc.compress(cfg, a)
     assert len(blob) == pytest.approx(len(blob_o), rel=0.005)
     assert blob != gpu.compress(dict(cfg, smp_ppm=0), _cuda(a))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp32_valu"])
+def test_smp_snapshot_bit_exact(gpu, orc, precision):
+    """Model passing (Sec. 4.3): the second block of a file starts from the
+    first block's parameters after ceil(5% of its steps) steps. Its segment
+    streams in the chained container equal, byte for byte, those of a
+    single-block run over its tokens started from the parameters the first
+    block's own run reaches at that step, and differ from a start one step
+    later; the first block's streams equal its seeded single-block run."""
+    cfg = model_small(precision=precision)
+    bs, t = cfg["bs"], cfg["t"]
+    L0, L1 = 800, 300
+    n0, n1 = 3 * bs * L0, 3 * bs * L1 + 5        # (3,3)-mers: l = (n - 3) // 3 + 1 tokens
+    a = _dna(n0 + n1, seed=12, rho=0.05)
+    chain = dict(cfg, block_len=[n0, n1], file_blocks=[2], smp_ppm=50000)
+    blob = gpu.compress(chain, _cuda(a))
+    assert np.array_equal(gpu.decompress(blob).cpu().numpy(), a)
+    p = cbf.parse(blob)
+    assert [b["L"] for b in p["blocks"]] == [L0, L1]
+    S = -(-50000 * L0 // 1000000)                 # ceil(5% of the first block's steps)
+    assert S > t                                  # the snapshot carries learned weights
+    tok0 = orc.encode_skmer(a[:n0], 3, 3)
+    tok1 = orc.encode_skmer(a[n0:], 3, 3)
+    _, _, s0 = gpu.model_trace(cfg, tok0, streams=True)
+    assert s0 == b"".join(p["blocks"][0]["streams"])
+    _, wS = gpu.model_trace(cfg, tok0, stop=S)
+    _, _, s1 = gpu.model_trace(cfg, tok1, init=wS, streams=True)
+    assert s1 == b"".join(p["blocks"][1]["streams"])
+    _, wS1 = gpu.model_trace(cfg, tok0, stop=S + 1)
+    _, _, s1b = gpu.model_trace(cfg, tok1, init=wS1, streams=True)
+    assert s1b != s1
 
 
 @pytest.mark.parametrize("raw", ["", "A", "AC", "ACG", "N" * 40, "ANNNNNC", "ACGT" * 9, "NACGTN" * 30])
@@ -455,18 +499,44 @@ def test_large_model_adam_global_activations(gpu, orc):
 
 
 # ---------------------------------------------------- full-size workload
-def test_full_size_static_workload_roundtrip(gpu, orc):
-    """The 64 MiB, 16-block static + dynamic workload at full size, in the
-    bench's launch configuration: bit-exact GPU round trip, metadata equal to
-    the oracle's, and teacher-forced P at sampled steps of block 0."""
+def _oracle_golden(name, a):
+    """Container size of the FP64 oracle on the whole workload input
+    (tests/golden/<name>_oracle.txt, written by the oracle alone), checked
+    against the input's SHA-256; None if that file is absent."""
+    import hashlib
+    path = os.path.join(GOLD, f"{name}_oracle.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(line.split(None, 1) for line in open(path) if line.strip() and not line.startswith("#"))
+    assert kv["input_sha256"].strip() == hashlib.sha256(memoryview(a)).hexdigest(), "golden input differs"
+    return int(kv["container_bytes"])
+
+
+def _check_golden(name, a, blob):
+    gold = _oracle_golden(name, a)
+    if gold is None:
+        pytest.skip(f"no full-size oracle result for {name} (tests/golden/make_oracle_goldens.py)")
+    rel = len(blob) / gold - 1
+    print(f"{name}: GPU {len(blob)} bytes, oracle {gold}, rel {rel:+.6f}")
+    assert abs(rel) <= 0.005
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_size_static_workload_roundtrip(gpu, orc, precision):
+    """The 64 MiB, 16-block static + dynamic workload at full size, on the
+    FP32 and BF16 matrix-core paths: bit-exact GPU round trip, metadata equal
+    to the oracle's, teacher-forced P at sampled steps of block 0 (FP32),
+    and the container within 0.5% of the oracle's on the whole input."""
     from synth.workloads import cfg2
     rec, cfg = cfg2()
+    cfg = dict(cfg, precision=precision)
     static = np.fromfile(os.path.join(GOLD, "static_cfg2.f32"), dtype=np.float32)
     a = synth.generate(rec)
     x = _cuda(a)
     blob = gpu.compress(cfg, x, static=static)
     back = gpu.decompress(blob, static=static)
     assert bool((back == x).all())
+    del back
     p = cbf.parse(blob)
     assert p["header"]["n_blocks"] == 16
     # block metadata (N runs) against the oracle's scan of the same bytes
@@ -489,4 +559,33 @@ def test_full_size_static_workload_roundtrip(gpu, orc):
         rows = np.arange(cfg["bs"]) * L + i
         ctx = np.stack([tok[r - cfg["t"]:r] for r in rows])
         Po, _, _, _ = orc.step(cfg, w64[:n], ctx, tok[rows], ws=static.astype(np.float64), a_alpha=w64[n])
-        assert np.max(np.abs(P_i[0].cpu().numpy() - Po)) <= 1e-4
+        assert np.max(np.abs(P_i[0].cpu().numpy() - Po)) <= (1e-4 if precision == "fp32" else 0.05)
+    _check_golden("static64", a, blob)
+
+
+def test_full_size_uneven_workload_vs_oracle(gpu):
+    """The 1 GiB, 256-block lognormal workload at full size on the BF16
+    matrix-core path, one persistent launch: bit-exact round trip and the
+    container within 0.5% of the FP64 oracle's on the whole input."""
+    from synth.workloads import cfg3
+    rec, cfg = cfg3()
+    cfg = dict(cfg, precision="bf16")
+    a = synth.generate(rec)
+    x = _cuda(a)
+    blob = gpu.compress(cfg, x)
+    assert bool((gpu.decompress(blob) == x).all())
+    _check_golden("uneven1g", a, blob)
+
+
+def test_full_size_archive_vs_oracle(gpu):
+    """The 64-file archive at full size (4 MiB blocks, model passing at 5%
+    within each file), BF16 matrix cores: bit-exact round trip and the
+    container within 0.5% of the FP64 oracle's."""
+    from synth.workloads import cfg5
+    recs, cfg = cfg5()
+    cfg = dict(cfg, precision="bf16")
+    a = np.concatenate([synth.generate(r) for r in recs])
+    x = _cuda(a)
+    blob = gpu.compress(cfg, x)
+    assert bool((gpu.decompress(blob) == x).all())
+    _check_golden("archive", a, blob)
