@@ -44,7 +44,8 @@ typedef enum {
   PMKLC_ERR_CORRUPT = -4,          /* container malformed or truncated */
   PMKLC_ERR_MODEL_MISMATCH = -5,   /* static weights or numeric path differ from the container's */
   PMKLC_ERR_DEVICE = -6,           /* a HIP call failed */
-  PMKLC_ERR_UNSUPPORTED = -7       /* valid configuration that this build has no kernel for */
+  PMKLC_ERR_UNSUPPORTED = -7,      /* valid configuration that this build has no kernel for */
+  PMKLC_ERR_SCRATCH_LIMIT = -8     /* input needs more than pmklc_compress_noalloc's fixed buffer */
 } pmklc_status;
 
 enum { PMKLC_SGD = 0, PMKLC_ADAM = 1 };
@@ -110,6 +111,27 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t 
 pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
                             uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
                             void *stream);
+
+/* pmklc_compress for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and the same container bytes as
+ * pmklc_compress, with the workspace taken from a fixed buffer that the
+ * library holds in device memory (64 MiB per device, reserved when the
+ * library's code is loaded on that device and held until the process ends)
+ * instead of a caller's ws_dev. The call makes no device allocation: no
+ * hipMalloc/hipFree, no timing events, no autotuner trial runs (the
+ * workgroup width is the cached choice for the model shape, else the
+ * default; no width changes a value). Inputs whose pmklc_compress_bound
+ * workspace exceeds 64 MiB give PMKLC_ERR_SCRATCH_LIMIT before any device
+ * work (about 6.5 million bases for the 16-wide embedding, 32-wide hidden
+ * model). The buffer is shared by every call on the device and keeps the
+ * last call's contents; the call clears what must start at zero. Calls
+ * from threads of one process are serialised per device by a lock; calls
+ * that overlap on one device through other means (another copy of the
+ * library in the same process) would race. in_dev, out_host, out_cap,
+ * out_len, stream and the errors are those of pmklc_compress. */
+pmklc_status pmklc_compress_noalloc(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n,
+                                    uint8_t *out_host, uint64_t out_cap, uint64_t *out_len, void *stream);
 
 /* Reads a container's header: *n_bases = decompressed size, *ws_bytes =
  * device workspace needed by pmklc_decompress. */

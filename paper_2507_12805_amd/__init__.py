@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libpmklc.so")
 _lib = None
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "invalid base", -3: "buffer too small", -4: "corrupt container",
-          -5: "model mismatch", -6: "device error", -7: "unsupported configuration"}
+          -5: "model mismatch", -6: "device error", -7: "unsupported configuration",
+          -8: "input exceeds the no-allocation scratch buffer"}
 
 
 class PmklcError(RuntimeError):
@@ -67,6 +68,7 @@ def load():
     L.pmklc_encode_skmer.argtypes = [_vp, _u64, _u32, _u32, _vp, _u64, _u64p, _vp]
     L.pmklc_compress_bound.argtypes = [cp, _u64, _u64p, _u64p]
     L.pmklc_compress.argtypes = [cp, _vp, _u64, _vp, _u64, _vp, _u64, _u64p, _vp]
+    L.pmklc_compress_noalloc.argtypes = [cp, _vp, _u64, _vp, _u64, _u64p, _vp]
     L.pmklc_decompress_info.argtypes = [_vp, _u64, _u64p, _u64p]
     L.pmklc_decompress.argtypes = [_vp, _u64, _vp, _u64, _vp, _u64, _vp, _u64, _u64p, _vp]
     L.pmklc_status_string.argtypes = [ctypes.c_int]
@@ -84,7 +86,8 @@ def load():
     L.pmklc_last_timing.restype = ctypes.c_int
     L.pmklc_param_count.argtypes = [cp]
     L.pmklc_param_count.restype = _u64
-    for f in ["pmklc_encode_skmer", "pmklc_compress_bound", "pmklc_compress", "pmklc_decompress_info",
+    for f in ["pmklc_encode_skmer", "pmklc_compress_bound", "pmklc_compress", "pmklc_compress_noalloc",
+              "pmklc_decompress_info",
               "pmklc_decompress", "pmklc_quantise", "pmklc_wnc_encode", "pmklc_wnc_decode", "pmklc_model_trace"]:
         getattr(L, f).restype = ctypes.c_int
     _lib = L
@@ -235,6 +238,26 @@ def compress(cfg: dict, data, static=None, workspace: Workspace | None = None, o
     _check(L.pmklc_compress(ctypes.byref(c), _dptr(x) if n else None, n, _dptr(ws), ws.numel(),
                             out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(olen), _stream()),
            "pmklc_compress")
+    return out[:olen.value].tobytes()
+
+
+def compress_noalloc(cfg: dict, data, static=None, out: np.ndarray | None = None) -> bytes:
+    """pmklc_compress_noalloc: the same container as compress(), with the
+    workspace taken from the library's fixed device buffer (no device
+    allocation by the call)."""
+    torch = _torch()
+    L = load()
+    x = _dev_tensor(data, torch.uint8)
+    n = x.numel()
+    c, keep = make_config(cfg, static)
+    mo = ctypes.c_uint64(0)
+    _check(L.pmklc_compress_bound(ctypes.byref(c), n, ctypes.byref(mo), None), "pmklc_compress_bound")
+    if out is None or out.size < mo.value:
+        out = np.empty(mo.value, dtype=np.uint8)
+    olen = ctypes.c_uint64(0)
+    _check(L.pmklc_compress_noalloc(ctypes.byref(c), _dptr(x) if n else None, n,
+                                    out.ctypes.data_as(ctypes.c_void_p), out.size, ctypes.byref(olen), _stream()),
+           "pmklc_compress_noalloc")
     return out[:olen.value].tobytes()
 
 

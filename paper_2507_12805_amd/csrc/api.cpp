@@ -26,6 +26,12 @@ namespace pmklc {
 constexpr int kStatusSlots = 64;
 __device__ __align__(256) unsigned long long g_status_words[kStatusSlots * 4];
 
+// The workspace of pmklc_compress_noalloc (callers that cannot allocate
+// device memory): a fixed buffer per device, held until the process ends.
+// Host code never passes the array's name to a kernel or copy: it uses the
+// device address looked up with hipGetSymbolAddress.
+constexpr uint64_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
 }  // namespace pmklc
 
 namespace {
@@ -831,6 +837,7 @@ const char *pmklc_status_string(pmklc_status s) {
     case PMKLC_ERR_MODEL_MISMATCH: return "model mismatch";
     case PMKLC_ERR_DEVICE: return "device error";
     case PMKLC_ERR_UNSUPPORTED: return "unsupported configuration";
+    case PMKLC_ERR_SCRATCH_LIMIT: return "input exceeds the no-allocation scratch buffer";
   }
   return "unknown";
 }
@@ -1064,6 +1071,14 @@ pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint6
   return PMKLC_OK;
 }
 
+// Per device: the address of its copy of `scratch` (looked up once, with
+// that device current) and the lock that serialises this process's
+// no-allocation calls on it.
+struct ScratchDev {
+  std::mutex mu;
+  void *ptr = nullptr;
+};
+ScratchDev g_scratch[kMaxDevices];
 }  // namespace
 
 extern "C" {
@@ -1072,6 +1087,25 @@ pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint
                             uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
                             void *stream) {
   return compress_impl(cfg, in_dev, n, ws_dev, ws_bytes, out_host, out_cap, out_len, stream, false);
+}
+
+pmklc_status pmklc_compress_noalloc(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, uint8_t *out_host,
+                                    uint64_t out_cap, uint64_t *out_len, void *stream) {
+  uint64_t need = 0;
+  pmklc_status rc = pmklc_compress_bound(cfg, n, nullptr, &need);
+  if (rc) return rc;
+  if (need > kScratchBytes) return PMKLC_ERR_SCRATCH_LIMIT;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return PMKLC_ERR_DEVICE;
+  ScratchDev &sd = g_scratch[dev];
+  std::lock_guard<std::mutex> lk(sd.mu);
+  if (!sd.ptr) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(pmklc::scratch)) != hipSuccess || !p) return PMKLC_ERR_DEVICE;
+    sd.ptr = p;
+  }
+  return compress_impl(cfg, in_dev, n, sd.ptr, kScratchBytes, out_host, out_cap, out_len, stream, true);
 }
 
 // --------------------------------------------------------------- decode
