@@ -85,8 +85,8 @@ struct StatusSlot {
 };
 
 // numeric path of a container: which kernel computed its probabilities
-constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathUniform = 255;
-enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2 };
+constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathBF16Chip = 4, kPathUniform = 255;
+enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kChipBf16 = 3 };
 constexpr int kHeaderBytes = 80;
 
 #define HIP_TRY(x)                                     \
@@ -257,7 +257,7 @@ pmklc_status fill_dims(uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t
 // layers).
 pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh,
                         const uint32_t *hidden, uint32_t selector, uint32_t opt, float lr, float b1, float b2,
-                        float eps, uint32_t precision, Model &m) {
+                        float eps, uint32_t precision, Model &m, bool allow_chip) {
   (void)s;
   Dims &d = m.d;
   pmklc_status rc = fill_dims(k, t, bs, E, nh, hidden, selector, opt, lr, b1, b2, eps, d);
@@ -337,13 +337,38 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
     m.kind = kMfmaF32;
   }
   if (m.kind != kGeneric) m.nt = 512;
+  // BF16 with a shape the on-chip kernel is compiled for: its extra LDS
+  // regions (weights and gradient partials), when they fit
+  if (m.kind == kMfmaBf16 && allow_chip && L.dpb >= 0 && chip_supports(d)) {
+    LdsLayout C = L;
+    uint64_t o = (uint64_t)C.total;
+    auto take = [&](uint64_t bytes) { uint64_t at = o; o = align_up(o + bytes, 16); return (int)at; };
+    C.w1c = take(2ull * d.D * d.H[0]);
+    C.w2t = take(4ull * d.V * (d.H[0] + 4));
+    C.bias = take(4ull * (d.H[0] + d.V));
+    C.gb = take(4ull * (d.H[0] + d.V));
+    C.eg = take(4ull * 8 * d.V * d.E);
+    if (o <= 160 * 1024) {
+      C.total = (int)o;
+      L = C;
+      m.kind = kChipBf16;
+    }
+  }
   return PMKLC_OK;
 }
 
-pmklc_status make_model(const pmklc_config *c, Model &m) {
-  return make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, c->selector, c->optimizer, c->lr,
-                    c->beta1, c->beta2, c->eps, c->precision, m);
+// the on-chip kernel is the BF16 default for the shapes it has; PMKLC_NO_CHIP=1
+// selects the global-weight BF16 kernel instead (a different numeric path)
+bool chip_default() {
+  const char *e = getenv("PMKLC_NO_CHIP");
+  return !(e && e[0] == '1');
 }
+
+pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip) {
+  return make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, c->selector, c->optimizer, c->lr,
+                    c->beta1, c->beta2, c->eps, c->precision, m, allow_chip);
+}
+pmklc_status make_model(const pmklc_config *c, Model &m) { return make_model(c, m, chip_default()); }
 
 // -------------------------------------------------------------- planning
 struct Plan {
@@ -483,6 +508,12 @@ uint64_t trial_bytes(const Model &m) {
   return A.used + 256;
 }
 
+hipError_t launch_kind(const Model &m, const StepArgs &a, const StepArgs *a_dev, int grid, int nt, hipStream_t st) {
+  if (m.kind == kGeneric) return launch_step(a, grid, nt, st);
+  if (m.kind == kChipBf16) return launch_step_chip(a, a_dev, grid, st);
+  return launch_step_mfma(a, a_dev, grid, m.kind == kMfmaBf16, nt, st);
+}
+
 // One synthetic block of t + 64 steps (constant tokens) in encode mode,
 // best of two runs, with the candidate width, in the trial region of the
 // caller's workspace (region: trial_bytes(m) bytes).
@@ -533,7 +564,7 @@ hipError_t time_candidate(Model m, int nt, uint8_t *region, uint64_t cap, hipStr
     e = hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st);
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     if (e == hipSuccess)
-      e = m.kind == kGeneric ? launch_step(a, 1, nt, st) : launch_step_mfma(a, w.args, 1, m.kind == kMfmaBf16, nt, st);
+      e = launch_kind(m, a, w.args, 1, nt, st);
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float t = 0.0f;
@@ -561,7 +592,8 @@ hipError_t d2h(std::vector<T> &v, const T *src, uint64_t count, hipStream_t st) 
 
 uint8_t path_of(uint32_t selector, int kind) {
   if (!(selector & PMKLC_SEL_DM)) return kPathUniform;
-  return kind == kMfmaBf16 ? kPathBF16 : kind == kMfmaF32 ? kPathFP32Mfma : kPathFP32Valu;
+  return kind == kChipBf16 ? kPathBF16Chip : kind == kMfmaBf16 ? kPathBF16 : kind == kMfmaF32 ? kPathFP32Mfma
+                                                                                       : kPathFP32Valu;
 }
 
 void write_header(Writer &o, const pmklc_config *c, uint8_t path, uint32_t scrc, uint64_t n, uint32_t n_files) {
@@ -653,6 +685,8 @@ int choose_nt(Model &m, const Work &w, hipStream_t st, bool tune = true) {
   if (m.kind == kGeneric) {
     cands = {256};
     if (m.d.bs <= 512) cands.push_back(512);
+  } else if (m.kind == kChipBf16) {
+    cands = {512};   // its register-resident weights are laid out for 8 waves
   } else {
     cands = {256, 512};
   }
@@ -790,8 +824,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
       if (bd[b].pred >= 0 || bd[b].has_snap) return PMKLC_ERR_UNSUPPORTED;
       HIP_TRY(hipMemsetAsync(one.queue, 0, sizeof(int), st));
       HIP_TRY(hipMemcpyAsync(w.args + b, &one, sizeof(StepArgs), hipMemcpyHostToDevice, st));
-      if (m.kind == kGeneric) HIP_TRY(launch_step(one, 1, m.nt, st));
-      else HIP_TRY(launch_step_mfma(one, w.args + b, 1, m.kind == kMfmaBf16, m.nt, st));
+      HIP_TRY(launch_kind(m, one, w.args + b, 1, m.nt, st));
     }
   } else {
     int dev = 0, ncu = 0;
@@ -800,8 +833,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
     int grid = (int)std::min<uint64_t>(std::min<uint64_t>(bd.size(), (uint64_t)std::max(ncu, 1)), kMaxGrid);
     hold[0] = a;
     HIP_TRY(hipMemcpyAsync(w.args, &hold[0], sizeof(StepArgs), hipMemcpyHostToDevice, st));
-    if (m.kind == kGeneric) HIP_TRY(launch_step(a, grid, m.nt, st));
-    else HIP_TRY(launch_step_mfma(a, w.args, grid, m.kind == kMfmaBf16, m.nt, st));
+    HIP_TRY(launch_kind(m, a, w.args, grid, m.nt, st));
   }
   if (tm) HIP_TRY(hipEventRecord(tm->b, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -1155,9 +1187,11 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.n_blocks = (uint32_t)r.le(4);
   uint32_t nf = (uint32_t)r.le(4);
   if (r.bad) return PMKLC_ERR_CORRUPT;
-  c.precision = o.path == kPathBF16 ? PMKLC_BF16 : o.path == kPathFP32Valu ? PMKLC_FP32_VALU : PMKLC_FP32;
+  c.precision = (o.path == kPathBF16 || o.path == kPathBF16Chip) ? PMKLC_BF16
+                : o.path == kPathFP32Valu ? PMKLC_FP32_VALU : PMKLC_FP32;
   if (check_cfg(&c)) return PMKLC_ERR_CORRUPT;
-  if (o.path != kPathUniform && o.path != kPathBF16 && o.path != kPathFP32Valu && o.path != kPathFP32Mfma)
+  if (o.path != kPathUniform && o.path != kPathBF16 && o.path != kPathFP32Valu && o.path != kPathFP32Mfma &&
+      o.path != kPathBF16Chip)
     return PMKLC_ERR_MODEL_MISMATCH;
   if (nf < 1 || (uint64_t)nf > len || (uint64_t)c.n_blocks * 2 > len) return PMKLC_ERR_CORRUPT;
   o.file_blocks.resize(nf);
@@ -1247,7 +1281,7 @@ pmklc_status pmklc_decompress_info(const uint8_t *cbf_host, uint64_t len, uint64
   pmklc_status rc = parse(cbf_host, len, o, true);
   if (rc) return rc;
   Model m;
-  rc = make_model(&o.c, m);
+  rc = make_model(&o.c, m, o.path == kPathBF16Chip);
   if (rc) return rc;
   Plan p;
   rc = plan_blocks(o.n, o.c.n_blocks, nullptr, 0, nullptr, false, p);
@@ -1271,7 +1305,7 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   pmklc_status rc = parse(cbf_host, len, o, true);
   if (rc) return rc;
   Model m;
-  rc = make_model(&o.c, m);
+  rc = make_model(&o.c, m, o.path == kPathBF16Chip);
   if (rc) return rc;
   if (path_of(o.c.selector, m.kind) != o.path) return PMKLC_ERR_MODEL_MISMATCH;
   if (m.d.static_on) {
@@ -1522,8 +1556,7 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   if (w.s1f && static_dev) chk(launch_w1_frag(static_dev + m.d.off_W[0], m.d.D, m.d.H[0], w.s1f, st));
   chk(hipMemcpyAsync(w.args, &a, sizeof(StepArgs), hipMemcpyHostToDevice, st));
   if (e == hipSuccess) {
-    if (m.kind == kGeneric) chk(launch_step(a, 1, m.nt, st));
-    else chk(launch_step_mfma(a, w.args, 1, m.kind == kMfmaBf16, m.nt, st));
+    chk(launch_kind(m, a, w.args, 1, m.nt, st));
   }
   int herr[2] = {0, 0};
   chk(hipMemcpyAsync(herr, w.ctr, 8, hipMemcpyDeviceToHost, st));

@@ -43,6 +43,10 @@ struct LdsLayout {
                       // it fits), or -1 when absent
   int act_global;     // 1: act[] and dh[] are float offsets into a per-workgroup global slab
   int act_slot;       // floats per workgroup slab
+  // on-chip kernel only (step_chip.hip): BF16 W1 copy in F1 fragment order,
+  // FP32 W2^T [V][H+4], biases [H+V], their gradients [H+V], and the eight
+  // wave partials of the embedding gradient [8][V][E]
+  int w1c, w2t, bias, gb, eg;
 };
 constexpr int kMaxGrid = 1024;   // upper bound on step-kernel workgroups (global slabs)
 
@@ -111,6 +115,9 @@ hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStrea
 
 hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);
 hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, hipStream_t st);
+// the on-chip BF16 kernel: shapes compiled in, and its launch (512 threads)
+bool chip_supports(const Dims &d);
+hipError_t launch_step_chip(const StepArgs &a, const StepArgs *a_dev, int grid, hipStream_t st);
 hipError_t launch_init_params(const Dims &d, uint64_t seed, float *out, hipStream_t st);
 hipError_t launch_quantise(const float *P, uint32_t rows, uint32_t V, uint32_t *cdf, hipStream_t st);
 hipError_t launch_wnc_encode(const uint32_t *lo, const uint32_t *hi, uint64_t m, uint32_t *out_words,

@@ -396,15 +396,19 @@ __device__ __forceinline__ float opt_delta(const Opt &o, float g, F *m, F *v) {
 // phases 0 staging, 1 forward, 2 softmax+quantiser, 3 coder, 4 loss
 // gradient, 5 network backward, 6 embedding update; the network may split
 // its backward into 8.. (B1, B2+B3, B4). Enabled when a sink is given.
+// The sums live in LDS (acc, 12 entries, touched by the one active thread
+// only), so that a disabled clock holds no registers through the loop.
 struct PhaseClock {
   unsigned long long *sink;
-  unsigned long long acc[12];
+  unsigned long long *acc;
   unsigned long long t0;
   bool on;
-  __device__ void init(unsigned long long *s, bool active) {
+  __device__ void init(unsigned long long *s, unsigned long long *acc_lds, bool active) {
     sink = s;
+    acc = acc_lds;
     on = s && active;
-    for (int q = 0; q < 12; q++) acc[q] = 0;
+    if (on)
+      for (int q = 0; q < 12; q++) acc[q] = 0;
     t0 = on ? wall_clock64() : 0;
   }
   __device__ __forceinline__ void mark(int phase) {
@@ -427,13 +431,20 @@ using namespace detail;
 // passing, token staging, mixer + softmax + quantiser, coders, loss
 // gradient, embedding and mixing-weight updates.  `Net` supplies the
 // forward (logits into lm, and lu when the static model is on) and the
-// backward of the MLP layers (weight updates and the embedding-gradient
-// scatter); both end with a workgroup barrier.
+// backward of the MLP layers (weight updates and the embedding gradient);
+// both end with a workgroup barrier.  A Net with kOnChip keeps its layer
+// parameters in registers and LDS during a block: it writes them back to
+// the parameter slab with flush() (before a snapshot and at the block's
+// end), hands over the embedding gradient through emb_grad(), and updates
+// what it keeps on chip besides the weight matrices in after_update(),
+// during the embedding-update phase.  The others sum the embedding
+// gradient into the fixed-point table demb.
 template <int NT, class Net>
 __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds, Net &net) {
   __shared__ int sh_b;
   __shared__ float sh_ga;
   __shared__ float sh_a;   // the mixing weight's raw parameter a (Eq. 1), kept beside its global copy
+  __shared__ unsigned long long sh_pc[12];   // phase clock sums (block 0, thread 0)
   const Dims &d = a.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bs = d.bs, V = d.V, E = d.E, t = d.t, RS = d.RS, mask = d.RS - 1, VS = d.VS;
@@ -512,10 +523,15 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       emb[qp] = W[d.off_emb + q];
       if (d.static_on) embs[qp] = a.stat[d.off_emb + q];
     }
-    for (int q = tid; q < V * d.ES; q += NT) demb[q] = 0;
+    if constexpr (!Net::kOnChip)
+      for (int q = tid; q < V * d.ES; q += NT) demb[q] = 0;
     __syncthreads();
 
     auto snapshot = [&]() {
+      if constexpr (Net::kOnChip) {
+        net.flush(W);
+        __syncthreads();
+      }
       float *dst = a.snap + (size_t)b * stride;
       for (int q = tid; q < stride; q += NT) {
         const int qe = q - d.off_emb;
@@ -551,7 +567,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     int probe_i = 0;
     const size_t tok0 = bd.tok_off;
     PhaseClock pc;
-    pc.init(a.phase_clk, b == 0 && tid == 0);
+    pc.init(a.phase_clk, sh_pc, b == 0 && tid == 0);
     net.pc = &pc;
 
     for (uint64_t i = 0; i < Lrun; i++) {
@@ -587,10 +603,12 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
           float srow;
           const bool probe = a.probe_P && b == 0 && probe_i < a.n_probe && a.probe_steps[probe_i] == i;
           float *pp = probe ? a.probe_P + ((size_t)probe_i * bs + j) * V + gl * spl : nullptr;
-          if (spl == 8) {
+          if (Net::kSpl == 8 || (Net::kSpl == 0 && spl == 8)) {
             float pr[8];
             srow = row_softmax_regs<8>(lr, ur, d.static_on, alpha, V, G, gl, crow, pr);
             if (pp) for (int q = 0; q < 8; q++) pp[q] = pr[q];
+          } else if (Net::kSpl != 0) {
+            __builtin_unreachable();
           } else if (spl == 4) {
             float pr[4];
             srow = row_softmax_regs<4>(lr, ur, d.static_on, alpha, V, G, gl, crow, pr);
@@ -684,11 +702,18 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         for (int q = tid; q < V * E; q += NT) {
           const int v = (int)__umulhi((uint32_t)q, d.Emag);
           const int qi = q + v * (d.ES - E), qp = q + v * (d.EP - E);
-          float gq = (float)((double)demb[qi] * (1.0 / (double)(1ull << kFixShift)));
-          demb[qi] = 0;
+          float gq;
+          if constexpr (Net::kOnChip) {
+            (void)qi;
+            gq = net.emb_grad(v, q - v * E);
+          } else {
+            gq = (float)((double)demb[qi] * (1.0 / (double)(1ull << kFixShift)));
+            demb[qi] = 0;
+          }
           const int pi = d.off_emb + q;
           emb[qp] = emb[qp] - opt_delta(opt, gq, M ? glb(M) + pi : nullptr, Vs ? glb(Vs) + pi : nullptr);
         }
+        if constexpr (Net::kOnChip) net.after_update(opt);
         if (d.static_on && tid == 0) {
           const float an = sh_a - opt_delta(opt, sh_ga, M ? glb(M) + d.P : nullptr, Vs ? glb(Vs) + d.P : nullptr);
           sh_a = an;
@@ -703,6 +728,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     }
 
     pc.flush();
+    if constexpr (Net::kOnChip) net.flush(W);
     if (tid < bs) {
       CoderState cs = cst[tid];
       if (a.mode == 0) {

@@ -176,6 +176,8 @@ __device__ __forceinline__ void bwd_w_tile(int d0, int o0, int rows, int Dout, f
 
 template <int NT>
 struct NetGeneric {
+  static constexpr bool kOnChip = false;
+  static constexpr int kSpl = 0;   // softmax symbols per lane: chosen at run time
   const StepArgs &a;
   const Dims &d;
   float *emb, *embs, *act[2], *lm, *lu, *dh[2];

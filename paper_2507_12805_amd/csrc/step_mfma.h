@@ -104,6 +104,8 @@ __device__ __forceinline__ void load_strided(const F *p, int stride, float *v) {
 // the other's registers out of its allocation
 template <int NT, class P, int MAXT, bool ADAM, int F1N>
 struct NetMfma {
+  static constexpr bool kOnChip = false;
+  static constexpr int kSpl = 0;   // softmax symbols per lane: chosen at run time
   static constexpr int NW = NT / 64;
   static constexpr int KS = P::KS, KL = P::KL;   // MAXT = bs / 16 row tiles
   static constexpr int KC = 16 / KL;             // k-steps per streamed chunk (16 raw floats per lane)

@@ -195,7 +195,10 @@ def test_plain_and_batched_schedules_give_identical_bytes(gpu):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp32_valu"])
 def test_autotuner_choices_give_identical_bytes(gpu, precision, monkeypatch):
-    """Every workgroup width the autotuner may pick yields the same container."""
+    """Every workgroup width the autotuner may pick yields the same container
+    (BF16: the global-weight kernel, which has two widths; the on-chip
+    kernel has one)."""
+    monkeypatch.setenv("PMKLC_NO_CHIP", "1")
     a = _dna(60000, seed=21, n_rate=0.001)
     cfg = model_small(n_blocks=3, precision=precision)
     blobs = []
@@ -219,14 +222,19 @@ def test_smp_chain_roundtrip_and_snapshot(gpu, orc):
     assert blob != gpu.compress(dict(cfg, smp_ppm=0), _cuda(a))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp32_valu"])
-def test_smp_snapshot_bit_exact(gpu, orc, precision):
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp32_valu", "bf16_global"])
+def test_smp_snapshot_bit_exact(gpu, orc, precision, monkeypatch):
     """Model passing (Sec. 4.3): the second block of a file starts from the
     first block's parameters after ceil(5% of its steps) steps. Its segment
     streams in the chained container equal, byte for byte, those of a
     single-block run over its tokens started from the parameters the first
     block's own run reaches at that step, and differ from a start one step
-    later; the first block's streams equal its seeded single-block run."""
+    later; the first block's streams equal its seeded single-block run.
+    (BF16 on the on-chip kernel, which writes its parameters back for the
+    snapshot, and on the global-weight kernel.)"""
+    if precision == "bf16_global":
+        monkeypatch.setenv("PMKLC_NO_CHIP", "1")
+        precision = "bf16"
     cfg = model_small(precision=precision)
     bs, t = cfg["bs"], cfg["t"]
     L0, L1 = 800, 300
@@ -329,21 +337,25 @@ def test_trajectory_probabilities_cfg1(gpu, orc, precision):
     assert abs(len(blob_g) - len(blob_o)) <= 0.005 * len(blob_o)
 
 
-@pytest.mark.parametrize("precision,path", [("fp32", 3), ("fp32_valu", 1), ("bf16", 2)])
-def test_numeric_paths_roundtrip_and_ratio(gpu, orc, precision, path):
+@pytest.mark.parametrize("precision,path,path2,nochip", [("fp32", 3, 3, "0"), ("fp32_valu", 1, 1, "0"),
+                                                          ("bf16", 4, 2, "0"), ("bf16", 2, 2, "1")])
+def test_numeric_paths_roundtrip_and_ratio(gpu, orc, precision, path, path2, nochip, monkeypatch):
     """Every numeric path: bit-exact GPU round trip, identical bytes from
     both launch schedules, ratio within 0.5% of the FP64 oracle on the first
-    workload and on a 1 MiB sample of the static + dynamic workload. BF16
+    workload (path) and on a 1 MiB sample of the static + dynamic workload
+    (path2). BF16 runs the on-chip kernel (path 4) where it has the shape,
+    or, with PMKLC_NO_CHIP=1, the global-weight kernel (path 2). BF16
     probabilities are reported (|dp| statistics), not held to 1e-4."""
     from synth.workloads import cfg2
+    monkeypatch.setenv("PMKLC_NO_CHIP", nochip)
     static = np.fromfile(os.path.join(GOLD, "static_cfg2.f32"), dtype=np.float32)
     rec2, c2 = cfg2(n=1 << 20, n_blocks=16)
-    cases = [(synth.generate(synth.recipe_cfg1()), model_small(), None),
-             (synth.generate(rec2), c2, static)]
-    for a, cfg, st in cases:
+    cases = [(synth.generate(synth.recipe_cfg1()), model_small(), None, path),
+             (synth.generate(rec2), c2, static, path2)]
+    for a, cfg, st, pid in cases:
         cfg = dict(cfg, precision=precision)
         blob = gpu.compress(cfg, _cuda(a), static=st)
-        assert blob[5] == path
+        assert blob[5] == pid
         assert np.array_equal(gpu.decompress(blob, static=st).cpu().numpy(), a)
         assert gpu.compress(dict(cfg, schedule="plain"), _cuda(a), static=st) == blob
         blob_o = orc.compress(cfg, a, static=st)
