@@ -25,7 +25,8 @@ struct Dims {
                                 // 16 tokens fall in distinct banks, float4 runs stay aligned)
   int HP;                       // row pitch (floats) of the hidden activations of the matrix-core
                                 // kernel in LDS (H[0] + 4, same reason)
-  int RS;                       // context ring length (power of two >= t + CH)
+  int RS;                       // context ring length in positions (power of two >= t + CH); the ring is
+                                // position-major: position q of row j is byte (q mod RS) * bs + j
   int CH;                       // tokens staged per row at a time (encode)
   uint32_t Emag;                // ceil(2^32 / E): k / E = umulhi(k, Emag) for k < 2^20, E < 4096
   int static_on;                // frozen static model mixed in (Eq. 1)

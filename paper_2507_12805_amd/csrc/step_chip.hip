@@ -19,7 +19,6 @@
 //
 // Operand layout of a 16x16 tile (lane l, r = l % 16, g = l / 16):
 //   16x16x32 BF16: A[r][8g .. 8g+7], B[8g .. 8g+7][r], C[4g+c][r] (c = 0..3)
-//   16x16x16 BF16: A[r][4g .. 4g+3], B[4g .. 4g+3][r], same C
 // Per step, rows j (BS), inputs d (D = T E), hidden h (H), symbols v (V):
 //   F1  H1 = ReLU(X W1 + b1)              units (row tile, hidden tile)
 //   F2  L  = H1 W2 + b2                   units (row tile, symbol tile)
@@ -29,8 +28,8 @@
 //   B4  dW1^T = dpre^T X -> W1 update     per d tile
 //   EG  dEmb = onehot(ctx)^T dX           per d tile: with E = 16 a d tile is
 //       one context position p, and sum_j [ctx_j,p = v] dX[j][16p + e] is a
-//       16x16x16 product of a one-hot fragment and B3's output as it lies
-//       in the accumulator (its C layout is the B layout of that product)
+//       product of one-hot fragments and B3's output as it lies in the
+//       accumulators (two row tiles' C layouts make one B fragment)
 // Every output element is one MFMA accumulation chain in a fixed order; the
 // embedding gradient is one chain per wave (its d tiles in order) and the
 // eight wave partials are added in wave order, so encode and decode agree
@@ -41,13 +40,10 @@ namespace pmklc {
 
 namespace {
 
-typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f32x4 mma16(s16x4 a, s16x4 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ bf16x8 bf8(const float *v) {
   bf16x8 f;
@@ -106,7 +102,7 @@ struct NetChip {
 
   // token of context position p (0..T-1) of row j at step i
   __device__ __forceinline__ int token(int j, int p, uint64_t i) const {
-    return ring[j * RS + (((int)(i - (uint64_t)T) + p) & (RS - 1))];
+    return ring[((((int)(i - (uint64_t)T) + p) & (RS - 1))) * BS + j];
   }
   __device__ __forceinline__ size_t w1_at(int q, int m) const {   // W1 index of this lane's run (q, m)
     return (size_t)(16 * (wave + NW * q) + r) * H + 16 * m + 4 * g;
@@ -276,13 +272,16 @@ struct NetChip {
 #pragma unroll
     for (int q = 0; q < DTW; q++) {
       const int mt = wave + NW * q, p = mt;   // E = 16: d tile mt is context position mt, e = r
-      // X fragments (B4's B operand): X[32 kb + 8 g + c][16 mt + r]
+      // X fragments (B4's B operand): X[32 kb + 8 g + c][16 mt + r]; the ring
+      // is position-major, so the 8 rows' tokens are one 8-byte read
+      const uint8_t *tp = ring + ((((int)(i - (uint64_t)T) + p) & (RS - 1))) * BS;
       bf16x8 xb[KB];
 #pragma unroll
       for (int kb = 0; kb < KB; kb++) {
+        const u32x2 t8 = *reinterpret_cast<const u32x2 *>(tp + 32 * kb + 8 * g);
         float xv[8];
 #pragma unroll
-        for (int c = 0; c < 8; c++) xv[c] = emb[token(32 * kb + 8 * g + c, p, i) * EP + r];
+        for (int c = 0; c < 8; c++) xv[c] = emb[((t8[c >> 2] >> (8 * (c & 3))) & 0xFFu) * EP + r];
         xb[kb] = bf8(xv);
       }
       // B4: dW1^T[h][d] for every hidden tile m (C: h = 16 m + 4 g + c, d = 16 mt + r)
@@ -314,27 +313,44 @@ struct NetChip {
                              w1m[q][2 * kh + 1][0], w1m[q][2 * kh + 1][1], w1m[q][2 * kh + 1][2], w1m[q][2 * kh + 1][3]};
         wb[kh] = bf8(wv);
       }
+      f32x4 acc3[MT];
 #pragma unroll
       for (int rt = 0; rt < MT; rt++) {
-        f32x4 acc3 = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        acc3[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kh = 0; kh < KH; kh++)
-          acc3 = mma32(*reinterpret_cast<const bf16x8 *>(dpb + ((rt * KH + kh) * 64 + lane) * 8), wb[kh], acc3);
-        // embedding gradient: the dX tile (rows 16 rt + 4 g + c, e = r) as the
-        // B operand, one-hot rows of the context tokens as the A operand
-        s16x4 bx;
+          acc3[rt] = mma32(*reinterpret_cast<const bf16x8 *>(dpb + ((rt * KH + kh) * 64 + lane) * 8), wb[kh], acc3[rt]);
+      }
+      // embedding gradient over row-tile pairs (2k, 2k+1), K = 32 rows in the
+      // slot order s < 4: row 32k + 4g + s, s >= 4: row 32k + 16 + 4g + s - 4,
+      // which is how the two dX tiles lie in the accumulators (C layout: rows
+      // 4g + c, column e = r).  B = those dX values; A = one-hot rows of the
+      // same rows' tokens at this position (BF16 1.0 where token = 16 vt + r).
+      // The 4 tokens of rows 16 rt + 4g .. +3 are one 4-byte read.
 #pragma unroll
-        for (int c = 0; c < 4; c++) bx[c] = __builtin_bit_cast(short, (__bf16)acc3[c]);
-        int tk[4];
+      for (int k = 0; k < MT / 2; k++) {
+        const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tp + 32 * k + 4 * g);
+        const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tp + 32 * k + 16 + 4 * g);
+        int x[8];
 #pragma unroll
-        for (int c = 0; c < 4; c++) tk[c] = token(16 * rt + 4 * g + c, p, i) - r;
+        for (int s2 = 0; s2 < 4; s2++) {
+          x[s2] = (int)((t0 >> (8 * s2)) & 0xFFu) - r;
+          x[4 + s2] = (int)((t1 >> (8 * s2)) & 0xFFu) - r;
+        }
+        const float dv[8] = {acc3[2 * k][0], acc3[2 * k][1], acc3[2 * k][2], acc3[2 * k][3],
+                             acc3[2 * k + 1][0], acc3[2 * k + 1][1], acc3[2 * k + 1][2], acc3[2 * k + 1][3]};
+        const bf16x8 bx = bf8(dv);
+        bf16x8 oh[VT];
 #pragma unroll
         for (int vt = 0; vt < VT; vt++) {
-          s16x4 oh;
+          u32x4 w;
 #pragma unroll
-          for (int c = 0; c < 4; c++) oh[c] = tk[c] == 16 * vt ? (short)0x3F80 : (short)0;   // BF16 1.0 or 0
-          acce[vt] = mma16(oh, bx, acce[vt]);
+          for (int s2 = 0; s2 < 4; s2++)
+            w[s2] = (x[2 * s2] == 16 * vt ? 0x3F80u : 0u) | (x[2 * s2 + 1] == 16 * vt ? 0x3F800000u : 0u);
+          oh[vt] = __builtin_bit_cast(bf16x8, w);
         }
+#pragma unroll
+        for (int vt = 0; vt < VT; vt++) acce[vt] = mma32(oh[vt], bx, acce[vt]);
       }
       // W1 update, and the BF16 copy: the four lanes of a quad hold 4
       // consecutive d with the same 4 consecutive h; a 4x4 transpose of the

@@ -447,7 +447,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
   __shared__ unsigned long long sh_pc[12];   // phase clock sums (block 0, thread 0)
   const Dims &d = a.d;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bs = d.bs, V = d.V, E = d.E, t = d.t, RS = d.RS, mask = d.RS - 1, VS = d.VS;
+  const int bs = d.bs, V = d.V, E = d.E, t = d.t, mask = d.RS - 1, VS = d.VS;
   float *emb = reinterpret_cast<float *>(lds + a.lay.emb);
   float *embs = reinterpret_cast<float *>(lds + a.lay.embs);
   uint8_t *ring = lds + a.lay.ring;
@@ -578,7 +578,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
         for (int q = tid; q < bs * CH; q += NT) {
           const int j = q >> chs, c = q & (CH - 1);
           uint64_t pos = i + (uint64_t)c;
-          if (pos < bd.L) ring[j * RS + (int)(pos & (uint64_t)mask)] = toks[tok0 + (size_t)j * bd.L + pos];
+          if (pos < bd.L) ring[(int)(pos & (uint64_t)mask) * bs + j] = toks[tok0 + (size_t)j * bd.L + pos];
         }
         __syncthreads();
       }
@@ -630,7 +630,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
       // ---- coding: lane j codes token i of segment j
       if (tid < bs) {
         const int j = tid;
-        const int rp = j * RS + (int)(i & (uint64_t)mask);
+        const int rp = (int)(i & (uint64_t)mask) * bs + j;
         const uint32_t unit = kTotal / (uint32_t)V;
         CoderState cs = cst[j];
         gu32 *slot = slot_of(j);

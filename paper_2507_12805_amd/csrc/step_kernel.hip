@@ -36,7 +36,7 @@ namespace {
 // ------------------------------------------------------------ GEMM tiles
 struct Ctx {   // context-window gather for the first layer
   const uint8_t *ring;
-  int RS, mask, base;   // ring row length, RS-1, (i - t)
+  int rows, mask, base;   // ring positions are rows bytes apart (one byte per row); RS-1; (i - t)
   const float *emb;
   int E, EP;            // embedding width, LDS row pitch
 };
@@ -55,7 +55,7 @@ __device__ __forceinline__ void fwd_tile(int r0, int c0, int Din, int Dout, cons
     for (int p = 0; p < t; p++) {
       int tk[4];
 #pragma unroll
-      for (int r = 0; r < 4; r++) tk[r] = g->ring[(r0 + r) * g->RS + ((g->base + p) & g->mask)];
+      for (int r = 0; r < 4; r++) tk[r] = g->ring[((g->base + p) & g->mask) * g->rows + (r0 + r)];
       for (int e = 0; e < g->E; e += 4) {
         float4 a[4], w[4];
 #pragma unroll
@@ -145,7 +145,7 @@ __device__ __forceinline__ void bwd_w_tile(int d0, int o0, int rows, int Dout, f
   for (int j = 0; j < rows; j++) {
     float4 a;
     if (g) {
-      int tk = g->ring[j * g->RS + ((g->base + p) & g->mask)];
+      int tk = g->ring[((g->base + p) & g->mask) * g->rows + j];
       a = *reinterpret_cast<const float4 *>(g->emb + tk * g->EP + e);
     } else {
       a = *reinterpret_cast<const float4 *>(in + j * Din + d0);
@@ -213,9 +213,9 @@ struct NetGeneric {
   // forward, layer by layer; DM and static tiles share one pass
   __device__ void forward(float *W, uint64_t i, float alpha) {
     (void)alpha;
-    const int bs = d.bs, nh = d.nh, RS = d.RS, mask = d.RS - 1, t = d.t, E = d.E;
-    Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E, d.EP};
-    Ctx gs{ring, RS, mask, (int)(i - (uint64_t)t), embs, E, d.EP};
+    const int bs = d.bs, nh = d.nh, mask = d.RS - 1, t = d.t, E = d.E;
+    Ctx g{ring, bs, mask, (int)(i - (uint64_t)t), emb, E, d.EP};
+    Ctx gs{ring, bs, mask, (int)(i - (uint64_t)t), embs, E, d.EP};
     for (int l = 0; l <= nh; l++) {
       const int Din = d.dim[l], Dout = d.dim[l + 1];
       const bool last = (l == nh);
@@ -238,8 +238,8 @@ struct NetGeneric {
   // lm holds dL/dL^m; gradients of every layer with the old weights, then
   // the optimiser update, layer by layer from the output down
   __device__ void backward(float *W, float *M, float *Vs, uint64_t i, const Opt &opt) {
-    const int bs = d.bs, nh = d.nh, RS = d.RS, mask = d.RS - 1, t = d.t, E = d.E;
-    const Ctx g{ring, RS, mask, (int)(i - (uint64_t)t), emb, E, d.EP};
+    const int bs = d.bs, nh = d.nh, mask = d.RS - 1, t = d.t, E = d.E;
+    const Ctx g{ring, bs, mask, (int)(i - (uint64_t)t), emb, E, d.EP};
     const float *dout = lm;
     int ldo = d.VS;
     for (int l = nh; l >= 0; l--) {
@@ -271,7 +271,7 @@ struct NetGeneric {
 #pragma unroll
             for (int q = 0; q < 4; q++) {
               const int dd = c0 + q, p = dd / E, e = dd % E;
-              const int tk = ring[j * RS + (((int)(i - (uint64_t)t) + p) & mask)];
+              const int tk = ring[((((int)(i - (uint64_t)t) + p) & mask)) * bs + j];
               atomicAdd(reinterpret_cast<unsigned long long *>(demb + tk * d.ES + e),
                         (unsigned long long)to_fixed(acc[r][q]));
             }

@@ -272,7 +272,7 @@ struct NetMfma {
 
   // token of context position p (0..t-1) of row j at step i
   __device__ __forceinline__ int token(int j, int p, uint64_t i) const {
-    return ring[j * d.RS + (((int)(i - (uint64_t)d.t) + p) & (d.RS - 1))];
+    return ring[((((int)(i - (uint64_t)d.t) + p) & (d.RS - 1))) * d.bs + j];
   }
   __device__ __forceinline__ void split_k(int kk, int &p, int &e) const {
     p = (int)__umulhi((uint32_t)kk, d.Emag);
