@@ -348,6 +348,7 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
     C.bias = take(4ull * (d.H[0] + d.V));
     C.gb = take(4ull * (d.H[0] + d.V));
     C.eg = take(4ull * 8 * d.V * d.E);
+    C.embh = take(2ull * d.V * (d.E + 8));
     if (o <= 160 * 1024) {
       C.total = (int)o;
       L = C;

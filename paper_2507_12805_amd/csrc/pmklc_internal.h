@@ -45,9 +45,10 @@ struct LdsLayout {
   int act_global;     // 1: act[] and dh[] are float offsets into a per-workgroup global slab
   int act_slot;       // floats per workgroup slab
   // on-chip kernel only (step_chip.hip): BF16 W1 copy in F1 fragment order,
-  // FP32 W2^T [V][H+4], biases [H+V], their gradients [H+V], and the eight
-  // wave partials of the embedding gradient [8][V][E]
-  int w1c, w2t, bias, gb, eg;
+  // FP32 W2^T [V][H+4], biases [H+V], their gradients [H+V], the eight
+  // wave partials of the embedding gradient [8][V][E], and a BF16 copy of
+  // the embedding [V][E+8]
+  int w1c, w2t, bias, gb, eg, embh;
 };
 constexpr int kMaxGrid = 1024;   // upper bound on step-kernel workgroups (global slabs)
 

@@ -20,7 +20,7 @@
 // Operand layout of a 16x16 tile (lane l, r = l % 16, g = l / 16):
 //   16x16x32 BF16: A[r][8g .. 8g+7], B[8g .. 8g+7][r], C[4g+c][r] (c = 0..3)
 // Per step, rows j (BS), inputs d (D = T E), hidden h (H), symbols v (V):
-//   F1  H1 = ReLU(X W1 + b1)              units (row tile, hidden tile)
+//   F1  H1 = ReLU(X W1 + b1)              units: row tiles (all hidden tiles)
 //   F2  L  = H1 W2 + b2                   units (row tile, symbol tile)
 //   B1  dpre = (dz W2^T) * [H1 > 0]       units (row tile, hidden tile)
 //   B2  dW2^T = dz^T H1 -> W2 update      units (symbol tile, hidden tile)
@@ -67,6 +67,7 @@ struct NetChip {
   static constexpr int DTW = DT / NW;                       // d tiles per wave
   static constexpr int HP = H + 4, VS = V + 4, EP = E + 4;  // LDS row pitches (floats), as in the layout
   static constexpr int W2P = H + 4;                          // pitch of W2^T rows
+  static constexpr int EPH = E + 8;                          // pitch of the BF16 embedding rows (16-byte runs)
   static constexpr int RS = ring_len(T);
   static_assert(E == 16, "a d tile is one context position");
   static_assert(H % 32 == 0 && V % 32 == 0 && BS % 32 == 0 && DT % NW == 0, "tile multiples");
@@ -76,7 +77,7 @@ struct NetChip {
   unsigned char *lds;
   float *emb, *h1, *lm, *w2t, *bias, *gb, *eg;
   uint8_t *ring;
-  __bf16 *dpt, *dpb, *w1c;
+  __bf16 *dpt, *dpb, *w1c, *embh;
   int tid, lane, wave, r, g;
   float w1m[DTW][HT][4];
   PhaseClock *pc = nullptr;
@@ -93,6 +94,7 @@ struct NetChip {
     dpt = reinterpret_cast<__bf16 *>(lds + a.lay.dpt);
     dpb = reinterpret_cast<__bf16 *>(lds + a.lay.dpb);
     w1c = reinterpret_cast<__bf16 *>(lds + a.lay.w1c);
+    embh = reinterpret_cast<__bf16 *>(lds + a.lay.embh);
     tid = threadIdx.x;
     lane = tid & 63;
     wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -151,30 +153,50 @@ struct NetChip {
     for (int w = 0; w < NW; w++) s += eg[(w * V + v) * E + e];
     return s;
   }
+  // the BF16 embedding copy follows every write of the FP32 embedding
+  __device__ __forceinline__ void emb_set(int v, int e, float x) { embh[v * EPH + e] = (__bf16)x; }
   // bias updates from the gradients gathered by the backward
   __device__ void after_update(const Opt &opt) {
     for (int c = tid; c < H + V; c += NT) bias[c] = bias[c] - opt_delta_c<false>(opt, gb[c], (float *)nullptr, (float *)nullptr);
   }
 
   __device__ void forward(float *, uint64_t i, float) {
-    // F1: X W1 + b1, ReLU; X fragments gathered from the embedding through
-    // the context ring (8 consecutive inputs = 8 columns of one position),
-    // W1 fragments from the LDS copy (one 16-byte read)
-    for (int u = wave; u < MT * HT; u += NW) {
-      const int rt = u / HT, n = u - rt * HT, j = 16 * rt + r;
-      f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // F1: X W1 + b1, ReLU.  A unit is one row tile and every hidden tile:
+    // each X fragment (8 consecutive inputs = 8 columns of one position, one
+    // 16-byte read of the BF16 embedding) feeds HT MFMAs; W1 fragments come
+    // from the LDS copy (one 16-byte read each)
+    for (int rt = wave; rt < MT; rt += NW) {
+      const int j = 16 * rt + r;
+      f32x4 acc[HT];
 #pragma unroll
-      for (int ks = 0; ks < KD; ks++) {
-        const int k = 32 * ks + 8 * g, p = k / E, e = k % E;
-        const float *er = emb + token(j, p, i) * EP + e;
-        const fvec4 x0 = *reinterpret_cast<const fvec4 *>(er), x1 = *reinterpret_cast<const fvec4 *>(er + 4);
-        const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-        const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(w1c + ((n * KD + ks) * 64 + lane) * 8);
-        acc = mma32(bf8(xv), bw, acc);
+      for (int n = 0; n < HT; n++) acc[n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      // every k-step's token first (independent reads, one wait), then the
+      // fragments a few k-steps at a time
+      int tk[KD];
+#pragma unroll
+      for (int ks = 0; ks < KD; ks++) tk[ks] = token(j, (32 * ks + 8 * g) / E, i);
+      constexpr int KG = 4;
+#pragma unroll
+      for (int k0 = 0; k0 < KD; k0 += KG) {
+        bf16x8 xa[KG], wf[KG][HT];
+#pragma unroll
+        for (int c = 0; c < KG; c++) {
+          xa[c] = *reinterpret_cast<const bf16x8 *>(embh + tk[k0 + c] * EPH + (32 * (k0 + c) + 8 * g) % E);
+#pragma unroll
+          for (int n = 0; n < HT; n++)
+            wf[c][n] = *reinterpret_cast<const bf16x8 *>(w1c + ((n * KD + k0 + c) * 64 + lane) * 8);
+        }
+#pragma unroll
+        for (int c = 0; c < KG; c++)
+#pragma unroll
+          for (int n = 0; n < HT; n++) acc[n] = mma32(xa[c], wf[c][n], acc[n]);
       }
-      const float b = bias[16 * n + r];
 #pragma unroll
-      for (int c = 0; c < 4; c++) h1[(16 * rt + 4 * g + c) * HP + 16 * n + r] = fmaxf(acc[c] + b, 0.0f);
+      for (int n = 0; n < HT; n++) {
+        const float b = bias[16 * n + r];
+#pragma unroll
+        for (int c = 0; c < 4; c++) h1[(16 * rt + 4 * g + c) * HP + 16 * n + r] = fmaxf(acc[n][c] + b, 0.0f);
+      }
     }
     __syncthreads();
     pc->mark(7);
@@ -272,18 +294,40 @@ struct NetChip {
 #pragma unroll
     for (int q = 0; q < DTW; q++) {
       const int mt = wave + NW * q, p = mt;   // E = 16: d tile mt is context position mt, e = r
-      // X fragments (B4's B operand): X[32 kb + 8 g + c][16 mt + r]; the ring
-      // is position-major, so the 8 rows' tokens are one 8-byte read
+      // this tile's tokens first: the ring is position-major, so the tokens
+      // of 8 (4) consecutive rows at this position are one 8-byte (4-byte)
+      // read; B3, which needs none of them, covers their latency
       const uint8_t *tp = ring + ((((int)(i - (uint64_t)T) + p) & (RS - 1))) * BS;
+      u32x2 t8[KB];
+#pragma unroll
+      for (int kb = 0; kb < KB; kb++) t8[kb] = *reinterpret_cast<const u32x2 *>(tp + 32 * kb + 8 * g);
+      uint32_t t4[MT];
+#pragma unroll
+      for (int rt = 0; rt < MT; rt++) t4[rt] = *reinterpret_cast<const uint32_t *>(tp + 16 * rt + 4 * g);
+      // B3 with the old W1: dX[j][d] = sum_h dpre[j][h] W1[d][h]; the
+      // lane's own master values are the W1^T fragment in B3's slot order
+      bf16x8 wb[KH];
+#pragma unroll
+      for (int kh = 0; kh < KH; kh++) {
+        const float wv[8] = {w1m[q][2 * kh][0], w1m[q][2 * kh][1], w1m[q][2 * kh][2], w1m[q][2 * kh][3],
+                             w1m[q][2 * kh + 1][0], w1m[q][2 * kh + 1][1], w1m[q][2 * kh + 1][2], w1m[q][2 * kh + 1][3]};
+        wb[kh] = bf8(wv);
+      }
+      f32x4 acc3[MT];
+#pragma unroll
+      for (int rt = 0; rt < MT; rt++) {
+        acc3[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kh = 0; kh < KH; kh++)
+          acc3[rt] = mma32(*reinterpret_cast<const bf16x8 *>(dpb + ((rt * KH + kh) * 64 + lane) * 8), wb[kh], acc3[rt]);
+      }
+      // X fragments (B4's B operand): X[32 kb + 8 g + c][16 mt + r] from the
+      // BF16 embedding
       bf16x8 xb[KB];
 #pragma unroll
-      for (int kb = 0; kb < KB; kb++) {
-        const u32x2 t8 = *reinterpret_cast<const u32x2 *>(tp + 32 * kb + 8 * g);
-        float xv[8];
+      for (int kb = 0; kb < KB; kb++)
 #pragma unroll
-        for (int c = 0; c < 8; c++) xv[c] = emb[((t8[c >> 2] >> (8 * (c & 3))) & 0xFFu) * EP + r];
-        xb[kb] = bf8(xv);
-      }
+        for (int c = 0; c < 8; c++) xb[kb][c] = embh[((t8[kb][c >> 2] >> (8 * (c & 3))) & 0xFFu) * EPH + r];
       // B4: dW1^T[h][d] for every hidden tile m (C: h = 16 m + 4 g + c, d = 16 mt + r)
       f32x4 acc4[HT];
 #pragma unroll
@@ -304,75 +348,52 @@ struct NetChip {
             accb1[m] = mma32(*reinterpret_cast<const bf16x8 *>(dpt + ((m * KB + kb) * 64 + lane) * 8), onef, accb1[m]);
         }
       }
-      // B3 with the old W1: dX[j][d] = sum_h dpre[j][h] W1[d][h]; the
-      // lane's own master values are the W1^T fragment in B3's slot order
-      bf16x8 wb[KH];
-#pragma unroll
-      for (int kh = 0; kh < KH; kh++) {
-        const float wv[8] = {w1m[q][2 * kh][0], w1m[q][2 * kh][1], w1m[q][2 * kh][2], w1m[q][2 * kh][3],
-                             w1m[q][2 * kh + 1][0], w1m[q][2 * kh + 1][1], w1m[q][2 * kh + 1][2], w1m[q][2 * kh + 1][3]};
-        wb[kh] = bf8(wv);
-      }
-      f32x4 acc3[MT];
-#pragma unroll
-      for (int rt = 0; rt < MT; rt++) {
-        acc3[rt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int kh = 0; kh < KH; kh++)
-          acc3[rt] = mma32(*reinterpret_cast<const bf16x8 *>(dpb + ((rt * KH + kh) * 64 + lane) * 8), wb[kh], acc3[rt]);
-      }
       // embedding gradient over row-tile pairs (2k, 2k+1), K = 32 rows in the
       // slot order s < 4: row 32k + 4g + s, s >= 4: row 32k + 16 + 4g + s - 4,
       // which is how the two dX tiles lie in the accumulators (C layout: rows
       // 4g + c, column e = r).  B = those dX values; A = one-hot rows of the
       // same rows' tokens at this position (BF16 1.0 where token = 16 vt + r).
-      // The 4 tokens of rows 16 rt + 4g .. +3 are one 4-byte read.
+      // Built per slot s as one 64-bit word holding the slot's value for all
+      // four symbol tiles (BF16 1.0 in 16-bit lane tok / 16 when tok % 16 =
+      // r, else 0); a byte permutation then gathers each tile's slot pairs.
+      static_assert(V == 64, "four symbol tiles per 64-bit slot word");
 #pragma unroll
       for (int k = 0; k < MT / 2; k++) {
-        const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tp + 32 * k + 4 * g);
-        const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tp + 32 * k + 16 + 4 * g);
-        int x[8];
+        uint32_t wlo[8], whi[8];
 #pragma unroll
-        for (int s2 = 0; s2 < 4; s2++) {
-          x[s2] = (int)((t0 >> (8 * s2)) & 0xFFu) - r;
-          x[4 + s2] = (int)((t1 >> (8 * s2)) & 0xFFu) - r;
+        for (int s2 = 0; s2 < 8; s2++) {
+          const uint32_t tok = (t4[2 * k + (s2 >> 2)] >> (8 * (s2 & 3))) & 0xFFu;
+          const uint64_t w = (tok & 15u) == (uint32_t)r ? (0x3F80ull << (16u * (tok >> 4))) : 0ull;
+          wlo[s2] = (uint32_t)w;
+          whi[s2] = (uint32_t)(w >> 32);
         }
         const float dv[8] = {acc3[2 * k][0], acc3[2 * k][1], acc3[2 * k][2], acc3[2 * k][3],
                              acc3[2 * k + 1][0], acc3[2 * k + 1][1], acc3[2 * k + 1][2], acc3[2 * k + 1][3]};
         const bf16x8 bx = bf8(dv);
-        bf16x8 oh[VT];
 #pragma unroll
         for (int vt = 0; vt < VT; vt++) {
-          u32x4 w;
+          // bytes 2h, 2h+1 of slot 2s2's word (low half) and of slot 2s2+1's
+          // (high half), h = vt % 2, from the low (vt < 2) or high dwords
+          const uint32_t sel = (vt & 1) ? 0x07060302u : 0x05040100u;
+          u32x4 wv;
 #pragma unroll
           for (int s2 = 0; s2 < 4; s2++)
-            w[s2] = (x[2 * s2] == 16 * vt ? 0x3F80u : 0u) | (x[2 * s2 + 1] == 16 * vt ? 0x3F800000u : 0u);
-          oh[vt] = __builtin_bit_cast(bf16x8, w);
+            wv[s2] = vt < 2 ? __builtin_amdgcn_perm(wlo[2 * s2 + 1], wlo[2 * s2], sel)
+                            : __builtin_amdgcn_perm(whi[2 * s2 + 1], whi[2 * s2], sel);
+          acce[vt] = mma32(__builtin_bit_cast(bf16x8, wv), bx, acce[vt]);
         }
-#pragma unroll
-        for (int vt = 0; vt < VT; vt++) acce[vt] = mma32(oh[vt], bx, acce[vt]);
       }
-      // W1 update, and the BF16 copy: the four lanes of a quad hold 4
-      // consecutive d with the same 4 consecutive h; a 4x4 transpose of the
-      // 16-bit values inside the quad leaves lane c with h = 4g + c at those
-      // 4 d, which are 8 contiguous bytes of the fragment-ordered copy
-      const uint32_t base = w1_frag_index(16 * mt + (r & ~3), 4 * g + (lane & 3), D);
-      const uint32_t c = lane & 3u;
+      // W1 update, and the BF16 copy: this lane's 4 consecutive h at d are 4
+      // lanes of one k-step in the fragment order, 16 bytes apart
+      const uint32_t base = w1_frag_index(16 * mt + r, 4 * g, D);
 #pragma unroll
       for (int m = 0; m < HT; m++) {
 #pragma unroll
-        for (int x = 0; x < 4; x++)
+        for (int x = 0; x < 4; x++) {
           w1m[q][m][x] = w1m[q][m][x] - opt_delta_c<false>(opt, acc4[m][x], (float *)nullptr, (float *)nullptr);
-        const uint32_t p01 = bf16x2_bits(w1m[q][m][0], w1m[q][m][1]), p23 = bf16x2_bits(w1m[q][m][2], w1m[q][m][3]);
-        const uint32_t x2 = quad_perm<0x4E>(c < 2 ? p23 : p01);
-        const uint32_t A = c < 2 ? p01 : x2, B = c < 2 ? x2 : p23;
-        const uint32_t sh = (c & 1u) ? 0u : 16u, sel = (c & 1u) ? 0x03020504u : 0x05040100u;
-        const uint32_t ya = quad_perm<0xB1>(A >> sh), yb = quad_perm<0xB1>(B >> sh);
-        const uint32_t Ew = __builtin_amdgcn_perm(ya, A, sel), Fw = __builtin_amdgcn_perm(yb, B, sel);
-        *reinterpret_cast<u32x2 *>(w1c + base + (uint32_t)m * ((uint32_t)D << 4)) = u32x2{Ew, Fw};
+          w1c[base + (uint32_t)m * ((uint32_t)D << 4) + 8u * (uint32_t)x] = (__bf16)w1m[q][m][x];
+        }
       }
-      // one d tile at a time: no loads of the next tile hoisted over this one
-      __builtin_amdgcn_sched_barrier(0);
     }
     // this wave's embedding-gradient partial (C: v = 16 vt + 4 g + c, e = r)
 #pragma unroll

@@ -435,7 +435,8 @@ using namespace detail;
 // both end with a workgroup barrier.  A Net with kOnChip keeps its layer
 // parameters in registers and LDS during a block: it writes them back to
 // the parameter slab with flush() (before a snapshot and at the block's
-// end), hands over the embedding gradient through emb_grad(), and updates
+// end), hands over the embedding gradient through emb_grad(), sees every
+// embedding value written (emb_set(), for a copy of its own), and updates
 // what it keeps on chip besides the weight matrices in after_update(),
 // during the embedding-update phase.  The others sum the embedding
 // gradient into the fixed-point table demb.
@@ -521,6 +522,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
     for (int q = tid; q < V * E; q += NT) {
       const int v = (int)__umulhi((uint32_t)q, d.Emag), qp = q + v * (d.EP - E);   // row v, pitch EP
       emb[qp] = W[d.off_emb + q];
+      if constexpr (Net::kOnChip) net.emb_set(v, q - v * E, emb[qp]);
       if (d.static_on) embs[qp] = a.stat[d.off_emb + q];
     }
     if constexpr (!Net::kOnChip)
@@ -712,6 +714,7 @@ __device__ __forceinline__ void run_blocks(const StepArgs &a, unsigned char *lds
           }
           const int pi = d.off_emb + q;
           emb[qp] = emb[qp] - opt_delta(opt, gq, M ? glb(M) + pi : nullptr, Vs ? glb(Vs) + pi : nullptr);
+          if constexpr (Net::kOnChip) net.emb_set(v, q - v * E, emb[qp]);
         }
         if constexpr (Net::kOnChip) net.after_update(opt);
         if (d.static_on && tid == 0) {
