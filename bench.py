@@ -36,7 +36,11 @@ PEAK = {"fp32_alu_tflops": 157.3, "bf16_mfma_tflops": 2500.0, "hbm_gbs": 8000.0}
 # Sources that define the step kernel; a stored HBM-traffic measurement is
 # reported only while their hash matches the one it was taken with.
 KERNEL_SOURCES = ["paper_2507_12805_amd/csrc/step_mfma.h", "paper_2507_12805_amd/csrc/step_mfma_inst.hip",
+                  "paper_2507_12805_amd/csrc/step_chip.hip",
                   "paper_2507_12805_amd/csrc/step_common.h", "paper_2507_12805_amd/csrc/pmklc_internal.h"]
+# the kernel that computed a container, by its numeric-path byte
+PATH_KERNEL = {1: "step_kernel (FP32 per-thread FMA)", 2: "step_mfma_kernel (BF16 matrix cores, weights in global memory)",
+               3: "step_mfma_kernel (FP32 matrix cores)", 4: "step_chip_kernel (BF16 matrix cores, network on chip)"}
 
 
 def kernel_source_hash() -> str:
@@ -305,7 +309,8 @@ def main():
                      "frac": round(achieved / peak, 6),
                      "traffic": stored_traffic(f"traffic_step_kernel_{a.workload}_{a.precision}")
                      if a.schedule == "batched" and a.scale == 1.0 else None,
-                     "kernel": "step_kernel", "flops_per_launch": int(flops_launch), "flops_per_row": fpr,
+                     "kernel": PATH_KERNEL.get(blob[5] if blob else 0, "step kernel"),
+                     "flops_per_launch": int(flops_launch), "flops_per_row": fpr,
                      "rows_per_launch": int(tim_c["model_rows"]), "max_steps": int(tim_c["max_steps"])},
     }
     res["threads_per_workgroup"] = int(tim_c["threads"])
