@@ -993,7 +993,7 @@ pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint6
   HIP_TRY(d2h(stats, w.stats, z.n_chunks, st));
   HIP_TRY(hipStreamSynchronize(st));
   std::vector<uint64_t> chunk_run0(z.n_chunks);
-  uint64_t run_total = 0, tok_total = 0, ex_total = 0, max_l = 0;
+  uint64_t run_total = 0, tok_total = 0, ex_total = 0;
   for (uint32_t b = 0; b < nblk; b++) {
     uint64_t nN = 0, nr = 0;
     uint64_t nc = (p.raw_len[b] + kScanChunk - 1) / kScanChunk;
@@ -1015,16 +1015,17 @@ pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint6
     q.tail_off = q.l ? (q.l - 1) * s + k : 0;
     q.ex_off = ex_total;
     ex_total += bs + 8;
-    max_l = std::max(max_l, q.l);
   }
   // ---- A1/A2: runs, tokens, extras
+  uint64_t n_sk = 0, n_tk = 0, n_raw = 0;
+  assign_tiles(sb.data(), (int)nblk, n_sk, n_tk, n_raw);
   HIP_TRY(h2d(w.seq, sb, st));
   HIP_TRY(h2d(w.chunk_run0, chunk_run0, st));
   if (run_total) {
     HIP_TRY(launch_runs(in_dev, w.seq, w.chunk_block, z.n_chunks, w.stats, w.chunk_run0, w.run_start, w.run_len, st));
     HIP_TRY(launch_run_sp(w.seq, (int)nblk, w.run_start, w.run_len, w.run_sp, w.run_cum, st));
   }
-  HIP_TRY(launch_tokenise(in_dev, w.seq, (int)nblk, max_l, w.run_sp, w.run_cum, (int)s, (int)k, w.tok, st));
+  HIP_TRY(launch_tokenise(in_dev, w.seq, (int)nblk, n_sk, n_tk, w.run_sp, w.run_cum, (int)s, (int)k, w.tok, st));
   HIP_TRY(launch_extras(in_dev, w.seq, (int)nblk, w.run_sp, w.run_cum, (int)s, (int)k, (int)bs, w.tok, w.extras, st));
 
   // ---- A3-A11: model loop + coder
@@ -1362,6 +1363,8 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   }
   HIP_TRY(h2d(w.seg_words, seg_words, st));
   HIP_TRY(h2d(w.desc, bd, st));
+  uint64_t n_sk = 0, n_tk = 0, n_raw = 0;
+  assign_tiles(o.sb.data(), (int)nblk, n_sk, n_tk, n_raw);
   HIP_TRY(h2d(w.seq, o.sb, st));
   HIP_TRY(h2d(w.extras, o.extras, st));
   HIP_TRY(h2d(w.run_start, o.run_start, st));
@@ -1374,9 +1377,7 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   count_work(m, bd, g_last);
   rc = run_step(m, w, 1, bd, PMKLC_BATCHED, st, &tm);
   if (rc) return rc;
-  uint64_t max_raw = 0;
-  for (const SeqBlock &q : o.sb) max_raw = std::max(max_raw, q.raw_len);
-  HIP_TRY(launch_detok(w.seq, (int)nblk, max_raw, w.run_start, w.run_len, w.run_cum, (int)o.c.s, (int)o.c.k, (int)bs,
+  HIP_TRY(launch_detok(w.seq, (int)nblk, n_raw, w.run_start, w.run_len, w.run_cum, (int)o.c.s, (int)o.c.k, (int)bs,
                        w.tok, w.extras, out_dev, st));
   std::vector<int> ctr;
   HIP_TRY(d2h(ctr, w.ctr, 2, st));

@@ -144,7 +144,15 @@ struct SeqBlock {              // per block, shared by the scan / tokenise / inv
   uint64_t tail_off;           // first tail base (stripped coordinates)
   uint64_t ex_off;             // offset of the block's extras (tail codes then remainder tokens)
   uint64_t L;                  // steps
+  // first workgroup of this block in the compact grids of the tokenisers
+  // and the inverse (prefix sums over the blocks before it; a block with no
+  // work there has as many workgroups as zero)
+  uint64_t t_sk;               // GskE tiles (4096 tokens) of a block without N runs
+  uint64_t t_tk;               // run-map tokeniser tiles (1024 tokens) of a block with N runs
+  uint64_t t_raw;              // inverse tiles (4096 raw bytes)
 };
+// sets t_sk, t_tk, t_raw and returns the grids' sizes
+void assign_tiles(SeqBlock *sb, int n_blocks, uint64_t &n_sk, uint64_t &n_tk, uint64_t &n_raw);
 
 constexpr int kScanChunk = 4096;   // raw bytes per scan chunk
 
@@ -162,13 +170,13 @@ hipError_t launch_runs(const uint8_t *in, const SeqBlock *blk, const uint64_t *c
                        hipStream_t st);
 hipError_t launch_run_sp(const SeqBlock *blk, int n_blocks, const uint32_t *run_start, uint32_t *run_len,
                          uint32_t *run_sp, uint32_t *run_cum, hipStream_t st);
-hipError_t launch_tokenise(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t max_l,
+hipError_t launch_tokenise(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t n_sk, uint64_t n_tk,
                            const uint32_t *run_sp, const uint32_t *run_cum, int s, int k, uint8_t *tok,
                            hipStream_t st);
 hipError_t launch_extras(const uint8_t *in, const SeqBlock *blk, int n_blocks, const uint32_t *run_sp,
                          const uint32_t *run_cum, int s, int k, int bs, const uint8_t *tok, uint8_t *extras,
                          hipStream_t st);
-hipError_t launch_detok(const SeqBlock *blk, int n_blocks, uint64_t max_raw, const uint32_t *run_start,
+hipError_t launch_detok(const SeqBlock *blk, int n_blocks, uint64_t n_raw, const uint32_t *run_start,
                         const uint32_t *run_len, const uint32_t *run_cum, int s, int k, int bs, const uint8_t *tok,
                         const uint8_t *extras, uint8_t *out, hipStream_t st);
 // streams: segment i is seg_bytes[i] bytes at byte offset src[i] (or words

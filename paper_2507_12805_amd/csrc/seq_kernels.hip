@@ -19,7 +19,33 @@ __device__ __forceinline__ bool is_acgt(uint32_t c) { return c == 'A' || c == 'C
 constexpr int kTokPerThread = 4;   // per-block tokeniser
 constexpr int kTokPerWG = 256 * kTokPerThread;
 
+// the block whose tiles (first tile blk[b].*F) contain `tile`: the last
+// block whose first tile is <= tile (blocks with no tiles share their
+// first tile with the next block)
+template <uint64_t SeqBlock::*F>
+__device__ __forceinline__ int block_of_tile(const SeqBlock *blk, int n, uint64_t tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int m = (lo + hi + 1) >> 1;
+    if (blk[m].*F <= tile) lo = m; else hi = m - 1;
+  }
+  return lo;
+}
+
 }  // namespace
+
+void assign_tiles_impl(SeqBlock *sb, int n_blocks, uint64_t &n_sk, uint64_t &n_tk, uint64_t &n_raw, int sk_tile) {
+  n_sk = n_tk = n_raw = 0;
+  for (int b = 0; b < n_blocks; b++) {
+    SeqBlock &q = sb[b];
+    q.t_sk = n_sk;
+    q.t_tk = n_tk;
+    q.t_raw = n_raw;
+    if (q.n_runs == 0) n_sk += (q.l + sk_tile - 1) / sk_tile;
+    else n_tk += (q.l + kTokPerWG - 1) / kTokPerWG;
+    n_raw += (q.raw_len + 4095) / 4096;
+  }
+}
 
 // ---------------------------------------------------------------- GskE
 // Direct ASCII -> tokens (no N allowed), one instance per (S, K).  A
@@ -38,14 +64,17 @@ constexpr int kSkBuf = kSkTokPerWG * 4 + 32;   // s <= 4, plus the k - s tail an
 __device__ __forceinline__ uint32_t codes4(uint32_t w) { return ((w >> 1) ^ (w >> 2)) & 0x03030303u; }
 __device__ __forceinline__ bool acgt4(uint32_t w) { return __builtin_amdgcn_perm(0u, 0x54474341u, codes4(w)) == w; }
 
-template <int S, int K>
-__global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__restrict__ in, uint64_t n,
-                                                           uint8_t *__restrict__ tok, uint64_t l, int *err) {
-  __shared__ __align__(16) uint8_t buf[kSkBuf + 16];
-  const uint64_t j0 = (uint64_t)blockIdx.x * kSkTokPerWG;
+// One workgroup's tile (4096 tokens starting at token 4096 * tile) of the
+// tokens of bases in[0, n); `last`: the sequence's last tile.  VALIDATE:
+// flag bytes outside {A,C,G,T} in err (the per-block tokeniser's input was
+// validated by the scan already).
+template <int S, int K, bool VALIDATE>
+__device__ __forceinline__ void skmer_tile(const uint8_t *__restrict__ in, uint64_t n, uint8_t *__restrict__ tok,
+                                           uint64_t l, int *err, uint64_t tile, bool last, uint8_t *buf) {
+  const uint64_t j0 = tile * kSkTokPerWG;
   const uint64_t b0 = j0 * (uint64_t)S;
   uint64_t b1 = (j0 + kSkTokPerWG) * (uint64_t)S + (uint64_t)(K - S);
-  if (b1 > n || blockIdx.x == gridDim.x - 1) b1 = n;
+  if (b1 > n || last) b1 = n;
   // frame: buf[i] holds input byte a0 + i, a0 = b0 rounded down to 16 bytes
   // of the input address; bytes of the frame outside [b0, b1) are not used
   const int pre = (int)(reinterpret_cast<uintptr_t>(in + b0) & 15u);
@@ -70,6 +99,7 @@ __global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__rest
       }
     }
     *reinterpret_cast<uint4 *>(buf + 16 * w) = make_uint4(v[0], v[1], v[2], v[3]);
+    if constexpr (!VALIDATE) continue;
     if (whole && 16 * w >= pre && 16 * w + 16 <= span) {
 #pragma unroll
       for (int q = 0; q < 4; q++) bad |= !acgt4(v[q]);
@@ -81,7 +111,7 @@ __global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__rest
       }
     }
   }
-  if (bad) atomicOr(err, 1);
+  if (VALIDATE && bad) atomicOr(err, 1);
   __syncthreads();
   // this thread's 16 tokens: bytes [first, first + 15 S + K) of the frame
   const int t16 = threadIdx.x * kSkTokPerThread;
@@ -133,10 +163,59 @@ __global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__rest
 }
 
 template <int S, int K>
+__global__ __launch_bounds__(256) void skmer_direct_kernel(const uint8_t *__restrict__ in, uint64_t n,
+                                                           uint8_t *__restrict__ tok, uint64_t l, int *err) {
+  __shared__ __align__(16) uint8_t buf[kSkBuf + 16];
+  skmer_tile<S, K, true>(in, n, tok, l, err, blockIdx.x, blockIdx.x == gridDim.x - 1, buf);
+}
+
+// The same over the blocks of a compress call (grid: tile, block): a block
+// without N runs is tokenised straight from its raw bytes, already
+// validated by the scan; blocks with N runs are left to tokenise_kernel.
+template <int S, int K>
+__global__ __launch_bounds__(256) void skmer_blocks_kernel(const uint8_t *__restrict__ in, const SeqBlock *blk,
+                                                           int n_blocks, uint8_t *__restrict__ tok) {
+  __shared__ __align__(16) uint8_t buf[kSkBuf + 16];
+  const int bi = block_of_tile<&SeqBlock::t_sk>(blk, n_blocks, blockIdx.x);
+  const SeqBlock b = blk[bi];
+  const uint64_t tile = blockIdx.x - b.t_sk, tiles = (b.l + kSkTokPerWG - 1) / kSkTokPerWG;
+  skmer_tile<S, K, false>(in + b.raw_off, b.nb, tok + b.tok_off, b.l, nullptr, tile, tile + 1 == tiles, buf);
+}
+
+void assign_tiles(SeqBlock *sb, int n_blocks, uint64_t &n_sk, uint64_t &n_tk, uint64_t &n_raw) {
+  assign_tiles_impl(sb, n_blocks, n_sk, n_tk, n_raw, kSkTokPerWG);
+}
+
+template <int S, int K>
 hipError_t launch_sk(const uint8_t *in, uint64_t n, uint8_t *tok, uint64_t l, int *err, hipStream_t st) {
   const uint64_t grid = l ? (l + kSkTokPerWG - 1) / kSkTokPerWG : 1;
   hipLaunchKernelGGL((skmer_direct_kernel<S, K>), dim3((unsigned)grid), dim3(256), 0, st, in, n, tok, l, err);
   return hipGetLastError();
+}
+
+template <int S, int K>
+hipError_t launch_skb(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t n_sk, uint8_t *tok,
+                      hipStream_t st) {
+  hipLaunchKernelGGL((skmer_blocks_kernel<S, K>), dim3((unsigned)n_sk), dim3(256), 0, st, in, blk, n_blocks, tok);
+  return hipGetLastError();
+}
+
+hipError_t launch_skmer_blocks(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t n_sk, int s, int k,
+                               uint8_t *tok, hipStream_t st) {
+  if (n_blocks == 0 || n_sk == 0) return hipSuccess;
+  switch (k * 8 + s) {
+    case 1 * 8 + 1: return launch_skb<1, 1>(in, blk, n_blocks, n_sk, tok, st);
+    case 2 * 8 + 1: return launch_skb<1, 2>(in, blk, n_blocks, n_sk, tok, st);
+    case 2 * 8 + 2: return launch_skb<2, 2>(in, blk, n_blocks, n_sk, tok, st);
+    case 3 * 8 + 1: return launch_skb<1, 3>(in, blk, n_blocks, n_sk, tok, st);
+    case 3 * 8 + 2: return launch_skb<2, 3>(in, blk, n_blocks, n_sk, tok, st);
+    case 3 * 8 + 3: return launch_skb<3, 3>(in, blk, n_blocks, n_sk, tok, st);
+    case 4 * 8 + 1: return launch_skb<1, 4>(in, blk, n_blocks, n_sk, tok, st);
+    case 4 * 8 + 2: return launch_skb<2, 4>(in, blk, n_blocks, n_sk, tok, st);
+    case 4 * 8 + 3: return launch_skb<3, 4>(in, blk, n_blocks, n_sk, tok, st);
+    case 4 * 8 + 4: return launch_skb<4, 4>(in, blk, n_blocks, n_sk, tok, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_skmer_direct(const uint8_t *in, uint64_t n, int s, int k, uint8_t *tok, uint64_t l, int *err,
@@ -158,36 +237,130 @@ hipError_t launch_skmer_direct(const uint8_t *in, uint64_t n, int s, int k, uint
 }
 
 // ------------------------------------------------------------- input scan
-// One workgroup per 4096-byte chunk of a block (chunks never straddle
-// blocks).  Counts N bytes, N-run starts and bytes outside {A,C,G,T,N}.
+// Four 4096-byte chunks per workgroup, one after the other (chunks never
+// straddle blocks).  Counts N bytes, N-run starts and bytes outside
+// {A,C,G,T,N} per chunk.  A chunk is read as 16-byte words of a 16-byte aligned frame (a word
+// that crosses either end of the chunk has its outside bytes masked off);
+// each dword is classified four bytes at a time: byte == 'N' by the exact
+// zero-byte test on w ^ 'NNNN' (bit 7 of each byte), ACGT by the
+// code-permutation test, run starts as N bytes whose previous byte is not N.
+__device__ __forceinline__ uint32_t n_bits4(uint32_t w) {   // 0x80 in each byte equal to 'N'
+  const uint32_t y = w ^ 0x4E4E4E4Eu;
+  return ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y | 0x7F7F7F7Fu) & 0x80808080u;
+}
+constexpr int kScanChunksPerWG = 4;
 __global__ __launch_bounds__(256) void scan_kernel(const uint8_t *__restrict__ in, const SeqBlock *blk,
-                                                   const uint64_t *chunk_block, ChunkStat *stats) {
-  __shared__ uint32_t sN, sR, sB;
-  const uint64_t c = blockIdx.x;
-  const SeqBlock b = blk[chunk_block[c]];
+                                                   const uint64_t *chunk_block, uint64_t n_chunks, ChunkStat *stats) {
+  __shared__ uint32_t red[kScanChunksPerWG][3];   // per chunk: N bytes, run starts, bad bytes
+  if (threadIdx.x < kScanChunksPerWG * 3) (&red[0][0])[threadIdx.x] = 0;
+  __syncthreads();
+  // every chunk's word for this thread first (the loads in flight
+  // together), then the counting; a chunk has at most 257 words in its
+  // frame, so thread 0 may own one more per chunk
+  uint4 wv[kScanChunksPerWG];
+  uint32_t prevbyte[kScanChunksPerWG];
+  const SeqBlock *bp[kScanChunksPerWG];
+  for (int cc = 0; cc < kScanChunksPerWG; cc++) {
+    const uint64_t c = (uint64_t)blockIdx.x * kScanChunksPerWG + cc;
+    wv[cc] = make_uint4(0u, 0u, 0u, 0u);
+    prevbyte[cc] = 0;
+    if (c >= n_chunks) continue;
+    const SeqBlock &b = blk[chunk_block[c]];
+    bp[cc] = &b;
+    const uint64_t cstart = (c - b.chunk0) * kScanChunk;
+    const uint64_t cend = min(cstart + kScanChunk, b.raw_len);
+    const uint8_t *base = in + b.raw_off;
+    const int pre = (int)(reinterpret_cast<uintptr_t>(base + cstart) & 15u);
+    const int span = pre + (int)(cend - cstart);
+    const int f0 = 16 * (int)threadIdx.x;
+    if (f0 >= pre && f0 + 16 <= span) wv[cc] = *reinterpret_cast<const uint4 *>(base + cstart - pre + f0);
+    const int64_t p0 = (int64_t)cstart - pre + f0;
+    if (p0 >= 1 && f0 < span) prevbyte[cc] = base[p0 - 1];
+  }
+  for (int cc = 0; cc < kScanChunksPerWG; cc++) {
+  const uint64_t c = (uint64_t)blockIdx.x * kScanChunksPerWG + cc;
+  if (c >= n_chunks) break;
+  const SeqBlock b = *bp[cc];
   const uint64_t cstart = (c - b.chunk0) * kScanChunk;
   const uint64_t cend = min(cstart + kScanChunk, b.raw_len);
-  if (threadIdx.x == 0) { sN = 0; sR = 0; sB = 0; }
-  __syncthreads();
+  const uint8_t *base = in + b.raw_off;
+  const int pre = (int)(reinterpret_cast<uintptr_t>(base + cstart) & 15u);
+  const int span = pre + (int)(cend - cstart);          // frame bytes [pre, span) are the chunk
+  const int nq = (span + 15) >> 4;
+  const uint8_t *frame = base + cstart - pre;           // 16-byte aligned
+  // bytes loaded: the chunk and the one before it (the first byte's
+  // predecessor), block positions [lo, cend)
+  const int flo = cstart > 0 ? pre - 1 : pre;
   uint32_t nN = 0, nR = 0, bad = 0;
-  for (uint64_t p = cstart + threadIdx.x; p < cend; p += 256) {
-    uint32_t ch = in[b.raw_off + p];
-    bool isN = ch == 'N';
-    nN += isN;
-    bad |= !(isN || is_acgt(ch));
-    if (isN && (p == 0 || in[b.raw_off + p - 1] != 'N')) nR++;
+  for (int q = threadIdx.x; q < nq; q += 256) {
+    const int f0 = 16 * q;
+    const bool whole = f0 >= pre && f0 + 16 <= span;
+    uint32_t v[4];
+    if (whole && q == (int)threadIdx.x) {
+      v[0] = wv[cc].x; v[1] = wv[cc].y; v[2] = wv[cc].z; v[3] = wv[cc].w;
+    } else if (whole) {
+      const uint4 x = *reinterpret_cast<const uint4 *>(frame + f0);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else {
+#pragma unroll
+      for (int d = 0; d < 4; d++) {
+        v[d] = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int f = f0 + 4 * d + e;
+          if (f >= flo && f < span) v[d] |= (uint32_t)frame[f] << (8 * e);
+        }
+      }
+    }
+    // N bit of the byte before this word (block position p0 - 1)
+    const int64_t p0 = (int64_t)cstart - pre + f0;
+    uint32_t prevN;
+    if (q == (int)threadIdx.x) prevN = prevbyte[cc] == 'N' ? 0x80u : 0u;
+    else prevN = (p0 >= 1 && base[p0 - 1] == 'N') ? 0x80u : 0u;
+#pragma unroll
+    for (int d = 0; d < 4; d++) {
+      uint32_t inb = 0x80808080u;   // in-chunk bytes (bit 7 of each)
+      if (!whole) {
+        inb = 0;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int f = f0 + 4 * d + e;
+          if (f >= pre && f < span) inb |= 0x80u << (8 * e);
+        }
+      }
+      const uint32_t nbu = n_bits4(v[d]);               // N bits of the loaded bytes
+      const uint32_t prevb = (nbu << 8) | prevN;        // each byte's predecessor's N bit
+      const uint32_t nb = nbu & inb;
+      nN += __popc(nb);
+      nR += __popc(nb & ~prevb);
+      prevN = (nbu >> 24) & 0x80u;
+      if (!(inb == 0x80808080u && acgt4(v[d]))) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const uint32_t ch = (v[d] >> (8 * e)) & 0xFFu;
+          if (((inb >> (8 * e)) & 0x80u) && !(ch == 'N' || is_acgt(ch))) bad = 1;
+        }
+      }
+    }
   }
-  if (nN) atomicAdd(&sN, nN);
-  if (nR) atomicAdd(&sR, nR);
-  if (bad) atomicOr(&sB, 1u);
+  // workgroup sums by LDS atomics from the threads that saw anything
+  // (integer sums: the order does not matter); most DNA has no N at all
+  if (nN) atomicAdd(&red[cc][0], nN);
+  if (nR) atomicAdd(&red[cc][1], nR);
+  if (bad) atomicOr(&red[cc][2], 1u);
+  }
   __syncthreads();
-  if (threadIdx.x == 0) stats[c] = ChunkStat{sN, sR, sB, 0};
+  if (threadIdx.x < kScanChunksPerWG) {
+    const uint64_t c = (uint64_t)blockIdx.x * kScanChunksPerWG + threadIdx.x;
+    if (c < n_chunks) stats[c] = ChunkStat{red[threadIdx.x][0], red[threadIdx.x][1], red[threadIdx.x][2], 0};
+  }
 }
 
 hipError_t launch_scan(const uint8_t *in, const SeqBlock *blk, const uint64_t *chunk_block, uint64_t n_chunks,
                        ChunkStat *stats, hipStream_t st) {
   if (n_chunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_kernel, dim3((unsigned)n_chunks), dim3(256), 0, st, in, blk, chunk_block, stats);
+  hipLaunchKernelGGL(scan_kernel, dim3((unsigned)((n_chunks + kScanChunksPerWG - 1) / kScanChunksPerWG)), dim3(256), 0,
+                     st, in, blk, chunk_block, n_chunks, stats);
   return hipGetLastError();
 }
 
@@ -299,13 +472,14 @@ struct RunMap {
 };
 }  // namespace
 
-// Per block tokenisation of the N-stripped bases (Sec. 4.1).  Grid:
-// (token chunk, block); each thread builds 4 tokens.
+// Per block tokenisation of the N-stripped bases (Sec. 4.1) for blocks with
+// N runs (each base located through the run map).  Grid: the blocks'
+// 1024-token tiles, compact; each thread builds 4 tokens.
 __global__ __launch_bounds__(256) void tokenise_kernel(const uint8_t *__restrict__ in, const SeqBlock *blk,
-                                                       const uint32_t *run_sp, const uint32_t *run_cum, int s, int k,
-                                                       uint8_t *__restrict__ tok) {
-  const SeqBlock b = blk[blockIdx.y];
-  const uint64_t jt = (uint64_t)blockIdx.x * kTokPerWG + (uint64_t)threadIdx.x * kTokPerThread;
+                                                       int n_blocks, const uint32_t *run_sp, const uint32_t *run_cum,
+                                                       int s, int k, uint8_t *__restrict__ tok) {
+  const SeqBlock b = blk[block_of_tile<&SeqBlock::t_tk>(blk, n_blocks, blockIdx.x)];
+  const uint64_t jt = (blockIdx.x - b.t_tk) * kTokPerWG + (uint64_t)threadIdx.x * kTokPerThread;
   if (jt >= b.l) return;
   const RunMap rm{run_sp + b.run0, run_cum + b.run0, b.n_runs};
   const uint8_t *raw = in + b.raw_off;
@@ -322,14 +496,17 @@ __global__ __launch_bounds__(256) void tokenise_kernel(const uint8_t *__restrict
   }
 }
 
-hipError_t launch_tokenise(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t max_l,
+hipError_t launch_tokenise(const uint8_t *in, const SeqBlock *blk, int n_blocks, uint64_t n_sk, uint64_t n_tk,
                            const uint32_t *run_sp, const uint32_t *run_cum, int s, int k, uint8_t *tok,
                            hipStream_t st) {
-  if (n_blocks == 0 || max_l == 0) return hipSuccess;
-  uint64_t gx = (max_l + kTokPerWG - 1) / kTokPerWG;
-  hipLaunchKernelGGL(tokenise_kernel, dim3((unsigned)gx, (unsigned)n_blocks), dim3(256), 0, st, in, blk, run_sp,
-                     run_cum, s, k, tok);
-  return hipGetLastError();
+  if (n_blocks == 0) return hipSuccess;
+  if (n_tk) {
+    hipLaunchKernelGGL(tokenise_kernel, dim3((unsigned)n_tk), dim3(256), 0, st, in, blk, n_blocks, run_sp, run_cum, s,
+                       k, tok);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_skmer_blocks(in, blk, n_blocks, n_sk, s, k, tok, st);
 }
 
 // Per block: the tail bases the last window leaves over (2-bit codes) and
@@ -365,12 +542,51 @@ hipError_t launch_extras(const uint8_t *in, const SeqBlock *blk, int n_blocks, c
 // from token j = (q-k)/s + 1 (digit k-s + (q-k) % s), the digit read as
 // (e >> 2(k-1-m)) & 3; bases past the last window are the tail codes.
 // Tokens at or past bs*L are the remainder tokens kept in extras.
-__global__ __launch_bounds__(256) void detok_kernel(const SeqBlock *blk, const uint32_t *run_start,
+__global__ __launch_bounds__(256) void detok_kernel(const SeqBlock *blk, int n_blocks, const uint32_t *run_start,
                                                     const uint32_t *run_len, const uint32_t *run_cum, int s, int k,
                                                     int bs, const uint8_t *__restrict__ tok,
                                                     const uint8_t *__restrict__ extras, uint8_t *__restrict__ out) {
-  const SeqBlock b = blk[blockIdx.y];
-  const uint64_t r0 = (uint64_t)blockIdx.x * 4096 + (uint64_t)threadIdx.x * 16;
+  const SeqBlock b = blk[block_of_tile<&SeqBlock::t_raw>(blk, n_blocks, blockIdx.x)];
+  const uint64_t tile = blockIdx.x - b.t_raw;   // this workgroup's 4096 raw bytes of the block
+  if (b.n_runs == 0) {
+    // no N runs: raw position = stripped position.  Thread t writes bytes
+    // t, t + 256, ... of the workgroup's 4096, so each store instruction
+    // covers consecutive bytes
+    // (block positions fit 32 bits; division by s = 1..4 by shifts or the
+    // exact 32-bit reciprocal of 3)
+    const uint32_t w0 = (uint32_t)tile * 4096u, len = (uint32_t)b.raw_len;
+    const uint32_t nseg = (uint32_t)(b.L * (uint64_t)bs), covered = (uint32_t)b.tail_off;
+    const uint32_t ntail = (uint32_t)(b.nb - b.tail_off);
+    const uint8_t *ex = extras + b.ex_off;
+    const uint8_t *tk = tok + b.tok_off;
+    uint8_t *o = out + b.raw_off;
+    auto div_s = [&](uint32_t x) {
+      return s == 3 ? __umulhi(x, 0xAAAAAAABu) >> 1 : x >> (s == 4 ? 2 : s == 2 ? 1 : 0);
+    };
+#pragma unroll 4
+    for (int x = 0; x < 16; x++) {
+      const uint32_t q = w0 + (uint32_t)(x * 256) + threadIdx.x;
+      if (q >= len) break;
+      uint32_t code;
+      if (q < covered) {
+        uint32_t j;
+        int m;
+        if (q < (uint32_t)k) { j = 0; m = (int)q; }
+        else {
+          const uint32_t dq = q - (uint32_t)k, qq = div_s(dq);
+          j = qq + 1;
+          m = k - s + (int)(dq - qq * (uint32_t)s);
+        }
+        const uint32_t e = j < nseg ? tk[j] : ex[ntail + (j - nseg)];
+        code = (e >> (2 * (k - 1 - m))) & 3u;
+      } else {
+        code = ex[q - covered];
+      }
+      o[q] = (uint8_t)(0x54474341u >> (8 * code));   // 'A' 'C' 'G' 'T'
+    }
+    return;
+  }
+  const uint64_t r0 = tile * 4096 + (uint64_t)threadIdx.x * 16;
   if (r0 >= b.raw_len) return;
   const uint32_t *rs = run_start + b.run0, *rl = run_len + b.run0, *rc = run_cum + b.run0;
   // #runs starting at or before r0
@@ -407,12 +623,11 @@ __global__ __launch_bounds__(256) void detok_kernel(const SeqBlock *blk, const u
   for (int q = 0; q < cnt; q++) out[b.raw_off + r0 + q] = o16[q];
 }
 
-hipError_t launch_detok(const SeqBlock *blk, int n_blocks, uint64_t max_raw, const uint32_t *run_start,
+hipError_t launch_detok(const SeqBlock *blk, int n_blocks, uint64_t n_raw, const uint32_t *run_start,
                         const uint32_t *run_len, const uint32_t *run_cum, int s, int k, int bs, const uint8_t *tok,
                         const uint8_t *extras, uint8_t *out, hipStream_t st) {
-  if (n_blocks == 0 || max_raw == 0) return hipSuccess;
-  uint64_t gx = (max_raw + 4095) / 4096;
-  hipLaunchKernelGGL(detok_kernel, dim3((unsigned)gx, (unsigned)n_blocks), dim3(256), 0, st, blk, run_start, run_len,
+  if (n_blocks == 0 || n_raw == 0) return hipSuccess;
+  hipLaunchKernelGGL(detok_kernel, dim3((unsigned)n_raw), dim3(256), 0, st, blk, n_blocks, run_start, run_len,
                      run_cum, s, k, bs, tok, extras, out);
   return hipGetLastError();
 }
