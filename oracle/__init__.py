@@ -15,6 +15,10 @@ Parity status per function (see the tests under ``tests/test_oracle_*``):
   compress      pinned: uniform closed form (2 bits/base at s = k), round
                 trip, edge cases; the learned-model ratio on synthetic data
                 is parity unpinned (the paper's datasets are unavailable)
+  private model pinned: training block gathered from its definition and run
+                through the pinned trace; coding pass equal to the public-
+                model container with the stored weights; the selector's
+                size rule at its boundary
 """
 from __future__ import annotations
 
@@ -63,7 +67,7 @@ class _Cfg(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("selector", ctypes.c_int32),
                 ("smp_ppm", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("n_blocks", ctypes.c_int32),
                 ("block_len", _u64p), ("n_files", ctypes.c_int32), ("file_blocks", _u64p),
-                ("init_override", _dp)]
+                ("init_override", _dp), ("ms_threshold", ctypes.c_uint64)]
 
 
 def _load():
@@ -257,7 +261,8 @@ def _mkcfg(cfg, n):
     c.lr, c.beta1, c.beta2, c.eps = cfg.get("lr", 1e-3), cfg.get("beta1", 0.9), cfg.get("beta2", 0.999), \
         cfg.get("eps", 1e-8)
     sel = cfg.get("selector", "dm")
-    c.selector = {"uniform": 0, "dm": 4, "spum_dm": 5}[sel]
+    c.selector = {"uniform": 0, "dm": 4, "spum_dm": 5, "sprm_dm": 6, "spum_sprm_dm": 7, "auto": 8}[sel]
+    c.ms_threshold = int(cfg.get("ms_threshold", 0))
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
     c.seed = int(cfg["seed"])
     keep = []

@@ -517,7 +517,8 @@ typedef struct {
     int32_t hidden[4];
     int32_t optimizer;
     float lr, beta1, beta2, eps;
-    int32_t selector;        /* bit0: static public model, bit2: dynamic model; 0 = uniform */
+    int32_t selector;        /* bit0: static public model, bit1: static private model, bit2: dynamic
+                                model; 0 = uniform; 8 = chosen by the Model Selector */
     uint32_t smp_ppm;        /* step-wise model passing point, parts per million of the block's steps; 0 = off */
     uint64_t seed;
     int32_t n_blocks;
@@ -525,11 +526,21 @@ typedef struct {
     int32_t n_files;
     const uint64_t *file_blocks; /* blocks per file, or NULL = one file */
     const double *init_override; /* test hook: initial DM parameters (+ a_alpha) of every chain head, or NULL */
+    uint64_t ms_threshold;   /* Model Selector size bound in input bytes; 0 = 500 * 10^6 */
 } or_config;
 
 #define SEL_SPUM 1
 #define SEL_SPRM 2
 #define SEL_DM 4
+#define SEL_AUTO 8
+
+/* Sec. 4.2.1: the selector enables the public static model for inputs of at
+ * most 500 MB and the private one above (MB read as 10^6 bytes). */
+#define MS_BYTES_DEFAULT 500000000ull
+/* Training of the private static model (Sec. 4.2.3, pipeline stage (b));
+ * the paper gives no budget or seed, these are this implementation's. */
+#define SPRM_STEPS 8192u
+#define SPRM_SEED_XOR 0x5350524Dull
 
 typedef struct {
     uint64_t raw_off, raw_len;
@@ -550,7 +561,17 @@ typedef struct {
 } or_block;
 
 static int model_on(const or_config *c) { return (c->selector & SEL_DM) != 0; }
-static int static_on(const or_config *c) { return (c->selector & SEL_SPUM) != 0; }
+static int static_on(const or_config *c) { return (c->selector & (SEL_SPUM | SEL_SPRM)) != 0; }
+static int private_on(const or_config *c) { return (c->selector & SEL_SPRM) != 0; }
+
+/* Sec. 4.2.1: S for an input of n bytes.  Above the size bound the private
+ * model and DM; otherwise the public model and DM when a public model is
+ * supplied (the paper's is built in; here the caller holds it), else DM. */
+static int32_t ms_select(const or_config *c, uint64_t n, int have_public) {
+    uint64_t bound = c->ms_threshold ? c->ms_threshold : MS_BYTES_DEFAULT;
+    if (n > bound) return SEL_SPRM | SEL_DM;
+    return have_public ? (SEL_SPUM | SEL_DM) : SEL_DM;
+}
 
 static uint64_t smp_steps(uint32_t ppm, uint64_t L) {
     return (uint64_t)(((unsigned __int128)ppm * L + 999999u) / 1000000u);
@@ -755,8 +776,10 @@ static int cfg_check(const or_config *c, or_shape *sh) {
     if (c->s < 1 || c->k < 1 || c->k > 4 || c->s > c->k) return OR_ERR_ARG;
     if (c->bs < 1 || c->bs > 65535 || c->t < 1 || c->t > 65535 || c->E < 1 || c->E > 65535) return OR_ERR_ARG;
     if (c->n_blocks < 1) return OR_ERR_ARG;
-    if (c->selector & ~(SEL_SPUM | SEL_DM)) return OR_ERR_ARG;
+    if (c->selector & ~(SEL_SPUM | SEL_SPRM | SEL_DM)) return OR_ERR_ARG;
     if (c->selector && !(c->selector & SEL_DM)) return OR_ERR_ARG;
+    /* the selector enables one of the two static models, never both */
+    if ((c->selector & SEL_SPUM) && (c->selector & SEL_SPRM)) return OR_ERR_ARG;
     if (c->smp_ppm > 1000000u) return OR_ERR_ARG;
     return shape_init(sh, c->k, c->t, c->E, c->nh, c->hidden);
 }
@@ -935,17 +958,77 @@ static int process_blocks(const or_config *cfg, const or_shape *sh, const double
     return rc_all;
 }
 
-int or_compress(const or_config *cfg, const uint8_t *in, uint64_t n, const float *static_w, uint64_t static_len,
+/* Sec. 4.2.3 with stage (b) of the pipeline (Fig. 2): the static private
+ * model is learned from the input itself before compression and stored in
+ * the compressed file.  Reading (the paper fixes neither the training data
+ * nor its length): the model has the dynamic model's shape; it starts from
+ * the seeded initialisation under seed ^ SPRM_SEED_XOR and takes the
+ * dynamic model's learning steps (Sec. 2 steps (2) and (4), its optimiser
+ * and learning rate, no static model mixed in) over one training block of
+ * bs segments of Lp tokens, segment j starting at token floor(j * l / bs)
+ * of the input's whole token sequence (the blocks' tokens in block order,
+ * l in all), Lp = min(floor(l / bs), SPRM_STEPS).  Spreading the segments
+ * over the whole input is what makes the model learn its global features.
+ * The result, rounded to FP32, is what the container stores and what both
+ * sides mix in as L^r. */
+static int sprm_train(const or_config *cfg, const or_shape *sh, const or_block *B, float *out) {
+    uint64_t n = sh->n, l = 0;
+    int nb = cfg->n_blocks, bs = cfg->bs;
+    for (int b = 0; b < nb; b++) l += B[b].l;
+    uint64_t Lp = l / (uint64_t)bs;
+    if (Lp > SPRM_STEPS) Lp = SPRM_STEPS;
+    double *w = (double *)malloc(sizeof(double) * (n + 1));
+    double *wf = (double *)malloc(sizeof(double) * (n + 1));
+    or_block pb;
+    memset(&pb, 0, sizeof pb);
+    pb.l = Lp * (uint64_t)bs;
+    pb.L = Lp;
+    pb.tok = (uint8_t *)malloc(pb.l + 1);
+    if (!w || !wf || !pb.tok) { free(w); free(wf); free(pb.tok); return OR_ERR_NOMEM; }
+    /* segment j: global tokens [floor(j l / bs), + Lp), read across blocks */
+    for (int j = 0; j < bs; j++) {
+        uint64_t g = (uint64_t)(((unsigned __int128)j * l) / (uint64_t)bs);
+        int b = 0;
+        uint64_t base = 0;
+        while (b < nb && g >= base + B[b].l) { base += B[b].l; b++; }
+        for (uint64_t p = 0; p < Lp; p++, g++) {
+            while (g >= base + B[b].l) { base += B[b].l; b++; }
+            pb.tok[(uint64_t)j * Lp + p] = B[b].tok[g - base];
+        }
+    }
+    init_params(sh, cfg->seed ^ SPRM_SEED_XOR, w);
+    w[n] = 0.0;
+    memcpy(wf, w, sizeof(double) * (n + 1));
+    or_config cd = *cfg;
+    cd.selector = SEL_DM;
+    cd.smp_ppm = 0;
+    or_probe pr = {0, NULL, NULL, 0, wf, NULL};
+    int rc = Lp ? run_block(&cd, sh, NULL, &pb, w, 0, NULL, &pr) : OR_OK;
+    if (!rc)
+        for (uint64_t i = 0; i < n; i++) out[i] = (float)wf[i];
+    block_free(&pb, bs);
+    free(w);
+    free(wf);
+    return rc;
+}
+
+int or_compress(const or_config *cfg_in, const uint8_t *in, uint64_t n, const float *static_w, uint64_t static_len,
                 uint8_t **out, uint64_t *out_len) {
+    or_config cfg_sel = *cfg_in;
+    const or_config *cfg = &cfg_sel;
+    if (cfg_sel.selector == SEL_AUTO) cfg_sel.selector = ms_select(cfg_in, n, static_w != NULL);
     or_shape sh;
     int rc = cfg_check(cfg, &sh);
     if (rc) return rc;
     double *ws = NULL;
+    float *priv = NULL;     /* the private static model, once trained */
     uint32_t scrc = 0;
     if (static_on(cfg)) {
-        if (!static_w || static_len != sh.n) return OR_ERR_MODEL;
         ws = (double *)malloc(sizeof(double) * sh.n);
         if (!ws) return OR_ERR_NOMEM;
+    }
+    if (static_on(cfg) && !private_on(cfg)) {
+        if (!static_w || static_len != sh.n) { free(ws); return OR_ERR_MODEL; }
         for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
         scrc = or_crc32((const uint8_t *)static_w, sh.n * 4);
     }
@@ -966,6 +1049,14 @@ int or_compress(const or_config *cfg, const uint8_t *in, uint64_t n, const float
             B[b].tok[j] = (uint8_t)e;
         }
     }
+    if (!rc && private_on(cfg)) {
+        priv = (float *)malloc(sizeof(float) * (sh.n + 1));
+        rc = priv ? sprm_train(cfg, &sh, B, priv) : OR_ERR_NOMEM;
+        if (!rc) {
+            for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)priv[i];
+            scrc = or_crc32((const uint8_t *)priv, sh.n * 4);
+        }
+    }
     if (!rc) rc = process_blocks(cfg, &sh, ws, B, 0, NULL);
     if (!rc) {
         or_buf o = {0};
@@ -973,6 +1064,8 @@ int or_compress(const or_config *cfg, const uint8_t *in, uint64_t n, const float
         write_header(&o, cfg, path, scrc, n);
         if (cfg->file_blocks) for (int f = 0; f < cfg->n_files; f++) put_varint(&o, cfg->file_blocks[f]);
         else put_varint(&o, (uint64_t)nb);
+        /* the private static model travels in the file (Sec. 4.2.3) */
+        if (priv) for (uint64_t i = 0; i < sh.n; i++) put_f32(&o, priv[i]);
         for (int b = 0; b < nb; b++) {
             or_block *k = &B[b];
             put_varint(&o, k->raw_len);
@@ -1003,6 +1096,7 @@ int or_compress(const or_config *cfg, const uint8_t *in, uint64_t n, const float
     for (int b = 0; b < nb; b++) block_free(&B[b], cfg->bs);
     free(B);
     free(ws);
+    free(priv);
     return rc;
 }
 
@@ -1047,9 +1141,19 @@ int or_decompress(const uint8_t *cbf, uint64_t len, const float *static_w, uint6
     if (!fblocks || !blen) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
     for (int f = 0; f < c.n_files; f++) fblocks[f] = get_varint(&r);
     c.file_blocks = fblocks;
+    if (r.err) { free(fblocks); free(blen); return OR_ERR_CORRUPT; }
     double *ws = NULL;
     int rc = OR_OK;
-    if (static_on(&c)) {
+    if (private_on(&c)) {
+        /* the stored private model: n FP32 values after the file table */
+        if (sh.n > (len - r.pos) / 4 || or_crc32(cbf + r.pos, sh.n * 4) != scrc) {
+            free(fblocks); free(blen);
+            return OR_ERR_CORRUPT;
+        }
+        ws = (double *)malloc(sizeof(double) * sh.n);
+        if (!ws) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
+        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)get_f32(&r);
+    } else if (static_on(&c)) {
         if (!static_w || static_len != sh.n || or_crc32((const uint8_t *)static_w, sh.n * 4) != scrc) {
             free(fblocks); free(blen);
             return OR_ERR_MODEL;

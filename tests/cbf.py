@@ -1,5 +1,6 @@
 """Reader for the compressed container, used by tests to compare the parts
-(header fields, block metadata, per-segment streams) of two containers."""
+(header fields, the stored private static model, block metadata,
+per-segment streams) of two containers."""
 import struct
 
 
@@ -34,6 +35,15 @@ def parse(blob: bytes) -> dict:
         v, pos = _varint(blob, pos)
         files.append(v)
     s, k, bs = h["s"], h["k"], h["bs"]
+    private = None
+    if h["selector"] & 2:
+        # the stored private static model: P FP32 values after the file table
+        dims = [h["t"] * h["E"]] + h["hidden"] + [4 ** k]
+        P = 4 ** k * h["E"] + sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+        private = blob[pos:pos + 4 * P]
+        assert len(private) == 4 * P
+        pos += 4 * P
+    h["meta_start"] = pos
     blocks = []
     for _ in range(h["n_blocks"]):
         b = {}
@@ -67,4 +77,4 @@ def parse(blob: bytes) -> dict:
             b["streams"].append(blob[pos:pos + n])
             pos += n
     assert pos == len(blob), (pos, len(blob))
-    return {"header": h, "files": files, "blocks": blocks}
+    return {"header": h, "files": files, "blocks": blocks, "private": private}
