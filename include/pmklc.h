@@ -58,12 +58,31 @@ enum { PMKLC_SGD = 0, PMKLC_ADAM = 1 };
  * numeric path made it, and only that path decodes it. */
 enum { PMKLC_FP32 = 0, PMKLC_BF16 = 1, PMKLC_FP32_VALU = 2 };
 enum { PMKLC_BATCHED = 0, PMKLC_PLAIN = 1 };      /* all blocks in one launch | one block per launch */
-/* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. */
+/* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. Accepted:
+ * 0, DM, SPUM|DM, SPRM|DM (the selector enables one static model at most),
+ * or AUTO.
+ *
+ * SPRM (Sec. 4.2.3, stage (b) of Fig. 2): before coding, the call trains a
+ * static private model on the input and stores it in the container (4 P
+ * bytes of FP32 after the file table; the header's static CRC-32 covers
+ * them). It has the dynamic model's shape, starts from the seeded
+ * initialisation under seed ^ 0x5350524D and takes the dynamic model's
+ * learning steps (its optimiser and rate, no coding, no mixing) over one
+ * training block of bs segments of Lp = min(floor(l / bs), 8192) tokens,
+ * segment j starting at token floor(j * l / bs) of the input's token
+ * sequence (all blocks' tokens in block order, l in all). The coding pass
+ * then mixes it by Eq. (1) exactly as it mixes a public static model.
+ *
+ * AUTO (the Model Selector, Sec. 4.2.1): resolved per call from the input
+ * size n in bytes: SPRM|DM when n > ms_threshold (0 = 500 * 10^6), else
+ * SPUM|DM when static_host is given, else DM. The container records the
+ * resolved selector. */
 enum {
   PMKLC_SEL_UNIFORM = 0,   /* no model: every token coded with the uniform distribution */
-  PMKLC_SEL_SPUM = 1,      /* S0: frozen static public model */
-  PMKLC_SEL_SPRM = 2,      /* S1: static private model (not built; rejected) */
-  PMKLC_SEL_DM = 4         /* S2: dynamic model */
+  PMKLC_SEL_SPUM = 1,      /* S0: frozen static public model, supplied in static_host */
+  PMKLC_SEL_SPRM = 2,      /* S1: static private model, trained on the input, stored in the container */
+  PMKLC_SEL_DM = 4,        /* S2: dynamic model */
+  PMKLC_SEL_AUTO = 8       /* the Model Selector's choice by input size (see above) */
 };
 
 typedef struct pmklc_config {
@@ -78,7 +97,7 @@ typedef struct pmklc_config {
   float lr, beta1, beta2, eps;
   uint32_t precision;       /* PMKLC_FP32 | PMKLC_BF16 | PMKLC_FP32_VALU */
   uint32_t schedule;        /* PMKLC_BATCHED | PMKLC_PLAIN */
-  uint32_t selector;        /* PMKLC_SEL_* mask: 0, DM, or SPUM|DM */
+  uint32_t selector;        /* PMKLC_SEL_*: 0, DM, SPUM|DM, SPRM|DM or AUTO */
   uint32_t smp_ppm;         /* step-wise model passing point in parts per million of a
                                block's steps (paper: 5% = 50000); 0 = off (Sec. 4.3) */
   uint64_t seed;            /* seed of the dynamic model's initial weights */
@@ -86,8 +105,9 @@ typedef struct pmklc_config {
   const uint64_t *block_len_host;   /* raw bytes per block, or NULL = equal split */
   uint32_t n_files;         /* files in the input; model passing never crosses a file */
   const uint64_t *file_blocks_host; /* blocks per file, or NULL = one file */
-  const float *static_host; /* frozen static model (parameter layout above, no alpha) */
+  const float *static_host; /* frozen static public model (parameter layout above, no alpha) */
   uint64_t static_len;      /* number of floats in static_host */
+  uint64_t ms_threshold;    /* PMKLC_SEL_AUTO's size bound in input bytes; 0 = 500 * 10^6 */
 } pmklc_config;
 
 /* Sec. 4.1 (GskE): maps ASCII bases A,C,G,T (0,1,2,3) to (s,k)-mer ids
@@ -139,9 +159,11 @@ pmklc_status pmklc_decompress_info(const uint8_t *cbf_host, uint64_t len, uint64
                                    uint64_t *ws_bytes);
 
 /* Sec. 2 (decompression): the same models, updated the same way, restore
- * the input from the container. static_host must be the static model the
- * container was made with (checked by CRC-32), else
- * PMKLC_ERR_MODEL_MISMATCH. out_dev receives n_bases bytes. */
+ * the input from the container. For a container made with the public
+ * static model, static_host must be that model (checked by CRC-32), else
+ * PMKLC_ERR_MODEL_MISMATCH; a private model is read from the container
+ * (checked by CRC-32, else PMKLC_ERR_CORRUPT) and static_host is ignored.
+ * out_dev receives n_bases bytes. */
 pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float *static_host,
                               uint64_t static_len, void *ws_dev, uint64_t ws_bytes, uint8_t *out_dev,
                               uint64_t out_cap, uint64_t *out_len, void *stream);

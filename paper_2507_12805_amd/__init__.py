@@ -7,7 +7,7 @@ If the library is missing, every entry point raises; there is no fallback.
 
 Configurations are plain dicts with the keys of ``synth.workloads``
 (s, k, t, bs, E, hidden, optimizer, lr, beta1, beta2, eps, selector,
-smp_ppm, seed, n_blocks / block_len, file_blocks) plus ``precision``
+smp_ppm, seed, n_blocks / block_len, file_blocks, ms_threshold) plus ``precision``
 ("fp32" | "bf16") and ``schedule`` ("batched" | "plain").
 """
 from __future__ import annotations
@@ -41,7 +41,8 @@ class _Config(ctypes.Structure):
                 ("selector", ctypes.c_uint32), ("smp_ppm", ctypes.c_uint32), ("seed", ctypes.c_uint64),
                 ("n_blocks", ctypes.c_uint32), ("block_len_host", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_files", ctypes.c_uint32), ("file_blocks_host", ctypes.POINTER(ctypes.c_uint64)),
-                ("static_host", ctypes.POINTER(ctypes.c_float)), ("static_len", ctypes.c_uint64)]
+                ("static_host", ctypes.POINTER(ctypes.c_float)), ("static_len", ctypes.c_uint64),
+                ("ms_threshold", ctypes.c_uint64)]
 
 
 class Timing(ctypes.Structure):
@@ -122,7 +123,7 @@ def _dev_tensor(x, dtype):
     return t.contiguous()
 
 
-SELECTORS = {"uniform": 0, "dm": 4, "spum_dm": 5}
+SELECTORS = {"uniform": 0, "dm": 4, "spum_dm": 5, "sprm_dm": 6, "spum_sprm_dm": 7, "auto": 8}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp32_valu": 2}
 
 
@@ -141,6 +142,7 @@ def make_config(cfg: dict, static=None):
     c.precision = PRECISIONS[cfg.get("precision", "fp32")]
     c.schedule = 1 if cfg.get("schedule", "batched") == "plain" else 0
     c.selector = SELECTORS[cfg.get("selector", "dm")]
+    c.ms_threshold = int(cfg.get("ms_threshold", 0))
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
     c.seed = int(cfg["seed"])
     keep = []

@@ -88,6 +88,12 @@ struct StatusSlot {
 constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathBF16Chip = 4, kPathUniform = 255;
 enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kChipBf16 = 3 };
 constexpr int kHeaderBytes = 80;
+// Sec. 4.2.1: the Model Selector's size bound (500 MB, read as 10^6 bytes)
+constexpr uint64_t kMsBytes = 500000000ull;
+// training of the static private model (Sec. 4.2.3): at most this many
+// steps, seeded initialisation under seed ^ kSprmSeedXor
+constexpr uint32_t kSprmSteps = 8192;
+constexpr uint64_t kSprmSeedXor = 0x5350524Dull;
 
 #define HIP_TRY(x)                                     \
   do {                                                 \
@@ -197,10 +203,11 @@ pmklc_status check_cfg(const pmklc_config *c) {
   for (uint32_t l = 0; l < c->n_hidden; l++)
     if (c->hidden[l] < 1 || c->hidden[l] > 65535) return PMKLC_ERR_INVALID_ARG;
   if (c->optimizer > 1 || c->precision > 2 || c->schedule > 1) return PMKLC_ERR_INVALID_ARG;
+  // one static model at most, always with the dynamic model (Sec. 4.2.1)
   if (c->selector != PMKLC_SEL_UNIFORM && c->selector != PMKLC_SEL_DM &&
-      c->selector != (PMKLC_SEL_SPUM | PMKLC_SEL_DM)) {
-    return (c->selector & PMKLC_SEL_SPRM) ? PMKLC_ERR_UNSUPPORTED : PMKLC_ERR_INVALID_ARG;
-  }
+      c->selector != (PMKLC_SEL_SPUM | PMKLC_SEL_DM) && c->selector != (PMKLC_SEL_SPRM | PMKLC_SEL_DM) &&
+      c->selector != PMKLC_SEL_AUTO)
+    return PMKLC_ERR_INVALID_ARG;
   if (c->smp_ppm > 1000000u) return PMKLC_ERR_INVALID_ARG;
   if (c->n_blocks < 1) return PMKLC_ERR_INVALID_ARG;
   return PMKLC_OK;
@@ -214,8 +221,6 @@ uint64_t param_count(uint32_t k, uint32_t t, uint32_t E, uint32_t nh, const uint
   return n;
 }
 
-// Shape + LDS plan of the step kernel; UNSUPPORTED when this build's kernel
-// cannot hold it (see the design notes: tile and LDS limits).
 // Shape and parameter offsets of the model (no kernel-support checks).
 pmklc_status fill_dims(uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh, const uint32_t *hidden,
                        uint32_t selector, uint32_t opt, float lr, float b1, float b2, float eps, Dims &d) {
@@ -228,7 +233,7 @@ pmklc_status fill_dims(uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t
   d.bs = (int)bs;
   d.nh = (int)nh;
   d.model_on = (selector & PMKLC_SEL_DM) ? 1 : 0;
-  d.static_on = (selector & PMKLC_SEL_SPUM) ? 1 : 0;
+  d.static_on = (selector & (PMKLC_SEL_SPUM | PMKLC_SEL_SPRM)) ? 1 : 0;
   d.optimizer = (int)opt;
   d.lr = lr; d.b1 = b1; d.b2 = b2; d.eps = eps;
   if (!d.model_on) d.nh = 0;   // uniform coding needs no model
@@ -371,6 +376,20 @@ pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip) {
 }
 pmklc_status make_model(const pmklc_config *c, Model &m) { return make_model(c, m, chip_default()); }
 
+// Sec. 4.2.1, the Model Selector: the configuration with S chosen for an
+// input of n bytes when the caller asked for the selector's choice (the
+// private static model above the size bound; else the public one when the
+// caller supplies it; else the dynamic model alone).
+pmklc_config ms_resolve(const pmklc_config *c, uint64_t n) {
+  pmklc_config r = *c;
+  if (c->selector == PMKLC_SEL_AUTO) {
+    const uint64_t bound = c->ms_threshold ? c->ms_threshold : kMsBytes;
+    r.selector = n > bound ? (PMKLC_SEL_SPRM | PMKLC_SEL_DM)
+                 : c->static_host ? (PMKLC_SEL_SPUM | PMKLC_SEL_DM) : PMKLC_SEL_DM;
+  }
+  return r;
+}
+
 // -------------------------------------------------------------- planning
 struct Plan {
   std::vector<uint64_t> raw_len, raw_off;
@@ -507,6 +526,27 @@ uint64_t trial_bytes(const Model &m) {
   Work w;
   layout(A, m, 1, trial_sizes(m), m.d.optimizer == 1, false, w, true);
   return A.used + 256;
+}
+
+// The static private model's training run (Sec. 4.2.3): the dynamic model
+// alone (its own kernel choice) on one block of bs segments of at most
+// Lp_max steps, laid out after the compression's own workspace.
+struct SprmRun {
+  Model m;
+  Work w;
+  uint32_t Lp_max = 0;
+};
+pmklc_status sprm_layout(Arena &A, const pmklc_config *c, uint64_t tokens_max, SprmRun &r) {
+  pmklc_config cd = *c;
+  cd.selector = PMKLC_SEL_DM;
+  pmklc_status rc = make_model(&cd, r.m);
+  if (rc) return rc;
+  r.Lp_max = (uint32_t)std::min<uint64_t>(tokens_max / c->bs, kSprmSteps);
+  Sizes z{};
+  z.tokens = (uint64_t)r.Lp_max * c->bs;
+  z.slot_words = (uint64_t)slot_words_for(r.Lp_max) * c->bs;
+  layout(A, r.m, 1, z, c->optimizer == PMKLC_ADAM, false, r.w, true);
+  return PMKLC_OK;
 }
 
 hipError_t launch_kind(const Model &m, const StepArgs &a, const StepArgs *a_dev, int grid, int nt, hipStream_t st) {
@@ -752,8 +792,9 @@ std::vector<int> queue_order(const std::vector<BlockDesc> &bd) {
   return ord;
 }
 
+// params_out: when given, block 0 writes its final parameters (+ a) there
 pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockDesc> &bd, uint32_t schedule,
-                      hipStream_t st, StepTimer *tm = nullptr, bool tune = true) {
+                      hipStream_t st, StepTimer *tm = nullptr, bool tune = true, float *params_out = nullptr) {
   m.nt = choose_nt(m, w, st, tune);
   g_last.threads = (uint32_t)m.nt;
   StepArgs a;
@@ -780,6 +821,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   a.act_scratch = w.act;
   a.w1f = w.w1f;
   a.s1f = w.s1f;
+  a.params_out = params_out;
   // a waiting block gives up only after ~10 s without a step of its running
   // predecessor (a hardware fault, not a slow model); PMKLC_SPIN_LIMIT
   // overrides the bound (tests of the give-up path)
@@ -902,9 +944,11 @@ pmklc_status pmklc_encode_skmer(const uint8_t *bases_dev, uint64_t n, uint32_t s
   return PMKLC_OK;
 }
 
-pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t *max_out, uint64_t *ws_bytes) {
-  pmklc_status rc = check_cfg(cfg);
+pmklc_status pmklc_compress_bound(const pmklc_config *cfg_in, uint64_t n, uint64_t *max_out, uint64_t *ws_bytes) {
+  pmklc_status rc = check_cfg(cfg_in);
   if (rc) return rc;
+  const pmklc_config cr = ms_resolve(cfg_in, n);
+  const pmklc_config *cfg = &cr;
   Model m;
   rc = make_model(cfg, m);
   if (rc) return rc;
@@ -929,6 +973,12 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t 
   Arena A{nullptr, ~0ull};
   Work w;
   layout(A, m, cfg->n_blocks, z, cfg->optimizer == PMKLC_ADAM, cfg->smp_ppm > 0, w);
+  if (cfg->selector & PMKLC_SEL_SPRM) {
+    SprmRun pr;
+    rc = sprm_layout(A, cfg, z.tokens, pr);
+    if (rc) return rc;
+    meta += 4ull * m.d.P;
+  }
   if (max_out) *max_out = meta + z.staging;
   if (ws_bytes) *ws_bytes = A.used + 256;
   return PMKLC_OK;
@@ -939,14 +989,17 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t 
 namespace {
 // pmklc_compress on a given workspace. noalloc: the no-allocation entry
 // point's call (no timing events, no autotuner trial runs).
-pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
+pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, uint64_t n, void *ws_dev,
                            uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
                            void *stream, bool noalloc) {
   const auto t0 = std::chrono::steady_clock::now();
   g_last = pmklc_timing{};
   StepTimer tm;
-  pmklc_status rc = check_cfg(cfg);
+  pmklc_status rc = check_cfg(cfg_in);
   if (rc) return rc;
+  const pmklc_config cr = ms_resolve(cfg_in, n);
+  const pmklc_config *cfg = &cr;
+  const bool sprm = (cfg->selector & PMKLC_SEL_SPRM) != 0;
   if (!out_len || (n && !in_dev) || !ws_dev) return PMKLC_ERR_INVALID_ARG;
   Model m;
   rc = make_model(cfg, m);
@@ -983,6 +1036,11 @@ pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint6
   Arena A{static_cast<uint8_t *>(ws_dev), ws_bytes};
   Work w;
   layout(A, m, nblk, z, cfg->optimizer == PMKLC_ADAM, smp, w);
+  SprmRun pr;
+  if (sprm) {
+    rc = sprm_layout(A, cfg, z.tokens, pr);
+    if (rc) return rc;
+  }
   if (A.over) return PMKLC_ERR_BUFFER_TOO_SMALL;
 
   // ---- A1: scan (validate, count N runs)
@@ -1034,12 +1092,40 @@ pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint6
   fill_blockdesc(m, sb, p, cfg->smp_ppm, bd, slot_total);
   HIP_TRY(h2d(w.desc, bd, st));
   uint32_t scrc = 0;
+  std::vector<float> priv;   // the static private model, as stored
   if (m.d.model_on) {
     HIP_TRY(launch_init_params(m.d, cfg->seed, w.init, st));
-    if (m.d.static_on) {
+    if (m.d.static_on && !sprm) {
       scrc = crc32(cfg->static_host, 4ull * m.d.P);
       HIP_TRY(hipMemcpyAsync(w.stat, cfg->static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
     }
+  }
+  if (sprm) {
+    // Sec. 4.2.3 / stage (b): train the private model on the input's own
+    // tokens, straight into the static-model slab of the coding pass
+    const uint64_t Lp = std::min<uint64_t>(tok_total / bs, kSprmSteps);
+    if (Lp > pr.Lp_max) return PMKLC_ERR_DEVICE;
+    HIP_TRY(launch_init_params(pr.m.d, cfg->seed ^ kSprmSeedXor, pr.w.init, st));
+    if (Lp > 0) {
+      HIP_TRY(launch_sprm_gather(w.tok, tok_total, bs, (uint32_t)Lp, pr.w.tok, st));
+      std::vector<BlockDesc> one(1);
+      one[0] = BlockDesc{};
+      one[0].L = (uint32_t)Lp;
+      one[0].slot_words = slot_words_for(Lp);
+      one[0].pred = -1;
+      HIP_TRY(h2d(pr.w.desc, one, st));
+      rc = run_step(pr.m, pr.w, 0, one, PMKLC_BATCHED, st, nullptr, false, w.stat);
+      if (rc) return rc;
+      std::vector<int> pctr;
+      HIP_TRY(d2h(pctr, pr.w.ctr, 2, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (pctr[1]) return PMKLC_ERR_DEVICE;
+    } else {
+      HIP_TRY(hipMemcpyAsync(w.stat, pr.w.init, 4ull * m.d.P, hipMemcpyDeviceToDevice, st));
+    }
+    HIP_TRY(d2h(priv, w.stat, (uint64_t)m.d.P, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    scrc = crc32(priv.data(), 4ull * m.d.P);
   }
   count_work(m, bd, g_last);
   rc = run_step(m, w, 0, bd, cfg->schedule, st, noalloc ? nullptr : &tm, !noalloc);
@@ -1059,6 +1145,7 @@ pmklc_status compress_impl(const pmklc_config *cfg, const uint8_t *in_dev, uint6
   Writer meta{out_host, out_cap};
   write_header(meta, cfg, path_of(cfg->selector, m.kind), scrc, n, (uint32_t)p.file_blocks.size());
   for (uint64_t fb : p.file_blocks) meta.varint(fb);
+  if (sprm) meta.put(priv.data(), 4ull * m.d.P);   // the private model travels in the file
   std::vector<uint64_t> seg_src, seg_dst;
   std::vector<uint32_t> seg_bytes;
   uint64_t stream_total = 0;
@@ -1156,6 +1243,7 @@ struct Parsed {
   std::vector<uint8_t> extras;        // per block: tail codes then remainder tokens (bs + 8 bytes each)
   std::vector<uint32_t> seg_bytes;    // [blocks with L>0][bs] in block order, flat per block b at b*bs
   uint64_t stream_off;                // first stream byte in the container
+  uint64_t private_off = 0;           // the stored static private model (4 P bytes), if any
 };
 
 pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
@@ -1191,7 +1279,7 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   if (r.bad) return PMKLC_ERR_CORRUPT;
   c.precision = (o.path == kPathBF16 || o.path == kPathBF16Chip) ? PMKLC_BF16
                 : o.path == kPathFP32Valu ? PMKLC_FP32_VALU : PMKLC_FP32;
-  if (check_cfg(&c)) return PMKLC_ERR_CORRUPT;
+  if (check_cfg(&c) || c.selector == PMKLC_SEL_AUTO) return PMKLC_ERR_CORRUPT;
   if (o.path != kPathUniform && o.path != kPathBF16 && o.path != kPathFP32Valu && o.path != kPathFP32Mfma &&
       o.path != kPathBF16Chip)
     return PMKLC_ERR_MODEL_MISMATCH;
@@ -1201,6 +1289,13 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   for (uint32_t f = 0; f < nf; f++) { o.file_blocks[f] = r.varint(); tot += o.file_blocks[f]; }
   if (r.bad || tot != c.n_blocks) return PMKLC_ERR_CORRUPT;
   c.n_files = nf;
+  if (c.selector & PMKLC_SEL_SPRM) {
+    // the private static model, checked against the header's CRC-32
+    const uint64_t P = param_count(c.k, c.t, c.embed, c.n_hidden, c.hidden);
+    if (P > (len - r.pos) / 4 || crc32(p + r.pos, 4 * P) != o.scrc) return PMKLC_ERR_CORRUPT;
+    o.private_off = r.pos;
+    r.pos += 4 * P;
+  }
   if (!full) return PMKLC_OK;
   const uint32_t nblk = c.n_blocks, bs = c.bs, s = c.s, k = c.k;
   o.sb.resize(nblk);
@@ -1310,7 +1405,8 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   rc = make_model(&o.c, m, o.path == kPathBF16Chip);
   if (rc) return rc;
   if (path_of(o.c.selector, m.kind) != o.path) return PMKLC_ERR_MODEL_MISMATCH;
-  if (m.d.static_on) {
+  const bool sprm = (o.c.selector & PMKLC_SEL_SPRM) != 0;
+  if (m.d.static_on && !sprm) {
     if (!static_host || static_len != (uint64_t)m.d.P || crc32(static_host, 4ull * m.d.P) != o.scrc)
       return PMKLC_ERR_MODEL_MISMATCH;
   }
@@ -1372,7 +1468,10 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   HIP_TRY(h2d(w.run_cum, o.run_cum, st));
   if (m.d.model_on) {
     HIP_TRY(launch_init_params(m.d, o.c.seed, w.init, st));
-    if (m.d.static_on) HIP_TRY(hipMemcpyAsync(w.stat, static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
+    if (m.d.static_on) {
+      const void *src = sprm ? static_cast<const void *>(cbf_host + o.private_off) : static_host;
+      HIP_TRY(hipMemcpyAsync(w.stat, src, 4ull * m.d.P, hipMemcpyHostToDevice, st));
+    }
   }
   count_work(m, bd, g_last);
   rc = run_step(m, w, 1, bd, PMKLC_BATCHED, st, &tm);

@@ -186,5 +186,9 @@ hipError_t launch_gather_streams(const uint32_t *slots, const uint64_t *seg_src_
 hipError_t launch_scatter_streams(const uint8_t *src, const uint64_t *seg_src, const uint64_t *seg_dst_word,
                                   const uint32_t *seg_bytes, const uint32_t *seg_words, uint64_t n_seg,
                                   uint32_t *slots, hipStream_t st);
+// static private model (Sec. 4.2.3): training block of bs segments of Lp
+// tokens, segment j from token floor(j * l / bs) of tok[0, l)
+hipError_t launch_sprm_gather(const uint8_t *tok, uint64_t l, uint32_t bs, uint32_t Lp, uint8_t *dst,
+                              hipStream_t st);
 
 }  // namespace pmklc

@@ -673,4 +673,25 @@ hipError_t launch_scatter_streams(const uint8_t *src, const uint64_t *seg_src, c
   return hipGetLastError();
 }
 
+
+// Training block of the static private model (Sec. 4.2.3): segment j is the
+// Lp tokens that start at token floor(j * l / bs) of the whole token array.
+// One workgroup per segment; floor(j l / bs) + Lp <= l since Lp <= l / bs.
+__global__ __launch_bounds__(256) void sprm_gather_kernel(const uint8_t *tok, uint64_t l, uint32_t bs, uint32_t Lp,
+                                                          uint8_t *dst) {
+  const uint32_t j = blockIdx.x;
+  const uint64_t start = (uint64_t)j * l / bs;
+  const uint8_t *s8 = tok + start;
+  uint8_t *d = dst + (uint64_t)j * Lp;
+  for (uint32_t q = threadIdx.x; q < Lp; q += 256) d[q] = s8[q];
+}
+
+hipError_t launch_sprm_gather(const uint8_t *tok, uint64_t l, uint32_t bs, uint32_t Lp, uint8_t *dst,
+                              hipStream_t st) {
+  if (Lp == 0) return hipSuccess;
+  if (bs == 0 || (uint64_t)Lp * bs > l || l > ~0ull / bs) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sprm_gather_kernel, dim3(bs), dim3(256), 0, st, tok, l, bs, Lp, dst);
+  return hipGetLastError();
+}
+
 }  // namespace pmklc
