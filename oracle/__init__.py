@@ -15,6 +15,9 @@ Parity status per function (see the tests under ``tests/test_oracle_*``):
   compress      pinned: uniform closed form (2 bits/base at s = k), round
                 trip, edge cases; the learned-model ratio on synthetic data
                 is parity unpinned (the paper's datasets are unavailable)
+  transformer   pinned: torch FP64 autograd with torch's own attention
+                routine, finite differences, t = 1 and zero-key closed
+                forms, learning-loop replay (SGD, Adam)
   private model pinned: training block gathered from its definition and run
                 through the pinned trace; coding pass equal to the public-
                 model container with the stored weights; the selector's
@@ -67,7 +70,8 @@ class _Cfg(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("selector", ctypes.c_int32),
                 ("smp_ppm", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("n_blocks", ctypes.c_int32),
                 ("block_len", _u64p), ("n_files", ctypes.c_int32), ("file_blocks", _u64p),
-                ("init_override", _dp), ("ms_threshold", ctypes.c_uint64)]
+                ("init_override", _dp), ("ms_threshold", ctypes.c_uint64), ("arch", ctypes.c_int32),
+                ("heads", ctypes.c_int32)]
 
 
 def _load():
@@ -85,11 +89,11 @@ def _load():
     L.or_wnc_decode.argtypes = [_u8p, ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_uint64, _u32p]
     L.or_crc32.argtypes = [_u8p, ctypes.c_uint64]
     L.or_crc32.restype = ctypes.c_uint32
-    L.or_param_count.argtypes = [ctypes.c_int] * 4 + [_i32p]
+    L.or_param_count.argtypes = [ctypes.c_int] * 4 + [_i32p, ctypes.c_int, ctypes.c_int]
     L.or_param_count.restype = ctypes.c_uint64
-    L.or_init_params.argtypes = [ctypes.c_int] * 4 + [_i32p, ctypes.c_uint64, _dp]
-    L.or_step.argtypes = [ctypes.c_int] * 4 + [_i32p, _dp, _dp, ctypes.c_double, _u8p, _u8p, ctypes.c_int, _dp,
-                                                _dp, _dp, _dp]
+    L.or_init_params.argtypes = [ctypes.c_int] * 4 + [_i32p, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _dp]
+    L.or_step.argtypes = [ctypes.c_int] * 4 + [_i32p, ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_double, _u8p,
+                                                _u8p, ctypes.c_int, _dp, _dp, _dp, _dp]
     L.or_opt_step.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                               _dp, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint64]
     L.or_opt_step.restype = None
@@ -196,16 +200,26 @@ def _hidden(cfg):
     return arr, len(h)
 
 
+ARCHS = {"mlp": 0, "transformer": 1}
+
+
+def _arch(cfg):
+    """(arch code, heads) of a configuration: "mlp" (default) or
+    "transformer" (hidden = [A, F], heads)."""
+    a = ARCHS[cfg.get("arch", "mlp")]
+    return a, int(cfg.get("heads", 0)) if a == 1 else 0
+
+
 def param_count(cfg) -> int:
     h, nh = _hidden(cfg)
-    return int(_load().or_param_count(cfg["k"], cfg["t"], cfg["E"], nh, _ptr(h, _i32p)))
+    return int(_load().or_param_count(cfg["k"], cfg["t"], cfg["E"], nh, _ptr(h, _i32p), *_arch(cfg)))
 
 
 def init_params(cfg, seed=None) -> np.ndarray:
     h, nh = _hidden(cfg)
     n = param_count(cfg)
     w = np.zeros(n, dtype=np.float64)
-    _check(_load().or_init_params(cfg["k"], cfg["t"], cfg["E"], nh, _ptr(h, _i32p),
+    _check(_load().or_init_params(cfg["k"], cfg["t"], cfg["E"], nh, _ptr(h, _i32p), *_arch(cfg),
                                   cfg["seed"] if seed is None else seed, _ptr(w, _dp)), "init_params")
     return w
 
@@ -213,6 +227,15 @@ def init_params(cfg, seed=None) -> np.ndarray:
 def param_slices(cfg) -> dict:
     """Offsets of each tensor in the flat parameter vector."""
     V = 4 ** cfg["k"]
+    if _arch(cfg)[0] == 1:
+        E, t, (A, F) = cfg["E"], cfg["t"], cfg["hidden"]
+        out, off = {}, 0
+        for name, shp in [("emb", (V, E)), ("pos", (t, E)), ("Wqkv", (E, 3 * A)), ("bqkv", (3 * A,)),
+                          ("Wo", (A, A)), ("bo", (A,)), ("W1", (A, F)), ("b1", (F,)), ("W2", (F, A)),
+                          ("b2", (A,)), ("Wh", (A, V)), ("bh", (V,))]:
+            out[name] = (off, shp)
+            off += int(np.prod(shp))
+        return out
     dims = [cfg["t"] * cfg["E"]] + list(cfg["hidden"]) + [V]
     off = 0
     out = {"emb": (off, (V, cfg["E"]))}
@@ -238,7 +261,7 @@ def step(cfg, w, ctx, tgt, ws=None, a_alpha=0.0, grad=True):
     g = np.zeros_like(w) if grad else None
     ga = ctypes.c_double(0)
     loss = ctypes.c_double(0)
-    _check(_load().or_step(cfg["k"], cfg["t"], cfg["E"], nh, _ptr(h, _i32p), _ptr(w, _dp), _ptr(ws, _dp),
+    _check(_load().or_step(cfg["k"], cfg["t"], cfg["E"], nh, _ptr(h, _i32p), *_arch(cfg), _ptr(w, _dp), _ptr(ws, _dp),
                            float(a_alpha), _ptr(ctx, _u8p), _ptr(tgt, _u8p), bs, _ptr(P, _dp), _ptr(g, _dp),
                            ctypes.byref(ga), ctypes.byref(loss)), "step")
     return P, g, ga.value, loss.value
@@ -263,6 +286,7 @@ def _mkcfg(cfg, n):
     sel = cfg.get("selector", "dm")
     c.selector = {"uniform": 0, "dm": 4, "spum_dm": 5, "sprm_dm": 6, "spum_sprm_dm": 7, "auto": 8}[sel]
     c.ms_threshold = int(cfg.get("ms_threshold", 0))
+    c.arch, c.heads = _arch(cfg)
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
     c.seed = int(cfg["seed"])
     keep = []

@@ -280,14 +280,57 @@ uint32_t or_crc32(const uint8_t *p, uint64_t n) {
 /* Flat parameter order: Emb[V][E], then per layer l: W_l[d_l][d_{l+1}]   */
 /* (input-major) and b_l[d_{l+1}]; d_0 = t*E, d_{nh+1} = V.              */
 /* ------------------------------------------------------------------ */
+/* arch 0: the MLP of the configurations (embedding, concatenation, hidden
+ * Dense + ReLU layers, linear head).  arch 1: the paper's Transformer DM
+ * (Sec. 4.2.4): embedding E plus a learned position embedding, one
+ * attention layer of `heads` heads and width A = hidden[0], a shared FFN of
+ * width F = hidden[1] with ReLU, a linear head to V, read at the last
+ * context position.  Parameter order for arch 1: Emb[V][E], Pos[t][E],
+ * Wqkv[E][3A], bqkv[3A], Wo[A][A], bo[A], W1[A][F], b1[F], W2[F][A], b2[A],
+ * Wh[A][V], bh[V] (off_W / off_b 0..4 in that order, fan[l] their fan-in). */
 typedef struct {
     int V, E, t, D, nh;
     int dims[6];
     uint64_t off_emb, off_W[5], off_b[5], n;
+    int arch, heads, A, F;
+    int fan[5];
+    uint64_t off_pos;
 } or_shape;
 
-static int shape_init(or_shape *sh, int k, int t, int E, int nh, const int32_t *hidden) {
+static int shape_init_tf(or_shape *sh, int k, int t, int E, int nh, const int32_t *hidden, int heads) {
+    if (nh != 2 || heads < 1 || hidden[0] < 1 || hidden[1] < 1 || hidden[0] % heads) return OR_ERR_ARG;
+    int A = hidden[0], F = hidden[1];
+    sh->V = 1 << (2 * k);
+    sh->E = E;
+    sh->t = t;
+    sh->D = E;
+    sh->nh = nh;
+    sh->arch = 1;
+    sh->heads = heads;
+    sh->A = A;
+    sh->F = F;
+    int rows[5] = {E, A, A, F, A}, cols[5] = {3 * A, A, F, A, sh->V};
+    uint64_t off = 0;
+    sh->off_emb = off;
+    off += (uint64_t)sh->V * E;
+    sh->off_pos = off;
+    off += (uint64_t)t * E;
+    for (int l = 0; l < 5; l++) {
+        sh->fan[l] = rows[l];
+        sh->off_W[l] = off;
+        off += (uint64_t)rows[l] * cols[l];
+        sh->off_b[l] = off;
+        off += (uint64_t)cols[l];
+    }
+    sh->n = off;
+    return OR_OK;
+}
+
+static int shape_init(or_shape *sh, int k, int t, int E, int nh, const int32_t *hidden, int arch, int heads) {
     if (k < 1 || k > 4 || t < 1 || E < 1 || nh < 0 || nh > 4) return OR_ERR_ARG;
+    memset(sh, 0, sizeof *sh);
+    if (arch == 1) return shape_init_tf(sh, k, t, E, nh, hidden, heads);
+    if (arch != 0) return OR_ERR_ARG;
     sh->V = 1 << (2 * k);
     sh->E = E;
     sh->t = t;
@@ -312,9 +355,9 @@ static int shape_init(or_shape *sh, int k, int t, int E, int nh, const int32_t *
     return OR_OK;
 }
 
-uint64_t or_param_count(int k, int t, int E, int nh, const int32_t *hidden) {
+uint64_t or_param_count(int k, int t, int E, int nh, const int32_t *hidden, int arch, int heads) {
     or_shape sh;
-    if (shape_init(&sh, k, t, E, nh, hidden)) return 0;
+    if (shape_init(&sh, k, t, E, nh, hidden, arch, heads)) return 0;
     return sh.n;
 }
 
@@ -328,21 +371,27 @@ static uint64_t splitmix_at(uint64_t seed, uint64_t i) {
 }
 
 /* Initial weights: u = top 24 bits / 2^24, w = fp32((2u - 1) * a) with
- * a = 1 for the embedding and a = 1/sqrt(fan_in) for every linear weight
- * and bias.  The oracle keeps the FP64 value of the FP32 number. */
+ * a = 1 for the embeddings (token and, for arch 1, position) and
+ * a = 1/sqrt(fan_in) for every linear weight and bias.  The oracle keeps
+ * the FP64 value of the FP32 number. */
 static void init_params(const or_shape *sh, uint64_t seed, double *w) {
+    int nl = sh->arch == 1 ? 5 : sh->nh + 1;
     for (uint64_t i = 0; i < sh->n; i++) {
         double a = 1.0;
-        for (int l = 0; l <= sh->nh; l++)
-            if (i >= sh->off_W[l] && i < sh->off_b[l] + (uint64_t)sh->dims[l + 1])
-                a = 1.0 / sqrt((double)sh->dims[l]);
+        for (int l = 0; l < nl; l++) {
+            uint64_t end = sh->arch == 1 ? (l + 1 < nl ? sh->off_W[l + 1] : sh->n)
+                                         : sh->off_b[l] + (uint64_t)sh->dims[l + 1];
+            if (i >= sh->off_W[l] && i < end)
+                a = 1.0 / sqrt((double)(sh->arch == 1 ? sh->fan[l] : sh->dims[l]));
+        }
         double u = (double)(splitmix_at(seed, i) >> 40) * (1.0 / 16777216.0);
         w[i] = (double)(float)((2.0 * u - 1.0) * a);
     }
 }
-int or_init_params(int k, int t, int E, int nh, const int32_t *hidden, uint64_t seed, double *w) {
+int or_init_params(int k, int t, int E, int nh, const int32_t *hidden, int arch, int heads, uint64_t seed,
+                   double *w) {
     or_shape sh;
-    int rc = shape_init(&sh, k, t, E, nh, hidden);
+    int rc = shape_init(&sh, k, t, E, nh, hidden, arch, heads);
     if (rc) return rc;
     init_params(&sh, seed, w);
     return OR_OK;
@@ -373,10 +422,141 @@ static void mlp_forward_row(const or_shape *sh, const double *w, const uint8_t *
         in = out;
     }
 }
+/* Transformer DM forward of one row (Sec. 4.2.4, reading): with context
+ * tokens c_0..c_{t-1} (oldest first),
+ *   x_p = Emb[c_p] + Pos[p],  [q_p | k_p | v_p] = x_p Wqkv + bqkv,
+ *   per head h over its dh = A/heads columns, at the last position:
+ *     s_p = q_{t-1,h} . k_{p,h} / sqrt(dh),  a = softmax(s),  o_h = sum_p a_p v_{p,h},
+ *   z = o Wo + bo,  u = ReLU(z W1 + b1),  g = u W2 + b2,  logits = g Wh + bh.
+ * The prediction reads the last position only, so the position-wise FFN
+ * is needed there alone.  act layout: X[t][E], QKV[t][3A], att[heads][t],
+ * O[A], Z[A], U[F], G[A]. */
+static uint64_t tf_act_len(const or_shape *sh) {
+    return (uint64_t)sh->t * sh->E + (uint64_t)sh->t * 3 * sh->A + (uint64_t)sh->heads * sh->t + 3ull * sh->A +
+           (uint64_t)sh->F + (uint64_t)sh->A;
+}
+static void linear_fwd(const double *in, int di, const double *W, const double *b, int dn, double *out) {
+    for (int o = 0; o < dn; o++) out[o] = b[o];
+    for (int d = 0; d < di; d++) {
+        const double *Wr = W + (uint64_t)d * dn;
+        for (int o = 0; o < dn; o++) out[o] += in[d] * Wr[o];
+    }
+}
+static void tf_forward_row(const or_shape *sh, const double *w, const uint8_t *ctx, double *act, double *logits) {
+    int t = sh->t, E = sh->E, A = sh->A, F = sh->F, H = sh->heads, dh = A / H;
+    double *X = act, *QKV = X + (uint64_t)t * E, *att = QKV + (uint64_t)t * 3 * A, *O = att + (uint64_t)H * t;
+    double *Z = O + A, *U = Z + A, *G = U + F;
+    for (int p = 0; p < t; p++)
+        for (int e = 0; e < E; e++)
+            X[p * E + e] = w[sh->off_emb + (uint64_t)ctx[p] * E + e] + w[sh->off_pos + (uint64_t)p * E + e];
+    for (int p = 0; p < t; p++)
+        linear_fwd(X + (uint64_t)p * E, E, w + sh->off_W[0], w + sh->off_b[0], 3 * A, QKV + (uint64_t)p * 3 * A);
+    const double *q = QKV + (uint64_t)(t - 1) * 3 * A;
+    double scale = 1.0 / sqrt((double)dh);
+    for (int h = 0; h < H; h++) {
+        double *a = att + (uint64_t)h * t;
+        for (int p = 0; p < t; p++) {
+            const double *k = QKV + (uint64_t)p * 3 * A + A;
+            double dot = 0.0;
+            for (int d = 0; d < dh; d++) dot += q[h * dh + d] * k[h * dh + d];
+            a[p] = dot * scale;
+        }
+        double mx = a[0];
+        for (int p = 1; p < t; p++) if (a[p] > mx) mx = a[p];
+        double sum = 0.0;
+        for (int p = 0; p < t; p++) { a[p] = exp(a[p] - mx); sum += a[p]; }
+        for (int p = 0; p < t; p++) a[p] /= sum;
+        for (int d = 0; d < dh; d++) {
+            double o = 0.0;
+            for (int p = 0; p < t; p++) o += a[p] * QKV[(uint64_t)p * 3 * A + 2 * A + h * dh + d];
+            O[h * dh + d] = o;
+        }
+    }
+    linear_fwd(O, A, w + sh->off_W[1], w + sh->off_b[1], A, Z);
+    linear_fwd(Z, A, w + sh->off_W[2], w + sh->off_b[2], F, U);
+    for (int f = 0; f < F; f++) U[f] = U[f] > 0.0 ? U[f] : 0.0;
+    linear_fwd(U, F, w + sh->off_W[3], w + sh->off_b[3], A, G);
+    linear_fwd(G, A, w + sh->off_W[4], w + sh->off_b[4], sh->V, logits);
+}
+/* Backward of a linear layer out = in W + b given dout: accumulates the
+ * weight and bias gradients and returns din = W dout (din may be NULL). */
+static void linear_bwd(const double *in, int di, const double *W, int dn, const double *dout, double *gW, double *gb,
+                       double *din) {
+    for (int o = 0; o < dn; o++) gb[o] += dout[o];
+    for (int d = 0; d < di; d++) {
+        const double *Wr = W + (uint64_t)d * dn;
+        double *gWr = gW + (uint64_t)d * dn;
+        double s = 0.0;
+        for (int o = 0; o < dn; o++) {
+            gWr[o] += in[d] * dout[o];
+            s += Wr[o] * dout[o];
+        }
+        if (din) din[d] = s;
+    }
+}
+static uint64_t tf_scratch_len(const or_shape *sh) {
+    return 3ull * sh->A + (uint64_t)sh->F + (uint64_t)sh->t * 3 * sh->A + (uint64_t)sh->t * sh->E + (uint64_t)sh->t;
+}
+/* Backward of one row through the forward above (pre-update weights),
+ * accumulating into grad; scratch holds tf_scratch_len doubles. */
+static void tf_backward_row(const or_shape *sh, const double *w, const uint8_t *ctx, const double *act,
+                            const double *dlogits, double *grad, double *scratch) {
+    int t = sh->t, E = sh->E, A = sh->A, F = sh->F, H = sh->heads, dh = A / H;
+    const double *X = act, *QKV = X + (uint64_t)t * E, *att = QKV + (uint64_t)t * 3 * A, *O = att + (uint64_t)H * t;
+    const double *Z = O + A, *U = Z + A, *G = U + F;
+    double *dG = scratch, *dU = dG + A, *dZ = dU + F, *dO = dZ + A, *dQKV = dO + A, *dX = dQKV + (uint64_t)t * 3 * A;
+    double *da = dX + (uint64_t)t * E;
+    linear_bwd(G, A, w + sh->off_W[4], sh->V, dlogits, grad + sh->off_W[4], grad + sh->off_b[4], dG);
+    linear_bwd(U, F, w + sh->off_W[3], A, dG, grad + sh->off_W[3], grad + sh->off_b[3], dU);
+    for (int f = 0; f < F; f++) dU[f] = U[f] > 0.0 ? dU[f] : 0.0;   /* ReLU'(0) = 0 */
+    linear_bwd(Z, A, w + sh->off_W[2], F, dU, grad + sh->off_W[2], grad + sh->off_b[2], dZ);
+    linear_bwd(O, A, w + sh->off_W[1], A, dZ, grad + sh->off_W[1], grad + sh->off_b[1], dO);
+    memset(dQKV, 0, sizeof(double) * (uint64_t)t * 3 * A);
+    const double *q = QKV + (uint64_t)(t - 1) * 3 * A;
+    double *dq = dQKV + (uint64_t)(t - 1) * 3 * A;
+    double scale = 1.0 / sqrt((double)dh);
+    for (int h = 0; h < H; h++) {
+        const double *a = att + (uint64_t)h * t;
+        double dot = 0.0;
+        for (int p = 0; p < t; p++) {
+            const double *v = QKV + (uint64_t)p * 3 * A + 2 * A + h * dh;
+            double *dv = dQKV + (uint64_t)p * 3 * A + 2 * A + h * dh;
+            da[p] = 0.0;
+            for (int d = 0; d < dh; d++) {
+                dv[d] = a[p] * dO[h * dh + d];
+                da[p] += dO[h * dh + d] * v[d];
+            }
+            dot += a[p] * da[p];
+        }
+        for (int p = 0; p < t; p++) {
+            double ds = a[p] * (da[p] - dot) * scale;   /* softmax backward, then the 1/sqrt(dh) */
+            const double *k = QKV + (uint64_t)p * 3 * A + A + h * dh;
+            double *dk = dQKV + (uint64_t)p * 3 * A + A + h * dh;
+            for (int d = 0; d < dh; d++) {
+                dq[h * dh + d] += ds * k[d];
+                dk[d] = ds * q[h * dh + d];
+            }
+        }
+    }
+    for (int p = 0; p < t; p++)
+        linear_bwd(X + (uint64_t)p * E, E, w + sh->off_W[0], 3 * A, dQKV + (uint64_t)p * 3 * A, grad + sh->off_W[0],
+                   grad + sh->off_b[0], dX + (uint64_t)p * E);
+    for (int p = 0; p < t; p++)
+        for (int e = 0; e < E; e++) {
+            grad[sh->off_emb + (uint64_t)ctx[p] * E + e] += dX[p * E + e];
+            grad[sh->off_pos + (uint64_t)p * E + e] += dX[p * E + e];
+        }
+}
+
 static uint64_t acts_len(const or_shape *sh) {
+    if (sh->arch == 1) return tf_act_len(sh);
     uint64_t s = 0;
     for (int l = 0; l <= sh->nh; l++) s += (uint64_t)sh->dims[l];
     return s;
+}
+static void forward_row(const or_shape *sh, const double *w, const uint8_t *ctx, double *acts, double *logits) {
+    if (sh->arch == 1) tf_forward_row(sh, w, ctx, acts, logits);
+    else mlp_forward_row(sh, w, ctx, acts, logits);
 }
 
 /* Backward of one row given dlogits; accumulates into grad (same layout as
@@ -430,9 +610,10 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
                      const uint8_t *tgt, int bs, double *P, double *grad, double *g_alpha, double *loss) {
     int V = sh->V;
     uint64_t al = acts_len(sh);
-    int maxd = 0;
-    for (int l = 0; l <= sh->nh + 1; l++) if (sh->dims[l] > maxd) maxd = sh->dims[l];
-    double *acts = (double *)malloc(sizeof(double) * (al + al + 4 * (uint64_t)V + 2 * (uint64_t)maxd));
+    uint64_t maxd = 0;
+    for (int l = 0; l <= sh->nh + 1; l++) if ((uint64_t)sh->dims[l] > maxd) maxd = (uint64_t)sh->dims[l];
+    uint64_t scr = sh->arch == 1 ? tf_scratch_len(sh) : 2 * maxd;
+    double *acts = (double *)malloc(sizeof(double) * (al + al + 4 * (uint64_t)V + scr));
     if (!acts) return OR_ERR_NOMEM;
     double *acts_s = acts + al;
     double *lm = acts_s + al, *lu = lm + V, *z = lu + V, *dz = z + V, *scratch = dz + V;
@@ -441,9 +622,9 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
     double ga = 0.0, L = 0.0;
     for (int j = 0; j < bs; j++) {
         const uint8_t *c = ctx + (uint64_t)j * sh->t;
-        mlp_forward_row(sh, w, c, acts, lm);
+        forward_row(sh, w, c, acts, lm);
         if (ws) {
-            mlp_forward_row(sh, ws, c, acts_s, lu);
+            forward_row(sh, ws, c, acts_s, lu);
             for (int v = 0; v < V; v++) z[v] = alpha * lu[v] + (1.0 - alpha) * lm[v];
         } else {
             for (int v = 0; v < V; v++) z[v] = lm[v];
@@ -461,7 +642,8 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
                 for (int v = 0; v < V; v++) ga += dz[v] * (lu[v] - lm[v]);
                 for (int v = 0; v < V; v++) dz[v] *= (1.0 - alpha);
             }
-            mlp_backward_row(sh, w, c, acts, dz, grad, scratch);
+            if (sh->arch == 1) tf_backward_row(sh, w, c, acts, dz, grad, scratch);
+            else mlp_backward_row(sh, w, c, acts, dz, grad, scratch);
         }
     }
     if (g_alpha) *g_alpha = ws ? ga * alpha * (1.0 - alpha) : 0.0;
@@ -471,11 +653,11 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
 }
 
 /* Exported single step for the forward/backward pins. */
-int or_step(int k, int t, int E, int nh, const int32_t *hidden, const double *w, const double *ws,
-            double a_alpha, const uint8_t *ctx, const uint8_t *tgt, int bs, double *P, double *grad,
-            double *g_alpha, double *loss) {
+int or_step(int k, int t, int E, int nh, const int32_t *hidden, int arch, int heads, const double *w,
+            const double *ws, double a_alpha, const uint8_t *ctx, const uint8_t *tgt, int bs, double *P,
+            double *grad, double *g_alpha, double *loss) {
     or_shape sh;
-    int rc = shape_init(&sh, k, t, E, nh, hidden);
+    int rc = shape_init(&sh, k, t, E, nh, hidden, arch, heads);
     if (rc) return rc;
     return step_grad(&sh, w, ws, a_alpha, ctx, tgt, bs, P, grad, g_alpha, loss);
 }
@@ -527,6 +709,8 @@ typedef struct {
     const uint64_t *file_blocks; /* blocks per file, or NULL = one file */
     const double *init_override; /* test hook: initial DM parameters (+ a_alpha) of every chain head, or NULL */
     uint64_t ms_threshold;   /* Model Selector size bound in input bytes; 0 = 500 * 10^6 */
+    int32_t arch;            /* dynamic model: 0 MLP, 1 Transformer (hidden = {A, F}, nh = 2) */
+    int32_t heads;           /* attention heads (arch 1) */
 } or_config;
 
 #define SEL_SPUM 1
@@ -780,8 +964,10 @@ static int cfg_check(const or_config *c, or_shape *sh) {
     if (c->selector && !(c->selector & SEL_DM)) return OR_ERR_ARG;
     /* the selector enables one of the two static models, never both */
     if ((c->selector & SEL_SPUM) && (c->selector & SEL_SPRM)) return OR_ERR_ARG;
+    /* the Transformer DM runs without a static model */
+    if (c->arch == 1 && (c->selector & (SEL_SPUM | SEL_SPRM))) return OR_ERR_ARG;
     if (c->smp_ppm > 1000000u) return OR_ERR_ARG;
-    return shape_init(sh, c->k, c->t, c->E, c->nh, c->hidden);
+    return shape_init(sh, c->k, c->t, c->E, c->nh, c->hidden, c->arch, c->arch == 1 ? c->heads : 0);
 }
 
 /* Split the N runs out of a block and map ACGT to 0..3. */
@@ -894,7 +1080,9 @@ static void write_header(or_buf *o, const or_config *cfg, int path, uint32_t sta
     put_f32(o, cfg->beta2);
     put_f32(o, cfg->eps);
     put_le(o, (uint64_t)cfg->selector, 1);
-    put_le(o, 0, 3);
+    put_le(o, (uint64_t)cfg->arch, 1);
+    put_le(o, cfg->arch == 1 ? (uint64_t)cfg->heads : 0, 1);
+    put_le(o, 0, 1);
     put_le(o, cfg->smp_ppm, 4);
     put_le(o, cfg->seed, 8);
     put_le(o, static_crc, 4);
@@ -1122,7 +1310,9 @@ int or_decompress(const uint8_t *cbf, uint64_t len, const float *static_w, uint6
     c.beta2 = get_f32(&r);
     c.eps = get_f32(&r);
     c.selector = (int32_t)get_le(&r, 1);
-    get_le(&r, 3);
+    c.arch = (int32_t)get_le(&r, 1);
+    c.heads = (int32_t)get_le(&r, 1);
+    get_le(&r, 1);
     c.smp_ppm = (uint32_t)get_le(&r, 4);
     c.seed = get_le(&r, 8);
     uint32_t scrc = (uint32_t)get_le(&r, 4);
