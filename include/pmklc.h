@@ -58,6 +58,19 @@ enum { PMKLC_SGD = 0, PMKLC_ADAM = 1 };
  * numeric path made it, and only that path decodes it. */
 enum { PMKLC_FP32 = 0, PMKLC_BF16 = 1, PMKLC_FP32_VALU = 2 };
 enum { PMKLC_BATCHED = 0, PMKLC_PLAIN = 1 };      /* all blocks in one launch | one block per launch */
+/* Dynamic model. PMKLC_ARCH_MLP: embedding E, concatenation of the t
+ * context embeddings, n_hidden Dense + ReLU layers, linear head (the
+ * configurations' model). PMKLC_ARCH_TRANSFORMER, the paper's DM
+ * (Sec. 4.2.4): embedding E plus a learned position embedding, one
+ * attention layer of `heads` heads and width A = hidden[0] whose query is
+ * the last context position, a shared ReLU FFN of width F = hidden[1],
+ * linear head; n_hidden = 2. Its parameter layout (FP32): Emb[V][E],
+ * Pos[t][E], Wqkv[E][3A], bqkv[3A], Wo[A][A], bo[A], W1[A][F], b1[F],
+ * W2[F][A], b2[A], Wh[A][V], bh[V]. It runs without a static model and
+ * without model passing (PMKLC_ERR_INVALID_ARG / PMKLC_ERR_UNSUPPORTED), in
+ * PMKLC_FP32 (FP32 matrix cores) or PMKLC_BF16, for A / heads a power of two
+ * <= 64, A <= 1024, E <= 1024, t <= 256, bs <= 1024, bs * t <= 65536. */
+enum { PMKLC_ARCH_MLP = 0, PMKLC_ARCH_TRANSFORMER = 1 };
 /* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. Accepted:
  * 0, DM, SPUM|DM, SPRM|DM (the selector enables one static model at most),
  * or AUTO.
@@ -108,6 +121,8 @@ typedef struct pmklc_config {
   const float *static_host; /* frozen static public model (parameter layout above, no alpha) */
   uint64_t static_len;      /* number of floats in static_host */
   uint64_t ms_threshold;    /* PMKLC_SEL_AUTO's size bound in input bytes; 0 = 500 * 10^6 */
+  uint32_t arch;            /* dynamic model: PMKLC_ARCH_MLP or PMKLC_ARCH_TRANSFORMER */
+  uint32_t heads;           /* attention heads (PMKLC_ARCH_TRANSFORMER) */
 } pmklc_config;
 
 /* Sec. 4.1 (GskE): maps ASCII bases A,C,G,T (0,1,2,3) to (s,k)-mer ids
@@ -232,9 +247,9 @@ typedef struct pmklc_timing {
 } pmklc_timing;
 pmklc_status pmklc_last_timing(pmklc_timing *t);
 
-/* The dynamic model as a differentiable op (Sec. 4.2.4 with the MLP
- * reading; Sec. 2 step (4)), for autograd use and gradient checks. Uses
- * cfg's k, t, embed, n_hidden (0..2) and hidden; any widths.
+/* The dynamic model as a differentiable op (Sec. 4.2.4; Sec. 2 step (4)),
+ * for autograd use and gradient checks. MLP: uses cfg's k, t, embed,
+ * n_hidden (0..2) and hidden; any widths.
  *   params_dev: n_params FP32 (layout above, no mixing weight);
  *   ctx_dev: rows x t token ids (u8, < 4^k; oldest first);
  *   logits_dev: rows x V FP32 output.
@@ -243,7 +258,12 @@ pmklc_status pmklc_last_timing(pmklc_timing *t);
  * activations are recomputed from ctx_dev, not stored. The embedding
  * gradient is summed in 64-bit fixed point (scale 2^44), so results do not
  * depend on scheduling. ws_dev must hold pmklc_dm_workspace bytes. A token
- * >= 4^k gives PMKLC_ERR_INVALID_ARG. */
+ * >= 4^k gives PMKLC_ERR_INVALID_ARG.
+ * With arch = PMKLC_ARCH_TRANSFORMER the op is the Transformer DM (same
+ * argument meanings, its own parameter layout above; rows <= 1024), run by
+ * the matrix-core kernels of the compression loop in cfg->precision (FP32 or
+ * BF16 GEMM inputs); its backward recomputes the activations and sums every
+ * gradient in a fixed order. */
 pmklc_status pmklc_dm_workspace(const pmklc_config *cfg, uint32_t rows, uint64_t *ws_bytes);
 pmklc_status pmklc_dm_forward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev,
                               uint32_t rows, float *logits_dev, void *ws_dev, uint64_t ws_bytes,

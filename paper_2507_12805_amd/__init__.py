@@ -7,7 +7,7 @@ If the library is missing, every entry point raises; there is no fallback.
 
 Configurations are plain dicts with the keys of ``synth.workloads``
 (s, k, t, bs, E, hidden, optimizer, lr, beta1, beta2, eps, selector,
-smp_ppm, seed, n_blocks / block_len, file_blocks, ms_threshold) plus ``precision``
+smp_ppm, seed, n_blocks / block_len, file_blocks, ms_threshold, arch, heads) plus ``precision``
 ("fp32" | "bf16") and ``schedule`` ("batched" | "plain").
 """
 from __future__ import annotations
@@ -42,7 +42,7 @@ class _Config(ctypes.Structure):
                 ("n_blocks", ctypes.c_uint32), ("block_len_host", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_files", ctypes.c_uint32), ("file_blocks_host", ctypes.POINTER(ctypes.c_uint64)),
                 ("static_host", ctypes.POINTER(ctypes.c_float)), ("static_len", ctypes.c_uint64),
-                ("ms_threshold", ctypes.c_uint64)]
+                ("ms_threshold", ctypes.c_uint64), ("arch", ctypes.c_uint32), ("heads", ctypes.c_uint32)]
 
 
 class Timing(ctypes.Structure):
@@ -125,6 +125,7 @@ def _dev_tensor(x, dtype):
 
 SELECTORS = {"uniform": 0, "dm": 4, "spum_dm": 5, "sprm_dm": 6, "spum_sprm_dm": 7, "auto": 8}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp32_valu": 2}
+ARCHS = {"mlp": 0, "transformer": 1}
 
 
 def make_config(cfg: dict, static=None):
@@ -143,6 +144,8 @@ def make_config(cfg: dict, static=None):
     c.schedule = 1 if cfg.get("schedule", "batched") == "plain" else 0
     c.selector = SELECTORS[cfg.get("selector", "dm")]
     c.ms_threshold = int(cfg.get("ms_threshold", 0))
+    c.arch = ARCHS[cfg.get("arch", "mlp")]
+    c.heads = int(cfg.get("heads", 0)) if c.arch == 1 else 0
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
     c.seed = int(cfg["seed"])
     keep = []

@@ -85,8 +85,10 @@ struct StatusSlot {
 };
 
 // numeric path of a container: which kernel computed its probabilities
-constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathBF16Chip = 4, kPathUniform = 255;
-enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kChipBf16 = 3 };
+constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathBF16Chip = 4, kPathTfBF16 = 5,
+                  kPathTfFP32 = 6, kPathUniform = 255;
+enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kChipBf16 = 3, kTfF32 = 4, kTfBf16 = 5 };
+bool is_tf(int kind) { return kind == kTfF32 || kind == kTfBf16; }
 constexpr int kHeaderBytes = 80;
 // Sec. 4.2.1: the Model Selector's size bound (500 MB, read as 10^6 bytes)
 constexpr uint64_t kMsBytes = 500000000ull;
@@ -192,6 +194,7 @@ struct Model {
   LdsLayout lay;
   int nt;
   int kind;
+  TfShape tf;   // the Transformer DM's shape (is_tf(kind))
 };
 
 pmklc_status check_cfg(const pmklc_config *c) {
@@ -210,10 +213,20 @@ pmklc_status check_cfg(const pmklc_config *c) {
     return PMKLC_ERR_INVALID_ARG;
   if (c->smp_ppm > 1000000u) return PMKLC_ERR_INVALID_ARG;
   if (c->n_blocks < 1) return PMKLC_ERR_INVALID_ARG;
+  if (c->arch > PMKLC_ARCH_TRANSFORMER) return PMKLC_ERR_INVALID_ARG;
+  if (c->arch == PMKLC_ARCH_TRANSFORMER) {
+    // hidden = {A, F}; no static model (Sec. 4.2.4's DM stands alone here)
+    if (c->n_hidden != 2 || c->heads < 1 || c->hidden[0] % c->heads) return PMKLC_ERR_INVALID_ARG;
+    if (c->selector & (PMKLC_SEL_SPUM | PMKLC_SEL_SPRM)) return PMKLC_ERR_INVALID_ARG;
+  }
   return PMKLC_OK;
 }
 
-uint64_t param_count(uint32_t k, uint32_t t, uint32_t E, uint32_t nh, const uint32_t *hidden) {
+uint64_t param_count(uint32_t k, uint32_t t, uint32_t E, uint32_t nh, const uint32_t *hidden, uint32_t arch = 0) {
+  if (arch == PMKLC_ARCH_TRANSFORMER) {
+    const uint64_t V = 1ull << (2 * k), A = hidden[0], F = hidden[1];
+    return V * E + (uint64_t)t * E + E * 3 * A + 3 * A + A * A + A + A * F + F + F * A + A + A * V + V;
+  }
   uint64_t V = 1ull << (2 * k);
   uint64_t prev = (uint64_t)t * E, n = V * E;
   for (uint32_t l = 0; l < nh; l++) { n += prev * hidden[l] + hidden[l]; prev = hidden[l]; }
@@ -370,9 +383,39 @@ bool chip_default() {
   return !(e && e[0] == '1');
 }
 
+// The Transformer DM (arch 1, dynamic model on): its shape, and the Dims
+// fields the shared host code reads (parameter slab, optimiser, sizes).
+pmklc_status make_tf_model(const pmklc_config *c, Model &m) {
+  memset(&m, 0, sizeof m);
+  TfShape &s = m.tf;
+  if (!tf_shape((int)c->k, (int)c->t, (int)c->embed, (int)c->hidden[0], (int)c->hidden[1], (int)c->heads, s))
+    return PMKLC_ERR_UNSUPPORTED;
+  if (c->precision == PMKLC_FP32_VALU || c->schedule != PMKLC_BATCHED || c->smp_ppm > 0 || c->bs > 1024 ||
+      (uint64_t)c->bs * c->t > 65536)
+    return PMKLC_ERR_UNSUPPORTED;
+  s.bs = (int)c->bs;
+  s.optimizer = (int)c->optimizer;
+  s.lr = c->lr; s.b1 = c->beta1; s.b2 = c->beta2; s.eps = c->eps;
+  s.bf16 = c->precision == PMKLC_BF16;
+  Dims &d = m.d;
+  d.V = s.V; d.E = s.E; d.t = s.t; d.bs = s.bs; d.nh = 2;
+  d.H[0] = s.A; d.H[1] = s.F;
+  d.P = (int)s.P;
+  d.stride = (int)s.stride;
+  d.model_on = 1;
+  d.optimizer = s.optimizer;
+  d.lr = s.lr; d.b1 = s.b1; d.b2 = s.b2; d.eps = s.eps;
+  d.CH = 32;
+  m.kind = s.bf16 ? kTfBf16 : kTfF32;
+  m.nt = 256;
+  return PMKLC_OK;
+}
+
 pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip) {
-  return make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, c->selector, c->optimizer, c->lr,
-                    c->beta1, c->beta2, c->eps, c->precision, m, allow_chip);
+  if (c->arch == PMKLC_ARCH_TRANSFORMER && (c->selector & PMKLC_SEL_DM)) return make_tf_model(c, m);
+  return make_model(c->s, c->k, c->t, c->bs, c->embed, c->arch == PMKLC_ARCH_TRANSFORMER ? 0 : c->n_hidden,
+                    c->hidden, c->selector, c->optimizer, c->lr, c->beta1, c->beta2, c->eps, c->precision, m,
+                    allow_chip);
 }
 pmklc_status make_model(const pmklc_config *c, Model &m) { return make_model(c, m, chip_default()); }
 
@@ -463,6 +506,10 @@ struct Work {
   unsigned long long *phase;   // [16] phase clock of block 0
   uint8_t *tune;          // the autotuner's trial block (inside the caller's workspace)
   uint64_t tune_bytes;
+  // the Transformer DM's loop: state, per-slot descriptors and buffers
+  TfState *tf_state;
+  TfSlot *tf_desc;
+  float *tf_f;
 };
 
 struct Sizes {
@@ -509,8 +556,17 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   const uint64_t w1n = m.kind == kMfmaBf16 ? (uint64_t)m.d.D * m.d.H[0] : 0;
   w.w1f = w1n ? A.take<uint16_t>((uint64_t)std::min<uint32_t>(n_blocks, kMaxGrid) * w1n) : nullptr;
   w.s1f = (w1n && m.d.static_on) ? A.take<uint16_t>(w1n) : nullptr;
-  w.tune_bytes = (!trial && m.d.model_on) ? trial_bytes(m) : 0;
+  w.tune_bytes = (!trial && m.d.model_on && !is_tf(m.kind)) ? trial_bytes(m) : 0;
   w.tune = w.tune_bytes ? A.take<uint8_t>(w.tune_bytes) : nullptr;
+  w.tf_state = nullptr;
+  w.tf_desc = nullptr;
+  w.tf_f = nullptr;
+  if (is_tf(m.kind)) {
+    TfBufs tb;
+    w.tf_state = A.take<TfState>(1);
+    w.tf_desc = A.take<TfSlot>(n_blocks);
+    w.tf_f = A.take<float>(tf_bufs_carve(m.tf, (int)n_blocks, nullptr, tb));
+  }
 }
 
 // The autotuner's trial: one synthetic block of t + 64 steps.
@@ -633,6 +689,7 @@ hipError_t d2h(std::vector<T> &v, const T *src, uint64_t count, hipStream_t st) 
 
 uint8_t path_of(uint32_t selector, int kind) {
   if (!(selector & PMKLC_SEL_DM)) return kPathUniform;
+  if (is_tf(kind)) return kind == kTfBf16 ? kPathTfBF16 : kPathTfFP32;
   return kind == kChipBf16 ? kPathBF16Chip : kind == kMfmaBf16 ? kPathBF16 : kind == kMfmaF32 ? kPathFP32Mfma
                                                                                        : kPathFP32Valu;
 }
@@ -654,7 +711,9 @@ void write_header(Writer &o, const pmklc_config *c, uint8_t path, uint32_t scrc,
   o.f32(c->beta2);
   o.f32(c->eps);
   o.le(c->selector, 1);
-  o.le(0, 3);
+  o.le(c->arch, 1);
+  o.le(c->arch == PMKLC_ARCH_TRANSFORMER ? c->heads : 0, 1);
+  o.le(0, 1);
   o.le(c->smp_ppm, 4);
   o.le(c->seed, 8);
   o.le(scrc, 4);
@@ -890,6 +949,60 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
   return PMKLC_OK;
 }
 
+// The Transformer DM's loop over all blocks, slots holding the blocks
+// longest first (a stable order, so slot contents are a function of the
+// block lengths alone).
+pmklc_status run_tf(const Model &m, const Work &w, int mode, const std::vector<BlockDesc> &bd, hipStream_t st,
+                    StepTimer *tm, const uint8_t *tokens_override = nullptr, TfRun *extra = nullptr) {
+  const int n = (int)bd.size();
+  g_last.threads = 256;
+  g_last.launches = 0;
+  if (n == 0) return PMKLC_OK;
+  std::vector<int> ord(n);
+  for (int b = 0; b < n; b++) ord[b] = b;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return bd[x].L > bd[y].L; });
+  std::vector<TfSlot> sl(n);
+  uint64_t maxL = 0;
+  for (int q = 0; q < n; q++) {
+    const BlockDesc &d = bd[ord[q]];
+    sl[q] = TfSlot{d.tok_off, d.slot_off, d.L, d.slot_words, ord[q], 0};
+    maxL = std::max<uint64_t>(maxL, d.L);
+  }
+  HIP_TRY(h2d(w.tf_desc, sl, st));
+  // the error word the callers read after the loop (shared with the MLP kernels)
+  if (w.ctr) HIP_TRY(hipMemsetAsync(w.ctr, 0, 64 * sizeof(int), st));
+  TfBufs b;
+  tf_bufs_carve(m.tf, n, w.tf_f, b);
+  b.state = w.tf_state;
+  b.slots_desc = w.tf_desc;
+  b.params = w.params;
+  b.adam_m = w.adam_m;
+  b.adam_v = w.adam_v;
+  b.init = w.init;
+  TfRun r;
+  if (extra) r = *extra;
+  else memset(&r, 0, sizeof r);
+  r.mode = mode;
+  r.n = n;
+  r.desc_host = sl.data();
+  r.tokens = const_cast<uint8_t *>(tokens_override ? tokens_override : w.tok);
+  r.stream_slots = w.slots;
+  r.seg_bits = w.seg_bits;
+  r.seg_words = w.seg_words;
+  r.max_L = maxL;
+  if (tm) {
+    HIP_TRY(hipEventCreate(&tm->a));
+    HIP_TRY(hipEventCreate(&tm->b));
+    HIP_TRY(hipEventRecord(tm->a, st));
+  }
+  HIP_TRY(tf_run(m.tf, b, r, st));
+  if (tm) HIP_TRY(hipEventRecord(tm->b, st));
+  TfState hs;
+  HIP_TRY(hipMemcpyAsync(&hs, w.tf_state, sizeof hs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return hs.pad[0] ? PMKLC_ERR_DEVICE : PMKLC_OK;
+}
+
 // after the stream has been synchronised
 void finish_timing(StepTimer &tm, std::chrono::steady_clock::time_point t0) {
   float ms = 0.0f;
@@ -919,7 +1032,7 @@ const char *pmklc_status_string(pmklc_status s) {
 
 uint64_t pmklc_param_count(const pmklc_config *c) {
   if (!c || c->k < 1 || c->k > 4 || c->n_hidden > 4) return 0;
-  return param_count(c->k, c->t, c->embed, c->n_hidden, c->hidden);
+  return param_count(c->k, c->t, c->embed, c->n_hidden, c->hidden, c->arch);
 }
 
 pmklc_status pmklc_encode_skmer(const uint8_t *bases_dev, uint64_t n, uint32_t s, uint32_t k, uint8_t *tokens_dev,
@@ -1094,7 +1207,7 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   uint32_t scrc = 0;
   std::vector<float> priv;   // the static private model, as stored
   if (m.d.model_on) {
-    HIP_TRY(launch_init_params(m.d, cfg->seed, w.init, st));
+    HIP_TRY(is_tf(m.kind) ? tf_init_params(m.tf, cfg->seed, w.init, st) : launch_init_params(m.d, cfg->seed, w.init, st));
     if (m.d.static_on && !sprm) {
       scrc = crc32(cfg->static_host, 4ull * m.d.P);
       HIP_TRY(hipMemcpyAsync(w.stat, cfg->static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
@@ -1128,7 +1241,8 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
     scrc = crc32(priv.data(), 4ull * m.d.P);
   }
   count_work(m, bd, g_last);
-  rc = run_step(m, w, 0, bd, cfg->schedule, st, noalloc ? nullptr : &tm, !noalloc);
+  rc = is_tf(m.kind) ? run_tf(m, w, 0, bd, st, noalloc ? nullptr : &tm)
+                     : run_step(m, w, 0, bd, cfg->schedule, st, noalloc ? nullptr : &tm, !noalloc);
   if (rc) return rc;
   std::vector<uint32_t> seg_bits, run_start, run_len;
   std::vector<uint8_t> extras;
@@ -1268,7 +1382,9 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.beta2 = r.f32();
   c.eps = r.f32();
   c.selector = (uint32_t)r.le(1);
-  r.le(3);
+  c.arch = (uint32_t)r.le(1);
+  c.heads = (uint32_t)r.le(1);
+  r.le(1);
   c.smp_ppm = (uint32_t)r.le(4);
   c.seed = r.le(8);
   o.scrc = (uint32_t)r.le(4);
@@ -1277,11 +1393,11 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.n_blocks = (uint32_t)r.le(4);
   uint32_t nf = (uint32_t)r.le(4);
   if (r.bad) return PMKLC_ERR_CORRUPT;
-  c.precision = (o.path == kPathBF16 || o.path == kPathBF16Chip) ? PMKLC_BF16
+  c.precision = (o.path == kPathBF16 || o.path == kPathBF16Chip || o.path == kPathTfBF16) ? PMKLC_BF16
                 : o.path == kPathFP32Valu ? PMKLC_FP32_VALU : PMKLC_FP32;
   if (check_cfg(&c) || c.selector == PMKLC_SEL_AUTO) return PMKLC_ERR_CORRUPT;
   if (o.path != kPathUniform && o.path != kPathBF16 && o.path != kPathFP32Valu && o.path != kPathFP32Mfma &&
-      o.path != kPathBF16Chip)
+      o.path != kPathBF16Chip && o.path != kPathTfBF16 && o.path != kPathTfFP32)
     return PMKLC_ERR_MODEL_MISMATCH;
   if (nf < 1 || (uint64_t)nf > len || (uint64_t)c.n_blocks * 2 > len) return PMKLC_ERR_CORRUPT;
   o.file_blocks.resize(nf);
@@ -1291,7 +1407,7 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.n_files = nf;
   if (c.selector & PMKLC_SEL_SPRM) {
     // the private static model, checked against the header's CRC-32
-    const uint64_t P = param_count(c.k, c.t, c.embed, c.n_hidden, c.hidden);
+    const uint64_t P = param_count(c.k, c.t, c.embed, c.n_hidden, c.hidden, c.arch);
     if (P > (len - r.pos) / 4 || crc32(p + r.pos, 4 * P) != o.scrc) return PMKLC_ERR_CORRUPT;
     o.private_off = r.pos;
     r.pos += 4 * P;
@@ -1467,14 +1583,14 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   HIP_TRY(h2d(w.run_len, o.run_len, st));
   HIP_TRY(h2d(w.run_cum, o.run_cum, st));
   if (m.d.model_on) {
-    HIP_TRY(launch_init_params(m.d, o.c.seed, w.init, st));
+    HIP_TRY(is_tf(m.kind) ? tf_init_params(m.tf, o.c.seed, w.init, st) : launch_init_params(m.d, o.c.seed, w.init, st));
     if (m.d.static_on) {
       const void *src = sprm ? static_cast<const void *>(cbf_host + o.private_off) : static_host;
       HIP_TRY(hipMemcpyAsync(w.stat, src, 4ull * m.d.P, hipMemcpyHostToDevice, st));
     }
   }
   count_work(m, bd, g_last);
-  rc = run_step(m, w, 1, bd, PMKLC_BATCHED, st, &tm);
+  rc = is_tf(m.kind) ? run_tf(m, w, 1, bd, st, &tm) : run_step(m, w, 1, bd, PMKLC_BATCHED, st, &tm);
   if (rc) return rc;
   HIP_TRY(launch_detok(w.seq, (int)nblk, n_raw, w.run_start, w.run_len, w.run_cum, (int)o.c.s, (int)o.c.k, (int)bs,
                        w.tok, w.extras, out_dev, st));
@@ -1488,6 +1604,39 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
 }
 
 // ------------------------------------------------ differentiable DM op
+// the Transformer op: one slot of bs = rows; workspace = state, one slot
+// descriptor, then the slot's buffers
+static pmklc_status tf_op_shape(const pmklc_config *cfg, uint32_t rows, TfShape &s) {
+  pmklc_status rc = check_cfg(cfg);
+  if (rc) return rc;
+  if (!tf_shape((int)cfg->k, (int)cfg->t, (int)cfg->embed, (int)cfg->hidden[0], (int)cfg->hidden[1],
+                (int)cfg->heads, s) ||
+      cfg->precision == PMKLC_FP32_VALU || rows > 1024 || (uint64_t)rows * cfg->t > 65536)
+    return PMKLC_ERR_UNSUPPORTED;
+  s.bs = (int)rows;
+  s.bf16 = cfg->precision == PMKLC_BF16;
+  return PMKLC_OK;
+}
+static uint64_t tf_op_bytes(const TfShape &s) {
+  TfBufs b;
+  return 512 + 4 * tf_bufs_carve(s, 1, nullptr, b) + 256;
+}
+static TfBufs tf_op_bufs(const TfShape &s, void *ws) {
+  TfBufs b;
+  memset(&b, 0, sizeof b);
+  uint8_t *p = static_cast<uint8_t *>(ws);
+  tf_bufs_carve(s, 1, reinterpret_cast<float *>(p + 512), b);
+  b.state = reinterpret_cast<TfState *>(p);
+  b.slots_desc = reinterpret_cast<TfSlot *>(p + 256);
+  return b;
+}
+static pmklc_status tf_op_err(const TfBufs &b, hipStream_t st) {
+  TfState hs;
+  HIP_TRY(hipMemcpyAsync(&hs, b.state, sizeof hs, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return hs.pad[0] ? PMKLC_ERR_INVALID_ARG : PMKLC_OK;
+}
+
 static pmklc_status dm_dims(const pmklc_config *cfg, Dims &d) {
   pmklc_status rc = check_cfg(cfg);
   if (rc) return rc;
@@ -1496,6 +1645,14 @@ static pmklc_status dm_dims(const pmklc_config *cfg, Dims &d) {
 }
 
 pmklc_status pmklc_dm_workspace(const pmklc_config *cfg, uint32_t rows, uint64_t *ws_bytes) {
+  if (cfg && cfg->struct_size == sizeof(pmklc_config) && cfg->arch == PMKLC_ARCH_TRANSFORMER) {
+    TfShape s;
+    pmklc_status rc = tf_op_shape(cfg, rows, s);
+    if (rc) return rc;
+    if (!ws_bytes) return PMKLC_ERR_INVALID_ARG;
+    *ws_bytes = tf_op_bytes(s);
+    return PMKLC_OK;
+  }
   Dims d;
   pmklc_status rc = dm_dims(cfg, d);
   if (rc) return rc;
@@ -1506,6 +1663,18 @@ pmklc_status pmklc_dm_workspace(const pmklc_config *cfg, uint32_t rows, uint64_t
 
 pmklc_status pmklc_dm_forward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev, uint32_t rows,
                               float *logits_dev, void *ws_dev, uint64_t ws_bytes, void *stream) {
+  if (cfg && cfg->struct_size == sizeof(pmklc_config) && cfg->arch == PMKLC_ARCH_TRANSFORMER) {
+    TfShape s;
+    pmklc_status rc = tf_op_shape(cfg, rows, s);
+    if (rc) return rc;
+    if (rows == 0) return PMKLC_OK;
+    if (!params_dev || !ctx_dev || !logits_dev || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+    if (ws_bytes < tf_op_bytes(s)) return PMKLC_ERR_BUFFER_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const TfBufs b = tf_op_bufs(s, ws_dev);
+    HIP_TRY(tf_forward_op(s, b, params_dev, ctx_dev, logits_dev, st));
+    return tf_op_err(b, st);
+  }
   Dims d;
   pmklc_status rc = dm_dims(cfg, d);
   if (rc) return rc;
@@ -1520,6 +1689,17 @@ pmklc_status pmklc_dm_forward(const pmklc_config *cfg, const float *params_dev, 
 pmklc_status pmklc_dm_backward(const pmklc_config *cfg, const float *params_dev, const uint8_t *ctx_dev, uint32_t rows,
                                const float *dlogits_dev, float *grad_dev, void *ws_dev, uint64_t ws_bytes,
                                void *stream) {
+  if (cfg && cfg->struct_size == sizeof(pmklc_config) && cfg->arch == PMKLC_ARCH_TRANSFORMER) {
+    TfShape s;
+    pmklc_status rc = tf_op_shape(cfg, rows, s);
+    if (rc) return rc;
+    if (!params_dev || !ctx_dev || !dlogits_dev || !grad_dev || !ws_dev || rows == 0) return PMKLC_ERR_INVALID_ARG;
+    if (ws_bytes < tf_op_bytes(s)) return PMKLC_ERR_BUFFER_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const TfBufs b = tf_op_bufs(s, ws_dev);
+    HIP_TRY(tf_backward_op(s, b, params_dev, ctx_dev, dlogits_dev, grad_dev, st));
+    return tf_op_err(b, st);
+  }
   Dims d;
   pmklc_status rc = dm_dims(cfg, d);
   if (rc) return rc;
@@ -1585,6 +1765,69 @@ pmklc_status pmklc_wnc_decode(const uint8_t *in_dev, uint64_t nbytes, const uint
   return PMKLC_OK;
 }
 
+// pmklc_model_trace for the Transformer DM: the compression loop's own
+// launches on one block, with probes and the final parameters
+static pmklc_status model_trace_tf(const pmklc_config *cfg, const Model &m, const uint8_t *tokens_dev, uint64_t l,
+                                   const float *init_dev, uint64_t stop, const uint64_t *probe_steps_host,
+                                   uint32_t n_probe, float *probs_dev, float *params_dev, uint8_t *streams_host,
+                                   uint64_t streams_cap, uint64_t *streams_len, hipStream_t st) {
+  const uint32_t bs = cfg->bs;
+  const uint64_t L = l / bs;
+  if (L > 0xFFFFFFFFull) return PMKLC_ERR_UNSUPPORTED;
+  for (uint32_t q = 1; q < n_probe; q++)
+    if (probe_steps_host[q] <= probe_steps_host[q - 1]) return PMKLC_ERR_INVALID_ARG;
+  Sizes z{};
+  z.slot_words = (uint64_t)slot_words_for(L) * bs;
+  Arena A{nullptr, ~0ull};
+  Work w;
+  layout(A, m, 1, z, cfg->optimizer == PMKLC_ADAM, false, w);
+  uint8_t *base = nullptr;
+  HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&base), A.used + 256, st));
+  Arena B{base, A.used + 256};
+  layout(B, m, 1, z, cfg->optimizer == PMKLC_ADAM, false, w);
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+  if (init_dev) chk(hipMemcpyAsync(w.init, init_dev, 4ull * (m.d.P + 1), hipMemcpyDeviceToDevice, st));
+  else chk(tf_init_params(m.tf, cfg->seed, w.init, st));
+  std::vector<BlockDesc> bd(1);
+  bd[0] = BlockDesc{};
+  bd[0].L = (uint32_t)L;
+  bd[0].slot_words = slot_words_for(L);
+  bd[0].pred = -1;
+  TfRun r;
+  memset(&r, 0, sizeof r);
+  r.probe_steps_host = probe_steps_host;
+  r.n_probe = (int)n_probe;
+  r.probe_P = probs_dev;
+  r.params_out = params_dev;
+  r.stop = stop;
+  pmklc_status rc = PMKLC_OK;
+  if (e == hipSuccess) rc = run_tf(m, w, 0, bd, st, nullptr, tokens_dev, &r);
+  std::vector<uint32_t> bits, slots;
+  if (e == hipSuccess && rc == PMKLC_OK && streams_len && L > 0) {
+    chk(d2h(bits, w.seg_bits, bs, st));
+    chk(d2h(slots, w.slots, (uint64_t)slot_words_for(L) * bs, st));
+  }
+  chk(hipStreamSynchronize(st));
+  (void)hipFreeAsync(base, st);
+  (void)hipStreamSynchronize(st);
+  if (e != hipSuccess) return PMKLC_ERR_DEVICE;
+  if (rc) return rc;
+  if (streams_len) {
+    uint64_t total = 0;
+    for (uint32_t b : bits) total += (b + 7) / 8;
+    *streams_len = total;
+    if (total > streams_cap) return PMKLC_ERR_BUFFER_TOO_SMALL;
+    uint64_t at = 0;
+    for (uint32_t j = 0; j < bits.size(); j++) {
+      const uint64_t nb = (bits[j] + 7) / 8;
+      memcpy(streams_host + at, reinterpret_cast<const uint8_t *>(slots.data() + (uint64_t)j * slot_words_for(L)), nb);
+      at += nb;
+    }
+  }
+  return PMKLC_OK;
+}
+
 pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_dev, uint64_t l, const float *static_dev,
                                const float *init_dev, uint64_t stop, const uint64_t *probe_steps_host, uint32_t n_probe,
                                float *probs_dev, float *params_dev, uint8_t *streams_host, uint64_t streams_cap,
@@ -1597,6 +1840,9 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   if (rc) return rc;
   if (m.d.static_on && !static_dev) return PMKLC_ERR_MODEL_MISMATCH;
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (is_tf(m.kind))
+    return model_trace_tf(cfg, m, tokens_dev, l, init_dev, stop, probe_steps_host, n_probe, probs_dev, params_dev,
+                          streams_host, streams_cap, streams_len, st);
   const uint32_t bs = cfg->bs;
   uint64_t L = l / bs;
   if (L > 0xFFFFFFFFull) return PMKLC_ERR_UNSUPPORTED;

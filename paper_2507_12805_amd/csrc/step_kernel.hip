@@ -352,6 +352,21 @@ __global__ void init_params_kernel(uint64_t seed, int P, InitScales sc, float *o
   out[i] = (float)((2.0 * u - 1.0) * a);
 }
 
+// the same draws for a model given as consecutive tensors (exclusive end
+// offsets) with their scales (at most 2 kMaxLayers + 1 tensors)
+hipError_t launch_init_scaled(uint64_t seed, int P, int n_tensors, const int *end, const double *scale, float *out,
+                              hipStream_t st) {
+  InitScales sc;
+  if (n_tensors < 1 || n_tensors > 2 * kMaxLayers + 1) return hipErrorInvalidValue;
+  sc.n_tensors = n_tensors;
+  for (int q = 0; q < n_tensors; q++) {
+    sc.end[q] = end[q];
+    sc.a[q] = scale[q];
+  }
+  hipLaunchKernelGGL(init_params_kernel, dim3((P + 1 + 255) / 256), dim3(256), 0, st, seed, P, sc, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_init_params(const Dims &d, uint64_t seed, float *out, hipStream_t st) {
   InitScales sc;
   sc.n_tensors = 0;

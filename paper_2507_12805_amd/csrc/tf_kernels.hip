@@ -1,0 +1,839 @@
+// The paper's Transformer dynamic model (Sec. 4.2.4) trained online, on the
+// matrix cores.
+//
+// A step of every active block is a fixed sequence of launches, each over
+// all active blocks at once (one batch entry per block): the context
+// gather, the products of the forward, the attention, the softmax +
+// quantiser + coder (the step_common.h routines of the MLP kernels), and the
+// backward, whose weight-gradient products update the weights in their
+// epilogue.  The model's weights (2.2 M for the paper's shape) do not fit on
+// chip, so unlike the MLP kernels the step is not one persistent workgroup
+// per block: the products are ordinary tiled GEMMs spread over the whole
+// GPU.
+//
+// Every output element is summed by one workgroup in a fixed order (split-K
+// partial sums are added in slice order by a second pass), and the split is
+// a function of the product's shape only, so the probabilities do not depend
+// on the number of blocks, the batch or the launch shape: the decoder and
+// every single-block run reproduce the encoder bit for bit.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pmklc_internal.h"
+#include "step_common.h"
+
+namespace pmklc {
+
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 64, kBN = 64, kBK = 32, kGT = 256;   // GEMM tile and workgroup
+enum Epi { kStore = 0, kUpdate = 1, kGrad = 2, kPartial = 3 };
+
+// One strided-batched product C = op(A) op(B), batch entry = slot.
+//   op(A) is M x K: A[m lda + k], or (TA) A[k lda + m];
+//   op(B) is K x N: B[k ldb + n], or (TB) B[n ldb + k].
+struct Gemm {
+  const float *A, *B;
+  float *C;
+  int64_t lda, ldb, ldc, sA, sB, sC;
+  int M, N, K;
+  const float *bias;   // kStore: bias[n] (per slot, stride sB2), or null
+  int64_t sBias;
+  const float *mask;   // kStore: C = 0 where mask[m ldm + n] <= 0, or null
+  int64_t ldm, sMask;
+  int relu;            // kStore: max(., 0)
+  float *m, *v;        // kUpdate (Adam): moments laid out like C
+  int64_t sMV;
+  float *part;         // kPartial: part[slot][slice][M][N]
+  int64_t sPart;
+  int split;           // K slices
+  const TfState *st;
+  int opt;
+  float lr, b1, b2, eps;
+};
+
+__device__ __forceinline__ Opt make_opt(const Gemm &g) {
+  Opt o;
+  o.kind = g.opt;
+  o.lr = g.lr; o.b1 = g.b1; o.b2 = g.b2; o.eps = g.eps;
+  o.c1 = g.st->c1;
+  o.c2 = g.st->c2;
+  return o;
+}
+
+// the epilogue of one output element: x is the sum over K (or a slice)
+template <int EPI>
+__device__ __forceinline__ void epilogue(const Gemm &g, int slot, int slice, int row, int col, float x) {
+  if constexpr (EPI == kPartial) {
+    g.part[slot * g.sPart + ((int64_t)slice * g.M + row) * g.N + col] = x;
+  } else if constexpr (EPI == kStore) {
+    if (g.bias) x += g.bias[slot * g.sBias + col];
+    if (g.relu) x = x > 0.0f ? x : 0.0f;
+    if (g.mask && !(g.mask[slot * g.sMask + (int64_t)row * g.ldm + col] > 0.0f)) x = 0.0f;
+    g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
+  } else if constexpr (EPI == kGrad) {
+    g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
+  } else {
+    const int64_t at = (int64_t)row * g.ldc + col;
+    const Opt o = make_opt(g);
+    float *mm = g.m ? g.m + slot * g.sMV + at : nullptr;
+    float *vv = g.v ? g.v + slot * g.sMV + at : nullptr;
+    g.C[slot * g.sC + at] -= opt_delta(o, x, mm, vv);
+  }
+}
+
+// 64 x 64 output tile per workgroup of four waves, 32 x 32 per wave (2 x 2
+// MFMA tiles of 16 x 16); K in chunks of 32 staged in LDS as FP32.  BF16:
+// one v_mfma_f32_16x16x32_bf16 per tile and chunk, operands rounded to
+// nearest even when the fragments are built; FP32: eight
+// v_mfma_f32_16x16x4f32.  Fragment layouts (lane l, r = l % 16,
+// q = l / 16): A[r][8q..8q+7] / B[8q..8q+7][r] (BF16), A[r][q] / B[q][r]
+// per 4-wide k-step (FP32); the accumulator holds C[4q + c][r].
+template <bool BF16, bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
+  const int slot = blockIdx.z / g.split, slice = blockIdx.z % g.split;
+  if (slot >= g.st->nact) return;
+  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  const float *A = g.A + slot * g.sA;
+  const float *B = g.B + slot * g.sB;
+  int kbeg = 0, kend = g.K;
+  if (g.split > 1) {
+    const int ks = ((g.K + g.split - 1) / g.split + kBK - 1) / kBK * kBK;
+    kbeg = slice * ks;
+    kend = min(g.K, kbeg + ks);
+  }
+  __shared__ float As[kBM][kBK + 1];
+  __shared__ float Bs[kBK][kBN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32, r = lane & 15, q = lane >> 4;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
+#pragma unroll 4
+    for (int e = tid; e < kBM * kBK; e += kGT) {
+      int mm, kk;
+      if (TA) { kk = e / kBM; mm = e % kBM; } else { mm = e / kBK; kk = e % kBK; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      float x = 0.0f;
+      if (gm < g.M && gk < kend) x = TA ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
+      As[mm][kk] = x;
+    }
+#pragma unroll 4
+    for (int e = tid; e < kBK * kBN; e += kGT) {
+      int kk, nn;
+      if (TB) { nn = e / kBK; kk = e % kBK; } else { kk = e / kBN; nn = e % kBN; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      float x = 0.0f;
+      if (gn < g.N && gk < kend) x = TB ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
+      Bs[kk][nn] = x;
+    }
+    __syncthreads();
+    if constexpr (BF16) {
+      bf16x8_t a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int c = 0; c < 8; c++) a[i][c] = (__bf16)As[wm + 16 * i + r][8 * q + c];
+#pragma unroll
+      for (int j = 0; j < 2; j++)
+#pragma unroll
+        for (int c = 0; c < 8; c++) b[j][c] = (__bf16)Bs[8 * q + c][wn + 16 * j + r];
+#pragma unroll
+      for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int s = 0; s < kBK / 4; s++) {
+        const float a0 = As[wm + r][4 * s + q], a1 = As[wm + 16 + r][4 * s + q];
+        const float b0 = Bs[4 * s + q][wn + r], b1 = Bs[4 * s + q][wn + 16 + r];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // the accumulators are read after the loop's branch: keep the matrix-core
+  // results' wait states explicit rather than relying on the scheduler
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < 2; i++)
+#pragma unroll
+    for (int j = 0; j < 2; j++)
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const int row = m0 + wm + 16 * i + 4 * q + c, col = n0 + wn + 16 * j + r;
+        if (row < g.M && col < g.N) epilogue<EPI>(g, slot, slice, row, col, acc[i][j][c]);
+      }
+}
+
+// second pass of a split product: the slices' partial sums added in slice
+// order, then the product's own epilogue
+template <int EPI>
+__global__ __launch_bounds__(256) void reduce_kernel(Gemm g) {
+  const int slot = blockIdx.y;
+  if (slot >= g.st->nact) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)g.M * g.N) return;
+  const int row = (int)(e / g.N), col = (int)(e % g.N);
+  const float *p = g.part + slot * g.sPart + e;
+  float x = 0.0f;
+  for (int s = 0; s < g.split; s++) x += p[(int64_t)s * g.M * g.N];
+  epilogue<EPI>(g, slot, 0, row, col, x);
+}
+
+// Fixed split per product shape (never per batch): the long-K products
+// whose tiles alone would leave most of the GPU idle.
+int split_for(int M, int N, int K) {
+  const int64_t tiles = (int64_t)((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
+  if (K >= 1024 && tiles <= 64) return kTfSplit;
+  return 1;
+}
+
+template <bool BF16, bool TA, bool TB, int EPI>
+hipError_t gemm_go(Gemm g, int nslots, hipStream_t st) {
+  if (nslots <= 0 || g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, nslots * g.split);
+  if (g.split > 1) {
+    hipLaunchKernelGGL((gemm_kernel<BF16, TA, TB, kPartial>), grid, dim3(kGT), 0, st, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t mn = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL((reduce_kernel<EPI>), dim3((unsigned)((mn + 255) / 256), nslots), dim3(256), 0, st, g);
+  } else {
+    hipLaunchKernelGGL((gemm_kernel<BF16, TA, TB, EPI>), grid, dim3(kGT), 0, st, g);
+  }
+  return hipGetLastError();
+}
+
+// C[M x N] = op(A) op(B) (+ epilogue) over nslots batch entries
+template <bool TA, bool TB, int EPI>
+hipError_t gemm(const TfShape &s, Gemm g, int nslots, hipStream_t st) {
+  g.split = split_for(g.M, g.N, g.K);
+  // the partial sums must fit the slot's buffer (sized from the shape, so
+  // the choice still depends on the shape alone)
+  if (g.split > 1 && (int64_t)g.M * g.N * g.split > g.sPart) g.split = 1;
+  return s.bf16 ? gemm_go<true, TA, TB, EPI>(g, nslots, st) : gemm_go<false, TA, TB, EPI>(g, nslots, st);
+}
+
+// ----------------------------------------------------------- small kernels
+// the context token (row, p) of slot `slot` at step i: the stream's
+// tok_off + row L + i - t + p, or (op) ctx[row t + p]
+__device__ __forceinline__ int ctx_token(const TfShape &s, const TfSlot &d, const uint8_t *toks, const uint8_t *ctx,
+                                         int i, int row, int p) {
+  if (ctx) return ctx[(int64_t)row * s.t + p];
+  return toks[d.tok_off + (uint64_t)row * d.L + (uint64_t)(i - s.t + p)];
+}
+
+// X[slot][(row t + p) E + e] = Emb[c][e] + Pos[p][e]
+__global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *st, const TfSlot *desc,
+                                                     const uint8_t *toks, const uint8_t *ctx, const float *params,
+                                                     float *X, int64_t sX, int *err) {
+  const int slot = blockIdx.y;
+  if (slot >= st->nact) return;
+  const int64_t n = (int64_t)s.bs * s.t * s.E;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= n) return;
+  const int e = (int)(q % s.E);
+  const int64_t rp = q / s.E;
+  const int p = (int)(rp % s.t), row = (int)(rp / s.t);
+  int c = ctx_token(s, desc[slot], toks, ctx, st->i, row, p);
+  if (c >= s.V) {
+    atomicOr(err, 1);
+    c = 0;
+  }
+  const float *W = params + slot * s.stride;
+  X[slot * sX + q] = W[s.off_emb + (int64_t)c * s.E + e] + W[s.off_pos + (int64_t)p * s.E + e];
+}
+
+// sum over the dh lanes of a head (aligned lane groups; every lane gets the
+// same value, the same order of operations)
+__device__ __forceinline__ float head_sum(float x, int dh) {
+  for (int o = 1; o < dh; o <<= 1) x += __shfl_xor(x, o, dh);
+  return x;
+}
+
+// Attention at the last position, one workgroup per (row, slot), one thread
+// per column x = h dh + d of the A-wide projections:
+// s_p = q_h . k_{p,h} / sqrt(dh), a = softmax(s), o_h = sum_p a_p v_{p,h}.
+// KV rows hold [k | v] (2A), Q rows q (A).  The probabilities a are kept
+// for the backward.
+__global__ void attn_fwd_kernel(TfShape s, const TfState *st, const float *Q, const float *KV, float *att,
+                                float *O, int64_t sQ, int64_t sKV, int64_t sAtt) {
+  const int slot = blockIdx.y;
+  if (slot >= st->nact) return;
+  extern __shared__ float sc[];   // [H][t]
+  const int row = blockIdx.x, x = threadIdx.x, h = x / s.dh, d = x % s.dh;
+  const int A = s.A, t = s.t;
+  const float scale = 1.0f / sqrtf((float)s.dh);
+  const float *kv = KV + slot * sKV + (int64_t)row * t * 2 * A;
+  const float qx = Q[slot * sQ + (int64_t)row * A + x];
+  for (int p = 0; p < t; p++) {
+    const float part = head_sum(qx * kv[(int64_t)p * 2 * A + x], s.dh);
+    if (d == 0) sc[h * t + p] = part * scale;
+  }
+  __syncthreads();
+  const float *sh = sc + h * t;
+  float mx = -INFINITY;
+  for (int p = 0; p < t; p++) mx = fmaxf(mx, sh[p]);
+  float sum = 0.0f;
+  for (int p = 0; p < t; p++) sum += __expf(sh[p] - mx);
+  const float inv = 1.0f / sum;
+  float o = 0.0f;
+  float *arow = att + slot * sAtt + ((int64_t)row * s.H + h) * t;
+  for (int p = 0; p < t; p++) {
+    const float a = __expf(sh[p] - mx) * inv;
+    o += a * kv[(int64_t)p * 2 * A + A + x];
+    if (d == 0) arow[p] = a;
+  }
+  O[slot * sQ + (int64_t)row * A + x] = o;
+}
+
+// Backward of the attention: dv_p = a_p do, da_p = do . v_p,
+// ds_p = a_p (da_p - sum_r a_r da_r) / sqrt(dh), dq = sum_p ds_p k_p,
+// dk_p = ds_p q (per head).
+__global__ void attn_bwd_kernel(TfShape s, const TfState *st, const float *Q, const float *KV, const float *att,
+                                const float *dO, float *dQ, float *dKV, int64_t sQ, int64_t sKV, int64_t sAtt) {
+  const int slot = blockIdx.y;
+  if (slot >= st->nact) return;
+  extern __shared__ float da[];   // [H][t]
+  const int row = blockIdx.x, x = threadIdx.x, h = x / s.dh, d = x % s.dh;
+  const int A = s.A, t = s.t;
+  const float scale = 1.0f / sqrtf((float)s.dh);
+  const float *kv = KV + slot * sKV + (int64_t)row * t * 2 * A;
+  float *dkv = dKV + slot * sKV + (int64_t)row * t * 2 * A;
+  const float *arow = att + slot * sAtt + ((int64_t)row * s.H + h) * t;
+  const float qx = Q[slot * sQ + (int64_t)row * A + x];
+  const float dox = dO[slot * sQ + (int64_t)row * A + x];
+  for (int p = 0; p < t; p++) {
+    const float part = head_sum(dox * kv[(int64_t)p * 2 * A + A + x], s.dh);
+    if (d == 0) da[h * t + p] = part;
+    dkv[(int64_t)p * 2 * A + A + x] = arow[p] * dox;
+  }
+  __syncthreads();
+  const float *dh_ = da + h * t;
+  float dot = 0.0f;
+  for (int p = 0; p < t; p++) dot += arow[p] * dh_[p];
+  float dq = 0.0f;
+  for (int p = 0; p < t; p++) {
+    const float ds = arow[p] * (dh_[p] - dot) * scale;
+    dq += ds * kv[(int64_t)p * 2 * A + x];
+    dkv[(int64_t)p * 2 * A + x] = ds * qx;
+  }
+  dQ[slot * sQ + (int64_t)row * A + x] = dq;
+}
+
+// column sums over `rows` rows (fixed order) of a bias gradient, then the
+// update of the bias (kUpdate) or its store (kGrad)
+template <int EPI>
+__global__ __launch_bounds__(256) void colsum_kernel(Gemm g, int rows) {
+  const int slot = blockIdx.y;
+  if (slot >= g.st->nact) return;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= g.N) return;
+  const float *D = g.A + slot * g.sA + n;
+  float x = 0.0f;
+  for (int r = 0; r < rows; r++) x += D[(int64_t)r * g.lda];
+  epilogue<EPI>(g, slot, 0, 0, n, x);
+}
+
+// Embedding gradient: dEmb[v][e] = sum over the (row, p) with token v of
+// dX[row t + p][e] (plus dXq at p = t - 1), positions in order; one
+// workgroup per (v, slot), E threads; the step's tokens staged in LDS.
+template <int EPI>
+__global__ void emb_grad_kernel(TfShape s, Gemm g, const TfSlot *desc, const uint8_t *toks, const uint8_t *ctx,
+                                const float *dX, const float *dXq, int64_t sX, int64_t sXq) {
+  const int slot = blockIdx.y;
+  if (slot >= g.st->nact) return;
+  extern __shared__ uint8_t tk[];   // [bs t]
+  const int v = blockIdx.x, e = threadIdx.x;
+  const int n = s.bs * s.t;
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
+    tk[q] = (uint8_t)ctx_token(s, desc[slot], toks, ctx, g.st->i, q / s.t, q % s.t);
+  __syncthreads();
+  if (e >= s.E) return;
+  const float *dx = dX + slot * sX + e;
+  const float *dq = dXq + slot * sXq + e;
+  float x = 0.0f;
+  for (int q = 0; q < n; q++) {
+    if (tk[q] != v) continue;
+    const int p = q % s.t;
+    x += dx[(int64_t)q * s.E];
+    if (p == s.t - 1) x += dq[(int64_t)(q / s.t) * s.E];
+  }
+  epilogue<EPI>(g, slot, 0, v, e, x);
+}
+
+// Position-embedding gradient: dPos[p][e] = sum over rows of dX[row t + p][e]
+// (plus dXq at p = t - 1), rows in order; one workgroup per (p, slot).
+template <int EPI>
+__global__ void pos_grad_kernel(TfShape s, Gemm g, const float *dX, const float *dXq, int64_t sX, int64_t sXq) {
+  const int slot = blockIdx.y;
+  if (slot >= g.st->nact) return;
+  const int p = blockIdx.x, e = threadIdx.x;
+  if (e >= s.E) return;
+  const float *dx = dX + slot * sX + (int64_t)p * s.E + e;
+  const float *dq = dXq + slot * sXq + e;
+  float x = 0.0f;
+  for (int r = 0; r < s.bs; r++) {
+    x += dx[(int64_t)r * s.t * s.E];
+    if (p == s.t - 1) x += dq[(int64_t)r * s.E];
+  }
+  epilogue<EPI>(g, slot, 0, p, e, x);
+}
+
+// Step bookkeeping (one thread): the step index, the active slots and, for
+// an update step, Adam's bias corrections as running FP32 powers.
+__global__ void begin_step_kernel(TfShape s, TfState *st, int i, int nact) {
+  st->i = i;
+  st->nact = nact;
+  if (i >= s.t) {
+    st->b1t *= s.b1;
+    st->b2t *= s.b2;
+    st->c1 = 1.0f - st->b1t;
+    st->c2 = 1.0f - st->b2t;
+  }
+}
+__global__ void init_state_kernel(TfState *st, int nact) {
+  st->i = -1;
+  st->nact = nact;
+  st->c1 = st->c2 = 1.0f;
+  st->b1t = st->b2t = 1.0f;
+  st->pad[0] = st->pad[1] = 0;
+}
+
+// every slot starts from the seeded parameters; Adam moments at zero
+__global__ __launch_bounds__(256) void slot_init_kernel(TfShape s, int n, const float *init, float *params,
+                                                        float *m, float *v) {
+  const int slot = blockIdx.y;
+  if (slot >= n) return;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < s.stride; q += (int64_t)gridDim.x * 256) {
+    params[slot * s.stride + q] = q <= s.P ? init[q] : 0.0f;
+    if (m) m[slot * s.stride + q] = 0.0f;
+    if (v) v[slot * s.stride + q] = 0.0f;
+  }
+}
+
+__global__ void coder_init_kernel(TfShape s, int n, const TfSlot *desc, CoderState *coder, const uint32_t *sslots,
+                                  const uint32_t *seg_words, int mode) {
+  const int slot = blockIdx.x;
+  if (slot >= n) return;
+  const TfSlot d = desc[slot];
+  for (int j = threadIdx.x; j < s.bs; j += blockDim.x) {
+    CoderState c;
+    c.ovf = 0;
+    c.nwords = 0;
+    if (mode == 0) {
+      enc_init(c.enc);
+    } else {
+      uint32_t nw = seg_words[(int64_t)d.block * s.bs + j];
+      c.nwords = nw > d.slot_words ? d.slot_words : nw;
+      dec_init(c.dec, (const gu32 *)(sslots + d.slot_off + (uint64_t)j * d.slot_words), c.nwords);
+    }
+    coder[(int64_t)slot * s.bs + j] = c;
+  }
+}
+
+__global__ void coder_finish_kernel(TfShape s, int n, const TfSlot *desc, CoderState *coder, uint32_t *sslots,
+                                    uint32_t *seg_bits, int *err) {
+  const int slot = blockIdx.x;
+  if (slot >= n) return;
+  const TfSlot d = desc[slot];
+  for (int j = threadIdx.x; j < s.bs; j += blockDim.x) {
+    CoderState c = coder[(int64_t)slot * s.bs + j];
+    enc_finish(c.enc, (gu32 *)(sslots + d.slot_off + (uint64_t)j * d.slot_words), d.slot_words, c.ovf);
+    seg_bits[(int64_t)d.block * s.bs + j] = (uint32_t)c.enc.nbits;
+    if (c.ovf) atomicOr(err, 2);
+  }
+}
+
+// Softmax + quantiser + coder + loss gradient of one slot's step (one
+// workgroup per slot): the logits rows become probabilities, lane j < bs
+// codes token i of segment j with its row's table (the uniform table before
+// step t), and the rows become dL/dlogits = (P - onehot) / bs.
+constexpr int kCodeT = 256;
+__global__ __launch_bounds__(kCodeT) void code_kernel(TfShape s, const TfState *st, const TfSlot *desc,
+                                                      uint8_t *toks, uint32_t *sslots, float *logits, int64_t sLog,
+                                                      uint32_t *cdf, int64_t sCdf, CoderState *coder, int mode,
+                                                      float *probe) {
+  const int slot = blockIdx.x;
+  if (slot >= st->nact) return;
+  __shared__ uint8_t tgt[1024];
+  const TfSlot d = desc[slot];
+  const int i = st->i, V = s.V, bs = s.bs, tid = threadIdx.x;
+  const bool uniform = i < s.t;
+  float *lg = logits + slot * sLog;
+  uint32_t *cd = cdf + slot * sCdf;
+  if (!uniform) {
+    const int spl = row_spl(V), G = V / spl, gs = __builtin_ctz((unsigned)G);
+    for (int j0 = 0; j0 < bs; j0 += kCodeT >> gs) {
+      const int j = j0 + (tid >> gs), gl = tid & (G - 1);
+      if (j >= bs) continue;
+      float *lr = lg + (int64_t)j * V;
+      uint32_t *crow = cd + (int64_t)j * (V + 1);
+      float *pp = probe ? probe + (int64_t)j * V + gl * spl : nullptr;
+      if (spl == 4) {
+        float pr[4];
+        row_softmax_regs<4>(lr, nullptr, false, 0.0f, V, G, gl, crow, pr);
+        if (pp) for (int c = 0; c < 4; c++) pp[c] = pr[c];
+      } else if (spl == 8) {
+        float pr[8];
+        row_softmax_regs<8>(lr, nullptr, false, 0.0f, V, G, gl, crow, pr);
+        if (pp) for (int c = 0; c < 8; c++) pp[c] = pr[c];
+      } else {
+        float pr[32];
+        row_softmax_regs<32>(lr, nullptr, false, 0.0f, V, G, gl, crow, pr);
+        if (pp) for (int c = 0; c < 32; c++) pp[c] = pr[c];
+      }
+    }
+  } else if (probe) {
+    for (int q = tid; q < bs * V; q += kCodeT) probe[q] = 1.0f / (float)V;
+  }
+  __syncthreads();
+  const uint32_t unit = kTotal / (uint32_t)V;
+  for (int j = tid; j < bs; j += kCodeT) {
+    CoderState cs = coder[(int64_t)slot * bs + j];
+    gu32 *sl = (gu32 *)(sslots + d.slot_off + (uint64_t)j * d.slot_words);
+    const uint64_t pos = d.tok_off + (uint64_t)j * d.L + (uint64_t)i;
+    const uint32_t *c = cd + (int64_t)j * (V + 1);
+    int e;
+    if (mode == 0) {
+      e = toks[pos];
+      uint32_t lo, hi;
+      if (uniform) { lo = (uint32_t)e * unit; hi = lo + unit; }
+      else { lo = c[e]; hi = c[e + 1]; }
+      enc_symbol(cs.enc, sl, d.slot_words, lo, hi, cs.ovf);
+    } else {
+      if (uniform) e = dec_symbol(cs.dec, sl, cs.nwords, V, [&](int q) { return (uint32_t)q * unit; });
+      else e = dec_symbol(cs.dec, sl, cs.nwords, V, [&](int q) { return c[q]; });
+      toks[pos] = (uint8_t)e;
+    }
+    tgt[j] = (uint8_t)e;
+    coder[(int64_t)slot * bs + j] = cs;
+  }
+  __syncthreads();
+  if (uniform) return;
+  const float inv_bs = 1.0f / (float)bs;
+  for (int q = tid; q < bs * V; q += kCodeT) {
+    const int j = q / V, v = q % V;
+    lg[q] = (lg[q] - (v == tgt[j] ? 1.0f : 0.0f)) * inv_bs;
+  }
+}
+
+// the op's own loss gradient is given: copy it into the logits rows
+__global__ __launch_bounds__(256) void copy_kernel(const float *src, float *dst, int64_t n) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q < n) dst[q] = src[q];
+}
+
+// ------------------------------------------------------------- host side
+struct Ctx {
+  const TfShape &s;
+  const TfBufs &b;
+  float *W;            // parameters of slot 0 (slot stride s.stride)
+  float *gW;           // kGrad: gradient slab (one slot) or null
+  const uint8_t *toks, *ctx;
+  int n;               // slots launched
+  hipStream_t st;
+};
+
+Gemm base_gemm(const Ctx &c) {
+  Gemm g;
+  memset(&g, 0, sizeof g);
+  g.st = c.b.state;
+  g.split = 1;
+  g.opt = c.s.optimizer;
+  g.lr = c.s.lr; g.b1 = c.s.b1; g.b2 = c.s.b2; g.eps = c.s.eps;
+  return g;
+}
+Gemm mk(const Ctx &c, const float *A, int64_t lda, int64_t sA, const float *B, int64_t ldb, int64_t sB, float *C,
+        int64_t ldc, int64_t sC, int M, int N, int K) {
+  Gemm g = base_gemm(c);
+  g.A = A; g.lda = lda; g.sA = sA;
+  g.B = B; g.ldb = ldb; g.sB = sB;
+  g.C = C; g.ldc = ldc; g.sC = sC;
+  g.M = M; g.N = N; g.K = K;
+  g.part = c.b.part;
+  g.sPart = c.b.sPart;
+  return g;
+}
+// a weight-gradient product or column sum whose epilogue updates the
+// weight at parameter offset `off` (kUpdate) or stores its gradient (kGrad)
+Gemm wgt(const Ctx &c, Gemm g, int64_t off) {
+  if (c.gW) {
+    g.C = c.gW + off;
+    g.sC = 0;
+  } else {
+    g.C = c.W + off;
+    g.sC = c.s.stride;
+    g.m = c.b.adam_m ? c.b.adam_m + off : nullptr;
+    g.v = c.b.adam_v ? c.b.adam_v + off : nullptr;
+    g.sMV = c.s.stride;
+  }
+  return g;
+}
+
+#define TRY(x)                        \
+  do {                                \
+    hipError_t e_ = (x);              \
+    if (e_ != hipSuccess) return e_;  \
+  } while (0)
+
+hipError_t forward(const Ctx &c, int *err) {
+  const TfShape &s = c.s;
+  const TfBufs &b = c.b;
+  const int bs = s.bs, t = s.t, E = s.E, A = s.A, F = s.F, V = s.V;
+  const int64_t S = s.stride;
+  float *W = c.W;
+  const int64_t nx = (int64_t)bs * t * E;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nx + 255) / 256), c.n), dim3(256), 0, c.st, s, b.state,
+                     b.slots_desc, c.toks, c.ctx, W, b.X, b.sX, err);
+  TRY(hipGetLastError());
+  // [k | v] for every position, q at the last
+  Gemm g = mk(c, b.X, E, b.sX, W + s.off_W[0] + A, 3 * A, S, b.KV, 2 * A, b.sKV, bs * t, 2 * A, E);
+  g.bias = W + s.off_b[0] + A;
+  g.sBias = S;
+  TRY((gemm<false, false, kStore>(s, g, c.n, c.st)));
+  g = mk(c, b.X + (int64_t)(t - 1) * E, (int64_t)t * E, b.sX, W + s.off_W[0], 3 * A, S, b.Q, A, b.sQ, bs, A, E);
+  g.bias = W + s.off_b[0];
+  g.sBias = S;
+  TRY((gemm<false, false, kStore>(s, g, c.n, c.st)));
+  hipLaunchKernelGGL(attn_fwd_kernel, dim3(bs, c.n), dim3(A), (size_t)s.H * t * sizeof(float), c.st, s, b.state,
+                     b.Q, b.KV, b.att, b.O, b.sQ, b.sKV, b.sAtt);
+  TRY(hipGetLastError());
+  struct L { const float *in; int64_t ldi, si; int K; int li; float *out; int N; int64_t so; int relu; };
+  const L layers[4] = {{b.O, A, b.sQ, A, 1, b.Z, A, b.sQ, 0},
+                       {b.Z, A, b.sQ, A, 2, b.U, F, b.sU, 1},
+                       {b.U, F, b.sU, F, 3, b.G, A, b.sQ, 0},
+                       {b.G, A, b.sQ, A, 4, b.logits, V, b.sLog, 0}};
+  for (const L &l : layers) {
+    g = mk(c, l.in, l.ldi, l.si, W + s.off_W[l.li], l.N, S, l.out, l.N, l.so, bs, l.N, l.K);
+    g.bias = W + s.off_b[l.li];
+    g.sBias = S;
+    g.relu = l.relu;
+    TRY((gemm<false, false, kStore>(s, g, c.n, c.st)));
+  }
+  return hipSuccess;
+}
+
+template <int EPI>
+hipError_t backward(const Ctx &c) {
+  const TfShape &s = c.s;
+  const TfBufs &b = c.b;
+  const int bs = s.bs, t = s.t, E = s.E, A = s.A, F = s.F, V = s.V;
+  const int64_t S = s.stride;
+  float *W = c.W;
+  auto colsum = [&](const float *D, int64_t ldd, int64_t sD, int rows, int N, int64_t off) -> hipError_t {
+    Gemm g = wgt(c, mk(c, D, ldd, sD, nullptr, 0, 0, nullptr, 0, 0, 1, N, rows), off);
+    hipLaunchKernelGGL((colsum_kernel<EPI>), dim3((N + 255) / 256, c.n), dim3(256), 0, c.st, g, rows);
+    return hipGetLastError();
+  };
+  // one dense layer out = in W + b, given dout: din = dout W^T (masked by
+  // the ReLU that produced `in` when given), then W and b
+  struct L { const float *in; int64_t ldi, si; int din_n; float *din; int64_t sdin; const float *mask;
+             const float *dout; int64_t ldo, so; int N; int li; };
+  const L layers[4] = {{b.G, A, b.sQ, A, b.dG, b.sQ, nullptr, b.logits, V, b.sLog, V, 4},
+                       {b.U, F, b.sU, F, b.dU, b.sU, b.U, b.dG, A, b.sQ, A, 3},
+                       {b.Z, A, b.sQ, A, b.dZ, b.sQ, nullptr, b.dU, F, b.sU, F, 2},
+                       {b.O, A, b.sQ, A, b.dO, b.sQ, nullptr, b.dZ, A, b.sQ, A, 1}};
+  for (const L &l : layers) {
+    // din = dout W^T: W is [din_n][N], read transposed
+    Gemm g = mk(c, l.dout, l.ldo, l.so, W + s.off_W[l.li], l.N, S, l.din, l.din_n, l.sdin, bs, l.din_n, l.N);
+    if (l.mask) {
+      g.mask = l.mask;
+      g.ldm = l.din_n;
+      g.sMask = l.sdin;
+    }
+    TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
+    // dW = in^T dout
+    g = wgt(c, mk(c, l.in, l.ldi, l.si, l.dout, l.ldo, l.so, nullptr, l.N, 0, l.din_n, l.N, bs), s.off_W[l.li]);
+    TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
+    TRY(colsum(l.dout, l.ldo, l.so, bs, l.N, s.off_b[l.li]));
+  }
+  hipLaunchKernelGGL(attn_bwd_kernel, dim3(bs, c.n), dim3(A), (size_t)s.H * t * sizeof(float), c.st, s, b.state,
+                     b.Q, b.KV, b.att, b.dO, b.dQ, b.dKV, b.sQ, b.sKV, b.sAtt);
+  TRY(hipGetLastError());
+  // dX = dKV Wkv^T, dXq = dQ Wq^T (before either weight changes)
+  Gemm g = mk(c, b.dKV, 2 * A, b.sKV, W + s.off_W[0] + A, 3 * A, S, b.dX, E, b.sX, bs * t, E, 2 * A);
+  TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
+  g = mk(c, b.dQ, A, b.sQ, W + s.off_W[0], 3 * A, S, b.dXq, E, (int64_t)bs * E, bs, E, A);
+  TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
+  // Wkv += X^T dKV, Wq += Xlast^T dQ (columns A..3A and 0..A of Wqkv)
+  g = wgt(c, mk(c, b.X, E, b.sX, b.dKV, 2 * A, b.sKV, nullptr, 3 * A, 0, E, 2 * A, bs * t), s.off_W[0] + A);
+  TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
+  g = wgt(c, mk(c, b.X + (int64_t)(t - 1) * E, (int64_t)t * E, b.sX, b.dQ, A, b.sQ, nullptr, 3 * A, 0, E, A, bs),
+          s.off_W[0]);
+  TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
+  TRY(colsum(b.dQ, A, b.sQ, bs, A, s.off_b[0]));
+  TRY(colsum(b.dKV, 2 * A, b.sKV, bs * t, 2 * A, s.off_b[0] + A));
+  // embeddings
+  Gemm ge = wgt(c, mk(c, nullptr, 0, 0, nullptr, 0, 0, nullptr, E, 0, V, E, 0), s.off_emb);
+  hipLaunchKernelGGL((emb_grad_kernel<EPI>), dim3(V, c.n), dim3(std::max(E, 64)), (size_t)bs * t, c.st, s, ge,
+                     b.slots_desc, c.toks, c.ctx, b.dX, b.dXq, b.sX, (int64_t)bs * E);
+  TRY(hipGetLastError());
+  Gemm gp = wgt(c, mk(c, nullptr, 0, 0, nullptr, 0, 0, nullptr, E, 0, t, E, 0), s.off_pos);
+  hipLaunchKernelGGL((pos_grad_kernel<EPI>), dim3(t, c.n), dim3(E), 0, c.st, s, gp, b.dX, b.dXq, b.sX,
+                     (int64_t)bs * E);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool tf_shape(int k, int t, int E, int A, int F, int H, TfShape &s) {
+  memset(&s, 0, sizeof s);
+  if (k < 1 || k > 4 || t < 1 || t > 256 || E < 1 || E > 1024 || A < 1 || A > 1024 || F < 1 || H < 1 || A % H)
+    return false;
+  const int dh = A / H;
+  if (dh > 64 || (dh & (dh - 1)) || H * t > 16384) return false;
+  s.V = 1 << (2 * k);
+  s.E = E; s.t = t; s.A = A; s.F = F; s.H = H; s.dh = dh;
+  const int64_t rows[5] = {E, A, A, F, A}, cols[5] = {3ll * A, A, F, A, s.V};
+  int64_t off = 0;
+  s.off_emb = off;
+  off += (int64_t)s.V * E;
+  s.off_pos = off;
+  off += (int64_t)t * E;
+  for (int l = 0; l < 5; l++) {
+    s.off_W[l] = off;
+    off += rows[l] * cols[l];
+    s.off_b[l] = off;
+    off += cols[l];
+  }
+  s.P = off;
+  s.stride = (off + 1 + 63) / 64 * 64;
+  return off < (1ll << 31);
+}
+
+uint64_t tf_bufs_carve(const TfShape &s, int n, float *base, TfBufs &b) {
+  const int64_t bs = s.bs, t = s.t, E = s.E, A = s.A, F = s.F, V = s.V, H = s.H;
+  uint64_t used = 0;
+  auto take = [&](int64_t per, int64_t &stride) -> float * {
+    stride = (per + 63) / 64 * 64;   // 256-byte aligned slots
+    float *p = base ? base + used : nullptr;
+    used += (uint64_t)stride * (uint64_t)n;
+    return p;
+  };
+  int64_t dummy;
+  b.X = take(bs * t * E, b.sX);
+  b.dX = take(bs * t * E, dummy);
+  b.KV = take(bs * t * 2 * A, b.sKV);
+  b.dKV = take(bs * t * 2 * A, dummy);
+  b.Q = take(bs * A, b.sQ);
+  b.O = take(bs * A, dummy);
+  b.Z = take(bs * A, dummy);
+  b.G = take(bs * A, dummy);
+  b.dG = take(bs * A, dummy);
+  b.dZ = take(bs * A, dummy);
+  b.dO = take(bs * A, dummy);
+  b.dQ = take(bs * A, dummy);
+  b.att = take(bs * H * t, b.sAtt);
+  b.U = take(bs * F, b.sU);
+  b.dU = take(bs * F, dummy);
+  b.logits = take(bs * V, b.sLog);
+  b.dXq = take(bs * E, dummy);
+  b.part = take((int64_t)kTfSplit * std::max<int64_t>(bs * A, E * 2 * A), b.sPart);
+  b.cdf = reinterpret_cast<uint32_t *>(take(bs * (V + 1), b.sCdf));
+  b.coder = take(bs * (int64_t)(sizeof(CoderState) / 4), dummy);
+  b.sA = b.sQ;
+  return used;
+}
+
+hipError_t tf_init_params(const TfShape &s, uint64_t seed, float *out, hipStream_t st) {
+  // the same SplitMix64 draws and scales as the MLP's initialiser: 1 for
+  // the embeddings, 1/sqrt(fan_in) for each linear layer's weight and bias
+  int end[6];
+  double sc[6];
+  const int64_t fan[5] = {s.E, s.A, s.A, s.F, s.A};
+  end[0] = (int)s.off_W[0];
+  sc[0] = 1.0;
+  for (int l = 0; l < 5; l++) {
+    end[l + 1] = (int)(l + 1 < 5 ? s.off_W[l + 1] : s.P);
+    sc[l + 1] = 1.0 / sqrt((double)fan[l]);
+  }
+  return launch_init_scaled(seed, (int)s.P, 6, end, sc, out, st);
+}
+
+hipError_t tf_run(const TfShape &s, const TfBufs &b, const TfRun &r, hipStream_t st) {
+  if (r.n <= 0) return hipSuccess;
+  int *err = &b.state->pad[0];
+  Ctx c{s, b, b.params, nullptr, r.tokens, nullptr, r.n, st};
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, st, b.state, r.n);
+  TRY(hipGetLastError());
+  hipLaunchKernelGGL(slot_init_kernel, dim3((unsigned)std::min<int64_t>((s.stride + 255) / 256, 1024), r.n),
+                     dim3(256), 0, st, s, r.n, b.init, b.params, b.adam_m, b.adam_v);
+  TRY(hipGetLastError());
+  hipLaunchKernelGGL(coder_init_kernel, dim3(r.n), dim3(256), 0, st, s, r.n, b.slots_desc,
+                     reinterpret_cast<CoderState *>(b.coder), r.stream_slots, r.seg_words, r.mode);
+  TRY(hipGetLastError());
+  const TfSlot *desc = r.desc_host;   // slot lengths, longest first
+  const uint64_t steps = r.stop ? std::min<uint64_t>(r.stop, r.max_L) : r.max_L;
+  int probe_i = 0;
+  int nact = r.n;
+  for (uint64_t i = 0; i < steps; i++) {
+    while (nact > 0 && desc[nact - 1].L <= i) nact--;
+    if (nact == 0) break;
+    c.n = nact;
+    hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, (int)i, nact);
+    TRY(hipGetLastError());
+    if (i >= (uint64_t)s.t) TRY(forward(c, err));
+    float *probe = nullptr;
+    if (r.probe_P && probe_i < r.n_probe && r.probe_steps_host[probe_i] == i)
+      probe = r.probe_P + (int64_t)(probe_i++) * s.bs * s.V;
+    hipLaunchKernelGGL(code_kernel, dim3(nact), dim3(kCodeT), 0, st, s, b.state, b.slots_desc, r.tokens,
+                       r.stream_slots, b.logits, b.sLog, b.cdf, b.sCdf, reinterpret_cast<CoderState *>(b.coder),
+                       r.mode, probe);
+    TRY(hipGetLastError());
+    if (i >= (uint64_t)s.t) TRY(backward<kUpdate>(c));
+  }
+  if (r.mode == 0) {
+    hipLaunchKernelGGL(coder_finish_kernel, dim3(r.n), dim3(256), 0, st, s, r.n, b.slots_desc,
+                       reinterpret_cast<CoderState *>(b.coder), r.stream_slots, r.seg_bits, err);
+    TRY(hipGetLastError());
+  }
+  if (r.params_out) TRY(hipMemcpyAsync(r.params_out, b.params, sizeof(float) * (s.P + 1), hipMemcpyDeviceToDevice, st));
+  return hipSuccess;
+}
+
+hipError_t tf_forward_op(const TfShape &s, const TfBufs &b, const float *params, const uint8_t *ctx, float *logits,
+                         hipStream_t st) {
+  int *err = &b.state->pad[0];
+  Ctx c{s, b, const_cast<float *>(params), nullptr, nullptr, ctx, 1, st};
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, st, b.state, 1);
+  TRY(hipGetLastError());
+  hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, s.t, 1);
+  TRY(hipGetLastError());
+  TRY(forward(c, err));
+  const int64_t n = (int64_t)s.bs * s.V;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b.logits, logits, n);
+  return hipGetLastError();
+}
+
+hipError_t tf_backward_op(const TfShape &s, const TfBufs &b, const float *params, const uint8_t *ctx,
+                          const float *dlogits, float *grad, hipStream_t st) {
+  int *err = &b.state->pad[0];
+  Ctx c{s, b, const_cast<float *>(params), grad, nullptr, ctx, 1, st};
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(1), 0, st, b.state, 1);
+  TRY(hipGetLastError());
+  hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, s.t, 1);
+  TRY(hipGetLastError());
+  // activations recomputed from the contexts, then the backward
+  TRY(forward(c, err));
+  const int64_t n = (int64_t)s.bs * s.V;
+  hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dlogits, b.logits, n);
+  TRY(hipGetLastError());
+  return backward<kGrad>(c);
+}
+
+}  // namespace pmklc
