@@ -172,11 +172,12 @@ struct TfBufs {
   float *params, *adam_m, *adam_v;   // [n][stride]
   const float *init;              // [stride] seeded parameters, copied into every slot
   float *X, *KV, *Q, *att, *O, *Z, *U, *G, *logits;   // activations
-  float *dG, *dU, *dZ, *dO, *dQ, *dKV, *dX, *dXq;     // gradients of activations
+  float *dG, *dU, *dZ, *dO, *dQ, *dKV, *dX;          // gradients of activations
   float *part;                    // split-K partial sums [n][kSplit][max M N]
   uint32_t *cdf;                  // [n][bs][V+1]
+  uint8_t *tokstep;               // [n][bs t] the step's context tokens (row-major)
   void *coder;                    // [n][bs] coder states
-  int64_t sX, sKV, sQ, sAtt, sA, sU, sLog, sPart, sCdf;   // per-slot strides (elements)
+  int64_t sX, sKV, sQ, sAtt, sA, sU, sLog, sPart, sCdf, sTok;   // per-slot strides (elements)
 };
 constexpr int kTfSplit = 8;   // split-K slices of the long-K weight gradients
 

@@ -18,6 +18,7 @@
 // every single-block run reproduce the encoder bit for bit.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstring>
 #include <vector>
 
@@ -31,8 +32,8 @@ namespace {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 64, kBN = 64, kBK = 32, kGT = 256;   // GEMM tile and workgroup
-enum Epi { kStore = 0, kUpdate = 1, kGrad = 2, kPartial = 3 };
+constexpr int kBM = 64, kBN = 64, kGT = 256;   // GEMM tile and workgroup
+enum Epi { kStore = 0, kUpdate = 1, kGrad = 2, kPartial = 3, kAccum = 4 };
 
 // One strided-batched product C = op(A) op(B), batch entry = slot.
 //   op(A) is M x K: A[m lda + k], or (TA) A[k lda + m];
@@ -52,6 +53,14 @@ struct Gemm {
   float *part;         // kPartial: part[slot][slice][M][N]
   int64_t sPart;
   int split;           // K slices
+  // TA only: A may be virtual.  aug: one more row of ones (row M of the
+  // product is then the column sums of op(B), a bias gradient, stored at
+  // C + M ldc, where each layer's bias follows its weight).  One-hot:
+  // A[k][m] = (key(k) == m), key = oh[k] (per slot, stride sOh) or k % oh_mod.
+  int aug;
+  const uint8_t *oh;
+  int64_t sOh;
+  int oh_mod;
   const TfState *st;
   int opt;
   float lr, b1, b2, eps;
@@ -70,7 +79,7 @@ __device__ __forceinline__ Opt make_opt(const Gemm &g) {
 template <int EPI>
 __device__ __forceinline__ void epilogue(const Gemm &g, int slot, int slice, int row, int col, float x) {
   if constexpr (EPI == kPartial) {
-    g.part[slot * g.sPart + ((int64_t)slice * g.M + row) * g.N + col] = x;
+    g.part[slot * g.sPart + ((int64_t)slice * (g.M + g.aug) + row) * g.N + col] = x;
   } else if constexpr (EPI == kStore) {
     if (g.bias) x += g.bias[slot * g.sBias + col];
     if (g.relu) x = x > 0.0f ? x : 0.0f;
@@ -78,6 +87,8 @@ __device__ __forceinline__ void epilogue(const Gemm &g, int slot, int slice, int
     g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
   } else if constexpr (EPI == kGrad) {
     g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
+  } else if constexpr (EPI == kAccum) {
+    g.C[slot * g.sC + (int64_t)row * g.ldc + col] += x;
   } else {
     const int64_t at = (int64_t)row * g.ldc + col;
     const Opt o = make_opt(g);
@@ -88,73 +99,110 @@ __device__ __forceinline__ void epilogue(const Gemm &g, int slot, int slice, int
 }
 
 // 64 x 64 output tile per workgroup of four waves, 32 x 32 per wave (2 x 2
-// MFMA tiles of 16 x 16); K in chunks of 32 staged in LDS as FP32.  BF16:
-// one v_mfma_f32_16x16x32_bf16 per tile and chunk, operands rounded to
-// nearest even when the fragments are built; FP32: eight
-// v_mfma_f32_16x16x4f32.  Fragment layouts (lane l, r = l % 16,
-// q = l / 16): A[r][8q..8q+7] / B[8q..8q+7][r] (BF16), A[r][q] / B[q][r]
-// per 4-wide k-step (FP32); the accumulator holds C[4q + c][r].
+// MFMA tiles of 16 x 16); K in chunks of 64.  A chunk is read from global
+// memory into registers while the previous one is multiplied, then stored
+// to LDS: BF16 (rounded to nearest even once, on the way in) as A[m][k] and
+// B transposed, B^T[n][k], rows padded to 72, so that every fragment is one
+// 16-byte read; FP32 as A[m][k] and B^T[n][k] rows of 65.
+// BF16: v_mfma_f32_16x16x32_bf16, lane l (r = l % 16, q = l / 16) holding
+// A[r][8q..8q+7] and B[8q..8q+7][r]; FP32: v_mfma_f32_16x16x4f32 with A[r][q]
+// and B[q][r] per 4-wide k-step.  The accumulator holds C[4q + c][r].
+constexpr int kCK = 64;                 // K chunk
+constexpr int kLdB = kCK + 8;           // BF16 LDS row (elements)
+constexpr int kLdF = kCK + 1;           // FP32 LDS row (elements)
+constexpr int kPer = kBM * kCK / kGT;   // elements of each operand per thread and chunk (16)
+
 template <bool BF16, bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   const int slot = blockIdx.z / g.split, slice = blockIdx.z % g.split;
   if (slot >= g.st->nact) return;
   const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
-  const float *A = g.A + slot * g.sA;
+  const int M = g.M + (TA ? g.aug : 0);
+  const float *A = TA && (g.oh || g.oh_mod) ? nullptr : g.A + slot * g.sA;
+  const uint8_t *oh = g.oh ? g.oh + slot * g.sOh : nullptr;
   const float *B = g.B + slot * g.sB;
   int kbeg = 0, kend = g.K;
   if (g.split > 1) {
-    const int ks = ((g.K + g.split - 1) / g.split + kBK - 1) / kBK * kBK;
+    const int ks = ((g.K + g.split - 1) / g.split + kCK - 1) / kCK * kCK;
     kbeg = slice * ks;
     kend = min(g.K, kbeg + ks);
   }
-  __shared__ float As[kBM][kBK + 1];
-  __shared__ float Bs[kBK][kBN + 1];
+  typedef typename std::conditional<BF16, __bf16, float>::type T;
+  constexpr int LD = BF16 ? kLdB : kLdF;
+  __shared__ __attribute__((aligned(16))) T As[kBM * LD];   // 16-byte fragment reads
+  __shared__ __attribute__((aligned(16))) T Bs[kBN * LD];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32, r = lane & 15, q = lane >> 4;
+  // element e = tid + 256 u of a chunk: TA / !TB walk the M / N index
+  // fastest (coalesced for those layouts), the others walk k fastest
+  auto a_mk = [&](int u, int &mm, int &kk) {
+    const int e = tid + kGT * u;
+    if (TA) { kk = e / kBM; mm = e % kBM; } else { mm = e / kCK; kk = e % kCK; }
+  };
+  auto b_nk = [&](int u, int &nn, int &kk) {
+    const int e = tid + kGT * u;
+    if (TB) { nn = e / kCK; kk = e % kCK; } else { kk = e / kBN; nn = e % kBN; }
+  };
+  float pa[kPer], pb[kPer];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      int mm, kk;
+      a_mk(u, mm, kk);
+      const int gm = m0 + mm, gk = k0 + kk;
+      float x = 0.0f;
+      if (gm < M && gk < kend) {
+        if (!TA) x = A[(int64_t)gm * g.lda + gk];
+        else if (oh) x = (int)oh[gk] == gm ? 1.0f : 0.0f;
+        else if (g.oh_mod) x = gk % g.oh_mod == gm ? 1.0f : 0.0f;
+        else x = gm == g.M ? 1.0f : A[(int64_t)gk * g.lda + gm];
+      }
+      pa[u] = x;
+      int nn, kb;
+      b_nk(u, nn, kb);
+      const int gn = n0 + nn, gkb = k0 + kb;
+      pb[u] = (gn < g.N && gkb < kend) ? (TB ? B[(int64_t)gn * g.ldb + gkb] : B[(int64_t)gkb * g.ldb + gn]) : 0.0f;
+    }
+  };
   f32x4_t acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
     for (int j = 0; j < 2; j++) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = kbeg; k0 < kend; k0 += kBK) {
-#pragma unroll 4
-    for (int e = tid; e < kBM * kBK; e += kGT) {
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += kCK) {
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
       int mm, kk;
-      if (TA) { kk = e / kBM; mm = e % kBM; } else { mm = e / kBK; kk = e % kBK; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      float x = 0.0f;
-      if (gm < g.M && gk < kend) x = TA ? A[(int64_t)gk * g.lda + gm] : A[(int64_t)gm * g.lda + gk];
-      As[mm][kk] = x;
-    }
-#pragma unroll 4
-    for (int e = tid; e < kBK * kBN; e += kGT) {
-      int kk, nn;
-      if (TB) { nn = e / kBK; kk = e % kBK; } else { kk = e / kBN; nn = e % kBN; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      float x = 0.0f;
-      if (gn < g.N && gk < kend) x = TB ? B[(int64_t)gn * g.ldb + gk] : B[(int64_t)gk * g.ldb + gn];
-      Bs[kk][nn] = x;
+      a_mk(u, mm, kk);
+      As[mm * LD + kk] = (T)pa[u];
+      int nn;
+      b_nk(u, nn, kk);
+      Bs[nn * LD + kk] = (T)pb[u];
     }
     __syncthreads();
+    if (k0 + kCK < kend) fetch(k0 + kCK);   // in flight during the products
     if constexpr (BF16) {
-      bf16x8_t a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; i++)
+      for (int ks = 0; ks < kCK / 32; ks++) {
+        bf16x8_t a[2], b[2];
 #pragma unroll
-        for (int c = 0; c < 8; c++) a[i][c] = (__bf16)As[wm + 16 * i + r][8 * q + c];
+        for (int i = 0; i < 2; i++)
+          a[i] = *reinterpret_cast<const bf16x8_t *>(&As[(wm + 16 * i + r) * LD + 32 * ks + 8 * q]);
 #pragma unroll
-      for (int j = 0; j < 2; j++)
+        for (int j = 0; j < 2; j++)
+          b[j] = *reinterpret_cast<const bf16x8_t *>(&Bs[(wn + 16 * j + r) * LD + 32 * ks + 8 * q]);
 #pragma unroll
-        for (int c = 0; c < 8; c++) b[j][c] = (__bf16)Bs[8 * q + c][wn + 16 * j + r];
+        for (int i = 0; i < 2; i++)
 #pragma unroll
-      for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 2; j++)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
     } else {
 #pragma unroll
-      for (int s = 0; s < kBK / 4; s++) {
-        const float a0 = As[wm + r][4 * s + q], a1 = As[wm + 16 + r][4 * s + q];
-        const float b0 = Bs[4 * s + q][wn + r], b1 = Bs[4 * s + q][wn + 16 + r];
+      for (int ks = 0; ks < kCK / 4; ks++) {
+        const float a0 = As[(wm + r) * LD + 4 * ks + q], a1 = As[(wm + 16 + r) * LD + 4 * ks + q];
+        const float b0 = Bs[(wn + r) * LD + 4 * ks + q], b1 = Bs[(wn + 16 + r) * LD + 4 * ks + q];
         acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
@@ -175,7 +223,7 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
 #pragma unroll
       for (int c = 0; c < 4; c++) {
         const int row = m0 + wm + 16 * i + 4 * q + c, col = n0 + wn + 16 * j + r;
-        if (row < g.M && col < g.N) epilogue<EPI>(g, slot, slice, row, col, acc[i][j][c]);
+        if (row < M && col < g.N) epilogue<EPI>(g, slot, slice, row, col, acc[i][j][c]);
       }
 }
 
@@ -185,32 +233,37 @@ template <int EPI>
 __global__ __launch_bounds__(256) void reduce_kernel(Gemm g) {
   const int slot = blockIdx.y;
   if (slot >= g.st->nact) return;
+  const int M = g.M + g.aug;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)g.M * g.N) return;
+  if (e >= (int64_t)M * g.N) return;
   const int row = (int)(e / g.N), col = (int)(e % g.N);
   const float *p = g.part + slot * g.sPart + e;
   float x = 0.0f;
-  for (int s = 0; s < g.split; s++) x += p[(int64_t)s * g.M * g.N];
+  for (int s = 0; s < g.split; s++) x += p[(int64_t)s * M * g.N];
   epilogue<EPI>(g, slot, 0, row, col, x);
 }
 
 // Fixed split per product shape (never per batch): the long-K products
-// whose tiles alone would leave most of the GPU idle.
-int split_for(int M, int N, int K) {
+// whose tiles alone would leave most of the GPU idle get about one slice
+// per 512 of K, as many as the slot's partial-sum buffer (cap floats) holds.
+int split_for(int M, int N, int K, int64_t cap) {
   const int64_t tiles = (int64_t)((M + kBM - 1) / kBM) * ((N + kBN - 1) / kBN);
-  if (K >= 1024 && tiles <= 64) return kTfSplit;
-  return 1;
+  if (K < 1024 || tiles > 64) return 1;
+  int64_t sp = std::min<int64_t>(32, K / 512);
+  sp = std::min<int64_t>(sp, cap / ((int64_t)M * N));
+  return (int)std::max<int64_t>(sp, 1);
 }
 
 template <bool BF16, bool TA, bool TB, int EPI>
 hipError_t gemm_go(Gemm g, int nslots, hipStream_t st) {
   if (nslots <= 0 || g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, nslots * g.split);
+  const int M = g.M + g.aug;
+  dim3 grid((g.N + kBN - 1) / kBN, (M + kBM - 1) / kBM, nslots * g.split);
   if (g.split > 1) {
     hipLaunchKernelGGL((gemm_kernel<BF16, TA, TB, kPartial>), grid, dim3(kGT), 0, st, g);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t mn = (int64_t)g.M * g.N;
+    const int64_t mn = (int64_t)M * g.N;
     hipLaunchKernelGGL((reduce_kernel<EPI>), dim3((unsigned)((mn + 255) / 256), nslots), dim3(256), 0, st, g);
   } else {
     hipLaunchKernelGGL((gemm_kernel<BF16, TA, TB, EPI>), grid, dim3(kGT), 0, st, g);
@@ -221,10 +274,9 @@ hipError_t gemm_go(Gemm g, int nslots, hipStream_t st) {
 // C[M x N] = op(A) op(B) (+ epilogue) over nslots batch entries
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(const TfShape &s, Gemm g, int nslots, hipStream_t st) {
-  g.split = split_for(g.M, g.N, g.K);
   // the partial sums must fit the slot's buffer (sized from the shape, so
   // the choice still depends on the shape alone)
-  if (g.split > 1 && (int64_t)g.M * g.N * g.split > g.sPart) g.split = 1;
+  g.split = split_for(g.M + g.aug, g.N, g.K, g.sPart);
   return s.bf16 ? gemm_go<true, TA, TB, EPI>(g, nslots, st) : gemm_go<false, TA, TB, EPI>(g, nslots, st);
 }
 
@@ -240,7 +292,8 @@ __device__ __forceinline__ int ctx_token(const TfShape &s, const TfSlot &d, cons
 // X[slot][(row t + p) E + e] = Emb[c][e] + Pos[p][e]
 __global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *st, const TfSlot *desc,
                                                      const uint8_t *toks, const uint8_t *ctx, const float *params,
-                                                     float *X, int64_t sX, int *err) {
+                                                     float *X, int64_t sX, uint8_t *tokstep, int64_t sTok,
+                                                     int *err) {
   const int slot = blockIdx.y;
   if (slot >= st->nact) return;
   const int64_t n = (int64_t)s.bs * s.t * s.E;
@@ -256,6 +309,7 @@ __global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *s
   }
   const float *W = params + slot * s.stride;
   X[slot * sX + q] = W[s.off_emb + (int64_t)c * s.E + e] + W[s.off_pos + (int64_t)p * s.E + e];
+  if (e == 0) tokstep[slot * sTok + rp] = (uint8_t)c;   // the embedding gradient's one-hot keys
 }
 
 // sum over the dh lanes of a head (aligned lane groups; every lane gets the
@@ -333,65 +387,6 @@ __global__ void attn_bwd_kernel(TfShape s, const TfState *st, const float *Q, co
     dkv[(int64_t)p * 2 * A + x] = ds * qx;
   }
   dQ[slot * sQ + (int64_t)row * A + x] = dq;
-}
-
-// column sums over `rows` rows (fixed order) of a bias gradient, then the
-// update of the bias (kUpdate) or its store (kGrad)
-template <int EPI>
-__global__ __launch_bounds__(256) void colsum_kernel(Gemm g, int rows) {
-  const int slot = blockIdx.y;
-  if (slot >= g.st->nact) return;
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= g.N) return;
-  const float *D = g.A + slot * g.sA + n;
-  float x = 0.0f;
-  for (int r = 0; r < rows; r++) x += D[(int64_t)r * g.lda];
-  epilogue<EPI>(g, slot, 0, 0, n, x);
-}
-
-// Embedding gradient: dEmb[v][e] = sum over the (row, p) with token v of
-// dX[row t + p][e] (plus dXq at p = t - 1), positions in order; one
-// workgroup per (v, slot), E threads; the step's tokens staged in LDS.
-template <int EPI>
-__global__ void emb_grad_kernel(TfShape s, Gemm g, const TfSlot *desc, const uint8_t *toks, const uint8_t *ctx,
-                                const float *dX, const float *dXq, int64_t sX, int64_t sXq) {
-  const int slot = blockIdx.y;
-  if (slot >= g.st->nact) return;
-  extern __shared__ uint8_t tk[];   // [bs t]
-  const int v = blockIdx.x, e = threadIdx.x;
-  const int n = s.bs * s.t;
-  for (int q = threadIdx.x; q < n; q += blockDim.x)
-    tk[q] = (uint8_t)ctx_token(s, desc[slot], toks, ctx, g.st->i, q / s.t, q % s.t);
-  __syncthreads();
-  if (e >= s.E) return;
-  const float *dx = dX + slot * sX + e;
-  const float *dq = dXq + slot * sXq + e;
-  float x = 0.0f;
-  for (int q = 0; q < n; q++) {
-    if (tk[q] != v) continue;
-    const int p = q % s.t;
-    x += dx[(int64_t)q * s.E];
-    if (p == s.t - 1) x += dq[(int64_t)(q / s.t) * s.E];
-  }
-  epilogue<EPI>(g, slot, 0, v, e, x);
-}
-
-// Position-embedding gradient: dPos[p][e] = sum over rows of dX[row t + p][e]
-// (plus dXq at p = t - 1), rows in order; one workgroup per (p, slot).
-template <int EPI>
-__global__ void pos_grad_kernel(TfShape s, Gemm g, const float *dX, const float *dXq, int64_t sX, int64_t sXq) {
-  const int slot = blockIdx.y;
-  if (slot >= g.st->nact) return;
-  const int p = blockIdx.x, e = threadIdx.x;
-  if (e >= s.E) return;
-  const float *dx = dX + slot * sX + (int64_t)p * s.E + e;
-  const float *dq = dXq + slot * sXq + e;
-  float x = 0.0f;
-  for (int r = 0; r < s.bs; r++) {
-    x += dx[(int64_t)r * s.t * s.E];
-    if (p == s.t - 1) x += dq[(int64_t)r * s.E];
-  }
-  epilogue<EPI>(g, slot, 0, p, e, x);
 }
 
 // Step bookkeeping (one thread): the step index, the active slots and, for
@@ -599,7 +594,7 @@ hipError_t forward(const Ctx &c, int *err) {
   float *W = c.W;
   const int64_t nx = (int64_t)bs * t * E;
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nx + 255) / 256), c.n), dim3(256), 0, c.st, s, b.state,
-                     b.slots_desc, c.toks, c.ctx, W, b.X, b.sX, err);
+                     b.slots_desc, c.toks, c.ctx, W, b.X, b.sX, b.tokstep, b.sTok, err);
   TRY(hipGetLastError());
   // [k | v] for every position, q at the last
   Gemm g = mk(c, b.X, E, b.sX, W + s.off_W[0] + A, 3 * A, S, b.KV, 2 * A, b.sKV, bs * t, 2 * A, E);
@@ -635,13 +630,10 @@ hipError_t backward(const Ctx &c) {
   const int bs = s.bs, t = s.t, E = s.E, A = s.A, F = s.F, V = s.V;
   const int64_t S = s.stride;
   float *W = c.W;
-  auto colsum = [&](const float *D, int64_t ldd, int64_t sD, int rows, int N, int64_t off) -> hipError_t {
-    Gemm g = wgt(c, mk(c, D, ldd, sD, nullptr, 0, 0, nullptr, 0, 0, 1, N, rows), off);
-    hipLaunchKernelGGL((colsum_kernel<EPI>), dim3((N + 255) / 256, c.n), dim3(256), 0, c.st, g, rows);
-    return hipGetLastError();
-  };
   // one dense layer out = in W + b, given dout: din = dout W^T (masked by
-  // the ReLU that produced `in` when given), then W and b
+  // the ReLU that produced `in` when given), then W and b together: the
+  // product in^T dout with a row of ones appended to in^T gives b's
+  // gradient as its last row, which lands on b (b follows W, same width)
   struct L { const float *in; int64_t ldi, si; int din_n; float *din; int64_t sdin; const float *mask;
              const float *dout; int64_t ldo, so; int N; int li; };
   const L layers[4] = {{b.G, A, b.sQ, A, b.dG, b.sQ, nullptr, b.logits, V, b.sLog, V, 4},
@@ -657,36 +649,35 @@ hipError_t backward(const Ctx &c) {
       g.sMask = l.sdin;
     }
     TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
-    // dW = in^T dout
     g = wgt(c, mk(c, l.in, l.ldi, l.si, l.dout, l.ldo, l.so, nullptr, l.N, 0, l.din_n, l.N, bs), s.off_W[l.li]);
+    g.aug = 1;
     TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
-    TRY(colsum(l.dout, l.ldo, l.so, bs, l.N, s.off_b[l.li]));
   }
   hipLaunchKernelGGL(attn_bwd_kernel, dim3(bs, c.n), dim3(A), (size_t)s.H * t * sizeof(float), c.st, s, b.state,
                      b.Q, b.KV, b.att, b.dO, b.dQ, b.dKV, b.sQ, b.sKV, b.sAtt);
   TRY(hipGetLastError());
-  // dX = dKV Wkv^T, dXq = dQ Wq^T (before either weight changes)
+  // dX = dKV Wkv^T, then dX[row t + t - 1] += dQ Wq^T (before either weight changes)
   Gemm g = mk(c, b.dKV, 2 * A, b.sKV, W + s.off_W[0] + A, 3 * A, S, b.dX, E, b.sX, bs * t, E, 2 * A);
   TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
-  g = mk(c, b.dQ, A, b.sQ, W + s.off_W[0], 3 * A, S, b.dXq, E, (int64_t)bs * E, bs, E, A);
-  TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
-  // Wkv += X^T dKV, Wq += Xlast^T dQ (columns A..3A and 0..A of Wqkv)
+  g = mk(c, b.dQ, A, b.sQ, W + s.off_W[0], 3 * A, S, b.dX + (int64_t)(t - 1) * E, (int64_t)t * E, b.sX, bs, E, A);
+  TRY((gemm<false, true, kAccum>(s, g, c.n, c.st)));
+  // Wkv and bkv from X^T dKV (+ ones row), Wq and bq from Xlast^T dQ (+ ones
+  // row): columns A..3A and 0..A of Wqkv, whose bias row follows it
   g = wgt(c, mk(c, b.X, E, b.sX, b.dKV, 2 * A, b.sKV, nullptr, 3 * A, 0, E, 2 * A, bs * t), s.off_W[0] + A);
+  g.aug = 1;
   TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
   g = wgt(c, mk(c, b.X + (int64_t)(t - 1) * E, (int64_t)t * E, b.sX, b.dQ, A, b.sQ, nullptr, 3 * A, 0, E, A, bs),
           s.off_W[0]);
+  g.aug = 1;
   TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
-  TRY(colsum(b.dQ, A, b.sQ, bs, A, s.off_b[0]));
-  TRY(colsum(b.dKV, 2 * A, b.sKV, bs * t, 2 * A, s.off_b[0] + A));
-  // embeddings
-  Gemm ge = wgt(c, mk(c, nullptr, 0, 0, nullptr, 0, 0, nullptr, E, 0, V, E, 0), s.off_emb);
-  hipLaunchKernelGGL((emb_grad_kernel<EPI>), dim3(V, c.n), dim3(std::max(E, 64)), (size_t)bs * t, c.st, s, ge,
-                     b.slots_desc, c.toks, c.ctx, b.dX, b.dXq, b.sX, (int64_t)bs * E);
-  TRY(hipGetLastError());
-  Gemm gp = wgt(c, mk(c, nullptr, 0, 0, nullptr, 0, 0, nullptr, E, 0, t, E, 0), s.off_pos);
-  hipLaunchKernelGGL((pos_grad_kernel<EPI>), dim3(t, c.n), dim3(E), 0, c.st, s, gp, b.dX, b.dXq, b.sX,
-                     (int64_t)bs * E);
-  return hipGetLastError();
+  // embeddings: dEmb = onehot(tokens)^T dX, dPos = onehot(position)^T dX
+  g = wgt(c, mk(c, nullptr, 0, 0, b.dX, E, b.sX, nullptr, E, 0, V, E, bs * t), s.off_emb);
+  g.oh = b.tokstep;
+  g.sOh = b.sTok;
+  TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
+  g = wgt(c, mk(c, nullptr, 0, 0, b.dX, E, b.sX, nullptr, E, 0, t, E, bs * t), s.off_pos);
+  g.oh_mod = t;
+  return gemm<true, false, EPI>(s, g, c.n, c.st);
 }
 
 }  // namespace
@@ -742,10 +733,12 @@ uint64_t tf_bufs_carve(const TfShape &s, int n, float *base, TfBufs &b) {
   b.U = take(bs * F, b.sU);
   b.dU = take(bs * F, dummy);
   b.logits = take(bs * V, b.sLog);
-  b.dXq = take(bs * E, dummy);
   b.part = take((int64_t)kTfSplit * std::max<int64_t>(bs * A, E * 2 * A), b.sPart);
   b.cdf = reinterpret_cast<uint32_t *>(take(bs * (V + 1), b.sCdf));
   b.coder = take(bs * (int64_t)(sizeof(CoderState) / 4), dummy);
+  int64_t stok;
+  b.tokstep = reinterpret_cast<uint8_t *>(take((bs * t + 3) / 4, stok));
+  b.sTok = stok * 4;
   b.sA = b.sQ;
   return used;
 }
