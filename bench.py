@@ -40,7 +40,9 @@ KERNEL_SOURCES = ["paper_2507_12805_amd/csrc/step_mfma.h", "paper_2507_12805_amd
                   "paper_2507_12805_amd/csrc/step_common.h", "paper_2507_12805_amd/csrc/pmklc_internal.h"]
 # the kernel that computed a container, by its numeric-path byte
 PATH_KERNEL = {1: "step_kernel (FP32 per-thread FMA)", 2: "step_mfma_kernel (BF16 matrix cores, weights in global memory)",
-               3: "step_mfma_kernel (FP32 matrix cores)", 4: "step_chip_kernel (BF16 matrix cores, network on chip)"}
+               3: "step_mfma_kernel (FP32 matrix cores)", 4: "step_chip_kernel (BF16 matrix cores, network on chip)",
+               5: "Transformer loop (gemm_kernel BF16 MFMA + attention + coder launches)",
+               6: "Transformer loop (gemm_kernel FP32 MFMA + attention + coder launches)"}
 
 
 def kernel_source_hash() -> str:
@@ -71,6 +73,12 @@ def flops_per_row(cfg: dict) -> int:
     model forward, its backward (weight and input gradients of every layer),
     and the static model's forward when mixed in."""
     V = 4 ** cfg["k"]
+    if cfg.get("arch") == "transformer":
+        # K/V for the t positions, q at the last, scores and weighted sum,
+        # Wo, the FFN, the head; backward twice the forward
+        t, E, (A, F) = cfg["t"], cfg["E"], cfg["hidden"]
+        fwd = 2 * (t * E * 2 * A + E * A + 2 * t * A + A * A + 2 * A * F + A * V)
+        return 3 * fwd
     dims = [cfg["t"] * cfg["E"]] + list(cfg["hidden"]) + [V]
     fwd = sum(2 * dims[i] * dims[i + 1] for i in range(len(dims) - 1))
     f = 3 * fwd
@@ -120,6 +128,11 @@ def workload(name: str, scale: float = 1.0):
         desc = ("static64: 64 MiB synthetic DNA (order-5 Markov, GC 0.35-0.65 per MiB, 10% repeats half "
                 "reverse-complement, 0.01% N runs), 16 equal blocks, (1,3)-mers, t=32, E=16, hidden [128], "
                 "bs=64, SGD 0.1, frozen static model + dynamic model mixed by Eq. 1")
+    elif name == "tf32m":
+        rec, cfg = W.tf_paper()
+        static = None
+        desc = ("tf32m: 32 MiB order-3 synthetic DNA, 16 equal blocks, (3,3)-mers, t=32, bs=320, the paper's "
+                "Transformer DM (embed 64, 8 heads of width 256, FFN 4096), Adam 1e-3")
     elif name == "small256k":
         rec, cfg = W.cfg1()
         static = None
@@ -219,7 +232,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive"])
+    ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive", "tf32m"])
     ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp32_valu"])
     ap.add_argument("--no-fp32-compare", action="store_true",
@@ -331,7 +344,8 @@ def main():
     sub_cfg = {q: v for q, v in cfg.items() if q not in ("block_len", "file_blocks", "smp_ppm")}
     sub_cfg.update(block_len=lens[:kb], n_blocks=kb)
     sample_desc = f"blocks 0-{kb - 1} of {len(lens)} ({sub_n} bases), model passing off"
-    if kb and a.schedule == "batched":
+    tf = cfg.get("arch") == "transformer"   # one launch sequence per step: no per-block launch form
+    if kb and a.schedule == "batched" and not tf:
         cp = dict(sub_cfg, precision="fp32", schedule="plain")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -366,8 +380,10 @@ def main():
     if not a.no_cpu_baseline:
         log("oracle on the CPU sample")
         ccfg = {k: v for k, v in cfg.items() if k not in ("block_len", "file_blocks", "smp_ppm")}
-        ccfg["n_blocks"] = a.cpu_sample_blocks
-        cb, oblob, sample = cpu_baseline(ccfg, static, data, a.cpu_sample_bytes)
+        ccfg["n_blocks"] = a.cpu_sample_blocks if not tf else 2
+        # the Transformer's FP64 oracle costs ~20 MFLOP a row: two blocks of
+        # 40 steps (8 learned) keep it to about a minute
+        cb, oblob, sample = cpu_baseline(ccfg, static, data, a.cpu_sample_bytes if not tf else 2 * 3 * 320 * 40)
         gcfg = ccfg
         gblob = P.compress(dict(gcfg, schedule="batched"), torch.from_numpy(sample).cuda(), static=static)
         cb["gpu_ratio_bits_per_base_same_sample"] = round(8.0 * len(gblob) / len(sample), 5)

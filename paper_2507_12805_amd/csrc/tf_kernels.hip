@@ -129,8 +129,13 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   }
   typedef typename std::conditional<BF16, __bf16, float>::type T;
   constexpr int LD = BF16 ? kLdB : kLdF;
-  __shared__ __attribute__((aligned(16))) T As[kBM * LD];   // 16-byte fragment reads
-  __shared__ __attribute__((aligned(16))) T Bs[kBN * LD];
+  // the two operand tiles, and after the products the output tile (FP32,
+  // rows of 65) for a coalesced epilogue
+  constexpr int kTile = (kBM + kBN) * LD * (int)sizeof(T);
+  constexpr int kOut = kBM * (kBN + 1) * 4;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kTile > kOut ? kTile : kOut];
+  T *As = reinterpret_cast<T *>(smem);        // 16-byte fragment reads
+  T *Bs = As + kBM * LD;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32, r = lane & 15, q = lane >> 4;
   // element e = tid + 256 u of a chunk: TA / !TB walk the M / N index
@@ -216,15 +221,22 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   __builtin_amdgcn_sched_barrier(0);
   asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
   __builtin_amdgcn_sched_barrier(0);
+  // the tile through LDS, then one row of 64 consecutive outputs per wave
+  // and pass: the epilogue's loads and stores (the optimiser's weight and
+  // moments above all) move whole 256-byte rows
+  float *Cs = reinterpret_cast<float *>(smem);
 #pragma unroll
   for (int i = 0; i < 2; i++)
 #pragma unroll
     for (int j = 0; j < 2; j++)
 #pragma unroll
-      for (int c = 0; c < 4; c++) {
-        const int row = m0 + wm + 16 * i + 4 * q + c, col = n0 + wn + 16 * j + r;
-        if (row < M && col < g.N) epilogue<EPI>(g, slot, slice, row, col, acc[i][j][c]);
-      }
+      for (int c = 0; c < 4; c++) Cs[(wm + 16 * i + 4 * q + c) * (kBN + 1) + wn + 16 * j + r] = acc[i][j][c];
+  __syncthreads();
+#pragma unroll 4
+  for (int e = tid; e < kBM * kBN; e += kGT) {
+    const int rl = e / kBN, cl = e % kBN, row = m0 + rl, col = n0 + cl;
+    if (row < M && col < g.N) epilogue<EPI>(g, slot, slice, row, col, Cs[rl * (kBN + 1) + cl]);
+  }
 }
 
 // second pass of a split product: the slices' partial sums added in slice

@@ -59,6 +59,17 @@ def cfg4(n: int = 1 << 32, n_blocks: int = 1024) -> tuple[Recipe, dict]:
     return r, model_small(t=64, E=64, hidden=[256, 256], bs=128, optimizer="adam", n_blocks=n_blocks)
 
 
+def tf_paper(n: int = 32 * MiB, n_blocks: int = 16) -> tuple[Recipe, dict]:
+    """The paper's dynamic model (Sec. 4.2.4): Transformer with a 64-d
+    embedding, 8-head attention of width 256 and a 4096-wide FFN, at the
+    paper's defaults (3,3)-mers, t 32, bs 320 (Sec. 5.1.4); Adam 1e-3 (the
+    paper names no optimiser); 32 MiB of the order-3 source in 16 equal
+    blocks."""
+    r = recipe_cfg1(seed=7, n=n)
+    return r, model_small(t=32, E=64, hidden=[256, 4096], bs=320, arch="transformer", heads=8, optimizer="adam",
+                          lr=1e-3, n_blocks=n_blocks)
+
+
 def cfg5(scale: float = 1.0, block: int = 4 * MiB) -> tuple[list[Recipe], dict]:
     """Mixed archive of 64 files; 4 MiB blocks per file; model passing at 5%
     of each block's steps between consecutive blocks of a file."""
