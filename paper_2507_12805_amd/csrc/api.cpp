@@ -86,9 +86,11 @@ struct StatusSlot {
 
 // numeric path of a container: which kernel computed its probabilities
 constexpr uint8_t kPathFP32Valu = 1, kPathBF16 = 2, kPathFP32Mfma = 3, kPathBF16Chip = 4, kPathTfBF16 = 5,
-                  kPathTfFP32 = 6, kPathUniform = 255;
-enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kChipBf16 = 3, kTfF32 = 4, kTfBf16 = 5 };
-bool is_tf(int kind) { return kind == kTfF32 || kind == kTfBf16; }
+                  kPathTfFP32 = 6, kPathSeqBF16 = 7, kPathSeqFP32 = 8, kPathUniform = 255;
+// kTf*: the Transformer DM; kSeq*: the MLP on the same launch sequence
+enum Kind { kGeneric = 0, kMfmaF32 = 1, kMfmaBf16 = 2, kChipBf16 = 3, kTfF32 = 4, kTfBf16 = 5, kSeqF32 = 6, kSeqBf16 = 7 };
+bool is_tf(int kind) { return kind >= kTfF32 && kind <= kSeqBf16; }   // runs the launch-sequence loop
+bool is_transformer(int kind) { return kind == kTfF32 || kind == kTfBf16; }
 constexpr int kHeaderBytes = 80;
 // Sec. 4.2.1: the Model Selector's size bound (500 MB, read as 10^6 bytes)
 constexpr uint64_t kMsBytes = 500000000ull;
@@ -273,13 +275,29 @@ pmklc_status fill_dims(uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t
 // Shape + LDS plan of the step kernel; UNSUPPORTED when this build's kernels
 // cannot hold it (tile multiples of 4, LDS <= 160 KB, at most two hidden
 // layers).
+// seq: the launch-sequence form of the MLP: -1 where the persistent kernels
+// cannot hold a BF16 model (or with PMKLC_SEQ_MLP=1 in the environment for
+// FP32), 1 always (decoding a container it made), 0 never
 pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_t E, uint32_t nh,
                         const uint32_t *hidden, uint32_t selector, uint32_t opt, float lr, float b1, float b2,
-                        float eps, uint32_t precision, Model &m, bool allow_chip) {
+                        float eps, uint32_t precision, Model &m, bool allow_chip, int seq) {
   (void)s;
   Dims &d = m.d;
   pmklc_status rc = fill_dims(k, t, bs, E, nh, hidden, selector, opt, lr, b1, b2, eps, d);
   if (rc) return rc;
+  auto make_seq = [&]() -> pmklc_status {
+    if (!d.model_on || d.static_on || precision == PMKLC_FP32_VALU || !mlp_seq_shape(d, m.tf))
+      return PMKLC_ERR_UNSUPPORTED;
+    m.tf.bf16 = precision == PMKLC_BF16;
+    memset(&m.lay, 0, sizeof m.lay);
+    m.kind = m.tf.bf16 ? kSeqBf16 : kSeqF32;
+    m.nt = 256;
+    return PMKLC_OK;
+  };
+  const char *env_seq = getenv("PMKLC_SEQ_MLP");
+  if (seq == 1 || (seq < 0 && precision == PMKLC_FP32 && env_seq && env_seq[0] == '1' && d.model_on &&
+                   !d.static_on))
+    return make_seq();
   if (d.model_on) {
     if (E % 4 || bs % 4 || d.V % 4) return PMKLC_ERR_UNSUPPORTED;
     for (uint32_t l = 0; l < nh; l++) if (hidden[l] % 4) return PMKLC_ERR_UNSUPPORTED;
@@ -340,7 +358,7 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
     L.act_global = glob;
     L.act_slot = (int)g;
     if (o <= 160 * 1024) break;
-    if (glob) return PMKLC_ERR_UNSUPPORTED;
+    if (glob) return (seq < 0 && precision == PMKLC_BF16) ? make_seq() : PMKLC_ERR_UNSUPPORTED;
   }
   m.nt = bs <= 256 ? 256 : 512;
   if (bs > 512) return PMKLC_ERR_UNSUPPORTED;
@@ -349,7 +367,7 @@ pmklc_status make_model(uint32_t s, uint32_t k, uint32_t t, uint32_t bs, uint32_
                        E % 8 == 0 && E < 4096 && d.D % 32 == 0;
   m.kind = kGeneric;
   if (precision == PMKLC_BF16) {
-    if (d.model_on && !mfma_ok) return PMKLC_ERR_UNSUPPORTED;
+    if (d.model_on && !mfma_ok) return seq < 0 ? make_seq() : PMKLC_ERR_UNSUPPORTED;
     m.kind = kMfmaBf16;
   } else if (precision == PMKLC_FP32 && mfma_ok) {
     m.kind = kMfmaF32;
@@ -411,11 +429,15 @@ pmklc_status make_tf_model(const pmklc_config *c, Model &m) {
   return PMKLC_OK;
 }
 
-pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip) {
+pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip, int seq = -1) {
   if (c->arch == PMKLC_ARCH_TRANSFORMER && (c->selector & PMKLC_SEL_DM)) return make_tf_model(c, m);
-  return make_model(c->s, c->k, c->t, c->bs, c->embed, c->arch == PMKLC_ARCH_TRANSFORMER ? 0 : c->n_hidden,
-                    c->hidden, c->selector, c->optimizer, c->lr, c->beta1, c->beta2, c->eps, c->precision, m,
-                    allow_chip);
+  pmklc_status rc = make_model(c->s, c->k, c->t, c->bs, c->embed, c->arch == PMKLC_ARCH_TRANSFORMER ? 0 : c->n_hidden,
+                               c->hidden, c->selector, c->optimizer, c->lr, c->beta1, c->beta2, c->eps, c->precision,
+                               m, allow_chip, seq);
+  if (rc == PMKLC_OK && is_tf(m.kind)) {
+    if (c->schedule != PMKLC_BATCHED || c->smp_ppm > 0) return PMKLC_ERR_UNSUPPORTED;
+  }
+  return rc;
 }
 pmklc_status make_model(const pmklc_config *c, Model &m) { return make_model(c, m, chip_default()); }
 
@@ -689,7 +711,8 @@ hipError_t d2h(std::vector<T> &v, const T *src, uint64_t count, hipStream_t st) 
 
 uint8_t path_of(uint32_t selector, int kind) {
   if (!(selector & PMKLC_SEL_DM)) return kPathUniform;
-  if (is_tf(kind)) return kind == kTfBf16 ? kPathTfBF16 : kPathTfFP32;
+  if (is_transformer(kind)) return kind == kTfBf16 ? kPathTfBF16 : kPathTfFP32;
+  if (is_tf(kind)) return kind == kSeqBf16 ? kPathSeqBF16 : kPathSeqFP32;
   return kind == kChipBf16 ? kPathBF16Chip : kind == kMfmaBf16 ? kPathBF16 : kind == kMfmaF32 ? kPathFP32Mfma
                                                                                        : kPathFP32Valu;
 }
@@ -1207,7 +1230,8 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   uint32_t scrc = 0;
   std::vector<float> priv;   // the static private model, as stored
   if (m.d.model_on) {
-    HIP_TRY(is_tf(m.kind) ? tf_init_params(m.tf, cfg->seed, w.init, st) : launch_init_params(m.d, cfg->seed, w.init, st));
+    HIP_TRY(is_transformer(m.kind) ? tf_init_params(m.tf, cfg->seed, w.init, st)
+                                   : launch_init_params(m.d, cfg->seed, w.init, st));
     if (m.d.static_on && !sprm) {
       scrc = crc32(cfg->static_host, 4ull * m.d.P);
       HIP_TRY(hipMemcpyAsync(w.stat, cfg->static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
@@ -1393,11 +1417,13 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.n_blocks = (uint32_t)r.le(4);
   uint32_t nf = (uint32_t)r.le(4);
   if (r.bad) return PMKLC_ERR_CORRUPT;
-  c.precision = (o.path == kPathBF16 || o.path == kPathBF16Chip || o.path == kPathTfBF16) ? PMKLC_BF16
+  c.precision = (o.path == kPathBF16 || o.path == kPathBF16Chip || o.path == kPathTfBF16 || o.path == kPathSeqBF16)
+                    ? PMKLC_BF16
                 : o.path == kPathFP32Valu ? PMKLC_FP32_VALU : PMKLC_FP32;
   if (check_cfg(&c) || c.selector == PMKLC_SEL_AUTO) return PMKLC_ERR_CORRUPT;
   if (o.path != kPathUniform && o.path != kPathBF16 && o.path != kPathFP32Valu && o.path != kPathFP32Mfma &&
-      o.path != kPathBF16Chip && o.path != kPathTfBF16 && o.path != kPathTfFP32)
+      o.path != kPathBF16Chip && o.path != kPathTfBF16 && o.path != kPathTfFP32 && o.path != kPathSeqBF16 &&
+      o.path != kPathSeqFP32)
     return PMKLC_ERR_MODEL_MISMATCH;
   if (nf < 1 || (uint64_t)nf > len || (uint64_t)c.n_blocks * 2 > len) return PMKLC_ERR_CORRUPT;
   o.file_blocks.resize(nf);
@@ -1494,7 +1520,7 @@ pmklc_status pmklc_decompress_info(const uint8_t *cbf_host, uint64_t len, uint64
   pmklc_status rc = parse(cbf_host, len, o, true);
   if (rc) return rc;
   Model m;
-  rc = make_model(&o.c, m, o.path == kPathBF16Chip);
+  rc = make_model(&o.c, m, o.path == kPathBF16Chip, o.path == kPathSeqBF16 || o.path == kPathSeqFP32 ? 1 : 0);
   if (rc) return rc;
   Plan p;
   rc = plan_blocks(o.n, o.c.n_blocks, nullptr, 0, nullptr, false, p);
@@ -1518,7 +1544,7 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   pmklc_status rc = parse(cbf_host, len, o, true);
   if (rc) return rc;
   Model m;
-  rc = make_model(&o.c, m, o.path == kPathBF16Chip);
+  rc = make_model(&o.c, m, o.path == kPathBF16Chip, o.path == kPathSeqBF16 || o.path == kPathSeqFP32 ? 1 : 0);
   if (rc) return rc;
   if (path_of(o.c.selector, m.kind) != o.path) return PMKLC_ERR_MODEL_MISMATCH;
   const bool sprm = (o.c.selector & PMKLC_SEL_SPRM) != 0;
@@ -1583,7 +1609,8 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   HIP_TRY(h2d(w.run_len, o.run_len, st));
   HIP_TRY(h2d(w.run_cum, o.run_cum, st));
   if (m.d.model_on) {
-    HIP_TRY(is_tf(m.kind) ? tf_init_params(m.tf, o.c.seed, w.init, st) : launch_init_params(m.d, o.c.seed, w.init, st));
+    HIP_TRY(is_transformer(m.kind) ? tf_init_params(m.tf, o.c.seed, w.init, st)
+                                   : launch_init_params(m.d, o.c.seed, w.init, st));
     if (m.d.static_on) {
       const void *src = sprm ? static_cast<const void *>(cbf_host + o.private_off) : static_host;
       HIP_TRY(hipMemcpyAsync(w.stat, src, 4ull * m.d.P, hipMemcpyHostToDevice, st));
@@ -1616,6 +1643,18 @@ static pmklc_status tf_op_shape(const pmklc_config *cfg, uint32_t rows, TfShape 
   s.bs = (int)rows;
   s.bf16 = cfg->precision == PMKLC_BF16;
   return PMKLC_OK;
+}
+// the MLP op on the same kernels (matrix cores, FP32 or BF16 inputs); false
+// for PMKLC_FP32_VALU or shapes outside them (the per-thread op then runs)
+static bool mlp_op_shape(const pmklc_config *cfg, uint32_t rows, TfShape &s) {
+  if (cfg->precision == PMKLC_FP32_VALU || cfg->arch != PMKLC_ARCH_MLP || rows < 1) return false;
+  Dims d;
+  if (fill_dims(cfg->k, cfg->t, rows, cfg->embed, cfg->n_hidden, cfg->hidden, PMKLC_SEL_DM, cfg->optimizer, cfg->lr,
+                cfg->beta1, cfg->beta2, cfg->eps, d))
+    return false;
+  if (!mlp_seq_shape(d, s)) return false;
+  s.bf16 = cfg->precision == PMKLC_BF16;
+  return true;
 }
 static uint64_t tf_op_bytes(const TfShape &s) {
   TfBufs b;
@@ -1653,6 +1692,12 @@ pmklc_status pmklc_dm_workspace(const pmklc_config *cfg, uint32_t rows, uint64_t
     *ws_bytes = tf_op_bytes(s);
     return PMKLC_OK;
   }
+  TfShape ms;
+  if (cfg && cfg->struct_size == sizeof(pmklc_config) && !check_cfg(cfg) && mlp_op_shape(cfg, rows, ms)) {
+    if (!ws_bytes) return PMKLC_ERR_INVALID_ARG;
+    *ws_bytes = tf_op_bytes(ms);
+    return PMKLC_OK;
+  }
   Dims d;
   pmklc_status rc = dm_dims(cfg, d);
   if (rc) return rc;
@@ -1673,6 +1718,15 @@ pmklc_status pmklc_dm_forward(const pmklc_config *cfg, const float *params_dev, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const TfBufs b = tf_op_bufs(s, ws_dev);
     HIP_TRY(tf_forward_op(s, b, params_dev, ctx_dev, logits_dev, st));
+    return tf_op_err(b, st);
+  }
+  TfShape ms;
+  if (cfg && cfg->struct_size == sizeof(pmklc_config) && !check_cfg(cfg) && mlp_op_shape(cfg, rows, ms)) {
+    if (!params_dev || !ctx_dev || !logits_dev || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+    if (ws_bytes < tf_op_bytes(ms)) return PMKLC_ERR_BUFFER_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const TfBufs b = tf_op_bufs(ms, ws_dev);
+    HIP_TRY(tf_forward_op(ms, b, params_dev, ctx_dev, logits_dev, st));
     return tf_op_err(b, st);
   }
   Dims d;
@@ -1698,6 +1752,15 @@ pmklc_status pmklc_dm_backward(const pmklc_config *cfg, const float *params_dev,
     hipStream_t st = static_cast<hipStream_t>(stream);
     const TfBufs b = tf_op_bufs(s, ws_dev);
     HIP_TRY(tf_backward_op(s, b, params_dev, ctx_dev, dlogits_dev, grad_dev, st));
+    return tf_op_err(b, st);
+  }
+  TfShape ms;
+  if (cfg && cfg->struct_size == sizeof(pmklc_config) && !check_cfg(cfg) && mlp_op_shape(cfg, rows, ms)) {
+    if (!params_dev || !ctx_dev || !dlogits_dev || !grad_dev || !ws_dev) return PMKLC_ERR_INVALID_ARG;
+    if (ws_bytes < tf_op_bytes(ms)) return PMKLC_ERR_BUFFER_TOO_SMALL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const TfBufs b = tf_op_bufs(ms, ws_dev);
+    HIP_TRY(tf_backward_op(ms, b, params_dev, ctx_dev, dlogits_dev, grad_dev, st));
     return tf_op_err(b, st);
   }
   Dims d;
@@ -1788,7 +1851,8 @@ static pmklc_status model_trace_tf(const pmklc_config *cfg, const Model &m, cons
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
   if (init_dev) chk(hipMemcpyAsync(w.init, init_dev, 4ull * (m.d.P + 1), hipMemcpyDeviceToDevice, st));
-  else chk(tf_init_params(m.tf, cfg->seed, w.init, st));
+  else chk(is_transformer(m.kind) ? tf_init_params(m.tf, cfg->seed, w.init, st)
+                                  : launch_init_params(m.d, cfg->seed, w.init, st));
   std::vector<BlockDesc> bd(1);
   bd[0] = BlockDesc{};
   bd[0].L = (uint32_t)L;

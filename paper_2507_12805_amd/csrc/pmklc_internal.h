@@ -136,8 +136,10 @@ hipError_t launch_wnc_decode(const uint32_t *words, uint32_t nwords, const uint3
 // logits = g Wh + bh.  Parameters in that order: Emb[V][E], Pos[t][E],
 // Wqkv[E][3A], bqkv, Wo[A][A], bo, W1[A][F], b1, W2[F][A], b2, Wh[A][V], bh.
 struct TfShape {
+  int arch;                                        // 1 Transformer; 0 the MLP on the same launch sequence
+  int nh, H0, H1;                                  // MLP: hidden layers and widths (input t E)
   int V, E, t, A, F, H, dh, bs;
-  int64_t off_emb, off_pos, off_W[5], off_b[5];   // W: Wqkv, Wo, W1, W2, Wh
+  int64_t off_emb, off_pos, off_W[5], off_b[5];   // W: Wqkv, Wo, W1, W2, Wh (MLP: its layers; no Pos)
   int64_t P, stride;                               // parameters; floats per block slab (>= P + 1)
   int optimizer;                                   // 0 SGD, 1 Adam
   float lr, b1, b2, eps;
@@ -147,6 +149,11 @@ struct TfShape {
 // shape is outside what the kernels take (A = H dh with dh a power of two
 // <= 64, A <= 1024, t <= 256)
 bool tf_shape(int k, int t, int E, int A, int F, int H, TfShape &s);
+// the configurations' MLP (Dims' shape and parameter layout) on the same
+// launch sequence: its layers as strided-batched matrix-core GEMMs, the
+// embedding gradient as a one-hot GEMM; false when outside (nh <= 2,
+// bs <= 1024)
+bool mlp_seq_shape(const Dims &d, TfShape &s);
 
 // Device state of a running loop, read by every kernel of a step so the
 // launches of one step are the same every step.
@@ -173,6 +180,8 @@ struct TfBufs {
   const float *init;              // [stride] seeded parameters, copied into every slot
   float *X, *KV, *Q, *att, *O, *Z, *U, *G, *logits;   // activations
   float *dG, *dU, *dZ, *dO, *dQ, *dKV, *dX;          // gradients of activations
+  float *act[2], *dact[2];        // MLP: hidden activations and their gradients
+  int64_t sAct[2];
   float *part;                    // split-K partial sums [n][kSplit][max M N]
   uint32_t *cdf;                  // [n][bs][V+1]
   uint8_t *tokstep;               // [n][bs t] the step's context tokens (row-major)

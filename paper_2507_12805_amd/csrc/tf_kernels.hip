@@ -301,7 +301,8 @@ __device__ __forceinline__ int ctx_token(const TfShape &s, const TfSlot &d, cons
   return toks[d.tok_off + (uint64_t)row * d.L + (uint64_t)(i - s.t + p)];
 }
 
-// X[slot][(row t + p) E + e] = Emb[c][e] + Pos[p][e]
+// X[slot][(row t + p) E + e] = Emb[c][e] + Pos[p][e] (for the MLP, without
+// Pos: the concatenated context embeddings, row-major)
 __global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *st, const TfSlot *desc,
                                                      const uint8_t *toks, const uint8_t *ctx, const float *params,
                                                      float *X, int64_t sX, uint8_t *tokstep, int64_t sTok,
@@ -320,7 +321,8 @@ __global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *s
     c = 0;
   }
   const float *W = params + slot * s.stride;
-  X[slot * sX + q] = W[s.off_emb + (int64_t)c * s.E + e] + W[s.off_pos + (int64_t)p * s.E + e];
+  const float pe = s.off_pos >= 0 ? W[s.off_pos + (int64_t)p * s.E + e] : 0.0f;   // the MLP has none
+  X[slot * sX + q] = W[s.off_emb + (int64_t)c * s.E + e] + pe;
   if (e == 0) tokstep[slot * sTok + rp] = (uint8_t)c;   // the embedding gradient's one-hot keys
 }
 
@@ -692,10 +694,99 @@ hipError_t backward(const Ctx &c) {
   return gemm<true, false, EPI>(s, g, c.n, c.st);
 }
 
+// The configurations' MLP on the launch sequence: x = concat(Emb[c_p]),
+// h_{l+1} = ReLU(h_l W_l + b_l), logits = h_nh W_nh + b_nh.
+hipError_t mlp_forward(const Ctx &c, int *err) {
+  const TfShape &s = c.s;
+  const TfBufs &b = c.b;
+  const int bs = s.bs, t = s.t, E = s.E;
+  const int64_t S = s.stride;
+  float *W = c.W;
+  const int64_t nx = (int64_t)bs * t * E;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nx + 255) / 256), c.n), dim3(256), 0, c.st, s, b.state,
+                     b.slots_desc, c.toks, c.ctx, W, b.X, b.sX, b.tokstep, b.sTok, err);
+  TRY(hipGetLastError());
+  const int dims[4] = {t * E, s.H0, s.H1, s.V};
+  const float *in = b.X;
+  int64_t ldi = t * E, si = b.sX;
+  for (int l = 0; l <= s.nh; l++) {
+    const int N = l == s.nh ? s.V : dims[l + 1];
+    float *out = l == s.nh ? b.logits : b.act[l];
+    const int64_t so = l == s.nh ? b.sLog : b.sAct[l];
+    Gemm g = mk(c, in, ldi, si, W + s.off_W[l], N, S, out, N, so, bs, N, (int)ldi);
+    g.bias = W + s.off_b[l];
+    g.sBias = S;
+    g.relu = l < s.nh;
+    TRY((gemm<false, false, kStore>(s, g, c.n, c.st)));
+    in = out;
+    ldi = N;
+    si = so;
+  }
+  return hipSuccess;
+}
+
+template <int EPI>
+hipError_t mlp_backward(const Ctx &c) {
+  const TfShape &s = c.s;
+  const TfBufs &b = c.b;
+  const int bs = s.bs, t = s.t, E = s.E, V = s.V;
+  const int64_t S = s.stride;
+  float *W = c.W;
+  const int dims[3] = {t * E, s.H0, s.H1};
+  for (int l = s.nh; l >= 0; l--) {
+    const int din_n = dims[l], N = l == s.nh ? V : dims[l + 1];
+    const float *dout = l == s.nh ? b.logits : b.dact[l];
+    const int64_t so = l == s.nh ? b.sLog : b.sAct[l];
+    const float *in = l == 0 ? b.X : b.act[l - 1];
+    const int64_t si = l == 0 ? b.sX : b.sAct[l - 1];
+    float *din = l == 0 ? b.dX : b.dact[l - 1];
+    // din = dout W_l^T, masked by the ReLU that produced `in` (not for x)
+    Gemm g = mk(c, dout, N, so, W + s.off_W[l], N, S, din, din_n, si, bs, din_n, N);
+    if (l > 0) {
+      g.mask = in;
+      g.ldm = din_n;
+      g.sMask = si;
+    }
+    TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
+    // W_l and b_l: in^T dout with a ones row for the bias, which follows W_l
+    g = wgt(c, mk(c, in, din_n, si, dout, N, so, nullptr, N, 0, din_n, N, bs), s.off_W[l]);
+    g.aug = 1;
+    TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
+  }
+  // dEmb = onehot(tokens)^T dX, dX viewed as [bs t][E]
+  Gemm g = wgt(c, mk(c, nullptr, 0, 0, b.dX, E, b.sX, nullptr, E, 0, V, E, bs * t), s.off_emb);
+  g.oh = b.tokstep;
+  g.sOh = b.sTok;
+  return gemm<true, false, EPI>(s, g, c.n, c.st);
+}
+
 }  // namespace
+
+bool mlp_seq_shape(const Dims &d, TfShape &s) {
+  memset(&s, 0, sizeof s);
+  if (d.nh > 2 || d.V > 256 || d.bs < 1 || d.bs > 1024 || d.E > 1024 || d.t > 65535) return false;
+  s.arch = 0;
+  s.nh = d.nh;
+  s.H0 = d.nh >= 1 ? d.H[0] : 0;
+  s.H1 = d.nh >= 2 ? d.H[1] : 0;
+  s.V = d.V; s.E = d.E; s.t = d.t; s.bs = d.bs;
+  s.H = 1; s.dh = 1;
+  s.off_emb = d.off_emb;
+  s.off_pos = -1;
+  for (int l = 0; l <= d.nh; l++) {
+    s.off_W[l] = d.off_W[l];
+    s.off_b[l] = d.off_b[l];
+  }
+  s.P = d.P;
+  s.stride = d.stride;
+  s.optimizer = d.optimizer;
+  s.lr = d.lr; s.b1 = d.b1; s.b2 = d.b2; s.eps = d.eps;
+  return true;
+}
 
 bool tf_shape(int k, int t, int E, int A, int F, int H, TfShape &s) {
   memset(&s, 0, sizeof s);
+  s.arch = 1;
   if (k < 1 || k > 4 || t < 1 || t > 256 || E < 1 || E > 1024 || A < 1 || A > 1024 || F < 1 || H < 1 || A % H)
     return false;
   const int dh = A / H;
@@ -729,6 +820,24 @@ uint64_t tf_bufs_carve(const TfShape &s, int n, float *base, TfBufs &b) {
     return p;
   };
   int64_t dummy;
+  if (s.arch == 0) {
+    b.X = take(bs * t * E, b.sX);
+    b.dX = take(bs * t * E, dummy);
+    const int64_t hw[2] = {s.H0, s.H1};
+    for (int l = 0; l < 2; l++) {
+      b.act[l] = take(l < s.nh ? bs * hw[l] : 0, b.sAct[l]);
+      b.dact[l] = take(l < s.nh ? bs * hw[l] : 0, dummy);
+    }
+    b.logits = take(bs * V, b.sLog);
+    b.part = take(std::max<int64_t>(8 * bs * std::max<int64_t>(std::max<int64_t>(s.H0, s.H1), V), 16 * V * E),
+                  b.sPart);
+    b.cdf = reinterpret_cast<uint32_t *>(take(bs * (V + 1), b.sCdf));
+    b.coder = take(bs * (int64_t)(sizeof(CoderState) / 4), dummy);
+    int64_t stok;
+    b.tokstep = reinterpret_cast<uint8_t *>(take((bs * t + 3) / 4, stok));
+    b.sTok = stok * 4;
+    return used;
+  }
   b.X = take(bs * t * E, b.sX);
   b.dX = take(bs * t * E, dummy);
   b.KV = take(bs * t * 2 * A, b.sKV);
@@ -792,7 +901,7 @@ hipError_t tf_run(const TfShape &s, const TfBufs &b, const TfRun &r, hipStream_t
     c.n = nact;
     hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, (int)i, nact);
     TRY(hipGetLastError());
-    if (i >= (uint64_t)s.t) TRY(forward(c, err));
+    if (i >= (uint64_t)s.t) TRY(s.arch == 1 ? forward(c, err) : mlp_forward(c, err));
     float *probe = nullptr;
     if (r.probe_P && probe_i < r.n_probe && r.probe_steps_host[probe_i] == i)
       probe = r.probe_P + (int64_t)(probe_i++) * s.bs * s.V;
@@ -800,7 +909,7 @@ hipError_t tf_run(const TfShape &s, const TfBufs &b, const TfRun &r, hipStream_t
                        r.stream_slots, b.logits, b.sLog, b.cdf, b.sCdf, reinterpret_cast<CoderState *>(b.coder),
                        r.mode, probe);
     TRY(hipGetLastError());
-    if (i >= (uint64_t)s.t) TRY(backward<kUpdate>(c));
+    if (i >= (uint64_t)s.t) TRY(s.arch == 1 ? backward<kUpdate>(c) : mlp_backward<kUpdate>(c));
   }
   if (r.mode == 0) {
     hipLaunchKernelGGL(coder_finish_kernel, dim3(r.n), dim3(256), 0, st, s, r.n, b.slots_desc,
@@ -819,7 +928,7 @@ hipError_t tf_forward_op(const TfShape &s, const TfBufs &b, const float *params,
   TRY(hipGetLastError());
   hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, s.t, 1);
   TRY(hipGetLastError());
-  TRY(forward(c, err));
+  TRY(s.arch == 1 ? forward(c, err) : mlp_forward(c, err));
   const int64_t n = (int64_t)s.bs * s.V;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b.logits, logits, n);
   return hipGetLastError();
@@ -834,11 +943,11 @@ hipError_t tf_backward_op(const TfShape &s, const TfBufs &b, const float *params
   hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, s.t, 1);
   TRY(hipGetLastError());
   // activations recomputed from the contexts, then the backward
-  TRY(forward(c, err));
+  TRY(s.arch == 1 ? forward(c, err) : mlp_forward(c, err));
   const int64_t n = (int64_t)s.bs * s.V;
   hipLaunchKernelGGL(copy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dlogits, b.logits, n);
   TRY(hipGetLastError());
-  return backward<kGrad>(c);
+  return s.arch == 1 ? backward<kGrad>(c) : mlp_backward<kGrad>(c);
 }
 
 }  // namespace pmklc
