@@ -14,6 +14,7 @@
 
 #include "../../include/pmklc.h"
 #include "pmklc_internal.h"
+#include "seq_loop.h"
 
 using namespace pmklc;
 

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "pmklc_internal.h"
+#include "seq_loop.h"
 #include "step_common.h"
 
 namespace pmklc {
