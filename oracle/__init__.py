@@ -18,6 +18,9 @@ Parity status per function (see the tests under ``tests/test_oracle_*``):
   transformer   pinned: torch FP64 autograd with torch's own attention
                 routine, finite differences, t = 1 and zero-key closed
                 forms, learning-loop replay (SGD, Adam)
+  BiGRU static  pinned: torch.nn.GRU (bidirectional, 1-2 layers, FP64) with
+                the oracle's weights, zero-recurrence closed form, Eq. (1)
+                mixing at the first learned step
   private model pinned: training block gathered from its definition and run
                 through the pinned trace; coding pass equal to the public-
                 model container with the stored weights; the selector's
@@ -71,7 +74,8 @@ class _Cfg(ctypes.Structure):
                 ("smp_ppm", ctypes.c_uint32), ("seed", ctypes.c_uint64), ("n_blocks", ctypes.c_int32),
                 ("block_len", _u64p), ("n_files", ctypes.c_int32), ("file_blocks", _u64p),
                 ("init_override", _dp), ("ms_threshold", ctypes.c_uint64), ("arch", ctypes.c_int32),
-                ("heads", ctypes.c_int32)]
+                ("heads", ctypes.c_int32), ("static_arch", ctypes.c_int32), ("static_E", ctypes.c_int32),
+                ("gru_h", ctypes.c_int32), ("gru_layers", ctypes.c_int32), ("dense", ctypes.c_int32)]
 
 
 def _load():
@@ -102,6 +106,10 @@ def _load():
     L.or_decompress.argtypes = [_u8p, ctypes.c_uint64, _fp, ctypes.c_uint64, ctypes.POINTER(_u8p), _u64p]
     L.or_trace_block.argtypes = [ctypes.POINTER(_Cfg), _u8p, ctypes.c_uint64, _fp, _dp, ctypes.c_uint64, _u64p,
                                  ctypes.c_uint64, _dp, _dp, _dp]
+    L.or_static_param_count.argtypes = [ctypes.POINTER(_Cfg)]
+    L.or_static_param_count.restype = ctypes.c_uint64
+    L.or_static_init.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_uint64, _dp]
+    L.or_static_forward.argtypes = [ctypes.POINTER(_Cfg), _dp, _u8p, ctypes.c_int, _dp]
     L.or_free.argtypes = [ctypes.c_void_p]
     L.or_free.restype = None
     L.or_num_threads.restype = ctypes.c_int
@@ -287,6 +295,10 @@ def _mkcfg(cfg, n):
     c.selector = {"uniform": 0, "dm": 4, "spum_dm": 5, "sprm_dm": 6, "spum_sprm_dm": 7, "auto": 8}[sel]
     c.ms_threshold = int(cfg.get("ms_threshold", 0))
     c.arch, c.heads = _arch(cfg)
+    if cfg.get("static_arch", "mlp") == "bigru":
+        c.static_arch = 1
+        c.static_E, c.gru_h = int(cfg.get("static_E", 16)), int(cfg.get("gru_h", 32))
+        c.gru_layers, c.dense = int(cfg.get("gru_layers", 2)), int(cfg.get("dense", 128))
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
     c.seed = int(cfg["seed"])
     keep = []
@@ -312,6 +324,31 @@ def _mkcfg(cfg, n):
         keep.append(arr)
         c.init_override = _ptr(arr, _dp)
     return c, keep
+
+
+def static_param_count(cfg) -> int:
+    """Parameters of the static public model (the DM's MLP shape, or the
+    BiGRU of static_arch "bigru")."""
+    c, keep = _mkcfg(cfg, 0)
+    return int(_load().or_static_param_count(ctypes.byref(c)))
+
+
+def static_init(cfg, seed) -> np.ndarray:
+    c, keep = _mkcfg(cfg, 0)
+    w = np.zeros(static_param_count(cfg), dtype=np.float64)
+    _check(_load().or_static_init(ctypes.byref(c), seed, _ptr(w, _dp)), "static_init")
+    return w
+
+
+def static_forward(cfg, ws, ctx) -> np.ndarray:
+    """Logits L^u [rows, V] of the static public model for contexts [rows, t]."""
+    c, keep = _mkcfg(cfg, 0)
+    ctx = np.ascontiguousarray(ctx, dtype=np.uint8)
+    ws = np.ascontiguousarray(ws, dtype=np.float64)
+    out = np.zeros((ctx.shape[0], 4 ** cfg["k"]), dtype=np.float64)
+    _check(_load().or_static_forward(ctypes.byref(c), _ptr(ws, _dp), _ptr(ctx, _u8p), ctx.shape[0], _ptr(out, _dp)),
+           "static_forward")
+    return out
 
 
 def _static_arg(static):

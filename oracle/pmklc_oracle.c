@@ -288,14 +288,57 @@ uint32_t or_crc32(const uint8_t *p, uint64_t n) {
  * context position.  Parameter order for arch 1: Emb[V][E], Pos[t][E],
  * Wqkv[E][3A], bqkv[3A], Wo[A][A], bo[A], W1[A][F], b1[F], W2[F][A], b2[A],
  * Wh[A][V], bh[V] (off_W / off_b 0..4 in that order, fan[l] their fan-in). */
-typedef struct {
+typedef struct or_shape_s {
     int V, E, t, D, nh;
     int dims[6];
     uint64_t off_emb, off_W[5], off_b[5], n;
     int arch, heads, A, F;
     int fan[5];
     uint64_t off_pos;
+    /* arch 2, the BiGRU static model: gh units per direction, gl layers,
+     * gd-wide Dense; per layer l and direction d (0 forward, 1 backward):
+     * W_ih [3gh][in_l], W_hh [3gh][gh], b_ih [3gh], b_hh [3gh] (gate rows
+     * r, z, n), in_0 = E, in_1 = 2gh; then Wd [2gh][gd], bd, Wl [gd][V], bl */
+    int gh, gl, gd;
+    uint64_t off_wih[2][2], off_whh[2][2], off_bih[2][2], off_bhh[2][2], off_dw, off_db, off_lw, off_lb;
+    /* the static model's shape when it differs from this (DM) shape, or NULL */
+    const struct or_shape_s *ssh;
 } or_shape;
+
+/* The static model of Sec. 4.2.2 (reading): a 16-d embedding (E here),
+ * gl bidirectional GRU layers (Cho et al. 2014, the gate form with the reset
+ * gate applied to W_hn h + b_hn), the last layer's final states of both
+ * directions (forward after position t-1, backward after position 0)
+ * concatenated, a Dense layer of width gd with ReLU, a linear head to V. */
+static int shape_init_gru(or_shape *sh, int k, int t, int E, int gh, int gl, int gd) {
+    if (k < 1 || k > 4 || t < 1 || E < 1 || gh < 1 || gh > 256 || gl < 1 || gl > 2 || gd < 1) return OR_ERR_ARG;
+    memset(sh, 0, sizeof *sh);
+    sh->arch = 2;
+    sh->V = 1 << (2 * k);
+    sh->E = E;
+    sh->t = t;
+    sh->gh = gh;
+    sh->gl = gl;
+    sh->gd = gd;
+    uint64_t off = 0;
+    sh->off_emb = off;
+    off += (uint64_t)sh->V * E;
+    for (int l = 0; l < gl; l++) {
+        int in = l == 0 ? E : 2 * gh;
+        for (int d = 0; d < 2; d++) {
+            sh->off_wih[l][d] = off; off += 3ull * gh * in;
+            sh->off_whh[l][d] = off; off += 3ull * gh * gh;
+            sh->off_bih[l][d] = off; off += 3ull * gh;
+            sh->off_bhh[l][d] = off; off += 3ull * gh;
+        }
+    }
+    sh->off_dw = off; off += 2ull * gh * gd;
+    sh->off_db = off; off += (uint64_t)gd;
+    sh->off_lw = off; off += (uint64_t)gd * sh->V;
+    sh->off_lb = off; off += (uint64_t)sh->V;
+    sh->n = off;
+    return OR_OK;
+}
 
 static int shape_init_tf(or_shape *sh, int k, int t, int E, int nh, const int32_t *hidden, int heads) {
     if (nh != 2 || heads < 1 || hidden[0] < 1 || hidden[1] < 1 || hidden[0] % heads) return OR_ERR_ARG;
@@ -375,6 +418,20 @@ static uint64_t splitmix_at(uint64_t seed, uint64_t i) {
  * a = 1/sqrt(fan_in) for every linear weight and bias.  The oracle keeps
  * the FP64 value of the FP32 number. */
 static void init_params(const or_shape *sh, uint64_t seed, double *w) {
+    if (sh->arch == 2) {
+        /* U(-a, a): a = 1 for the embedding, 1/sqrt(gh) for the GRU weights
+         * and biases (the usual GRU range), 1/sqrt(fan_in) for the two
+         * dense layers */
+        for (uint64_t i = 0; i < sh->n; i++) {
+            double a = 1.0;
+            if (i >= sh->off_wih[0][0] && i < sh->off_dw) a = 1.0 / sqrt((double)sh->gh);
+            else if (i >= sh->off_dw && i < sh->off_lw) a = 1.0 / sqrt(2.0 * sh->gh);
+            else if (i >= sh->off_lw) a = 1.0 / sqrt((double)sh->gd);
+            double u = (double)(splitmix_at(seed, i) >> 40) * (1.0 / 16777216.0);
+            w[i] = (double)(float)((2.0 * u - 1.0) * a);
+        }
+        return;
+    }
     int nl = sh->arch == 1 ? 5 : sh->nh + 1;
     for (uint64_t i = 0; i < sh->n; i++) {
         double a = 1.0;
@@ -548,14 +605,68 @@ static void tf_backward_row(const or_shape *sh, const double *w, const uint8_t *
         }
 }
 
+static double sigmoid(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* BiGRU static model forward of one row; act holds gl t 2gh + 6gh + gd
+ * doubles: each layer's output sequence [t][2gh] (forward half, backward
+ * half), the gate scratch, the Dense output. */
+static uint64_t gru_act_len(const or_shape *sh) {
+    return (uint64_t)sh->gl * sh->t * 2 * sh->gh + 6ull * sh->gh + (uint64_t)sh->gd;
+}
+static void gru_forward_row(const or_shape *sh, const double *w, const uint8_t *ctx, double *act, double *logits) {
+    int t = sh->t, E = sh->E, h = sh->gh;
+    double *gx = act + (uint64_t)sh->gl * t * 2 * h, *gh_ = gx + 3 * h, *dense = gh_ + 3 * h;
+    const double *last = NULL;
+    for (int l = 0; l < sh->gl; l++) {
+        int in = l == 0 ? E : 2 * h;
+        double *out = act + (uint64_t)l * t * 2 * h;
+        for (int d = 0; d < 2; d++) {
+            const double *Wih = w + sh->off_wih[l][d], *Whh = w + sh->off_whh[l][d];
+            const double *bih = w + sh->off_bih[l][d], *bhh = w + sh->off_bhh[l][d];
+            double hs[256];
+            for (int u = 0; u < h; u++) hs[u] = 0.0;
+            for (int step = 0; step < t; step++) {
+                int p = d == 0 ? step : t - 1 - step;
+                const double *x = l == 0 ? w + sh->off_emb + (uint64_t)ctx[p] * E : last + (uint64_t)p * 2 * h;
+                for (int g = 0; g < 3 * h; g++) {
+                    double a = bih[g], b = bhh[g];
+                    for (int i = 0; i < in; i++) a += Wih[(uint64_t)g * in + i] * x[i];
+                    for (int i = 0; i < h; i++) b += Whh[(uint64_t)g * h + i] * hs[i];
+                    gx[g] = a;
+                    gh_[g] = b;
+                }
+                for (int u = 0; u < h; u++) {
+                    double r = sigmoid(gx[u] + gh_[u]);
+                    double z = sigmoid(gx[h + u] + gh_[h + u]);
+                    double nn = tanh(gx[2 * h + u] + r * gh_[2 * h + u]);
+                    hs[u] = (1.0 - z) * nn + z * hs[u];
+                    out[(uint64_t)p * 2 * h + d * h + u] = hs[u];
+                }
+            }
+        }
+        last = out;
+    }
+    /* final states: forward after position t-1, backward after position 0 */
+    double feat[512];
+    for (int u = 0; u < h; u++) {
+        feat[u] = last[(uint64_t)(t - 1) * 2 * h + u];
+        feat[h + u] = last[h + u];
+    }
+    linear_fwd(feat, 2 * h, w + sh->off_dw, w + sh->off_db, sh->gd, dense);
+    for (int o = 0; o < sh->gd; o++) dense[o] = dense[o] > 0.0 ? dense[o] : 0.0;
+    linear_fwd(dense, sh->gd, w + sh->off_lw, w + sh->off_lb, sh->V, logits);
+}
+
 static uint64_t acts_len(const or_shape *sh) {
+    if (sh->arch == 2) return gru_act_len(sh);
     if (sh->arch == 1) return tf_act_len(sh);
     uint64_t s = 0;
     for (int l = 0; l <= sh->nh; l++) s += (uint64_t)sh->dims[l];
     return s;
 }
 static void forward_row(const or_shape *sh, const double *w, const uint8_t *ctx, double *acts, double *logits) {
-    if (sh->arch == 1) tf_forward_row(sh, w, ctx, acts, logits);
+    if (sh->arch == 2) gru_forward_row(sh, w, ctx, acts, logits);
+    else if (sh->arch == 1) tf_forward_row(sh, w, ctx, acts, logits);
     else mlp_forward_row(sh, w, ctx, acts, logits);
 }
 
@@ -609,14 +720,15 @@ static void mlp_backward_row(const or_shape *sh, const double *w, const uint8_t 
 static int step_grad(const or_shape *sh, const double *w, const double *ws, double a_alpha, const uint8_t *ctx,
                      const uint8_t *tgt, int bs, double *P, double *grad, double *g_alpha, double *loss) {
     int V = sh->V;
-    uint64_t al = acts_len(sh);
+    const or_shape *ssh = sh->ssh ? sh->ssh : sh;   /* the static model's shape */
+    uint64_t al = acts_len(sh), als = acts_len(ssh);
     uint64_t maxd = 0;
     for (int l = 0; l <= sh->nh + 1; l++) if ((uint64_t)sh->dims[l] > maxd) maxd = (uint64_t)sh->dims[l];
     uint64_t scr = sh->arch == 1 ? tf_scratch_len(sh) : 2 * maxd;
-    double *acts = (double *)malloc(sizeof(double) * (al + al + 4 * (uint64_t)V + scr));
+    double *acts = (double *)malloc(sizeof(double) * (al + als + 4 * (uint64_t)V + scr));
     if (!acts) return OR_ERR_NOMEM;
     double *acts_s = acts + al;
-    double *lm = acts_s + al, *lu = lm + V, *z = lu + V, *dz = z + V, *scratch = dz + V;
+    double *lm = acts_s + als, *lu = lm + V, *z = lu + V, *dz = z + V, *scratch = dz + V;
     double alpha = 1.0 / (1.0 + exp(-a_alpha));
     if (grad) memset(grad, 0, sizeof(double) * sh->n);
     double ga = 0.0, L = 0.0;
@@ -624,7 +736,7 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
         const uint8_t *c = ctx + (uint64_t)j * sh->t;
         forward_row(sh, w, c, acts, lm);
         if (ws) {
-            forward_row(sh, ws, c, acts_s, lu);
+            forward_row(ssh, ws, c, acts_s, lu);
             for (int v = 0; v < V; v++) z[v] = alpha * lu[v] + (1.0 - alpha) * lm[v];
         } else {
             for (int v = 0; v < V; v++) z[v] = lm[v];
@@ -711,6 +823,8 @@ typedef struct {
     uint64_t ms_threshold;   /* Model Selector size bound in input bytes; 0 = 500 * 10^6 */
     int32_t arch;            /* dynamic model: 0 MLP, 1 Transformer (hidden = {A, F}, nh = 2) */
     int32_t heads;           /* attention heads (arch 1) */
+    int32_t static_arch;     /* static public model: 0 the DM's shape, 1 BiGRU (Sec. 4.2.2) */
+    int32_t static_E, gru_h, gru_layers, dense;   /* BiGRU: embedding, units per direction, layers, Dense */
 } or_config;
 
 #define SEL_SPUM 1
@@ -751,6 +865,17 @@ static int private_on(const or_config *c) { return (c->selector & SEL_SPRM) != 0
 /* Sec. 4.2.1: S for an input of n bytes.  Above the size bound the private
  * model and DM; otherwise the public model and DM when a public model is
  * supplied (the paper's is built in; here the caller holds it), else DM. */
+/* The static public model's shape when it is not the DM's (BiGRU); sh->ssh
+ * then points to it.  ssh must outlive sh's use. */
+static int static_shape(const or_config *c, or_shape *sh, or_shape *ssh) {
+    sh->ssh = NULL;
+    if (c->static_arch != 1) return OR_OK;
+    int rc = shape_init_gru(ssh, c->k, c->t, c->static_E, c->gru_h, c->gru_layers, c->dense);
+    if (rc) return rc;
+    sh->ssh = ssh;
+    return OR_OK;
+}
+
 static int32_t ms_select(const or_config *c, uint64_t n, int have_public) {
     uint64_t bound = c->ms_threshold ? c->ms_threshold : MS_BYTES_DEFAULT;
     if (n > bound) return SEL_SPRM | SEL_DM;
@@ -966,6 +1091,9 @@ static int cfg_check(const or_config *c, or_shape *sh) {
     if ((c->selector & SEL_SPUM) && (c->selector & SEL_SPRM)) return OR_ERR_ARG;
     /* the Transformer DM runs without a static model */
     if (c->arch == 1 && (c->selector & (SEL_SPUM | SEL_SPRM))) return OR_ERR_ARG;
+    /* the BiGRU static model is the public one */
+    if (c->static_arch < 0 || c->static_arch > 1) return OR_ERR_ARG;
+    if (c->static_arch == 1 && (c->selector & SEL_SPRM)) return OR_ERR_ARG;
     if (c->smp_ppm > 1000000u) return OR_ERR_ARG;
     return shape_init(sh, c->k, c->t, c->E, c->nh, c->hidden, c->arch, c->arch == 1 ? c->heads : 0);
 }
@@ -1082,11 +1210,17 @@ static void write_header(or_buf *o, const or_config *cfg, int path, uint32_t sta
     put_le(o, (uint64_t)cfg->selector, 1);
     put_le(o, (uint64_t)cfg->arch, 1);
     put_le(o, cfg->arch == 1 ? (uint64_t)cfg->heads : 0, 1);
-    put_le(o, 0, 1);
+    put_le(o, cfg->static_arch == 1 ? (uint64_t)(1 | (cfg->gru_layers << 4)) : 0, 1);
     put_le(o, cfg->smp_ppm, 4);
     put_le(o, cfg->seed, 8);
     put_le(o, static_crc, 4);
-    put_le(o, 0, 4);
+    if (cfg->static_arch == 1) {
+        put_le(o, (uint64_t)cfg->static_E, 1);
+        put_le(o, (uint64_t)cfg->gru_h, 1);
+        put_le(o, (uint64_t)cfg->dense, 2);
+    } else {
+        put_le(o, 0, 4);
+    }
     put_le(o, n, 8);
     put_le(o, (uint64_t)cfg->n_blocks, 4);
     put_le(o, (uint64_t)(cfg->file_blocks ? cfg->n_files : 1), 4);
@@ -1205,20 +1339,22 @@ int or_compress(const or_config *cfg_in, const uint8_t *in, uint64_t n, const fl
     or_config cfg_sel = *cfg_in;
     const or_config *cfg = &cfg_sel;
     if (cfg_sel.selector == SEL_AUTO) cfg_sel.selector = ms_select(cfg_in, n, static_w != NULL);
-    or_shape sh;
+    or_shape sh, ssh;
     int rc = cfg_check(cfg, &sh);
+    if (!rc) rc = static_shape(cfg, &sh, &ssh);
     if (rc) return rc;
+    const uint64_t sn = sh.ssh ? sh.ssh->n : sh.n;   /* static parameters */
     double *ws = NULL;
     float *priv = NULL;     /* the private static model, once trained */
     uint32_t scrc = 0;
     if (static_on(cfg)) {
-        ws = (double *)malloc(sizeof(double) * sh.n);
+        ws = (double *)malloc(sizeof(double) * sn);
         if (!ws) return OR_ERR_NOMEM;
     }
     if (static_on(cfg) && !private_on(cfg)) {
-        if (!static_w || static_len != sh.n) { free(ws); return OR_ERR_MODEL; }
-        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
-        scrc = or_crc32((const uint8_t *)static_w, sh.n * 4);
+        if (!static_w || static_len != sn) { free(ws); return OR_ERR_MODEL; }
+        for (uint64_t i = 0; i < sn; i++) ws[i] = (double)static_w[i];
+        scrc = or_crc32((const uint8_t *)static_w, sn * 4);
     }
     or_block *B = NULL;
     rc = plan_blocks(cfg, n, &B);
@@ -1312,19 +1448,26 @@ int or_decompress(const uint8_t *cbf, uint64_t len, const float *static_w, uint6
     c.selector = (int32_t)get_le(&r, 1);
     c.arch = (int32_t)get_le(&r, 1);
     c.heads = (int32_t)get_le(&r, 1);
-    get_le(&r, 1);
+    {
+        int sb = (int)get_le(&r, 1);
+        c.static_arch = sb & 15;
+        c.gru_layers = sb >> 4;
+    }
     c.smp_ppm = (uint32_t)get_le(&r, 4);
     c.seed = get_le(&r, 8);
     uint32_t scrc = (uint32_t)get_le(&r, 4);
-    get_le(&r, 4);
+    c.static_E = (int32_t)get_le(&r, 1);
+    c.gru_h = (int32_t)get_le(&r, 1);
+    c.dense = (int32_t)get_le(&r, 2);
     uint64_t n = get_le(&r, 8);
     c.n_blocks = (int32_t)get_le(&r, 4);
     c.n_files = (int32_t)get_le(&r, 4);
     if (r.err) return OR_ERR_CORRUPT;
     if (c.nh > 4) return OR_ERR_CORRUPT;
     if (!(path == PATH_ORACLE && c.selector) && !(path == PATH_UNIFORM && !c.selector)) return OR_ERR_MODEL;
-    or_shape sh;
-    if (cfg_check(&c, &sh)) return OR_ERR_CORRUPT;
+    or_shape sh, ssh;
+    if (cfg_check(&c, &sh) || static_shape(&c, &sh, &ssh)) return OR_ERR_CORRUPT;
+    const uint64_t sn = sh.ssh ? sh.ssh->n : sh.n;
     if (c.n_files < 1 || (uint64_t)c.n_files > len || (uint64_t)c.n_blocks * 2 > len) return OR_ERR_CORRUPT;
     uint64_t *fblocks = (uint64_t *)malloc(sizeof(uint64_t) * (uint64_t)c.n_files);
     uint64_t *blen = (uint64_t *)malloc(sizeof(uint64_t) * (uint64_t)c.n_blocks);
@@ -1344,13 +1487,13 @@ int or_decompress(const uint8_t *cbf, uint64_t len, const float *static_w, uint6
         if (!ws) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
         for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)get_f32(&r);
     } else if (static_on(&c)) {
-        if (!static_w || static_len != sh.n || or_crc32((const uint8_t *)static_w, sh.n * 4) != scrc) {
+        if (!static_w || static_len != sn || or_crc32((const uint8_t *)static_w, sn * 4) != scrc) {
             free(fblocks); free(blen);
             return OR_ERR_MODEL;
         }
-        ws = (double *)malloc(sizeof(double) * sh.n);
+        ws = (double *)malloc(sizeof(double) * sn);
         if (!ws) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
-        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
+        for (uint64_t i = 0; i < sn; i++) ws[i] = (double)static_w[i];
     }
     /* first pass over the block table to learn raw lengths */
     or_block *B = (or_block *)calloc((uint64_t)c.n_blocks, sizeof(or_block));
@@ -1476,14 +1619,16 @@ fail:
 int or_trace_block(const or_config *cfg, const uint8_t *tokens, uint64_t l, const float *static_w,
                    const double *init, uint64_t stop, const uint64_t *steps, uint64_t n_steps, double *P_out,
                    double *loss_out, double *w_final) {
-    or_shape sh;
+    or_shape sh, ssh;
     int rc = cfg_check(cfg, &sh);
+    if (!rc) rc = static_shape(cfg, &sh, &ssh);
     if (rc) return rc;
+    const uint64_t sn = sh.ssh ? sh.ssh->n : sh.n;
     double *ws = NULL;
     if (static_on(cfg)) {
-        ws = (double *)malloc(sizeof(double) * sh.n);
+        ws = (double *)malloc(sizeof(double) * sn);
         if (!ws) return OR_ERR_NOMEM;
-        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)static_w[i];
+        for (uint64_t i = 0; i < sn; i++) ws[i] = (double)static_w[i];
     }
     or_block blk;
     memset(&blk, 0, sizeof blk);
@@ -1511,4 +1656,35 @@ int or_num_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* The static public model alone, for its pins: parameter count, seeded
+ * initialisation and the logits L^u of `rows` contexts (cfg's static_arch
+ * and BiGRU fields; static_arch 0 is the DM's own MLP shape). */
+static int static_only_shape(const or_config *c, or_shape *s) {
+    if (c->static_arch == 1) return shape_init_gru(s, c->k, c->t, c->static_E, c->gru_h, c->gru_layers, c->dense);
+    return shape_init(s, c->k, c->t, c->E, c->nh, c->hidden, 0, 0);
+}
+
+uint64_t or_static_param_count(const void *cfg) {
+    or_shape s;
+    return static_only_shape((const or_config *)cfg, &s) ? 0 : s.n;
+}
+int or_static_init(const void *cfg, uint64_t seed, double *w) {
+    or_shape s;
+    int rc = static_only_shape((const or_config *)cfg, &s);
+    if (rc) return rc;
+    init_params(&s, seed, w);
+    return OR_OK;
+}
+int or_static_forward(const void *cfg, const double *ws, const uint8_t *ctx, int rows, double *logits) {
+    or_shape s;
+    int rc = static_only_shape((const or_config *)cfg, &s);
+    if (rc) return rc;
+    double *act = (double *)malloc(sizeof(double) * (acts_len(&s) + 1));
+    if (!act) return OR_ERR_NOMEM;
+    for (int j = 0; j < rows; j++)
+        forward_row(&s, ws, ctx + (uint64_t)j * s.t, act, logits + (uint64_t)j * s.V);
+    free(act);
+    return OR_OK;
 }
