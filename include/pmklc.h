@@ -71,6 +71,21 @@ enum { PMKLC_BATCHED = 0, PMKLC_PLAIN = 1 };      /* all blocks in one launch | 
  * PMKLC_FP32 (FP32 matrix cores) or PMKLC_BF16, for A / heads a power of two
  * <= 64, A <= 1024, E <= 1024, t <= 256, bs <= 1024, bs * t <= 65536. */
 enum { PMKLC_ARCH_MLP = 0, PMKLC_ARCH_TRANSFORMER = 1 };
+/* Static public model (Sec. 4.2.2). PMKLC_STATIC_MLP: the dynamic model's
+ * own shape. PMKLC_STATIC_BIGRU: an embedding of static_embed (paper: 16),
+ * gru_layers (1 or 2; paper: 2) bidirectional GRU layers of gru_hidden units
+ * per direction (gates r, z, n with n = tanh(W_in x + b_in + r (W_hn h +
+ * b_hn)), h' = (1 - z) n + z h), the last layer's final states of both
+ * directions (forward after the last context position, backward after the
+ * first) concatenated, Dense of `dense` units (paper: 128) with ReLU, linear
+ * head to V. Layout (FP32): Emb[V][static_embed]; per layer, forward then
+ * backward direction: W_ih[3h][in] (in = static_embed, then 2h),
+ * W_hh[3h][h], b_ih[3h], b_hh[3h]; Wd[2h][dense], bd; Wl[dense][V], bl.
+ * Mixed by Eq. 1 with an MLP dynamic model on the launch-sequence loop
+ * (numeric path 7 / 8); the recurrence runs in FP32 on both precisions.
+ * gru_hidden <= 128, static_embed <= 256. The private model keeps the
+ * dynamic model's shape (a BiGRU private model gives PMKLC_ERR_INVALID_ARG). */
+enum { PMKLC_STATIC_MLP = 0, PMKLC_STATIC_BIGRU = 1 };
 /* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. Accepted:
  * 0, DM, SPUM|DM, SPRM|DM (the selector enables one static model at most),
  * or AUTO.
@@ -123,6 +138,8 @@ typedef struct pmklc_config {
   uint64_t ms_threshold;    /* PMKLC_SEL_AUTO's size bound in input bytes; 0 = 500 * 10^6 */
   uint32_t arch;            /* dynamic model: PMKLC_ARCH_MLP or PMKLC_ARCH_TRANSFORMER */
   uint32_t heads;           /* attention heads (PMKLC_ARCH_TRANSFORMER) */
+  uint32_t static_arch;     /* static public model: PMKLC_STATIC_MLP or PMKLC_STATIC_BIGRU */
+  uint32_t static_embed, gru_hidden, gru_layers, dense;   /* PMKLC_STATIC_BIGRU's widths */
 } pmklc_config;
 
 /* Sec. 4.1 (GskE): maps ASCII bases A,C,G,T (0,1,2,3) to (s,k)-mer ids

@@ -7,7 +7,8 @@ If the library is missing, every entry point raises; there is no fallback.
 
 Configurations are plain dicts with the keys of ``synth.workloads``
 (s, k, t, bs, E, hidden, optimizer, lr, beta1, beta2, eps, selector,
-smp_ppm, seed, n_blocks / block_len, file_blocks, ms_threshold, arch, heads) plus ``precision``
+smp_ppm, seed, n_blocks / block_len, file_blocks, ms_threshold, arch, heads,
+static_arch, static_E, gru_h, gru_layers, dense) plus ``precision``
 ("fp32" | "bf16") and ``schedule`` ("batched" | "plain").
 """
 from __future__ import annotations
@@ -42,7 +43,9 @@ class _Config(ctypes.Structure):
                 ("n_blocks", ctypes.c_uint32), ("block_len_host", ctypes.POINTER(ctypes.c_uint64)),
                 ("n_files", ctypes.c_uint32), ("file_blocks_host", ctypes.POINTER(ctypes.c_uint64)),
                 ("static_host", ctypes.POINTER(ctypes.c_float)), ("static_len", ctypes.c_uint64),
-                ("ms_threshold", ctypes.c_uint64), ("arch", ctypes.c_uint32), ("heads", ctypes.c_uint32)]
+                ("ms_threshold", ctypes.c_uint64), ("arch", ctypes.c_uint32), ("heads", ctypes.c_uint32),
+                ("static_arch", ctypes.c_uint32), ("static_embed", ctypes.c_uint32), ("gru_hidden", ctypes.c_uint32),
+                ("gru_layers", ctypes.c_uint32), ("dense", ctypes.c_uint32)]
 
 
 class Timing(ctypes.Structure):
@@ -146,6 +149,10 @@ def make_config(cfg: dict, static=None):
     c.ms_threshold = int(cfg.get("ms_threshold", 0))
     c.arch = ARCHS[cfg.get("arch", "mlp")]
     c.heads = int(cfg.get("heads", 0)) if c.arch == 1 else 0
+    if cfg.get("static_arch", "mlp") == "bigru":
+        c.static_arch = 1
+        c.static_embed, c.gru_hidden = int(cfg.get("static_E", 16)), int(cfg.get("gru_h", 32))
+        c.gru_layers, c.dense = int(cfg.get("gru_layers", 2)), int(cfg.get("dense", 128))
     c.smp_ppm = int(cfg.get("smp_ppm", 0))
     c.seed = int(cfg["seed"])
     keep = []

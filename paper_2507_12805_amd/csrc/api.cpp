@@ -217,6 +217,14 @@ pmklc_status check_cfg(const pmklc_config *c) {
   if (c->smp_ppm > 1000000u) return PMKLC_ERR_INVALID_ARG;
   if (c->n_blocks < 1) return PMKLC_ERR_INVALID_ARG;
   if (c->arch > PMKLC_ARCH_TRANSFORMER) return PMKLC_ERR_INVALID_ARG;
+  if (c->static_arch > PMKLC_STATIC_BIGRU) return PMKLC_ERR_INVALID_ARG;
+  if (c->static_arch == PMKLC_STATIC_BIGRU) {
+    // the BiGRU model is the public one, mixed with the MLP dynamic model
+    if ((c->selector & PMKLC_SEL_SPRM) || c->arch != PMKLC_ARCH_MLP) return PMKLC_ERR_INVALID_ARG;
+    if (c->static_embed < 1 || c->gru_hidden < 1 || c->gru_layers < 1 || c->gru_layers > 2 || c->dense < 1 ||
+        c->static_embed > 255 || c->gru_hidden > 255 || c->dense > 65535)
+      return PMKLC_ERR_INVALID_ARG;
+  }
   if (c->arch == PMKLC_ARCH_TRANSFORMER) {
     // hidden = {A, F}; no static model (Sec. 4.2.4's DM stands alone here)
     if (c->n_hidden != 2 || c->heads < 1 || c->hidden[0] % c->heads) return PMKLC_ERR_INVALID_ARG;
@@ -432,6 +440,17 @@ pmklc_status make_tf_model(const pmklc_config *c, Model &m) {
 
 pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip, int seq = -1) {
   if (c->arch == PMKLC_ARCH_TRANSFORMER && (c->selector & PMKLC_SEL_DM)) return make_tf_model(c, m);
+  if (c->static_arch == PMKLC_STATIC_BIGRU && (c->selector & PMKLC_SEL_DM) && (c->selector & PMKLC_SEL_SPUM)) {
+    // the MLP on the launch-sequence loop, the BiGRU model beside it
+    if (c->selector & PMKLC_SEL_SPRM) return PMKLC_ERR_INVALID_ARG;
+    pmklc_status rc = make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, PMKLC_SEL_DM,
+                                 c->optimizer, c->lr, c->beta1, c->beta2, c->eps, c->precision, m, false, 1);
+    if (rc) return rc;
+    if (c->schedule != PMKLC_BATCHED || c->smp_ppm > 0) return PMKLC_ERR_UNSUPPORTED;
+    if (!bigru_shape((int)c->static_embed, (int)c->gru_hidden, (int)c->gru_layers, (int)c->dense, m.tf))
+      return PMKLC_ERR_UNSUPPORTED;
+    return PMKLC_OK;
+  }
   pmklc_status rc = make_model(c->s, c->k, c->t, c->bs, c->embed, c->arch == PMKLC_ARCH_TRANSFORMER ? 0 : c->n_hidden,
                                c->hidden, c->selector, c->optimizer, c->lr, c->beta1, c->beta2, c->eps, c->precision,
                                m, allow_chip, seq);
@@ -441,6 +460,11 @@ pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip, int se
   return rc;
 }
 pmklc_status make_model(const pmklc_config *c, Model &m) { return make_model(c, m, chip_default()); }
+
+// the static public model: present, and its parameter count
+bool bigru_on(const Model &m) { return is_tf(m.kind) && m.tf.sarch == 1; }
+bool has_static(const Model &m) { return m.d.static_on || bigru_on(m); }
+uint64_t static_count(const Model &m) { return bigru_on(m) ? (uint64_t)m.tf.sP : (uint64_t)m.d.P; }
 
 // Sec. 4.2.1, the Model Selector: the configuration with S chosen for an
 // input of n bytes when the caller asked for the selector's choice (the
@@ -533,6 +557,7 @@ struct Work {
   TfState *tf_state;
   TfSlot *tf_desc;
   float *tf_f;
+  float *tf_stat;         // the BiGRU static model's parameters
 };
 
 struct Sizes {
@@ -584,11 +609,13 @@ void layout(Arena &A, const Model &m, uint32_t n_blocks, const Sizes &z, bool ad
   w.tf_state = nullptr;
   w.tf_desc = nullptr;
   w.tf_f = nullptr;
+  w.tf_stat = nullptr;
   if (is_tf(m.kind)) {
     TfBufs tb;
     w.tf_state = A.take<TfState>(1);
     w.tf_desc = A.take<TfSlot>(n_blocks);
     w.tf_f = A.take<float>(tf_bufs_carve(m.tf, (int)n_blocks, nullptr, tb));
+    w.tf_stat = m.tf.sarch ? A.take<float>((uint64_t)m.tf.sP) : nullptr;
   }
 }
 
@@ -737,11 +764,14 @@ void write_header(Writer &o, const pmklc_config *c, uint8_t path, uint32_t scrc,
   o.le(c->selector, 1);
   o.le(c->arch, 1);
   o.le(c->arch == PMKLC_ARCH_TRANSFORMER ? c->heads : 0, 1);
-  o.le(0, 1);
+  const bool gru = c->static_arch == PMKLC_STATIC_BIGRU && (c->selector & PMKLC_SEL_SPUM);
+  o.le(gru ? 1 | (c->gru_layers << 4) : 0, 1);
   o.le(c->smp_ppm, 4);
   o.le(c->seed, 8);
   o.le(scrc, 4);
-  o.le(0, 4);
+  o.le(gru ? c->static_embed : 0, 1);
+  o.le(gru ? c->gru_hidden : 0, 1);
+  o.le(gru ? c->dense : 0, 2);
   o.le(n, 8);
   o.le(c->n_blocks, 4);
   o.le(n_files, 4);
@@ -1003,6 +1033,7 @@ pmklc_status run_tf(const Model &m, const Work &w, int mode, const std::vector<B
   b.adam_m = w.adam_m;
   b.adam_v = w.adam_v;
   b.init = w.init;
+  b.stat = w.tf_stat;
   TfRun r;
   if (extra) r = *extra;
   else memset(&r, 0, sizeof r);
@@ -1141,8 +1172,7 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   Model m;
   rc = make_model(cfg, m);
   if (rc) return rc;
-  if ((cfg->selector & PMKLC_SEL_SPUM) &&
-      (!cfg->static_host || cfg->static_len != (uint64_t)m.d.P))
+  if ((cfg->selector & PMKLC_SEL_SPUM) && (!cfg->static_host || cfg->static_len != static_count(m)))
     return PMKLC_ERR_MODEL_MISMATCH;
   const bool smp = cfg->smp_ppm > 0 && (cfg->selector & PMKLC_SEL_DM);
   Plan p;
@@ -1233,9 +1263,10 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   if (m.d.model_on) {
     HIP_TRY(is_transformer(m.kind) ? tf_init_params(m.tf, cfg->seed, w.init, st)
                                    : launch_init_params(m.d, cfg->seed, w.init, st));
-    if (m.d.static_on && !sprm) {
-      scrc = crc32(cfg->static_host, 4ull * m.d.P);
-      HIP_TRY(hipMemcpyAsync(w.stat, cfg->static_host, 4ull * m.d.P, hipMemcpyHostToDevice, st));
+    if (has_static(m) && !sprm) {
+      scrc = crc32(cfg->static_host, 4 * static_count(m));
+      HIP_TRY(hipMemcpyAsync(bigru_on(m) ? w.tf_stat : w.stat, cfg->static_host, 4 * static_count(m),
+                             hipMemcpyHostToDevice, st));
     }
   }
   if (sprm) {
@@ -1409,11 +1440,17 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.selector = (uint32_t)r.le(1);
   c.arch = (uint32_t)r.le(1);
   c.heads = (uint32_t)r.le(1);
-  r.le(1);
+  {
+    const uint32_t sb = (uint32_t)r.le(1);
+    c.static_arch = sb & 15;
+    c.gru_layers = sb >> 4;
+  }
   c.smp_ppm = (uint32_t)r.le(4);
   c.seed = r.le(8);
   o.scrc = (uint32_t)r.le(4);
-  r.le(4);
+  c.static_embed = (uint32_t)r.le(1);
+  c.gru_hidden = (uint32_t)r.le(1);
+  c.dense = (uint32_t)r.le(2);
   o.n = r.le(8);
   c.n_blocks = (uint32_t)r.le(4);
   uint32_t nf = (uint32_t)r.le(4);
@@ -1549,8 +1586,8 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   if (rc) return rc;
   if (path_of(o.c.selector, m.kind) != o.path) return PMKLC_ERR_MODEL_MISMATCH;
   const bool sprm = (o.c.selector & PMKLC_SEL_SPRM) != 0;
-  if (m.d.static_on && !sprm) {
-    if (!static_host || static_len != (uint64_t)m.d.P || crc32(static_host, 4ull * m.d.P) != o.scrc)
+  if (has_static(m) && !sprm) {
+    if (!static_host || static_len != static_count(m) || crc32(static_host, 4 * static_count(m)) != o.scrc)
       return PMKLC_ERR_MODEL_MISMATCH;
   }
   if (o.n > out_cap) { *out_len = o.n; return PMKLC_ERR_BUFFER_TOO_SMALL; }
@@ -1612,9 +1649,10 @@ pmklc_status pmklc_decompress(const uint8_t *cbf_host, uint64_t len, const float
   if (m.d.model_on) {
     HIP_TRY(is_transformer(m.kind) ? tf_init_params(m.tf, o.c.seed, w.init, st)
                                    : launch_init_params(m.d, o.c.seed, w.init, st));
-    if (m.d.static_on) {
+    if (has_static(m)) {
       const void *src = sprm ? static_cast<const void *>(cbf_host + o.private_off) : static_host;
-      HIP_TRY(hipMemcpyAsync(w.stat, src, 4ull * m.d.P, hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(bigru_on(m) ? w.tf_stat : w.stat, src, 4 * static_count(m), hipMemcpyHostToDevice,
+                             st));
     }
   }
   count_work(m, bd, g_last);
@@ -1832,7 +1870,7 @@ pmklc_status pmklc_wnc_decode(const uint8_t *in_dev, uint64_t nbytes, const uint
 // pmklc_model_trace for the Transformer DM: the compression loop's own
 // launches on one block, with probes and the final parameters
 static pmklc_status model_trace_tf(const pmklc_config *cfg, const Model &m, const uint8_t *tokens_dev, uint64_t l,
-                                   const float *init_dev, uint64_t stop, const uint64_t *probe_steps_host,
+                                   const float *static_dev, const float *init_dev, uint64_t stop, const uint64_t *probe_steps_host,
                                    uint32_t n_probe, float *probs_dev, float *params_dev, uint8_t *streams_host,
                                    uint64_t streams_cap, uint64_t *streams_len, hipStream_t st) {
   const uint32_t bs = cfg->bs;
@@ -1854,6 +1892,10 @@ static pmklc_status model_trace_tf(const pmklc_config *cfg, const Model &m, cons
   if (init_dev) chk(hipMemcpyAsync(w.init, init_dev, 4ull * (m.d.P + 1), hipMemcpyDeviceToDevice, st));
   else chk(is_transformer(m.kind) ? tf_init_params(m.tf, cfg->seed, w.init, st)
                                   : launch_init_params(m.d, cfg->seed, w.init, st));
+  if (bigru_on(m)) {
+    if (!static_dev) e = hipErrorInvalidValue;
+    else chk(hipMemcpyAsync(w.tf_stat, static_dev, 4ull * m.tf.sP, hipMemcpyDeviceToDevice, st));
+  }
   std::vector<BlockDesc> bd(1);
   bd[0] = BlockDesc{};
   bd[0].L = (uint32_t)L;
@@ -1903,10 +1945,10 @@ pmklc_status pmklc_model_trace(const pmklc_config *cfg, const uint8_t *tokens_de
   Model m;
   rc = make_model(cfg, m);
   if (rc) return rc;
-  if (m.d.static_on && !static_dev) return PMKLC_ERR_MODEL_MISMATCH;
+  if (has_static(m) && !static_dev) return PMKLC_ERR_MODEL_MISMATCH;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (is_tf(m.kind))
-    return model_trace_tf(cfg, m, tokens_dev, l, init_dev, stop, probe_steps_host, n_probe, probs_dev, params_dev,
+    return model_trace_tf(cfg, m, tokens_dev, l, static_dev, init_dev, stop, probe_steps_host, n_probe, probs_dev, params_dev,
                           streams_host, streams_cap, streams_len, st);
   const uint32_t bs = cfg->bs;
   uint64_t L = l / bs;

@@ -21,7 +21,15 @@ struct TfShape {
   int optimizer;                                   // 0 SGD, 1 Adam
   float lr, b1, b2, eps;
   int bf16;                                        // GEMM inputs rounded to BF16 (else FP32 MFMA)
+  // the BiGRU static public model mixed in by Eq. 1 (sarch 1), or none (0):
+  // embedding sE, gl layers of gh units per direction, Dense gd; offsets in
+  // its own parameter vector (sP floats), layer l, direction d
+  int sarch, sE, gh, gl, gd;
+  int64_t s_emb, s_wih[2][2], s_whh[2][2], s_bih[2][2], s_bhh[2][2], s_dw, s_db, s_lw, s_lb, sP;
 };
+// the BiGRU static model's shape into s (false outside the kernel's limits:
+// gh <= 128, 1 <= gl <= 2, sE <= 256, gd >= 1)
+bool bigru_shape(int sE, int gh, int gl, int gd, TfShape &s);
 // fills everything but bs/optimiser/bf16 from the widths; false when the
 // shape is outside what the kernels take (A = H dh with dh a power of two
 // <= 64, A <= 1024, t <= 256)
@@ -62,6 +70,8 @@ struct TfBufs {
   float *part;                    // split-K partial sums [n][kSplit][max M N]
   uint32_t *cdf;                  // [n][bs][V+1]
   uint8_t *tokstep;               // [n][bs t] the step's context tokens (row-major)
+  const float *stat;              // the BiGRU static model's parameters (sP floats, shared), or null
+  float *lu;                      // [n][bs][V] its logits, then L^u - L^m for the mixing weight
   void *coder;                    // [n][bs] coder states
   int64_t sX, sKV, sQ, sAtt, sA, sU, sLog, sPart, sCdf, sTok;   // per-slot strides (elements)
 };

@@ -474,39 +474,53 @@ __global__ void coder_finish_kernel(TfShape s, int n, const TfSlot *desc, CoderS
 // codes token i of segment j with its row's table (the uniform table before
 // step t), and the rows become dL/dlogits = (P - onehot) / bs.
 constexpr int kCodeT = 256;
+// With the static model (lu given): Eq. 1 mixes alpha L^u + (1 - alpha) L^m,
+// alpha = sigmoid(a) with a the slot's parameter P; the rows of lu become
+// L^u - L^m, the loss gradient of the dynamic model is scaled by 1 - alpha,
+// and a takes its own optimiser step from sum_rows (sum_v P_v (L^u_v - L^m_v)
+// - (L^u_e - L^m_e)) / bs * alpha (1 - alpha), rows summed in order.
 __global__ __launch_bounds__(kCodeT) void code_kernel(TfShape s, const TfState *st, const TfSlot *desc,
                                                       uint8_t *toks, uint32_t *sslots, float *logits, int64_t sLog,
                                                       uint32_t *cdf, int64_t sCdf, CoderState *coder, int mode,
-                                                      float *probe) {
+                                                      float *probe, float *lu, float *params, float *adam_m,
+                                                      float *adam_v) {
   const int slot = blockIdx.x;
   if (slot >= st->nact) return;
   __shared__ uint8_t tgt[1024];
+  __shared__ float srow_s[1024];
   const TfSlot d = desc[slot];
   const int i = st->i, V = s.V, bs = s.bs, tid = threadIdx.x;
   const bool uniform = i < s.t;
   float *lg = logits + slot * sLog;
+  float *ul = lu ? lu + slot * sLog : nullptr;
   uint32_t *cd = cdf + slot * sCdf;
+  const bool mix = ul != nullptr;
+  float *ap = mix ? params + slot * s.stride + s.P : nullptr;
+  const float alpha = mix ? 1.0f / (1.0f + expf(-*ap)) : 0.0f;
   if (!uniform) {
     const int spl = row_spl(V), G = V / spl, gs = __builtin_ctz((unsigned)G);
     for (int j0 = 0; j0 < bs; j0 += kCodeT >> gs) {
       const int j = j0 + (tid >> gs), gl = tid & (G - 1);
       if (j >= bs) continue;
       float *lr = lg + (int64_t)j * V;
+      float *ur = mix ? ul + (int64_t)j * V : nullptr;
       uint32_t *crow = cd + (int64_t)j * (V + 1);
       float *pp = probe ? probe + (int64_t)j * V + gl * spl : nullptr;
+      float sr;
       if (spl == 4) {
         float pr[4];
-        row_softmax_regs<4>(lr, nullptr, false, 0.0f, V, G, gl, crow, pr);
+        sr = row_softmax_regs<4>(lr, ur, mix, alpha, V, G, gl, crow, pr);
         if (pp) for (int c = 0; c < 4; c++) pp[c] = pr[c];
       } else if (spl == 8) {
         float pr[8];
-        row_softmax_regs<8>(lr, nullptr, false, 0.0f, V, G, gl, crow, pr);
+        sr = row_softmax_regs<8>(lr, ur, mix, alpha, V, G, gl, crow, pr);
         if (pp) for (int c = 0; c < 8; c++) pp[c] = pr[c];
       } else {
         float pr[32];
-        row_softmax_regs<32>(lr, nullptr, false, 0.0f, V, G, gl, crow, pr);
+        sr = row_softmax_regs<32>(lr, ur, mix, alpha, V, G, gl, crow, pr);
         if (pp) for (int c = 0; c < 32; c++) pp[c] = pr[c];
       }
+      if (mix && gl == 0) srow_s[j] = sr;
     }
   } else if (probe) {
     for (int q = tid; q < bs * V; q += kCodeT) probe[q] = 1.0f / (float)V;
@@ -536,10 +550,129 @@ __global__ __launch_bounds__(kCodeT) void code_kernel(TfShape s, const TfState *
   __syncthreads();
   if (uniform) return;
   const float inv_bs = 1.0f / (float)bs;
+  const float scale = mix ? inv_bs * (1.0f - alpha) : inv_bs;
   for (int q = tid; q < bs * V; q += kCodeT) {
     const int j = q / V, v = q % V;
-    lg[q] = (lg[q] - (v == tgt[j] ? 1.0f : 0.0f)) * inv_bs;
+    lg[q] = (lg[q] - (v == tgt[j] ? 1.0f : 0.0f)) * scale;
   }
+  if (mix && tid == 0) {
+    float acc = 0.0f;
+    for (int j = 0; j < bs; j++) acc += srow_s[j] - ul[(int64_t)j * V + tgt[j]];
+    Opt o;
+    o.kind = s.optimizer;
+    o.lr = s.lr; o.b1 = s.b1; o.b2 = s.b2; o.eps = s.eps;
+    o.c1 = st->c1;
+    o.c2 = st->c2;
+    float *mm = adam_m ? adam_m + slot * s.stride + s.P : nullptr;
+    float *vv = adam_v ? adam_v + slot * s.stride + s.P : nullptr;
+    *ap -= opt_delta(o, acc * inv_bs * (alpha * (1.0f - alpha)), mm, vv);
+  }
+}
+
+// The BiGRU static public model's logits for every row of a slot's step:
+// one workgroup per R rows, one thread per (direction, gate row); the
+// current layer's weights in LDS, the rows' hidden states, gate parts and
+// the first layer's output sequence beside them.  Per position the
+// threads form the 3h input and hidden parts of their gate row for the R
+// rows, then h threads per direction combine them (r, z, n, h'); the two
+// directions run side by side.  FP32 throughout; every sum in order.
+__device__ __forceinline__ float sigm(float x) { return 1.0f / (1.0f + __expf(-x)); }
+__device__ __forceinline__ float tanh_f(float x) { return 1.0f - 2.0f / (__expf(2.0f * x) + 1.0f); }
+
+__global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const uint8_t *tokstep, int64_t sTok,
+                             float *lu, int64_t sLu, int R) {
+  const int slot = blockIdx.y;
+  if (slot >= st->nact) return;
+  extern __shared__ float sm[];
+  const int h = s.gh, G = 3 * h, t = s.t, V = s.V, E = s.sE;
+  const int IN = E > 2 * h ? E : 2 * h;
+  const int tid = threadIdx.x, d = tid / G, g = tid % G;   // direction, gate row (blockDim = 2G)
+  const int row0 = blockIdx.x * R, rows = min(R, s.bs - row0);
+  float *wih = sm;                              // [2][G][IN]
+  float *whh = wih + 2 * G * IN;                // [2][G][h]
+  float *hs = whh + 2 * G * h;                  // [R][2][h]
+  float *ga = hs + R * 2 * h;                   // [R][2][G]
+  float *gb = ga + R * 2 * G;                   // [R][2][G]
+  float *seq = gb + R * 2 * G;                  // [R][t][2h] first layer's outputs
+  float *dn = seq + R * t * 2 * h;              // [R][gd]
+  const uint8_t *tk = tokstep + slot * sTok;
+  for (int l = 0; l < s.gl; l++) {
+    const int in = l == 0 ? E : 2 * h;
+    __syncthreads();
+    for (int q = tid; q < 2 * G * in; q += blockDim.x) {
+      const int dd = q / (G * in), rr = q % (G * in);
+      wih[dd * G * IN + (rr / in) * IN + rr % in] = W[s.s_wih[l][dd] + rr];
+    }
+    for (int q = tid; q < 2 * G * h; q += blockDim.x) {
+      const int dd = q / (G * h), rr = q % (G * h);
+      whh[dd * G * h + rr] = W[s.s_whh[l][dd] + rr];
+    }
+    for (int q = tid; q < R * 2 * h; q += blockDim.x) hs[q] = 0.0f;
+    const float bi = W[s.s_bih[l][d] + g], bh = W[s.s_bhh[l][d] + g];
+    const float *wi = wih + (d * G + g) * IN, *wh = whh + (d * G + g) * h;
+    __syncthreads();
+    for (int step = 0; step < t; step++) {
+      const int p = d == 0 ? step : t - 1 - step;
+      for (int r = 0; r < rows; r++) {
+        float a = bi, b = bh;
+        if (l == 0) {
+          const float *x = W + s.s_emb + (int64_t)tk[(int64_t)(row0 + r) * t + p] * E;
+          for (int k = 0; k < E; k++) a += wi[k] * x[k];
+        } else {
+          const float *x = seq + (r * t + p) * 2 * h;
+          for (int k = 0; k < 2 * h; k++) a += wi[k] * x[k];
+        }
+        const float *hp = hs + (r * 2 + d) * h;
+        for (int k = 0; k < h; k++) b += wh[k] * hp[k];
+        ga[(r * 2 + d) * G + g] = a;
+        gb[(r * 2 + d) * G + g] = b;
+      }
+      __syncthreads();
+      if (g < h) {
+        for (int r = 0; r < rows; r++) {
+          const float *xa = ga + (r * 2 + d) * G, *xb = gb + (r * 2 + d) * G;
+          const float rg = sigm(xa[g] + xb[g]);
+          const float zg = sigm(xa[h + g] + xb[h + g]);
+          const float ng = tanh_f(xa[2 * h + g] + rg * xb[2 * h + g]);
+          float *hp = hs + (r * 2 + d) * h;
+          const float hn = (1.0f - zg) * ng + zg * hp[g];
+          hp[g] = hn;
+          if (l == 0 && s.gl == 2) seq[(r * t + p) * 2 * h + d * h + g] = hn;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // head: final states [forward | backward] -> Dense + ReLU -> linear
+  for (int q = tid; q < rows * s.gd; q += blockDim.x) {
+    const int r = q / s.gd, o = q % s.gd;
+    float a = W[s.s_db + o];
+    const float *hr = hs + r * 2 * h;
+    for (int k = 0; k < 2 * h; k++) a += hr[k] * W[s.s_dw + (int64_t)k * s.gd + o];
+    dn[r * s.gd + o] = a > 0.0f ? a : 0.0f;
+  }
+  __syncthreads();
+  for (int q = tid; q < rows * V; q += blockDim.x) {
+    const int r = q / V, v = q % V;
+    float a = W[s.s_lb + v];
+    const float *dr = dn + r * s.gd;
+    for (int o = 0; o < s.gd; o++) a += dr[o] * W[s.s_lw + (int64_t)o * V + v];
+    lu[slot * sLu + (int64_t)(row0 + r) * V + v] = a;
+  }
+}
+
+// rows per workgroup of bigru_kernel and its LDS bytes (0: does not fit)
+int bigru_rows(const TfShape &s, size_t &bytes) {
+  const int h = s.gh, G = 3 * h, IN = s.sE > 2 * h ? s.sE : 2 * h;
+  for (int R = 8; R >= 1; R >>= 1) {
+    const size_t f = (size_t)2 * G * IN + 2 * G * h + R * 2 * h + 2 * R * 2 * G + (size_t)R * s.t * 2 * h + R * s.gd;
+    if (f * 4 <= 150 * 1024) {
+      bytes = f * 4;
+      return R;
+    }
+  }
+  bytes = 0;
+  return 0;
 }
 
 // the op's own loss gradient is given: copy it into the logits rows
@@ -763,6 +896,31 @@ hipError_t mlp_backward(const Ctx &c) {
 
 }  // namespace
 
+bool bigru_shape(int sE, int gh, int gl, int gd, TfShape &s) {
+  if (sE < 1 || sE > 256 || gh < 1 || gh > 128 || gl < 1 || gl > 2 || gd < 1) return false;
+  s.sarch = 1;
+  s.sE = sE; s.gh = gh; s.gl = gl; s.gd = gd;
+  int64_t off = 0;
+  s.s_emb = off;
+  off += (int64_t)s.V * sE;
+  for (int l = 0; l < gl; l++) {
+    const int64_t in = l == 0 ? sE : 2 * gh;
+    for (int d = 0; d < 2; d++) {
+      s.s_wih[l][d] = off; off += 3ll * gh * in;
+      s.s_whh[l][d] = off; off += 3ll * gh * gh;
+      s.s_bih[l][d] = off; off += 3ll * gh;
+      s.s_bhh[l][d] = off; off += 3ll * gh;
+    }
+  }
+  s.s_dw = off; off += 2ll * gh * gd;
+  s.s_db = off; off += gd;
+  s.s_lw = off; off += (int64_t)gd * s.V;
+  s.s_lb = off; off += s.V;
+  s.sP = off;
+  size_t lds;
+  return bigru_rows(s, lds) > 0;
+}
+
 bool mlp_seq_shape(const Dims &d, TfShape &s) {
   memset(&s, 0, sizeof s);
   if (d.nh > 2 || d.V > 256 || d.bs < 1 || d.bs > 1024 || d.E > 1024 || d.t > 65535) return false;
@@ -830,6 +988,7 @@ uint64_t tf_bufs_carve(const TfShape &s, int n, float *base, TfBufs &b) {
       b.dact[l] = take(l < s.nh ? bs * hw[l] : 0, dummy);
     }
     b.logits = take(bs * V, b.sLog);
+    b.lu = take(s.sarch ? bs * V : 0, dummy);
     b.part = take(std::max<int64_t>(8 * bs * std::max<int64_t>(std::max<int64_t>(s.H0, s.H1), V), 16 * V * E),
                   b.sPart);
     b.cdf = reinterpret_cast<uint32_t *>(take(bs * (V + 1), b.sCdf));
@@ -902,13 +1061,28 @@ hipError_t tf_run(const TfShape &s, const TfBufs &b, const TfRun &r, hipStream_t
     c.n = nact;
     hipLaunchKernelGGL(begin_step_kernel, dim3(1), dim3(1), 0, st, s, b.state, (int)i, nact);
     TRY(hipGetLastError());
-    if (i >= (uint64_t)s.t) TRY(s.arch == 1 ? forward(c, err) : mlp_forward(c, err));
+    if (i >= (uint64_t)s.t) {
+      TRY(s.arch == 1 ? forward(c, err) : mlp_forward(c, err));
+      if (s.sarch == 1) {
+        size_t lds = 0;
+        const int R = bigru_rows(s, lds);
+        static bool lds_set = false;   // dynamic LDS beyond 64 KB needs the kernel's attribute once
+        if (!lds_set) {
+          TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&bigru_kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024));
+          lds_set = true;
+        }
+        hipLaunchKernelGGL(bigru_kernel, dim3((s.bs + R - 1) / R, nact), dim3(6 * s.gh), lds, st, s, b.state, b.stat,
+                           b.tokstep, b.sTok, b.lu, b.sLog, R);
+        TRY(hipGetLastError());
+      }
+    }
     float *probe = nullptr;
     if (r.probe_P && probe_i < r.n_probe && r.probe_steps_host[probe_i] == i)
       probe = r.probe_P + (int64_t)(probe_i++) * s.bs * s.V;
     hipLaunchKernelGGL(code_kernel, dim3(nact), dim3(kCodeT), 0, st, s, b.state, b.slots_desc, r.tokens,
                        r.stream_slots, b.logits, b.sLog, b.cdf, b.sCdf, reinterpret_cast<CoderState *>(b.coder),
-                       r.mode, probe);
+                       r.mode, probe, s.sarch == 1 ? b.lu : nullptr, b.params, b.adam_m, b.adam_v);
     TRY(hipGetLastError());
     if (i >= (uint64_t)s.t) TRY(s.arch == 1 ? backward<kUpdate>(c) : mlp_backward<kUpdate>(c));
   }
