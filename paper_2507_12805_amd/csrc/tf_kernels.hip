@@ -65,6 +65,9 @@ struct Gemm {
   const TfState *st;
   int opt;
   float lr, b1, b2, eps;
+  // 16-byte accesses allowed (base 16-byte aligned, every stride a multiple
+  // of 4 floats): va / vb for the operands' loads, vc for the epilogue's
+  int va, vb, vc;
 };
 
 __device__ __forceinline__ Opt make_opt(const Gemm &g) {
@@ -96,6 +99,64 @@ __device__ __forceinline__ void epilogue(const Gemm &g, int slot, int slice, int
     float *mm = g.m ? g.m + slot * g.sMV + at : nullptr;
     float *vv = g.v ? g.v + slot * g.sMV + at : nullptr;
     g.C[slot * g.sC + at] -= opt_delta(o, x, mm, vv);
+  }
+}
+
+// the same for 4 consecutive columns col..col+3 < N, when g.vc allows
+// 16-byte accesses: the same operations per element, four at a time
+template <int EPI>
+__device__ __forceinline__ void epilogue4(const Gemm &g, int slot, int slice, int row, int col, const float *x) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  f4 y = {x[0], x[1], x[2], x[3]};
+  if constexpr (EPI == kPartial) {
+    *reinterpret_cast<f4 *>(g.part + slot * g.sPart + ((int64_t)slice * (g.M + g.aug) + row) * g.N + col) = y;
+  } else if constexpr (EPI == kStore) {
+    if (g.bias) {
+      const f4 b = *reinterpret_cast<const f4 *>(g.bias + slot * g.sBias + col);
+#pragma unroll
+      for (int c = 0; c < 4; c++) y[c] += b[c];
+    }
+    if (g.relu) {
+#pragma unroll
+      for (int c = 0; c < 4; c++) y[c] = y[c] > 0.0f ? y[c] : 0.0f;
+    }
+    if (g.mask) {
+      const f4 k = *reinterpret_cast<const f4 *>(g.mask + slot * g.sMask + (int64_t)row * g.ldm + col);
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+        if (!(k[c] > 0.0f)) y[c] = 0.0f;
+    }
+    *reinterpret_cast<f4 *>(g.C + slot * g.sC + (int64_t)row * g.ldc + col) = y;
+  } else if constexpr (EPI == kGrad) {
+    *reinterpret_cast<f4 *>(g.C + slot * g.sC + (int64_t)row * g.ldc + col) = y;
+  } else if constexpr (EPI == kAccum) {
+    f4 *c4 = reinterpret_cast<f4 *>(g.C + slot * g.sC + (int64_t)row * g.ldc + col);
+    f4 z = *c4;
+#pragma unroll
+    for (int c = 0; c < 4; c++) z[c] += y[c];
+    *c4 = z;
+  } else {
+    const int64_t at = (int64_t)row * g.ldc + col;
+    const Opt o = make_opt(g);
+    f4 *w4 = reinterpret_cast<f4 *>(g.C + slot * g.sC + at);
+    f4 w = *w4;
+    if (g.m) {
+      f4 *m4 = reinterpret_cast<f4 *>(g.m + slot * g.sMV + at), *v4 = reinterpret_cast<f4 *>(g.v + slot * g.sMV + at);
+      f4 mm = *m4, vv = *v4;
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        float mc = mm[c], vc = vv[c];
+        w[c] -= opt_delta(o, y[c], &mc, &vc);
+        mm[c] = mc;
+        vv[c] = vc;
+      }
+      *m4 = mm;
+      *v4 = vv;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; c++) w[c] -= opt_delta(o, y[c], (float *)nullptr, (float *)nullptr);
+    }
+    *w4 = w;
   }
 }
 
@@ -139,35 +200,73 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   T *Bs = As + kBM * LD;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32, r = lane & 15, q = lane >> 4;
-  // element e = tid + 256 u of a chunk: TA / !TB walk the M / N index
-  // fastest (coalesced for those layouts), the others walk k fastest
+  // a chunk's operands in groups of 4 elements along the index that is
+  // contiguous in memory (k for A / B^T stored row-major, m / n otherwise):
+  // group e = tid + 256 u (u < 4), 16 groups per 64-wide line; (mm, kk) is
+  // the group's first element.  In-bounds groups of an operand whose layout
+  // allows it are one 16-byte load, the others element by element
   auto a_mk = [&](int u, int &mm, int &kk) {
     const int e = tid + kGT * u;
-    if (TA) { kk = e / kBM; mm = e % kBM; } else { mm = e / kCK; kk = e % kCK; }
+    if (TA) { kk = e >> 4; mm = (e & 15) * 4; } else { mm = e >> 4; kk = (e & 15) * 4; }
   };
   auto b_nk = [&](int u, int &nn, int &kk) {
     const int e = tid + kGT * u;
-    if (TB) { nn = e / kCK; kk = e % kCK; } else { kk = e / kBN; nn = e % kBN; }
+    if (TB) { nn = e >> 4; kk = (e & 15) * 4; } else { kk = e >> 4; nn = (e & 15) * 4; }
   };
+  typedef float f4 __attribute__((ext_vector_type(4)));
   float pa[kPer], pb[kPer];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < kPer; u++) {
+    for (int u = 0; u < kPer / 4; u++) {
       int mm, kk;
       a_mk(u, mm, kk);
       const int gm = m0 + mm, gk = k0 + kk;
-      float x = 0.0f;
-      if (gm < M && gk < kend) {
-        if (!TA) x = A[(int64_t)gm * g.lda + gk];
-        else if (oh) x = (int)oh[gk] == gm ? 1.0f : 0.0f;
-        else if (g.oh_mod) x = gk % g.oh_mod == gm ? 1.0f : 0.0f;
-        else x = gm == g.M ? 1.0f : A[(int64_t)gk * g.lda + gm];
+      float *x = pa + 4 * u;
+      if (!TA) {
+        if (g.va && gm < M && gk + 3 < kend) {
+          const f4 v = *reinterpret_cast<const f4 *>(A + (int64_t)gm * g.lda + gk);
+#pragma unroll
+          for (int c = 0; c < 4; c++) x[c] = v[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; c++) x[c] = gm < M && gk + c < kend ? A[(int64_t)gm * g.lda + gk + c] : 0.0f;
+        }
+      } else if (oh || g.oh_mod) {
+        const int key = gk < kend ? (oh ? (int)oh[gk] : gk % g.oh_mod) : -1;
+#pragma unroll
+        for (int c = 0; c < 4; c++) x[c] = gm + c < M && key == gm + c ? 1.0f : 0.0f;
+      } else if (g.va && gk < kend && gm + 3 < g.M) {
+        const f4 v = *reinterpret_cast<const f4 *>(A + (int64_t)gk * g.lda + gm);
+#pragma unroll
+        for (int c = 0; c < 4; c++) x[c] = v[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          const int gmc = gm + c;
+          x[c] = gmc < M && gk < kend ? (gmc == g.M ? 1.0f : A[(int64_t)gk * g.lda + gmc]) : 0.0f;
+        }
       }
-      pa[u] = x;
       int nn, kb;
       b_nk(u, nn, kb);
       const int gn = n0 + nn, gkb = k0 + kb;
-      pb[u] = (gn < g.N && gkb < kend) ? (TB ? B[(int64_t)gn * g.ldb + gkb] : B[(int64_t)gkb * g.ldb + gn]) : 0.0f;
+      float *y = pb + 4 * u;
+      if (TB) {
+        if (g.vb && gn < g.N && gkb + 3 < kend) {
+          const f4 v = *reinterpret_cast<const f4 *>(B + (int64_t)gn * g.ldb + gkb);
+#pragma unroll
+          for (int c = 0; c < 4; c++) y[c] = v[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; c++) y[c] = gn < g.N && gkb + c < kend ? B[(int64_t)gn * g.ldb + gkb + c] : 0.0f;
+        }
+      } else if (g.vb && gkb < kend && gn + 3 < g.N) {
+        const f4 v = *reinterpret_cast<const f4 *>(B + (int64_t)gkb * g.ldb + gn);
+#pragma unroll
+        for (int c = 0; c < 4; c++) y[c] = v[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; c++) y[c] = gn + c < g.N && gkb < kend ? B[(int64_t)gkb * g.ldb + gn + c] : 0.0f;
+      }
     }
   };
   f32x4_t acc[2][2];
@@ -178,13 +277,16 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += kCK) {
 #pragma unroll
-    for (int u = 0; u < kPer; u++) {
+    for (int u = 0; u < kPer / 4; u++) {
       int mm, kk;
       a_mk(u, mm, kk);
-      As[mm * LD + kk] = (T)pa[u];
+      // along k the group's four values are adjacent in the LDS row
+#pragma unroll
+      for (int c = 0; c < 4; c++) As[TA ? (mm + c) * LD + kk : mm * LD + kk + c] = (T)pa[4 * u + c];
       int nn;
       b_nk(u, nn, kk);
-      Bs[nn * LD + kk] = (T)pb[u];
+#pragma unroll
+      for (int c = 0; c < 4; c++) Bs[TB ? nn * LD + kk + c : (nn + c) * LD + kk] = (T)pb[4 * u + c];
     }
     __syncthreads();
     if (k0 + kCK < kend) fetch(k0 + kCK);   // in flight during the products
@@ -222,9 +324,10 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   __builtin_amdgcn_sched_barrier(0);
   asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
   __builtin_amdgcn_sched_barrier(0);
-  // the tile through LDS, then one row of 64 consecutive outputs per wave
-  // and pass: the epilogue's loads and stores (the optimiser's weight and
-  // moments above all) move whole 256-byte rows
+  // the tile through LDS, then 4 consecutive outputs per thread, 16 threads
+  // per 64-wide row: the epilogue's loads and stores (the optimiser's weight
+  // and moments above all) move whole 256-byte rows, 16 bytes per thread
+  // where the layout allows
   float *Cs = reinterpret_cast<float *>(smem);
 #pragma unroll
   for (int i = 0; i < 2; i++)
@@ -233,10 +336,20 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
 #pragma unroll
       for (int c = 0; c < 4; c++) Cs[(wm + 16 * i + 4 * q + c) * (kBN + 1) + wn + 16 * j + r] = acc[i][j][c];
   __syncthreads();
-#pragma unroll 4
-  for (int e = tid; e < kBM * kBN; e += kGT) {
-    const int rl = e / kBN, cl = e % kBN, row = m0 + rl, col = n0 + cl;
-    if (row < M && col < g.N) epilogue<EPI>(g, slot, slice, row, col, Cs[rl * (kBN + 1) + cl]);
+#pragma unroll
+  for (int u = 0; u < kBM * kBN / (4 * kGT); u++) {
+    const int e = tid + kGT * u, rl = e >> 4, cl = (e & 15) * 4, row = m0 + rl, col = n0 + cl;
+    if (row >= M) continue;
+    float x[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) x[c] = Cs[rl * (kBN + 1) + cl + c];
+    if (g.vc && col + 3 < g.N) {
+      epilogue4<EPI>(g, slot, slice, row, col, x);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; c++)
+        if (col + c < g.N) epilogue<EPI>(g, slot, slice, row, col + c, x[c]);
+    }
   }
 }
 
@@ -290,6 +403,17 @@ hipError_t gemm(const TfShape &s, Gemm g, int nslots, hipStream_t st) {
   // the partial sums must fit the slot's buffer (sized from the shape, so
   // the choice still depends on the shape alone)
   g.split = split_for(g.M + g.aug, g.N, g.K, g.sPart);
+  auto al = [](const void *p, std::initializer_list<int64_t> strides) {
+    if (reinterpret_cast<uintptr_t>(p) % 16) return false;
+    for (int64_t x : strides)
+      if (x % 4) return false;
+    return true;
+  };
+  g.va = g.A && al(g.A, {g.lda, g.sA});
+  g.vb = al(g.B, {g.ldb, g.sB});
+  g.vc = al(g.C, {g.ldc, g.sC}) && (!g.bias || al(g.bias, {g.sBias})) && (!g.mask || al(g.mask, {g.ldm, g.sMask})) &&
+         (!g.m || (al(g.m, {g.sMV}) && g.v && al(g.v, {g.sMV}))) &&
+         (g.split == 1 || (al(g.part, {g.sPart}) && g.N % 4 == 0));
   return s.bf16 ? gemm_go<true, TA, TB, EPI>(g, nslots, st) : gemm_go<false, TA, TB, EPI>(g, nslots, st);
 }
 
@@ -327,31 +451,38 @@ __global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *s
   if (e == 0) tokstep[slot * sTok + rp] = (uint8_t)c;   // the embedding gradient's one-hot keys
 }
 
-// sum over the dh lanes of a head (aligned lane groups; every lane gets the
-// same value, the same order of operations)
-__device__ __forceinline__ float head_sum(float x, int dh) {
-  for (int o = 1; o < dh; o <<= 1) x += __shfl_xor(x, o, dh);
-  return x;
-}
-
 // Attention at the last position, one workgroup per (row, slot), one thread
 // per column x = h dh + d of the A-wide projections:
 // s_p = q_h . k_{p,h} / sqrt(dh), a = softmax(s), o_h = sum_p a_p v_{p,h}.
 // KV rows hold [k | v] (2A), Q rows q (A).  The probabilities a are kept
-// for the backward.
+// for the backward.  The row's keys pass through LDS pc positions at a time
+// (rows padded to A + 1), where one thread per (head, position) adds its
+// dh products in order; the softmax and the weighted sum of values are per
+// column.  LDS: scores [H][t], q [A], key chunk [pc][A + 1].
 __global__ void attn_fwd_kernel(TfShape s, const TfState *st, const float *Q, const float *KV, float *att,
-                                float *O, int64_t sQ, int64_t sKV, int64_t sAtt) {
+                                float *O, int64_t sQ, int64_t sKV, int64_t sAtt, int pc) {
   const int slot = blockIdx.y;
   if (slot >= st->nact) return;
-  extern __shared__ float sc[];   // [H][t]
-  const int row = blockIdx.x, x = threadIdx.x, h = x / s.dh, d = x % s.dh;
-  const int A = s.A, t = s.t;
-  const float scale = 1.0f / sqrtf((float)s.dh);
+  extern __shared__ float sm[];
+  const int A = s.A, t = s.t, H = s.H, dh = s.dh, LA = A + 1;
+  float *sc = sm, *qs = sc + H * t, *ks = qs + A;
+  const int row = blockIdx.x, x = threadIdx.x, h = x / dh, d = x % dh;
+  const float scale = 1.0f / sqrtf((float)dh);
   const float *kv = KV + slot * sKV + (int64_t)row * t * 2 * A;
-  const float qx = Q[slot * sQ + (int64_t)row * A + x];
-  for (int p = 0; p < t; p++) {
-    const float part = head_sum(qx * kv[(int64_t)p * 2 * A + x], s.dh);
-    if (d == 0) sc[h * t + p] = part * scale;
+  qs[x] = Q[slot * sQ + (int64_t)row * A + x];
+  for (int p0 = 0; p0 < t; p0 += pc) {
+    const int np = min(pc, t - p0);
+    __syncthreads();   // q written; the previous chunk read
+#pragma unroll 8
+    for (int p = 0; p < np; p++) ks[p * LA + x] = kv[(int64_t)(p0 + p) * 2 * A + x];
+    __syncthreads();
+    for (int u = x; u < H * np; u += A) {
+      const int hh = u / np, p = u - hh * np;
+      const float *qa = qs + hh * dh, *ka = ks + p * LA + hh * dh;
+      float acc = 0.0f;
+      for (int e = 0; e < dh; e++) acc += qa[e] * ka[e];
+      sc[hh * t + p0 + p] = acc * scale;
+    }
   }
   __syncthreads();
   const float *sh = sc + h * t;
@@ -361,7 +492,8 @@ __global__ void attn_fwd_kernel(TfShape s, const TfState *st, const float *Q, co
   for (int p = 0; p < t; p++) sum += __expf(sh[p] - mx);
   const float inv = 1.0f / sum;
   float o = 0.0f;
-  float *arow = att + slot * sAtt + ((int64_t)row * s.H + h) * t;
+  float *arow = att + slot * sAtt + ((int64_t)row * H + h) * t;
+#pragma unroll 8
   for (int p = 0; p < t; p++) {
     const float a = __expf(sh[p] - mx) * inv;
     o += a * kv[(int64_t)p * 2 * A + A + x];
@@ -372,36 +504,71 @@ __global__ void attn_fwd_kernel(TfShape s, const TfState *st, const float *Q, co
 
 // Backward of the attention: dv_p = a_p do, da_p = do . v_p,
 // ds_p = a_p (da_p - sum_r a_r da_r) / sqrt(dh), dq = sum_p ds_p k_p,
-// dk_p = ds_p q (per head).
+// dk_p = ds_p q (per head).  The values pass through LDS as the keys do in
+// the forward (da_p by one thread per (head, position)); LDS: da [H][t],
+// do [A], value chunk [pc][A + 1].
 __global__ void attn_bwd_kernel(TfShape s, const TfState *st, const float *Q, const float *KV, const float *att,
-                                const float *dO, float *dQ, float *dKV, int64_t sQ, int64_t sKV, int64_t sAtt) {
+                                const float *dO, float *dQ, float *dKV, int64_t sQ, int64_t sKV, int64_t sAtt, int pc) {
   const int slot = blockIdx.y;
   if (slot >= st->nact) return;
-  extern __shared__ float da[];   // [H][t]
-  const int row = blockIdx.x, x = threadIdx.x, h = x / s.dh, d = x % s.dh;
-  const int A = s.A, t = s.t;
-  const float scale = 1.0f / sqrtf((float)s.dh);
+  extern __shared__ float sm[];
+  const int A = s.A, t = s.t, H = s.H, dh = s.dh, LA = A + 1;
+  float *da = sm, *ds_ = da + H * t, *vs = ds_ + A;
+  const int row = blockIdx.x, x = threadIdx.x, h = x / dh;
+  const float scale = 1.0f / sqrtf((float)dh);
   const float *kv = KV + slot * sKV + (int64_t)row * t * 2 * A;
   float *dkv = dKV + slot * sKV + (int64_t)row * t * 2 * A;
-  const float *arow = att + slot * sAtt + ((int64_t)row * s.H + h) * t;
+  const float *arow = att + slot * sAtt + ((int64_t)row * H + h) * t;
   const float qx = Q[slot * sQ + (int64_t)row * A + x];
   const float dox = dO[slot * sQ + (int64_t)row * A + x];
-  for (int p = 0; p < t; p++) {
-    const float part = head_sum(dox * kv[(int64_t)p * 2 * A + A + x], s.dh);
-    if (d == 0) da[h * t + p] = part;
-    dkv[(int64_t)p * 2 * A + A + x] = arow[p] * dox;
+  ds_[x] = dox;
+  for (int p0 = 0; p0 < t; p0 += pc) {
+    const int np = min(pc, t - p0);
+    __syncthreads();
+#pragma unroll 8
+    for (int p = 0; p < np; p++) {
+      vs[p * LA + x] = kv[(int64_t)(p0 + p) * 2 * A + A + x];
+      dkv[(int64_t)(p0 + p) * 2 * A + A + x] = arow[p0 + p] * dox;
+    }
+    __syncthreads();
+    for (int u = x; u < H * np; u += A) {
+      const int hh = u / np, p = u - hh * np;
+      const float *oa = ds_ + hh * dh, *va = vs + p * LA + hh * dh;
+      float acc = 0.0f;
+      for (int e = 0; e < dh; e++) acc += oa[e] * va[e];
+      da[hh * t + p0 + p] = acc;
+    }
   }
   __syncthreads();
   const float *dh_ = da + h * t;
   float dot = 0.0f;
   for (int p = 0; p < t; p++) dot += arow[p] * dh_[p];
   float dq = 0.0f;
+#pragma unroll 8
   for (int p = 0; p < t; p++) {
     const float ds = arow[p] * (dh_[p] - dot) * scale;
     dq += ds * kv[(int64_t)p * 2 * A + x];
     dkv[(int64_t)p * 2 * A + x] = ds * qx;
   }
   dQ[slot * sQ + (int64_t)row * A + x] = dq;
+}
+
+// LDS of the attention kernels: H t scores, A of q (do), a chunk of pc
+// positions of keys (values) in rows of A + 1, pc as many as 36 KB holds
+int attn_chunk(const TfShape &s) { return std::max(1, std::min(s.t, 9216 / (s.A + 1))); }
+size_t attn_lds(const TfShape &s) {
+  return ((size_t)s.H * s.t + s.A + (size_t)attn_chunk(s) * (s.A + 1)) * sizeof(float);
+}
+hipError_t attn_allow_lds(const TfShape &s) {
+  static bool done = false;
+  if (done || attn_lds(s) <= 65536) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&attn_fwd_kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&attn_bwd_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  done = e == hipSuccess;
+  return e;
 }
 
 // Step bookkeeping (one thread): the step index, the active slots and, for
@@ -753,8 +920,9 @@ hipError_t forward(const Ctx &c, int *err) {
   g.bias = W + s.off_b[0];
   g.sBias = S;
   TRY((gemm<false, false, kStore>(s, g, c.n, c.st)));
-  hipLaunchKernelGGL(attn_fwd_kernel, dim3(bs, c.n), dim3(A), (size_t)s.H * t * sizeof(float), c.st, s, b.state,
-                     b.Q, b.KV, b.att, b.O, b.sQ, b.sKV, b.sAtt);
+  TRY(attn_allow_lds(s));
+  hipLaunchKernelGGL(attn_fwd_kernel, dim3(bs, c.n), dim3(A), attn_lds(s), c.st, s, b.state, b.Q, b.KV, b.att,
+                     b.O, b.sQ, b.sKV, b.sAtt, attn_chunk(s));
   TRY(hipGetLastError());
   struct L { const float *in; int64_t ldi, si; int K; int li; float *out; int N; int64_t so; int relu; };
   const L layers[4] = {{b.O, A, b.sQ, A, 1, b.Z, A, b.sQ, 0},
@@ -801,8 +969,9 @@ hipError_t backward(const Ctx &c) {
     g.aug = 1;
     TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
   }
-  hipLaunchKernelGGL(attn_bwd_kernel, dim3(bs, c.n), dim3(A), (size_t)s.H * t * sizeof(float), c.st, s, b.state,
-                     b.Q, b.KV, b.att, b.dO, b.dQ, b.dKV, b.sQ, b.sKV, b.sAtt);
+  TRY(attn_allow_lds(s));
+  hipLaunchKernelGGL(attn_bwd_kernel, dim3(bs, c.n), dim3(A), attn_lds(s), c.st, s, b.state, b.Q, b.KV, b.att,
+                     b.dO, b.dQ, b.dKV, b.sQ, b.sKV, b.sAtt, attn_chunk(s));
   TRY(hipGetLastError());
   // dX = dKV Wkv^T, then dX[row t + t - 1] += dQ Wq^T (before either weight changes)
   Gemm g = mk(c, b.dKV, 2 * A, b.sKV, W + s.off_W[0] + A, 3 * A, S, b.dX, E, b.sX, bs * t, E, 2 * A);
