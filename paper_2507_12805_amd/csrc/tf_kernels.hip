@@ -200,29 +200,31 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   T *Bs = As + kBM * LD;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 32, wn = (w >> 1) * 32, r = lane & 15, q = lane >> 4;
-  // a chunk's operands in groups of 4 elements along the index that is
-  // contiguous in memory (k for A / B^T stored row-major, m / n otherwise):
-  // group e = tid + 256 u (u < 4), 16 groups per 64-wide line; (mm, kk) is
-  // the group's first element.  In-bounds groups of an operand whose layout
-  // allows it are one 16-byte load, the others element by element
-  auto a_mk = [&](int u, int &mm, int &kk) {
+  // a chunk's operands, 16 elements of each per thread.  An operand stored
+  // with k contiguous (A, or B^T when TB) is read in groups of 4 along k:
+  // group e = tid + 256 u (u < 4), 16 groups per 64-wide line.  One stored
+  // transposed (A^T when TA, B otherwise) is read as one 4 x 4 sub-block
+  // per thread: 4 consecutive m (n) from 4 (tid % 16) at the 4 consecutive
+  // k from 4 (tid / 16), one 4-wide load per k, so that both go to LDS as
+  // runs of 4 along k.  In-bounds loads whose layout allows it are 16-byte
+  // loads, the others element by element.  pa / pb[4 u + c]: element c of
+  // group u, or of sub-block row k = 4 (tid / 16) + u.
+  auto kgroup = [&](int u, int &line, int &kk) {
     const int e = tid + kGT * u;
-    if (TA) { kk = e >> 4; mm = (e & 15) * 4; } else { mm = e >> 4; kk = (e & 15) * 4; }
+    line = e >> 4;
+    kk = (e & 15) * 4;
   };
-  auto b_nk = [&](int u, int &nn, int &kk) {
-    const int e = tid + kGT * u;
-    if (TB) { nn = e >> 4; kk = (e & 15) * 4; } else { kk = e >> 4; nn = (e & 15) * 4; }
-  };
+  const int sub_mn = (tid & 15) * 4, sub_k = (tid >> 4) * 4;
   typedef float f4 __attribute__((ext_vector_type(4)));
   float pa[kPer], pb[kPer];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < kPer / 4; u++) {
-      int mm, kk;
-      a_mk(u, mm, kk);
-      const int gm = m0 + mm, gk = k0 + kk;
       float *x = pa + 4 * u;
       if (!TA) {
+        int mm, kk;
+        kgroup(u, mm, kk);
+        const int gm = m0 + mm, gk = k0 + kk;
         if (g.va && gm < M && gk + 3 < kend) {
           const f4 v = *reinterpret_cast<const f4 *>(A + (int64_t)gm * g.lda + gk);
 #pragma unroll
@@ -231,41 +233,75 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
 #pragma unroll
           for (int c = 0; c < 4; c++) x[c] = gm < M && gk + c < kend ? A[(int64_t)gm * g.lda + gk + c] : 0.0f;
         }
-      } else if (oh || g.oh_mod) {
-        const int key = gk < kend ? (oh ? (int)oh[gk] : gk % g.oh_mod) : -1;
-#pragma unroll
-        for (int c = 0; c < 4; c++) x[c] = gm + c < M && key == gm + c ? 1.0f : 0.0f;
-      } else if (g.va && gk < kend && gm + 3 < g.M) {
-        const f4 v = *reinterpret_cast<const f4 *>(A + (int64_t)gk * g.lda + gm);
-#pragma unroll
-        for (int c = 0; c < 4; c++) x[c] = v[c];
       } else {
+        const int gm = m0 + sub_mn, gk = k0 + sub_k + u;
+        if (oh || g.oh_mod) {
+          const int key = gk < kend ? (oh ? (int)oh[gk] : gk % g.oh_mod) : -1;
 #pragma unroll
-        for (int c = 0; c < 4; c++) {
-          const int gmc = gm + c;
-          x[c] = gmc < M && gk < kend ? (gmc == g.M ? 1.0f : A[(int64_t)gk * g.lda + gmc]) : 0.0f;
+          for (int c = 0; c < 4; c++) x[c] = gm + c < M && key == gm + c ? 1.0f : 0.0f;
+        } else if (g.va && gk < kend && gm + 3 < g.M) {
+          const f4 v = *reinterpret_cast<const f4 *>(A + (int64_t)gk * g.lda + gm);
+#pragma unroll
+          for (int c = 0; c < 4; c++) x[c] = v[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; c++) {
+            const int gmc = gm + c;
+            x[c] = gmc < M && gk < kend ? (gmc == g.M ? 1.0f : A[(int64_t)gk * g.lda + gmc]) : 0.0f;
+          }
         }
       }
-      int nn, kb;
-      b_nk(u, nn, kb);
-      const int gn = n0 + nn, gkb = k0 + kb;
       float *y = pb + 4 * u;
       if (TB) {
-        if (g.vb && gn < g.N && gkb + 3 < kend) {
-          const f4 v = *reinterpret_cast<const f4 *>(B + (int64_t)gn * g.ldb + gkb);
+        int nn, kk;
+        kgroup(u, nn, kk);
+        const int gn = n0 + nn, gk = k0 + kk;
+        if (g.vb && gn < g.N && gk + 3 < kend) {
+          const f4 v = *reinterpret_cast<const f4 *>(B + (int64_t)gn * g.ldb + gk);
 #pragma unroll
           for (int c = 0; c < 4; c++) y[c] = v[c];
         } else {
 #pragma unroll
-          for (int c = 0; c < 4; c++) y[c] = gn < g.N && gkb + c < kend ? B[(int64_t)gn * g.ldb + gkb + c] : 0.0f;
+          for (int c = 0; c < 4; c++) y[c] = gn < g.N && gk + c < kend ? B[(int64_t)gn * g.ldb + gk + c] : 0.0f;
         }
-      } else if (g.vb && gkb < kend && gn + 3 < g.N) {
-        const f4 v = *reinterpret_cast<const f4 *>(B + (int64_t)gkb * g.ldb + gn);
-#pragma unroll
-        for (int c = 0; c < 4; c++) y[c] = v[c];
       } else {
+        const int gn = n0 + sub_mn, gk = k0 + sub_k + u;
+        if (g.vb && gk < kend && gn + 3 < g.N) {
+          const f4 v = *reinterpret_cast<const f4 *>(B + (int64_t)gk * g.ldb + gn);
 #pragma unroll
-        for (int c = 0; c < 4; c++) y[c] = gn + c < g.N && gkb < kend ? B[(int64_t)gkb * g.ldb + gn + c] : 0.0f;
+          for (int c = 0; c < 4; c++) y[c] = v[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; c++) y[c] = gn + c < g.N && gk < kend ? B[(int64_t)gk * g.ldb + gn + c] : 0.0f;
+        }
+      }
+    }
+  };
+  // one operand's 16 elements to LDS, row-major [m or n][k]: a group's 4
+  // values are adjacent along k; a sub-block's column c is the run of 4
+  // along k at row sub_mn + c (BF16: one 8-byte store per run)
+  auto stage = [&](T *S, const float *v, bool kcontig) {
+    if (kcontig) {
+#pragma unroll
+      for (int u = 0; u < kPer / 4; u++) {
+        int line, kk;
+        kgroup(u, line, kk);
+#pragma unroll
+        for (int c = 0; c < 4; c++) S[line * LD + kk + c] = (T)v[4 * u + c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        if constexpr (BF16) {
+          typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+          bf4 run;
+#pragma unroll
+          for (int u = 0; u < 4; u++) run[u] = (__bf16)v[4 * u + c];
+          *reinterpret_cast<bf4 *>(&S[(sub_mn + c) * LD + sub_k]) = run;
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; u++) S[(sub_mn + c) * LD + sub_k + u] = v[4 * u + c];
+        }
       }
     }
   };
@@ -276,18 +312,8 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
     for (int j = 0; j < 2; j++) acc[i][j] = f32x4_t{0.0f, 0.0f, 0.0f, 0.0f};
   if (kbeg < kend) fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += kCK) {
-#pragma unroll
-    for (int u = 0; u < kPer / 4; u++) {
-      int mm, kk;
-      a_mk(u, mm, kk);
-      // along k the group's four values are adjacent in the LDS row
-#pragma unroll
-      for (int c = 0; c < 4; c++) As[TA ? (mm + c) * LD + kk : mm * LD + kk + c] = (T)pa[4 * u + c];
-      int nn;
-      b_nk(u, nn, kk);
-#pragma unroll
-      for (int c = 0; c < 4; c++) Bs[TB ? nn * LD + kk + c : (nn + c) * LD + kk] = (T)pb[4 * u + c];
-    }
+    stage(As, pa, !TA);
+    stage(Bs, pb, TB);
     __syncthreads();
     if (k0 + kCK < kend) fetch(k0 + kCK);   // in flight during the products
     if constexpr (BF16) {
