@@ -42,7 +42,9 @@ KERNEL_SOURCES = ["paper_2507_12805_amd/csrc/step_mfma.h", "paper_2507_12805_amd
 PATH_KERNEL = {1: "step_kernel (FP32 per-thread FMA)", 2: "step_mfma_kernel (BF16 matrix cores, weights in global memory)",
                3: "step_mfma_kernel (FP32 matrix cores)", 4: "step_chip_kernel (BF16 matrix cores, network on chip)",
                5: "Transformer loop (gemm_kernel BF16 MFMA + attention + coder launches)",
-               6: "Transformer loop (gemm_kernel FP32 MFMA + attention + coder launches)"}
+               6: "Transformer loop (gemm_kernel FP32 MFMA + attention + coder launches)",
+               7: "MLP launch-sequence loop (gemm_kernel BF16 MFMA + coder launches)",
+               8: "MLP launch-sequence loop (gemm_kernel FP32 MFMA + coder launches)"}
 
 
 def kernel_source_hash() -> str:
@@ -133,6 +135,11 @@ def workload(name: str, scale: float = 1.0):
         static = None
         desc = ("tf32m: 32 MiB order-3 synthetic DNA, 16 equal blocks, (3,3)-mers, t=32, bs=320, the paper's "
                 "Transformer DM (embed 64, 8 heads of width 256, FFN 4096), Adam 1e-3")
+    elif name == "fourth4g":
+        rec, cfg = W.cfg4()
+        static = None
+        desc = ("fourth4g: 4 GiB order-3 synthetic DNA (5% repeats), 1024 equal blocks, (3,3)-mers, t=64, E=64, "
+                "hidden [256, 256], bs=128, Adam 1e-3")
     elif name == "small256k":
         rec, cfg = W.cfg1()
         static = None
@@ -232,7 +239,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive", "tf32m"])
+    ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive", "tf32m",
+                                                                "fourth4g"])
     ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp32_valu"])
     ap.add_argument("--no-fp32-compare", action="store_true",
@@ -344,7 +352,9 @@ def main():
     sub_cfg = {q: v for q, v in cfg.items() if q not in ("block_len", "file_blocks", "smp_ppm")}
     sub_cfg.update(block_len=lens[:kb], n_blocks=kb)
     sample_desc = f"blocks 0-{kb - 1} of {len(lens)} ({sub_n} bases), model passing off"
-    tf = cfg.get("arch") == "transformer"   # one launch sequence per step: no per-block launch form
+    # the launch-sequence loop (paths 5-8) runs every block's step in one
+    # sequence of launches: it has no per-block launch form
+    tf = cfg.get("arch") == "transformer" or (blob[5] in (5, 6, 7, 8) if blob else False)
     if kb and a.schedule == "batched" and not tf:
         cp = dict(sub_cfg, precision="fp32", schedule="plain")
         torch.cuda.synchronize()

@@ -159,7 +159,10 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg, uint64_t n, uint64_t 
  * in_dev: n bytes of ASCII A/C/G/T/N (N runs are stored aside; any other
  * byte gives PMKLC_ERR_INVALID_BASE). ws_dev: workspace of at least the
  * bound's ws_bytes. out_host: container, capacity out_cap; *out_len its
- * length. */
+ * length. With PMKLC_PROGRESS=<k> in the environment, the models run as a
+ * sequence of launches per step (the Transformer, the BiGRU static model,
+ * the MLPs too large for one CU) wait for the stream every k steps and
+ * print the step reached to stderr (pmklc_decompress too). */
 pmklc_status pmklc_compress(const pmklc_config *cfg, const uint8_t *in_dev, uint64_t n, void *ws_dev,
                             uint64_t ws_bytes, uint8_t *out_host, uint64_t out_cap, uint64_t *out_len,
                             void *stream);

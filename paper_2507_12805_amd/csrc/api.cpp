@@ -1045,6 +1045,7 @@ pmklc_status run_tf(const Model &m, const Work &w, int mode, const std::vector<B
   r.seg_bits = w.seg_bits;
   r.seg_words = w.seg_words;
   r.max_L = maxL;
+  if (const char *pg = getenv("PMKLC_PROGRESS")) r.progress = strtoull(pg, nullptr, 10);
   if (tm) {
     HIP_TRY(hipEventCreate(&tm->a));
     HIP_TRY(hipEventCreate(&tm->b));

@@ -91,6 +91,9 @@ struct TfRun {
   float *probe_P;
   float *params_out;
   uint64_t stop;                  // 0 = all steps
+  // > 0: every `progress` steps the host waits for the stream and prints
+  // the step reached to stderr (long runs report their own progress)
+  uint64_t progress;
 };
 // carves the per-slot buffers of n slots out of `base` (null: sizes only);
 // returns the floats used.  state, slots_desc, params, adam_m/v and init

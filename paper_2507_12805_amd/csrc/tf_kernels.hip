@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cmath>
 #include <type_traits>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -1280,6 +1281,12 @@ hipError_t tf_run(const TfShape &s, const TfBufs &b, const TfRun &r, hipStream_t
                        r.mode, probe, s.sarch == 1 ? b.lu : nullptr, b.params, b.adam_m, b.adam_v);
     TRY(hipGetLastError());
     if (i >= (uint64_t)s.t) TRY(s.arch == 1 ? backward<kUpdate>(c) : mlp_backward<kUpdate>(c));
+    if (r.progress && (i + 1) % r.progress == 0) {
+      TRY(hipStreamSynchronize(st));
+      fprintf(stderr, "[pmklc] %s: step %llu of %llu, %d blocks active\n", r.mode ? "decompress" : "compress",
+              (unsigned long long)(i + 1), (unsigned long long)steps, nact);
+      fflush(stderr);
+    }
   }
   if (r.mode == 0) {
     hipLaunchKernelGGL(coder_finish_kernel, dim3(r.n), dim3(256), 0, st, s, r.n, b.slots_desc,
