@@ -110,6 +110,8 @@ def _load():
     L.or_static_param_count.restype = ctypes.c_uint64
     L.or_static_init.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_uint64, _dp]
     L.or_static_forward.argtypes = [ctypes.POINTER(_Cfg), _dp, _u8p, ctypes.c_int, _dp]
+    L.or_static_step.argtypes = [ctypes.POINTER(_Cfg), _dp, _u8p, _u8p, ctypes.c_int, _dp, _dp,
+                                 ctypes.POINTER(ctypes.c_double)]
     L.or_free.argtypes = [ctypes.c_void_p]
     L.or_free.restype = None
     L.or_num_threads.restype = ctypes.c_int
@@ -349,6 +351,22 @@ def static_forward(cfg, ws, ctx) -> np.ndarray:
     _check(_load().or_static_forward(ctypes.byref(c), _ptr(ws, _dp), _ptr(ctx, _u8p), ctx.shape[0], _ptr(out, _dp)),
            "static_forward")
     return out
+
+
+def static_step(cfg, ws, ctx, tgt):
+    """(P [rows, V], gradient, loss) of one learning step of the static
+    model alone (its private-model training step)."""
+    c, keep = _mkcfg(cfg, 0)
+    ctx = np.ascontiguousarray(ctx, dtype=np.uint8)
+    tgt = np.ascontiguousarray(tgt, dtype=np.uint8)
+    ws = np.ascontiguousarray(ws, dtype=np.float64)
+    rows, V = ctx.shape[0], 4 ** cfg["k"]
+    P = np.zeros((rows, V), dtype=np.float64)
+    g = np.zeros(ws.size, dtype=np.float64)
+    loss = ctypes.c_double(0.0)
+    _check(_load().or_static_step(ctypes.byref(c), _ptr(ws, _dp), _ptr(ctx, _u8p), _ptr(tgt, _u8p), rows,
+                                  _ptr(P, _dp), _ptr(g, _dp), ctypes.byref(loss)), "static_step")
+    return P, g, loss.value
 
 
 def _static_arg(static):

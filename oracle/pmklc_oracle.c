@@ -657,6 +657,111 @@ static void gru_forward_row(const or_shape *sh, const double *w, const uint8_t *
     linear_fwd(dense, sh->gd, w + sh->off_lw, w + sh->off_lb, sh->V, logits);
 }
 
+/* Backward of the one-layer BiGRU static model for one row, given dlogits
+ * (used when the private static model has this shape and is trained on the
+ * input).  act is the row's forward (gru_forward_row): the layer's output
+ * sequence and the post-ReLU Dense output.  Back-propagation through time,
+ * written from the gate equations of gru_forward_row: for each direction,
+ * from its final state back to its first position, with the gates of a
+ * position recomputed from the stored states.  With s the pre-activations
+ * (a = W_i x + b_i, b = W_h h + b_h per gate row):
+ *   r = sig(a_r + b_r), z = sig(a_z + b_z), n = tanh(a_n + r b_n),
+ *   h' = (1 - z) n + z h;
+ *   dn = dh' (1 - z), dz = dh' (h - n), dh = dh' z (direct part);
+ *   dA_n = dn (1 - n^2), dA_r = dA_n b_n r (1 - r), dA_z = dz z (1 - z);
+ *   input rows (dA_r, dA_z, dA_n) -> dW_i += . x, db_i, dx += W_i^T .;
+ *   hidden rows (dA_r, dA_z, dA_n r) -> dW_h += . h, db_h, dh += W_h^T .;
+ * dx lands on the embedding row of the position's token. */
+static uint64_t gru_scratch_len(const or_shape *sh) {
+    return (uint64_t)sh->gd + 13ull * sh->gh + (uint64_t)sh->E + 8;
+}
+static void gru_backward_row(const or_shape *sh, const double *w, const uint8_t *ctx, const double *act,
+                             const double *dlogits, double *grad, double *scratch) {
+    int t = sh->t, E = sh->E, h = sh->gh, gd = sh->gd, V = sh->V;
+    const double *out = act, *dense = act + (uint64_t)t * 2 * h + 6ull * h;
+    double *dd = scratch, *dfeat = dd + gd, *ga = dfeat + 2 * h, *gb = ga + 3 * h, *gi = gb + 3 * h,
+           *dh = gi + 3 * h, *dx = dh + h;   /* gd + 12 h + E doubles */
+    double feat[512];
+    for (int u = 0; u < h; u++) {
+        feat[u] = out[(uint64_t)(t - 1) * 2 * h + u];
+        feat[h + u] = out[h + u];
+    }
+    /* head and Dense (ReLU) */
+    for (int o = 0; o < gd; o++) {
+        double sacc = 0.0;
+        for (int v = 0; v < V; v++) {
+            grad[sh->off_lw + (uint64_t)o * V + v] += dense[o] * dlogits[v];
+            sacc += w[sh->off_lw + (uint64_t)o * V + v] * dlogits[v];
+        }
+        dd[o] = dense[o] > 0.0 ? sacc : 0.0;
+    }
+    for (int v = 0; v < V; v++) grad[sh->off_lb + v] += dlogits[v];
+    for (int i = 0; i < 2 * h; i++) {
+        double sacc = 0.0;
+        for (int o = 0; o < gd; o++) {
+            grad[sh->off_dw + (uint64_t)i * gd + o] += feat[i] * dd[o];
+            sacc += w[sh->off_dw + (uint64_t)i * gd + o] * dd[o];
+        }
+        dfeat[i] = sacc;
+    }
+    for (int o = 0; o < gd; o++) grad[sh->off_db + o] += dd[o];
+    /* through time, each direction from its final state */
+    for (int d = 0; d < 2; d++) {
+        const double *Wih = w + sh->off_wih[0][d], *Whh = w + sh->off_whh[0][d];
+        const double *bih = w + sh->off_bih[0][d], *bhh = w + sh->off_bhh[0][d];
+        double *gWih = grad + sh->off_wih[0][d], *gWhh = grad + sh->off_whh[0][d];
+        double *gbih = grad + sh->off_bih[0][d], *gbhh = grad + sh->off_bhh[0][d];
+        for (int u = 0; u < h; u++) dh[u] = dfeat[d * h + u];
+        for (int step = t - 1; step >= 0; step--) {
+            int p = d == 0 ? step : t - 1 - step;
+            int pp = d == 0 ? p - 1 : p + 1;          /* the position processed before p */
+            const double *hp = step > 0 ? out + (uint64_t)pp * 2 * h + d * h : NULL;
+            const double *x = w + sh->off_emb + (uint64_t)ctx[p] * E;
+            for (int g = 0; g < 3 * h; g++) {
+                double a = bih[g], b = bhh[g];
+                for (int i = 0; i < E; i++) a += Wih[(uint64_t)g * E + i] * x[i];
+                if (hp)
+                    for (int i = 0; i < h; i++) b += Whh[(uint64_t)g * h + i] * hp[i];
+                ga[g] = a;
+                gb[g] = b;
+            }
+            for (int u = 0; u < h; u++) {
+                double r = sigmoid(ga[u] + gb[u]);
+                double z = sigmoid(ga[h + u] + gb[h + u]);
+                double nn = tanh(ga[2 * h + u] + r * gb[2 * h + u]);
+                double hprev = hp ? hp[u] : 0.0;
+                double dn = dh[u] * (1.0 - z), dz = dh[u] * (hprev - nn);
+                double dan = dn * (1.0 - nn * nn);
+                gi[u] = dan * gb[2 * h + u] * r * (1.0 - r);
+                gi[h + u] = dz * z * (1.0 - z);
+                gi[2 * h + u] = dan;
+                dh[u] = dh[u] * z;                     /* direct part of dh */
+                ga[u] = r;                             /* keep r for the hidden rows */
+            }
+            /* input rows */
+            for (int e = 0; e < E; e++) dx[e] = 0.0;
+            for (int g = 0; g < 3 * h; g++) {
+                gbih[g] += gi[g];
+                for (int i = 0; i < E; i++) {
+                    gWih[(uint64_t)g * E + i] += gi[g] * x[i];
+                    dx[i] += Wih[(uint64_t)g * E + i] * gi[g];
+                }
+            }
+            for (int e = 0; e < E; e++) grad[sh->off_emb + (uint64_t)ctx[p] * E + e] += dx[e];
+            /* hidden rows: (dA_r, dA_z, dA_n r) */
+            for (int g = 0; g < 3 * h; g++) {
+                double gh = g < 2 * h ? gi[g] : gi[g] * ga[g - 2 * h];
+                gbhh[g] += gh;
+                if (hp)
+                    for (int i = 0; i < h; i++) {
+                        gWhh[(uint64_t)g * h + i] += gh * hp[i];
+                        dh[i] += Whh[(uint64_t)g * h + i] * gh;
+                    }
+            }
+        }
+    }
+}
+
 static uint64_t acts_len(const or_shape *sh) {
     if (sh->arch == 2) return gru_act_len(sh);
     if (sh->arch == 1) return tf_act_len(sh);
@@ -724,7 +829,7 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
     uint64_t al = acts_len(sh), als = acts_len(ssh);
     uint64_t maxd = 0;
     for (int l = 0; l <= sh->nh + 1; l++) if ((uint64_t)sh->dims[l] > maxd) maxd = (uint64_t)sh->dims[l];
-    uint64_t scr = sh->arch == 1 ? tf_scratch_len(sh) : 2 * maxd;
+    uint64_t scr = sh->arch == 1 ? tf_scratch_len(sh) : sh->arch == 2 ? gru_scratch_len(sh) : 2 * maxd;
     double *acts = (double *)malloc(sizeof(double) * (al + als + 4 * (uint64_t)V + scr));
     if (!acts) return OR_ERR_NOMEM;
     double *acts_s = acts + al;
@@ -755,6 +860,7 @@ static int step_grad(const or_shape *sh, const double *w, const double *ws, doub
                 for (int v = 0; v < V; v++) dz[v] *= (1.0 - alpha);
             }
             if (sh->arch == 1) tf_backward_row(sh, w, c, acts, dz, grad, scratch);
+            else if (sh->arch == 2) gru_backward_row(sh, w, c, acts, dz, grad, scratch);
             else mlp_backward_row(sh, w, c, acts, dz, grad, scratch);
         }
     }
@@ -1091,9 +1197,10 @@ static int cfg_check(const or_config *c, or_shape *sh) {
     if ((c->selector & SEL_SPUM) && (c->selector & SEL_SPRM)) return OR_ERR_ARG;
     /* the Transformer DM runs without a static model */
     if (c->arch == 1 && (c->selector & (SEL_SPUM | SEL_SPRM))) return OR_ERR_ARG;
-    /* the BiGRU static model is the public one */
+    /* a BiGRU static model: the public one (1 or 2 layers), or the private
+     * one with one layer (Sec. 4.2.2 / 4.2.3) */
     if (c->static_arch < 0 || c->static_arch > 1) return OR_ERR_ARG;
-    if (c->static_arch == 1 && (c->selector & SEL_SPRM)) return OR_ERR_ARG;
+    if (c->static_arch == 1 && (c->selector & SEL_SPRM) && c->gru_layers != 1) return OR_ERR_ARG;
     if (c->smp_ppm > 1000000u) return OR_ERR_ARG;
     return shape_init(sh, c->k, c->t, c->E, c->nh, c->hidden, c->arch, c->arch == 1 ? c->heads : 0);
 }
@@ -1283,7 +1390,8 @@ static int process_blocks(const or_config *cfg, const or_shape *sh, const double
 /* Sec. 4.2.3 with stage (b) of the pipeline (Fig. 2): the static private
  * model is learned from the input itself before compression and stored in
  * the compressed file.  Reading (the paper fixes neither the training data
- * nor its length): the model has the dynamic model's shape; it starts from
+ * nor its length): the model has the static model's shape (the one-layer
+ * BiGRU of Sec. 4.2.2 when configured, else the dynamic model's); it starts from
  * the seeded initialisation under seed ^ SPRM_SEED_XOR and takes the
  * dynamic model's learning steps (Sec. 2 steps (2) and (4), its optimiser
  * and learning rate, no static model mixed in) over one training block of
@@ -1374,11 +1482,13 @@ int or_compress(const or_config *cfg_in, const uint8_t *in, uint64_t n, const fl
         }
     }
     if (!rc && private_on(cfg)) {
-        priv = (float *)malloc(sizeof(float) * (sh.n + 1));
-        rc = priv ? sprm_train(cfg, &sh, B, priv) : OR_ERR_NOMEM;
+        /* the private model has the static model's shape: the BiGRU one when
+         * configured, else the dynamic model's */
+        priv = (float *)malloc(sizeof(float) * (sn + 1));
+        rc = priv ? sprm_train(cfg, sh.ssh ? sh.ssh : &sh, B, priv) : OR_ERR_NOMEM;
         if (!rc) {
-            for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)priv[i];
-            scrc = or_crc32((const uint8_t *)priv, sh.n * 4);
+            for (uint64_t i = 0; i < sn; i++) ws[i] = (double)priv[i];
+            scrc = or_crc32((const uint8_t *)priv, sn * 4);
         }
     }
     if (!rc) rc = process_blocks(cfg, &sh, ws, B, 0, NULL);
@@ -1389,7 +1499,7 @@ int or_compress(const or_config *cfg_in, const uint8_t *in, uint64_t n, const fl
         if (cfg->file_blocks) for (int f = 0; f < cfg->n_files; f++) put_varint(&o, cfg->file_blocks[f]);
         else put_varint(&o, (uint64_t)nb);
         /* the private static model travels in the file (Sec. 4.2.3) */
-        if (priv) for (uint64_t i = 0; i < sh.n; i++) put_f32(&o, priv[i]);
+        if (priv) for (uint64_t i = 0; i < sn; i++) put_f32(&o, priv[i]);
         for (int b = 0; b < nb; b++) {
             or_block *k = &B[b];
             put_varint(&o, k->raw_len);
@@ -1478,14 +1588,14 @@ int or_decompress(const uint8_t *cbf, uint64_t len, const float *static_w, uint6
     double *ws = NULL;
     int rc = OR_OK;
     if (private_on(&c)) {
-        /* the stored private model: n FP32 values after the file table */
-        if (sh.n > (len - r.pos) / 4 || or_crc32(cbf + r.pos, sh.n * 4) != scrc) {
+        /* the stored private model: its FP32 values after the file table */
+        if (sn > (len - r.pos) / 4 || or_crc32(cbf + r.pos, sn * 4) != scrc) {
             free(fblocks); free(blen);
             return OR_ERR_CORRUPT;
         }
-        ws = (double *)malloc(sizeof(double) * sh.n);
+        ws = (double *)malloc(sizeof(double) * sn);
         if (!ws) { free(fblocks); free(blen); return OR_ERR_NOMEM; }
-        for (uint64_t i = 0; i < sh.n; i++) ws[i] = (double)get_f32(&r);
+        for (uint64_t i = 0; i < sn; i++) ws[i] = (double)get_f32(&r);
     } else if (static_on(&c)) {
         if (!static_w || static_len != sn || or_crc32((const uint8_t *)static_w, sn * 4) != scrc) {
             free(fblocks); free(blen);
@@ -1676,6 +1786,17 @@ int or_static_init(const void *cfg, uint64_t seed, double *w) {
     if (rc) return rc;
     init_params(&s, seed, w);
     return OR_OK;
+}
+/* One learning step of the static model as a standalone model (the private
+ * model's training step): P, the gradient of the mean cross-entropy of the
+ * rows' targets, the loss (Sec. 2 steps (3)-(4)). */
+int or_static_step(const void *cfg, const double *ws, const uint8_t *ctx, const uint8_t *tgt, int rows, double *P,
+                   double *grad, double *loss) {
+    or_shape s;
+    int rc = static_only_shape((const or_config *)cfg, &s);
+    if (rc) return rc;
+    if (s.arch == 2 && grad && s.gl != 1) return OR_ERR_ARG;   /* training: one BiGRU layer */
+    return step_grad(&s, ws, NULL, 0.0, ctx, tgt, rows, P, grad, NULL, loss);
 }
 int or_static_forward(const void *cfg, const double *ws, const uint8_t *ctx, int rows, double *logits) {
     or_shape s;

@@ -37,9 +37,17 @@ def parse(blob: bytes) -> dict:
     s, k, bs = h["s"], h["k"], h["bs"]
     private = None
     if h["selector"] & 2:
-        # the stored private static model: P FP32 values after the file table
-        dims = [h["t"] * h["E"]] + h["hidden"] + [4 ** k]
-        P = 4 ** k * h["E"] + sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
+        # the stored private static model: P FP32 values after the file table,
+        # in the BiGRU static model's shape (header byte 43) or the DM's
+        V = 4 ** k
+        if blob[43] & 15 == 1:
+            Es, gh, gl = blob[60], blob[61], blob[43] >> 4
+            gd, = struct.unpack_from("<H", blob, 62)
+            P = V * Es + sum(2 * (3 * gh * (Es if l == 0 else 2 * gh) + 3 * gh * gh + 6 * gh) for l in range(gl))
+            P += 2 * gh * gd + gd + gd * V + V
+        else:
+            dims = [h["t"] * h["E"]] + h["hidden"] + [V]
+            P = V * h["E"] + sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1))
         private = blob[pos:pos + 4 * P]
         assert len(private) == 4 * P
         pos += 4 * P
