@@ -71,7 +71,8 @@ enum { PMKLC_BATCHED = 0, PMKLC_PLAIN = 1 };      /* all blocks in one launch | 
  * PMKLC_FP32 (FP32 matrix cores) or PMKLC_BF16, for A / heads a power of two
  * <= 64, A <= 1024, E <= 1024, t <= 256, bs <= 1024, bs * t <= 65536. */
 enum { PMKLC_ARCH_MLP = 0, PMKLC_ARCH_TRANSFORMER = 1 };
-/* Static public model (Sec. 4.2.2). PMKLC_STATIC_MLP: the dynamic model's
+/* Static model (Sec. 4.2.2; the public one, or the private one of Sec.
+ * 4.2.3, which has the same shape). PMKLC_STATIC_MLP: the dynamic model's
  * own shape. PMKLC_STATIC_BIGRU: an embedding of static_embed (paper: 16),
  * gru_layers (1 or 2; paper: 2) bidirectional GRU layers of gru_hidden units
  * per direction (gates r, z, n with n = tanh(W_in x + b_in + r (W_hn h +
@@ -83,8 +84,12 @@ enum { PMKLC_ARCH_MLP = 0, PMKLC_ARCH_TRANSFORMER = 1 };
  * W_hh[3h][h], b_ih[3h], b_hh[3h]; Wd[2h][dense], bd; Wl[dense][V], bl.
  * Mixed by Eq. 1 with an MLP dynamic model on the launch-sequence loop
  * (numeric path 7 / 8); the recurrence runs in FP32 on both precisions.
- * gru_hidden <= 128, static_embed <= 256. The private model keeps the
- * dynamic model's shape (a BiGRU private model gives PMKLC_ERR_INVALID_ARG). */
+ * gru_hidden <= 128, static_embed <= 256. As the private model (selector
+ * SPRM|DM, or the Model Selector's choice above its bound) the BiGRU has one
+ * layer (paper: 1; gru_layers = 2 gives PMKLC_ERR_INVALID_ARG) and is trained
+ * on the input in FP32 before coding (the training block and steps of
+ * pmklc_config.selector's SPRM), for static_embed <= 32 and gru_hidden <= 64
+ * (else PMKLC_ERR_UNSUPPORTED); the container stores it in this layout. */
 enum { PMKLC_STATIC_MLP = 0, PMKLC_STATIC_BIGRU = 1 };
 /* Model selector S = {S0, S1, S2} of Sec. 4.2.1 as a bit mask. Accepted:
  * 0, DM, SPUM|DM, SPRM|DM (the selector enables one static model at most),
@@ -93,9 +98,10 @@ enum { PMKLC_STATIC_MLP = 0, PMKLC_STATIC_BIGRU = 1 };
  * SPRM (Sec. 4.2.3, stage (b) of Fig. 2): before coding, the call trains a
  * static private model on the input and stores it in the container (4 P
  * bytes of FP32 after the file table; the header's static CRC-32 covers
- * them). It has the dynamic model's shape, starts from the seeded
+ * them). It has the static model's shape (static_arch: the dynamic model's,
+ * or the one-layer BiGRU), starts from the seeded
  * initialisation under seed ^ 0x5350524D and takes the dynamic model's
- * learning steps (its optimiser and rate, no coding, no mixing) over one
+ * learning steps (its optimiser and rate, no mixing) over one
  * training block of bs segments of Lp = min(floor(l / bs), 8192) tokens,
  * segment j starting at token floor(j * l / bs) of the input's token
  * sequence (all blocks' tokens in block order, l in all). The coding pass
@@ -138,7 +144,7 @@ typedef struct pmklc_config {
   uint64_t ms_threshold;    /* PMKLC_SEL_AUTO's size bound in input bytes; 0 = 500 * 10^6 */
   uint32_t arch;            /* dynamic model: PMKLC_ARCH_MLP or PMKLC_ARCH_TRANSFORMER */
   uint32_t heads;           /* attention heads (PMKLC_ARCH_TRANSFORMER) */
-  uint32_t static_arch;     /* static public model: PMKLC_STATIC_MLP or PMKLC_STATIC_BIGRU */
+  uint32_t static_arch;     /* static model: PMKLC_STATIC_MLP or PMKLC_STATIC_BIGRU */
   uint32_t static_embed, gru_hidden, gru_layers, dense;   /* PMKLC_STATIC_BIGRU's widths */
 } pmklc_config;
 

@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmklc.so")
-SOURCES = ["step_kernel.hip", "step_mfma.hip", "step_chip.hip", "seq_kernels.hip", "dm_op.hip", "tf_kernels.hip",
+SOURCES = ["step_kernel.hip", "step_mfma.hip", "step_chip.hip", "seq_kernels.hip", "dm_op.hip", "tf_kernels.hip", "gru_train.hip",
            "api.cpp"]
 # the matrix-core step kernel's instances, one object per GEMM precision,
 # optimiser and workgroup width (compiled side by side)

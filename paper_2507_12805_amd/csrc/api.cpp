@@ -219,8 +219,10 @@ pmklc_status check_cfg(const pmklc_config *c) {
   if (c->arch > PMKLC_ARCH_TRANSFORMER) return PMKLC_ERR_INVALID_ARG;
   if (c->static_arch > PMKLC_STATIC_BIGRU) return PMKLC_ERR_INVALID_ARG;
   if (c->static_arch == PMKLC_STATIC_BIGRU) {
-    // the BiGRU model is the public one, mixed with the MLP dynamic model
-    if ((c->selector & PMKLC_SEL_SPRM) || c->arch != PMKLC_ARCH_MLP) return PMKLC_ERR_INVALID_ARG;
+    // the BiGRU model mixed with the MLP dynamic model: the public one (one
+    // or two layers), or the private one (one layer, trained on the input)
+    if (c->arch != PMKLC_ARCH_MLP) return PMKLC_ERR_INVALID_ARG;
+    if ((c->selector & PMKLC_SEL_SPRM) && c->gru_layers != 1) return PMKLC_ERR_INVALID_ARG;
     if (c->static_embed < 1 || c->gru_hidden < 1 || c->gru_layers < 1 || c->gru_layers > 2 || c->dense < 1 ||
         c->static_embed > 255 || c->gru_hidden > 255 || c->dense > 65535)
       return PMKLC_ERR_INVALID_ARG;
@@ -243,6 +245,14 @@ uint64_t param_count(uint32_t k, uint32_t t, uint32_t E, uint32_t nh, const uint
   for (uint32_t l = 0; l < nh; l++) { n += prev * hidden[l] + hidden[l]; prev = hidden[l]; }
   n += prev * V + V;
   return n;
+}
+
+// parameters of the BiGRU static model a configuration names
+uint64_t bigru_param_count(const pmklc_config &c) {
+  const uint64_t V = 1ull << (2 * c.k), E = c.static_embed, h = c.gru_hidden, gd = c.dense;
+  uint64_t n = V * E;
+  for (uint32_t l = 0; l < c.gru_layers; l++) n += 2 * (3 * h * (l == 0 ? E : 2 * h) + 3 * h * h + 6 * h);
+  return n + 2 * h * gd + gd + gd * V + V;
 }
 
 // Shape and parameter offsets of the model (no kernel-support checks).
@@ -440,15 +450,16 @@ pmklc_status make_tf_model(const pmklc_config *c, Model &m) {
 
 pmklc_status make_model(const pmklc_config *c, Model &m, bool allow_chip, int seq = -1) {
   if (c->arch == PMKLC_ARCH_TRANSFORMER && (c->selector & PMKLC_SEL_DM)) return make_tf_model(c, m);
-  if (c->static_arch == PMKLC_STATIC_BIGRU && (c->selector & PMKLC_SEL_DM) && (c->selector & PMKLC_SEL_SPUM)) {
+  if (c->static_arch == PMKLC_STATIC_BIGRU && (c->selector & PMKLC_SEL_DM) &&
+      (c->selector & (PMKLC_SEL_SPUM | PMKLC_SEL_SPRM))) {
     // the MLP on the launch-sequence loop, the BiGRU model beside it
-    if (c->selector & PMKLC_SEL_SPRM) return PMKLC_ERR_INVALID_ARG;
     pmklc_status rc = make_model(c->s, c->k, c->t, c->bs, c->embed, c->n_hidden, c->hidden, PMKLC_SEL_DM,
                                  c->optimizer, c->lr, c->beta1, c->beta2, c->eps, c->precision, m, false, 1);
     if (rc) return rc;
     if (c->schedule != PMKLC_BATCHED || c->smp_ppm > 0) return PMKLC_ERR_UNSUPPORTED;
     if (!bigru_shape((int)c->static_embed, (int)c->gru_hidden, (int)c->gru_layers, (int)c->dense, m.tf))
       return PMKLC_ERR_UNSUPPORTED;
+    if ((c->selector & PMKLC_SEL_SPRM) && !gru_train_supported(m.tf)) return PMKLC_ERR_UNSUPPORTED;
     return PMKLC_OK;
   }
   pmklc_status rc = make_model(c->s, c->k, c->t, c->bs, c->embed, c->arch == PMKLC_ARCH_TRANSFORMER ? 0 : c->n_hidden,
@@ -641,8 +652,25 @@ struct SprmRun {
   Model m;
   Work w;
   uint32_t Lp_max = 0;
+  // the BiGRU private model: its training block, scratch, Adam moments
+  bool gru = false;
+  uint8_t *gtok = nullptr;
+  float *gbuf = nullptr, *gm = nullptr, *gv = nullptr;
 };
-pmklc_status sprm_layout(Arena &A, const pmklc_config *c, uint64_t tokens_max, SprmRun &r) {
+pmklc_status sprm_layout(Arena &A, const pmklc_config *c, uint64_t tokens_max, SprmRun &r, const Model &cm) {
+  if (bigru_on(cm)) {
+    r.gru = true;
+    r.Lp_max = (uint32_t)std::min<uint64_t>(tokens_max / c->bs, kSprmSteps);
+    uint64_t ps;
+    int nwg;
+    r.gtok = A.take<uint8_t>((uint64_t)r.Lp_max * c->bs + 1);
+    r.gbuf = A.take<float>(gru_train_floats(cm.tf, ps, nwg));
+    if (c->optimizer == PMKLC_ADAM) {
+      r.gm = A.take<float>((uint64_t)cm.tf.sP);
+      r.gv = A.take<float>((uint64_t)cm.tf.sP);
+    }
+    return PMKLC_OK;
+  }
   pmklc_config cd = *c;
   cd.selector = PMKLC_SEL_DM;
   pmklc_status rc = make_model(&cd, r.m);
@@ -764,7 +792,7 @@ void write_header(Writer &o, const pmklc_config *c, uint8_t path, uint32_t scrc,
   o.le(c->selector, 1);
   o.le(c->arch, 1);
   o.le(c->arch == PMKLC_ARCH_TRANSFORMER ? c->heads : 0, 1);
-  const bool gru = c->static_arch == PMKLC_STATIC_BIGRU && (c->selector & PMKLC_SEL_SPUM);
+  const bool gru = c->static_arch == PMKLC_STATIC_BIGRU && (c->selector & (PMKLC_SEL_SPUM | PMKLC_SEL_SPRM));
   o.le(gru ? 1 | (c->gru_layers << 4) : 0, 1);
   o.le(c->smp_ppm, 4);
   o.le(c->seed, 8);
@@ -1118,6 +1146,8 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg_in, uint64_t n, uint64
   if (rc) return rc;
   const pmklc_config cr = ms_resolve(cfg_in, n);
   const pmklc_config *cfg = &cr;
+  rc = check_cfg(cfg);   // the selector's choice must be a valid configuration too
+  if (rc) return rc;
   Model m;
   rc = make_model(cfg, m);
   if (rc) return rc;
@@ -1144,9 +1174,9 @@ pmklc_status pmklc_compress_bound(const pmklc_config *cfg_in, uint64_t n, uint64
   layout(A, m, cfg->n_blocks, z, cfg->optimizer == PMKLC_ADAM, cfg->smp_ppm > 0, w);
   if (cfg->selector & PMKLC_SEL_SPRM) {
     SprmRun pr;
-    rc = sprm_layout(A, cfg, z.tokens, pr);
+    rc = sprm_layout(A, cfg, z.tokens, pr, m);
     if (rc) return rc;
-    meta += 4ull * m.d.P;
+    meta += 4ull * static_count(m);
   }
   if (max_out) *max_out = meta + z.staging;
   if (ws_bytes) *ws_bytes = A.used + 256;
@@ -1168,6 +1198,8 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   if (rc) return rc;
   const pmklc_config cr = ms_resolve(cfg_in, n);
   const pmklc_config *cfg = &cr;
+  rc = check_cfg(cfg);   // the selector's choice must be a valid configuration too
+  if (rc) return rc;
   const bool sprm = (cfg->selector & PMKLC_SEL_SPRM) != 0;
   if (!out_len || (n && !in_dev) || !ws_dev) return PMKLC_ERR_INVALID_ARG;
   Model m;
@@ -1206,7 +1238,7 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   layout(A, m, nblk, z, cfg->optimizer == PMKLC_ADAM, smp, w);
   SprmRun pr;
   if (sprm) {
-    rc = sprm_layout(A, cfg, z.tokens, pr);
+    rc = sprm_layout(A, cfg, z.tokens, pr, m);
     if (rc) return rc;
   }
   if (A.over) return PMKLC_ERR_BUFFER_TOO_SMALL;
@@ -1275,6 +1307,15 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
     // tokens, straight into the static-model slab of the coding pass
     const uint64_t Lp = std::min<uint64_t>(tok_total / bs, kSprmSteps);
     if (Lp > pr.Lp_max) return PMKLC_ERR_DEVICE;
+    if (pr.gru) {
+      // the one-layer BiGRU private model, trained in place in the static slab
+      HIP_TRY(gru_init_params(m.tf, cfg->seed ^ kSprmSeedXor, w.tf_stat, st));
+      if (Lp > 0) {
+        HIP_TRY(launch_sprm_gather(w.tok, tok_total, bs, (uint32_t)Lp, pr.gtok, st));
+        HIP_TRY(gru_train(m.tf, pr.gtok, Lp, w.tf_stat, pr.gbuf, pr.gm, pr.gv, st));
+      }
+      HIP_TRY(d2h(priv, w.tf_stat, (uint64_t)m.tf.sP, st));
+    } else {
     HIP_TRY(launch_init_params(pr.m.d, cfg->seed ^ kSprmSeedXor, pr.w.init, st));
     if (Lp > 0) {
       HIP_TRY(launch_sprm_gather(w.tok, tok_total, bs, (uint32_t)Lp, pr.w.tok, st));
@@ -1294,8 +1335,9 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
       HIP_TRY(hipMemcpyAsync(w.stat, pr.w.init, 4ull * m.d.P, hipMemcpyDeviceToDevice, st));
     }
     HIP_TRY(d2h(priv, w.stat, (uint64_t)m.d.P, st));
+    }
     HIP_TRY(hipStreamSynchronize(st));
-    scrc = crc32(priv.data(), 4ull * m.d.P);
+    scrc = crc32(priv.data(), 4ull * static_count(m));
   }
   count_work(m, bd, g_last);
   rc = is_tf(m.kind) ? run_tf(m, w, 0, bd, st, noalloc ? nullptr : &tm)
@@ -1316,7 +1358,7 @@ pmklc_status compress_impl(const pmklc_config *cfg_in, const uint8_t *in_dev, ui
   Writer meta{out_host, out_cap};
   write_header(meta, cfg, path_of(cfg->selector, m.kind), scrc, n, (uint32_t)p.file_blocks.size());
   for (uint64_t fb : p.file_blocks) meta.varint(fb);
-  if (sprm) meta.put(priv.data(), 4ull * m.d.P);   // the private model travels in the file
+  if (sprm) meta.put(priv.data(), 4ull * static_count(m));   // the private model travels in the file
   std::vector<uint64_t> seg_src, seg_dst;
   std::vector<uint32_t> seg_bytes;
   uint64_t stream_total = 0;
@@ -1472,7 +1514,9 @@ pmklc_status parse(const uint8_t *p, uint64_t len, Parsed &o, bool full) {
   c.n_files = nf;
   if (c.selector & PMKLC_SEL_SPRM) {
     // the private static model, checked against the header's CRC-32
-    const uint64_t P = param_count(c.k, c.t, c.embed, c.n_hidden, c.hidden, c.arch);
+    const uint64_t P = c.static_arch == PMKLC_STATIC_BIGRU
+                           ? bigru_param_count(c)
+                           : param_count(c.k, c.t, c.embed, c.n_hidden, c.hidden, c.arch);
     if (P > (len - r.pos) / 4 || crc32(p + r.pos, 4 * P) != o.scrc) return PMKLC_ERR_CORRUPT;
     o.private_off = r.pos;
     r.pos += 4 * P;

@@ -101,6 +101,17 @@ struct TfRun {
 uint64_t tf_bufs_carve(const TfShape &s, int n, float *base, TfBufs &b);
 hipError_t tf_run(const TfShape &s, const TfBufs &b, const TfRun &r, hipStream_t st);
 hipError_t tf_init_params(const TfShape &s, uint64_t seed, float *out, hipStream_t st);
+// The one-layer BiGRU static private model (gru_train.hip): its seeded
+// initialisation; whether the training kernels take the shape (embedding
+// <= 32, units per direction <= 64, one layer); the training scratch in
+// floats (part_stride, nwg: the per-workgroup partial gradients); the
+// training itself on the gathered block tok [bs][Lp], W updated in place
+// (adam_m / adam_v: sP floats each for Adam, else null).
+hipError_t gru_init_params(const TfShape &s, uint64_t seed, float *out, hipStream_t st);
+bool gru_train_supported(const TfShape &s);
+uint64_t gru_train_floats(const TfShape &s, uint64_t &part_stride, int &nwg);
+hipError_t gru_train(const TfShape &s, const uint8_t *tok, uint64_t Lp, float *W, float *buf, float *adam_m,
+                     float *adam_v, hipStream_t st);
 // the model as a differentiable op over `rows` contexts (one slot of bs = rows)
 hipError_t tf_forward_op(const TfShape &s, const TfBufs &b, const float *params, const uint8_t *ctx,
                          float *logits, hipStream_t st);

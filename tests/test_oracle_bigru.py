@@ -130,5 +130,5 @@ def test_container(orc):
             orc.decompress(blob, static=bad)
         assert e.value.code == -5
     with pytest.raises(orc.OracleError) as e:
-        orc.compress(dict(cfg, selector="sprm_dm"), a)       # the private model keeps the DM's shape
+        orc.compress(dict(cfg, selector="sprm_dm"), a)       # a BiGRU private model has one layer
     assert e.value.code == -1
