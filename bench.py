@@ -84,8 +84,14 @@ def flops_per_row(cfg: dict) -> int:
     dims = [cfg["t"] * cfg["E"]] + list(cfg["hidden"]) + [V]
     fwd = sum(2 * dims[i] * dims[i + 1] for i in range(len(dims) - 1))
     f = 3 * fwd
-    if cfg.get("selector") == "spum_dm":
-        f += fwd
+    if cfg.get("selector") in ("spum_dm", "sprm_dm"):
+        if cfg.get("static_arch") == "bigru":
+            # both directions' gates over the t positions per layer, Dense, head
+            E, h, gd, L = cfg["static_E"], cfg["gru_h"], cfg["dense"], cfg["gru_layers"]
+            f += sum(2 * cfg["t"] * 3 * h * ((E if l == 0 else 2 * h) + h) * 2 for l in range(L))
+            f += 2 * (2 * h * gd + gd * V)
+        else:
+            f += fwd
     return f
 
 
@@ -135,6 +141,12 @@ def workload(name: str, scale: float = 1.0):
         static = None
         desc = ("tf32m: 32 MiB order-3 synthetic DNA, 16 equal blocks, (3,3)-mers, t=32, bs=320, the paper's "
                 "Transformer DM (embed 64, 8 heads of width 256, FFN 4096), Adam 1e-3")
+    elif name == "bigru64":
+        rec, cfg = W.bigru_private()
+        static = None
+        desc = ("bigru64: the static64 input and dynamic model ((1,3)-mers, t=32, E=16, hidden [128], bs=64, "
+                "SGD 0.1) with the paper's one-layer BiGRU (embedding 16, 32 units per direction, Dense 128) as "
+                "the static private model, trained on the input (8192 steps) and mixed by Eq. 1")
     elif name == "fourth4g":
         rec, cfg = W.cfg4()
         static = None
@@ -240,7 +252,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive", "tf32m",
-                                                                "fourth4g"])
+                                                                "fourth4g", "bigru64"])
     ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp32_valu"])
     ap.add_argument("--no-fp32-compare", action="store_true",

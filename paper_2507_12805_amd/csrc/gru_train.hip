@@ -5,14 +5,15 @@
 // of bs segments of Lp tokens; steps t..Lp-1 each make one update from the
 // mean cross-entropy of the bs rows.  FP32 throughout.
 //
-// One learned step i is five launches on the caller's stream:
+// One learned step i is six launches on the caller's stream:
 //   gru_fwd_kernel    the recurrence of both directions per R rows (one
 //                     thread per (direction, gate row), as the inference
 //                     kernel), every position's state kept for the backward,
 //                     the Dense (ReLU) output and the logits;
 //   gru_loss_kernel   softmax and dL/dlogits = (P - onehot) / bs;
-//   gru_dense_kernel  the head and Dense layers' gradients and dL/dfeat
-//                     (one workgroup, sums over the rows in order);
+//   gru_du_kernel, gru_dgrad_kernel
+//                     the head and Dense layers' gradients and dL/dfeat
+//                     (one output per thread, sums over the rows in order);
 //   gru_bptt_kernel   back-propagation through time per R rows (one thread
 //                     per (direction, gate row), its weight-gradient rows in
 //                     registers; gates recomputed from the kept states; the
@@ -52,24 +53,32 @@ __device__ __forceinline__ int ctx_tok(const uint8_t *tok, uint64_t Lp, int i, i
 // the state after position p of each direction (forward half, backward
 // half); dn[row][gd] the post-ReLU Dense output; lg[row][V] the logits.
 // LDS: W_ih [2][G][E], W_hh [2][G][h], states [R][2][h], pre-activations
-// [R][2][G] twice.
+// [R][2][G] twice, the rows' context embeddings [R][t][E].
 __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *tok, uint64_t Lp, int i,
                                                       const float *W, float *seq, float *dn, float *lg, int R) {
   extern __shared__ float sm[];
   const int h = s.gh, G = 3 * h, t = s.t, E = s.sE, V = s.V, gd = s.gd;
   const int tid = threadIdx.x, d = tid / G, g = tid % G;
   const int row0 = blockIdx.x * R, rows = min(R, s.bs - row0);
-  float *wih = sm, *whh = wih + 2 * G * E, *hs = whh + 2 * G * h, *ga = hs + R * 2 * h, *gb = ga + R * 2 * G;
-  for (int q = tid; q < 2 * G * E; q += blockDim.x) wih[q] = W[s.s_wih[0][q / (G * E)] + q % (G * E)];
-  for (int q = tid; q < 2 * G * h; q += blockDim.x) whh[q] = W[s.s_whh[0][q / (G * h)] + q % (G * h)];
+  const int LE = E + 1, LH = h + 1;   // weight rows padded to an odd stride (no bank conflicts)
+  float *wih = sm, *whh = wih + 2 * G * LE, *hs = whh + 2 * G * LH, *ga = hs + R * 2 * h, *gb = ga + R * 2 * G,
+        *xs = gb + R * 2 * G;
+  for (int q = tid; q < 2 * G * E; q += blockDim.x)
+    wih[(q / E) * LE + q % E] = W[s.s_wih[0][q / (G * E)] + q % (G * E)];
+  for (int q = tid; q < 2 * G * h; q += blockDim.x)
+    whh[(q / h) * LH + q % h] = W[s.s_whh[0][q / (G * h)] + q % (G * h)];
   for (int q = tid; q < R * 2 * h; q += blockDim.x) hs[q] = 0.0f;
+  for (int q = tid; q < rows * t * E; q += blockDim.x) {
+    const int r = q / (t * E), p = (q / E) % t;
+    xs[q] = W[s.s_emb + (int64_t)ctx_tok(tok, Lp, i, t, row0 + r, p) * E + q % E];
+  }
   const float bi = W[s.s_bih[0][d] + g], bh = W[s.s_bhh[0][d] + g];
-  const float *wi = wih + (d * G + g) * E, *wh = whh + (d * G + g) * h;
+  const float *wi = wih + (d * G + g) * LE, *wh = whh + (d * G + g) * LH;
   __syncthreads();
   for (int step = 0; step < t; step++) {
     const int p = d == 0 ? step : t - 1 - step;
     for (int r = 0; r < rows; r++) {
-      const float *x = W + s.s_emb + (int64_t)ctx_tok(tok, Lp, i, t, row0 + r, p) * E;
+      const float *x = xs + (r * t + p) * E;
       float a = bi, b = bh;
       for (int k = 0; k < E; k++) a += wi[k] * x[k];
       const float *hp = hs + (r * 2 + d) * h;
@@ -97,6 +106,7 @@ __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *
     const int r = q / gd, o = q % gd;
     float a = W[s.s_db + o];
     const float *hr = hs + r * 2 * h;
+    #pragma unroll 8
     for (int k = 0; k < 2 * h; k++) a += hr[k] * W[s.s_dw + (int64_t)k * gd + o];
     dn[(int64_t)(row0 + r) * gd + o] = a > 0.0f ? a : 0.0f;
   }
@@ -105,6 +115,7 @@ __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *
     const int r = q / V, v = q % V;
     float a = W[s.s_lb + v];
     const float *dr = dn + (int64_t)(row0 + r) * gd;
+    #pragma unroll 8
     for (int o = 0; o < gd; o++) a += dr[o] * W[s.s_lw + (int64_t)o * V + v];
     lg[(int64_t)(row0 + r) * V + v] = a;
   }
@@ -125,47 +136,53 @@ __global__ __launch_bounds__(256) void gru_loss_kernel(TfShape s, const uint8_t 
   for (int v = 0; v < V; v++) z[v] = (__expf(z[v] - mx) * inv - (v == e ? 1.0f : 0.0f)) * scale;
 }
 
-// The head and Dense layers' backward (one workgroup): du = (dz Wl^T) * [dn >
-// 0]; gradients of Wl, bl, Wd, bd into gr (the parameter layout), dfeat = du
-// Wd^T.  Sums over rows run in row order.
-__global__ __launch_bounds__(1024) void gru_dense_kernel(TfShape s, const float *W, const float *seq, const float *dn,
-                                                        const float *dz, float *du, float *gr, float *dfeat) {
+// The head and Dense layers' backward, one output per thread: du = (dz
+// Wl^T) * [dn > 0]; then the gradients of Wl, bl, Wd, bd into gr (the
+// parameter layout) and dfeat = du Wd^T.  Sums over rows run in row order.
+__global__ __launch_bounds__(256) void gru_du_kernel(TfShape s, const float *W, const float *dn, const float *dz,
+                                                     float *du) {
+  const int V = s.V, gd = s.gd;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= s.bs * gd) return;
+  const int j = q / gd, o = q % gd;
+  float a = 0.0f;
+  #pragma unroll 8
+  for (int v = 0; v < V; v++) a += dz[(int64_t)j * V + v] * W[s.s_lw + (int64_t)o * V + v];
+  du[q] = dn[q] > 0.0f ? a : 0.0f;
+}
+__global__ __launch_bounds__(256) void gru_dgrad_kernel(TfShape s, const float *W, const float *seq, const float *dn,
+                                                        const float *dz, const float *du, float *gr, float *dfeat) {
   const int h = s.gh, t = s.t, V = s.V, gd = s.gd, bs = s.bs, F = 2 * h;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n_lw = gd * V, n_lb = V, n_dw = F * gd, n_db = gd, n_df = bs * F;
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_lw + n_lb + n_dw + n_db + n_df) return;
   auto feat = [&](int j, int k) {
     return k < h ? seq[((int64_t)j * t + t - 1) * F + k] : seq[((int64_t)j * t) * F + k];
   };
-  for (int q = tid; q < bs * gd; q += nt) {
-    const int j = q / gd, o = q % gd;
-    float a = 0.0f;
-    for (int v = 0; v < V; v++) a += dz[(int64_t)j * V + v] * W[s.s_lw + (int64_t)o * V + v];
-    du[q] = dn[q] > 0.0f ? a : 0.0f;
-  }
-  __syncthreads();
-  const int n_lw = gd * V, n_lb = V, n_dw = F * gd, n_db = gd, n_df = bs * F;
-  for (int q = tid; q < n_lw + n_lb + n_dw + n_db + n_df; q += nt) {
-    float a = 0.0f;
-    if (q < n_lw) {
-      const int o = q / V, v = q % V;
-      for (int j = 0; j < bs; j++) a += dn[(int64_t)j * gd + o] * dz[(int64_t)j * V + v];
-      gr[s.s_lw + q] = a;
-    } else if (q < n_lw + n_lb) {
-      const int v = q - n_lw;
-      for (int j = 0; j < bs; j++) a += dz[(int64_t)j * V + v];
-      gr[s.s_lb + v] = a;
-    } else if (q < n_lw + n_lb + n_dw) {
-      const int r = q - n_lw - n_lb, k = r / gd, o = r % gd;
-      for (int j = 0; j < bs; j++) a += feat(j, k) * du[(int64_t)j * gd + o];
-      gr[s.s_dw + r] = a;
-    } else if (q < n_lw + n_lb + n_dw + n_db) {
-      const int o = q - n_lw - n_lb - n_dw;
-      for (int j = 0; j < bs; j++) a += du[(int64_t)j * gd + o];
-      gr[s.s_db + o] = a;
-    } else {
-      const int r = q - n_lw - n_lb - n_dw - n_db, j = r / F, k = r % F;
-      for (int o = 0; o < gd; o++) a += du[(int64_t)j * gd + o] * W[s.s_dw + (int64_t)k * gd + o];
-      dfeat[r] = a;
-    }
+  float a = 0.0f;
+  if (q < n_lw) {
+    const int o = q / V, v = q % V;
+    #pragma unroll 8
+    for (int j = 0; j < bs; j++) a += dn[(int64_t)j * gd + o] * dz[(int64_t)j * V + v];
+    gr[s.s_lw + q] = a;
+  } else if (q < n_lw + n_lb) {
+    const int v = q - n_lw;
+    for (int j = 0; j < bs; j++) a += dz[(int64_t)j * V + v];
+    gr[s.s_lb + v] = a;
+  } else if (q < n_lw + n_lb + n_dw) {
+    const int r = q - n_lw - n_lb, k = r / gd, o = r % gd;
+    #pragma unroll 8
+    for (int j = 0; j < bs; j++) a += feat(j, k) * du[(int64_t)j * gd + o];
+    gr[s.s_dw + r] = a;
+  } else if (q < n_lw + n_lb + n_dw + n_db) {
+    const int o = q - n_lw - n_lb - n_dw;
+    for (int j = 0; j < bs; j++) a += du[(int64_t)j * gd + o];
+    gr[s.s_db + o] = a;
+  } else {
+    const int r = q - n_lw - n_lb - n_dw - n_db, j = r / F, k = r % F;
+    #pragma unroll 8
+    for (int o = 0; o < gd; o++) a += du[(int64_t)j * gd + o] * W[s.s_dw + (int64_t)k * gd + o];
+    dfeat[r] = a;
   }
 }
 
@@ -180,7 +197,8 @@ __global__ __launch_bounds__(1024) void gru_dense_kernel(TfShape s, const float 
 // gradient of the GRU tensors (their layout from s_wih[0][0]) and, after
 // them, of the embedding per direction [2][V][E].
 // LDS: W_ih [2][G][E], W_hh [2][G][h], pre-activations [R][2][G] twice,
-// input and hidden rows [R][2][G] twice, dh [R][2][h], embedding [2][V][E].
+// input and hidden rows [R][2][G] twice, dh [R][2][h], embedding [2][V][E],
+// the rows' context embeddings [R][t][E] and kept states [R][t][2h].
 __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t *tok, uint64_t Lp, int i,
                                                        const float *W, const float *seq, const float *dfeat,
                                                        float *part, int64_t part_stride, int R) {
@@ -188,17 +206,26 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
   const int h = s.gh, G = 3 * h, t = s.t, E = s.sE, V = s.V, F = 2 * h;
   const int tid = threadIdx.x, d = tid / G, g = tid % G;
   const int row0 = blockIdx.x * R, rows = min(R, s.bs - row0);
-  float *wih = sm, *whh = wih + 2 * G * E, *ga = whh + 2 * G * h, *gb = ga + R * 2 * G, *gi = gb + R * 2 * G,
-        *gh = gi + R * 2 * G, *dh = gh + R * 2 * G, *de = dh + R * 2 * h;
-  for (int q = tid; q < 2 * G * E; q += blockDim.x) wih[q] = W[s.s_wih[0][q / (G * E)] + q % (G * E)];
-  for (int q = tid; q < 2 * G * h; q += blockDim.x) whh[q] = W[s.s_whh[0][q / (G * h)] + q % (G * h)];
+  const int LE = E + 1, LH = h + 1;   // weight rows padded to an odd stride (no bank conflicts)
+  float *wih = sm, *whh = wih + 2 * G * LE, *ga = whh + 2 * G * LH, *gb = ga + R * 2 * G, *gi = gb + R * 2 * G,
+        *gh = gi + R * 2 * G, *dh = gh + R * 2 * G, *de = dh + R * 2 * h, *xs = de + 2 * V * E,
+        *hsq = xs + R * t * E;
+  for (int q = tid; q < 2 * G * E; q += blockDim.x)
+    wih[(q / E) * LE + q % E] = W[s.s_wih[0][q / (G * E)] + q % (G * E)];
+  for (int q = tid; q < 2 * G * h; q += blockDim.x)
+    whh[(q / h) * LH + q % h] = W[s.s_whh[0][q / (G * h)] + q % (G * h)];
   for (int q = tid; q < 2 * V * E; q += blockDim.x) de[q] = 0.0f;
+  for (int q = tid; q < rows * t * E; q += blockDim.x) {
+    const int r = q / (t * E), p = (q / E) % t;
+    xs[q] = W[s.s_emb + (int64_t)ctx_tok(tok, Lp, i, t, row0 + r, p) * E + q % E];
+  }
+  for (int q = tid; q < rows * t * F; q += blockDim.x) hsq[q] = seq[(int64_t)row0 * t * F + q];
   for (int q = tid; q < R * 2 * h; q += blockDim.x) {
     const int r = q / F, dd = (q / h) % 2, u = q % h;
     dh[q] = r < rows ? dfeat[(int64_t)(row0 + r) * F + dd * h + u] : 0.0f;
   }
   const float bi = W[s.s_bih[0][d] + g], bh = W[s.s_bhh[0][d] + g];
-  const float *wi = wih + (d * G + g) * E, *wh = whh + (d * G + g) * h;
+  const float *wi = wih + (d * G + g) * LE, *wh = whh + (d * G + g) * LH;
   float awi[kEmax], awh[kHmax], abi = 0.0f, abh = 0.0f;
 #pragma unroll
   for (int k = 0; k < kEmax; k++) awi[k] = 0.0f;
@@ -210,11 +237,11 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
     const int pp = d == 0 ? p - 1 : p + 1;    // the position processed before p (step > 0)
     // pre-activations of this position from the kept states
     for (int r = 0; r < rows; r++) {
-      const float *x = W + s.s_emb + (int64_t)ctx_tok(tok, Lp, i, t, row0 + r, p) * E;
+      const float *x = xs + (r * t + p) * E;
       float a = bi, b = bh;
       for (int k = 0; k < E; k++) a += wi[k] * x[k];
       if (step > 0) {
-        const float *hp = seq + ((int64_t)(row0 + r) * t + pp) * F + d * h;
+        const float *hp = hsq + (r * t + pp) * F + d * h;
         for (int k = 0; k < h; k++) b += wh[k] * hp[k];
       }
       ga[(r * 2 + d) * G + g] = a;
@@ -227,7 +254,7 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
         const float rg = sg(ga[o + g] + gb[o + g]);
         const float zg = sg(ga[o + h + g] + gb[o + h + g]);
         const float ng = th(ga[o + 2 * h + g] + rg * gb[o + 2 * h + g]);
-        const float hprev = step > 0 ? seq[((int64_t)(row0 + r) * t + pp) * F + d * h + g] : 0.0f;
+        const float hprev = step > 0 ? hsq[(r * t + pp) * F + d * h + g] : 0.0f;
         float *dhr = dh + (r * 2 + d) * h;
         const float dhu = dhr[g];
         const float dnn = dhu * (1.0f - zg), dzz = dhu * (hprev - ng);
@@ -246,7 +273,7 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
     for (int r = 0; r < rows; r++) {
       const int o = (r * 2 + d) * G;
       const int tk = ctx_tok(tok, Lp, i, t, row0 + r, p);
-      const float *x = W + s.s_emb + (int64_t)tk * E;
+      const float *x = xs + (r * t + p) * E;
       // this thread's gate row: weight and bias gradients
       const float vi = gi[o + g], vh = gh[o + g];
       abi += vi;
@@ -255,7 +282,7 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
       for (int k = 0; k < kEmax; k++)
         if (k < E) awi[k] += vi * x[k];
       if (step > 0) {
-        const float *hp = seq + ((int64_t)(row0 + r) * t + pp) * F + d * h;
+        const float *hp = hsq + (r * t + pp) * F + d * h;
 #pragma unroll
         for (int k = 0; k < kHmax; k++)
           if (k < h) awh[k] += vh * hp[k];
@@ -263,12 +290,12 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
       // dh of the previous position (unit g) and dx (component g) of this one
       if (g < h && step > 0) {
         float a = 0.0f;
-        for (int q = 0; q < G; q++) a += whh[(d * G + q) * h + g] * gh[o + q];
+        for (int q = 0; q < G; q++) a += whh[(d * G + q) * LH + g] * gh[o + q];
         dh[(r * 2 + d) * h + g] += a;
       }
       for (int e = g; e < E; e += G) {
         float a = 0.0f;
-        for (int q = 0; q < G; q++) a += wih[(d * G + q) * E + e] * gi[o + q];
+        for (int q = 0; q < G; q++) a += wih[(d * G + q) * LE + e] * gi[o + q];
         de[(d * V + tk) * E + e] += a;
       }
     }
@@ -317,14 +344,17 @@ __global__ __launch_bounds__(256) void gru_update_kernel(TfShape s, float *W, co
 // rows per workgroup and LDS bytes of the two recurrent kernels
 size_t fwd_lds(const TfShape &s, int R) {
   const int h = s.gh, G = 3 * h;
-  return ((size_t)2 * G * s.sE + 2 * G * h + (size_t)R * 2 * h + 2 * (size_t)R * 2 * G) * 4;
+  return ((size_t)2 * G * (s.sE + 1) + 2 * G * (h + 1) + (size_t)R * 2 * h + 2 * (size_t)R * 2 * G +
+          (size_t)R * s.t * s.sE) * 4;
 }
 size_t bptt_lds(const TfShape &s, int R) {
   const int h = s.gh, G = 3 * h;
-  return ((size_t)2 * G * s.sE + 2 * G * h + 4 * (size_t)R * 2 * G + (size_t)R * 2 * h + 2 * (size_t)s.V * s.sE) * 4;
+  return ((size_t)2 * G * (s.sE + 1) + 2 * G * (h + 1) + 4 * (size_t)R * 2 * G + (size_t)R * 2 * h +
+          2 * (size_t)s.V * s.sE +
+          (size_t)R * s.t * s.sE + (size_t)R * s.t * 2 * h) * 4;
 }
 int pick_rows(const TfShape &s, size_t (*lds)(const TfShape &, int)) {
-  for (int R = 4; R >= 1; R >>= 1)
+  for (int R = 2; R >= 1; R >>= 1)
     if (lds(s, R) <= 150 * 1024) return R;
   return 0;
 }
@@ -393,6 +423,8 @@ hipError_t gru_train(const TfShape &s, const uint8_t *tok, uint64_t Lp, float *W
   const int threads = 6 * s.gh;
   const int gfwd = (s.bs + Rf - 1) / Rf;
   const unsigned nup = (unsigned)((s.sP + 255) / 256);
+  const unsigned ngrad =
+      (unsigned)(((int64_t)s.gd * s.V + s.V + 2ll * s.gh * s.gd + s.gd + (int64_t)s.bs * 2 * s.gh + 255) / 256);
   uint64_t tau = 0;
   for (uint64_t i = (uint64_t)s.t; i < Lp; i++) {
     tau++;
@@ -402,7 +434,9 @@ hipError_t gru_train(const TfShape &s, const uint8_t *tok, uint64_t Lp, float *W
     hipLaunchKernelGGL(gru_fwd_kernel, dim3(gfwd), dim3(threads), fwd_lds(s, Rf), st, s, tok, Lp, (int)i, W, seq, dn,
                        lg, Rf);
     hipLaunchKernelGGL(gru_loss_kernel, dim3((s.bs + 255) / 256), dim3(256), 0, st, s, tok, Lp, (int)i, lg);
-    hipLaunchKernelGGL(gru_dense_kernel, dim3(1), dim3(1024), 0, st, s, W, seq, dn, lg, du, gr, dfeat);
+    hipLaunchKernelGGL(gru_du_kernel, dim3((unsigned)((s.bs * s.gd + 255) / 256)), dim3(256), 0, st, s, W, dn, lg,
+                       du);
+    hipLaunchKernelGGL(gru_dgrad_kernel, dim3(ngrad), dim3(256), 0, st, s, W, seq, dn, lg, du, gr, dfeat);
     hipLaunchKernelGGL(gru_bptt_kernel, dim3(nwg), dim3(threads), bptt_lds(s, Rb), st, s, tok, Lp, (int)i, W, seq,
                        dfeat, part, (int64_t)ps, Rb);
     hipLaunchKernelGGL(gru_update_kernel, dim3(nup), dim3(256), 0, st, s, W, gr, part, (int64_t)ps, nwg,

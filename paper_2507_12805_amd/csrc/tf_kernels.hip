@@ -763,10 +763,11 @@ __global__ __launch_bounds__(kCodeT) void code_kernel(TfShape s, const TfState *
   }
 }
 
-// The BiGRU static public model's logits for every row of a slot's step:
-// one workgroup per R rows, one thread per (direction, gate row); the
-// current layer's weights in LDS, the rows' hidden states, gate parts and
-// the first layer's output sequence beside them.  Per position the
+// The BiGRU static model's logits for every row of a slot's step: one
+// workgroup per R rows, one thread per (direction, gate row); the current
+// layer's weights in LDS, the rows' hidden states, gate parts, context
+// embeddings and (two layers) the first layer's output sequence beside
+// them.  Per position the
 // threads form the 3h input and hidden parts of their gate row for the R
 // rows, then h threads per direction combine them (r, z, n, h'); the two
 // directions run side by side.  FP32 throughout; every sum in order.
@@ -779,38 +780,47 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
   if (slot >= st->nact) return;
   extern __shared__ float sm[];
   const int h = s.gh, G = 3 * h, t = s.t, V = s.V, E = s.sE;
-  const int IN = E > 2 * h ? E : 2 * h;
+  const int IN = s.gl == 2 && 2 * h > E ? 2 * h : E;    // widest layer input
   const int tid = threadIdx.x, d = tid / G, g = tid % G;   // direction, gate row (blockDim = 2G)
   const int row0 = blockIdx.x * R, rows = min(R, s.bs - row0);
-  float *wih = sm;                              // [2][G][IN]
-  float *whh = wih + 2 * G * IN;                // [2][G][h]
-  float *hs = whh + 2 * G * h;                  // [R][2][h]
+  // weight rows padded to an odd stride: a thread reading its own row and
+  // lanes reading one column both hit distinct banks
+  const int LI = IN + 1, LH = h + 1;
+  float *wih = sm;                              // [2][G][IN + 1]
+  float *whh = wih + 2 * G * LI;                // [2][G][h + 1]
+  float *hs = whh + 2 * G * LH;                 // [R][2][h]
   float *ga = hs + R * 2 * h;                   // [R][2][G]
   float *gb = ga + R * 2 * G;                   // [R][2][G]
-  float *seq = gb + R * 2 * G;                  // [R][t][2h] first layer's outputs
-  float *dn = seq + R * t * 2 * h;              // [R][gd]
+  float *seq = gb + R * 2 * G;                  // [R][t][2h] first layer's outputs (two layers)
+  float *dn = seq + (s.gl == 2 ? R * t * 2 * h : 0);   // [R][gd]
+  float *xs = dn + R * s.gd;                    // [R][t][E] the rows' context embeddings
   const uint8_t *tk = tokstep + slot * sTok;
+  // the first layer's inputs, read once per step instead of once per position
+  for (int q = tid; q < rows * t * E; q += blockDim.x) {
+    const int r = q / (t * E), p = (q / E) % t;
+    xs[q] = W[s.s_emb + (int64_t)tk[(int64_t)(row0 + r) * t + p] * E + q % E];
+  }
   for (int l = 0; l < s.gl; l++) {
     const int in = l == 0 ? E : 2 * h;
     __syncthreads();
     for (int q = tid; q < 2 * G * in; q += blockDim.x) {
       const int dd = q / (G * in), rr = q % (G * in);
-      wih[dd * G * IN + (rr / in) * IN + rr % in] = W[s.s_wih[l][dd] + rr];
+      wih[dd * G * LI + (rr / in) * LI + rr % in] = W[s.s_wih[l][dd] + rr];
     }
     for (int q = tid; q < 2 * G * h; q += blockDim.x) {
       const int dd = q / (G * h), rr = q % (G * h);
-      whh[dd * G * h + rr] = W[s.s_whh[l][dd] + rr];
+      whh[dd * G * LH + (rr / h) * LH + rr % h] = W[s.s_whh[l][dd] + rr];
     }
     for (int q = tid; q < R * 2 * h; q += blockDim.x) hs[q] = 0.0f;
     const float bi = W[s.s_bih[l][d] + g], bh = W[s.s_bhh[l][d] + g];
-    const float *wi = wih + (d * G + g) * IN, *wh = whh + (d * G + g) * h;
+    const float *wi = wih + (d * G + g) * LI, *wh = whh + (d * G + g) * LH;
     __syncthreads();
     for (int step = 0; step < t; step++) {
       const int p = d == 0 ? step : t - 1 - step;
       for (int r = 0; r < rows; r++) {
         float a = bi, b = bh;
         if (l == 0) {
-          const float *x = W + s.s_emb + (int64_t)tk[(int64_t)(row0 + r) * t + p] * E;
+          const float *x = xs + (r * t + p) * E;
           for (int k = 0; k < E; k++) a += wi[k] * x[k];
         } else {
           const float *x = seq + (r * t + p) * 2 * h;
@@ -842,6 +852,7 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
     const int r = q / s.gd, o = q % s.gd;
     float a = W[s.s_db + o];
     const float *hr = hs + r * 2 * h;
+    #pragma unroll 8
     for (int k = 0; k < 2 * h; k++) a += hr[k] * W[s.s_dw + (int64_t)k * s.gd + o];
     dn[r * s.gd + o] = a > 0.0f ? a : 0.0f;
   }
@@ -850,16 +861,21 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
     const int r = q / V, v = q % V;
     float a = W[s.s_lb + v];
     const float *dr = dn + r * s.gd;
+    #pragma unroll 8
     for (int o = 0; o < s.gd; o++) a += dr[o] * W[s.s_lw + (int64_t)o * V + v];
     lu[slot * sLu + (int64_t)(row0 + r) * V + v] = a;
   }
 }
 
-// rows per workgroup of bigru_kernel and its LDS bytes (0: does not fit)
+// rows per workgroup of bigru_kernel and its LDS bytes (0: does not fit):
+// at most 2 rows, so that a step's grid holds bs / 2 workgroups per block
+// (the rows of a workgroup run one after another, and no value depends on
+// how they are grouped)
 int bigru_rows(const TfShape &s, size_t &bytes) {
-  const int h = s.gh, G = 3 * h, IN = s.sE > 2 * h ? s.sE : 2 * h;
-  for (int R = 8; R >= 1; R >>= 1) {
-    const size_t f = (size_t)2 * G * IN + 2 * G * h + R * 2 * h + 2 * R * 2 * G + (size_t)R * s.t * 2 * h + R * s.gd;
+  const int h = s.gh, G = 3 * h, IN = s.gl == 2 && 2 * h > s.sE ? 2 * h : s.sE;
+  for (int R = 2; R >= 1; R >>= 1) {
+    const size_t f = (size_t)2 * G * (IN + 1) + 2 * G * (h + 1) + R * 2 * h + 2 * R * 2 * G +
+                     (s.gl == 2 ? (size_t)R * s.t * 2 * h : 0) + R * s.gd + (size_t)R * s.t * s.sE;
     if (f * 4 <= 150 * 1024) {
       bytes = f * 4;
       return R;

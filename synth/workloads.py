@@ -38,6 +38,15 @@ def cfg2(n: int = 1 << 26, n_blocks: int = 16) -> tuple[Recipe, dict]:
     return recipe_cfg2(n=n), model_small(s=1, k=3, hidden=[128], selector="spum_dm", n_blocks=n_blocks, lr=CFG2_LR)
 
 
+def bigru_private(n: int = 1 << 26, n_blocks: int = 16) -> tuple[Recipe, dict]:
+    """The 64 MiB input and dynamic model of cfg2 with the paper's BiGRU as
+    the static private model (Sec. 4.2.2 widths, one layer: 16-d embedding,
+    32 units per direction, Dense 128), trained on the input before coding
+    and mixed by Eq. 1."""
+    return recipe_cfg2(n=n), model_small(s=1, k=3, hidden=[128], selector="sprm_dm", n_blocks=n_blocks, lr=CFG2_LR,
+                                         static_arch="bigru", static_E=16, gru_h=32, gru_layers=1, dense=128)
+
+
 def cfg2_static_pretrain(n: int = 1 << 20) -> tuple[Recipe, dict]:
     """The sequence and DM-only run whose final weights become the frozen
     static model of cfg2 (same shape as cfg2's DM)."""
