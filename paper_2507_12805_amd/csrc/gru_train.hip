@@ -80,8 +80,10 @@ __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *
     for (int r = 0; r < rows; r++) {
       const float *x = xs + (r * t + p) * E;
       float a = bi, b = bh;
+#pragma unroll 8
       for (int k = 0; k < E; k++) a += wi[k] * x[k];
       const float *hp = hs + (r * 2 + d) * h;
+#pragma unroll 8
       for (int k = 0; k < h; k++) b += wh[k] * hp[k];
       ga[(r * 2 + d) * G + g] = a;
       gb[(r * 2 + d) * G + g] = b;
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *
     const int r = q / gd, o = q % gd;
     float a = W[s.s_db + o];
     const float *hr = hs + r * 2 * h;
-    #pragma unroll 8
+#pragma unroll 8
     for (int k = 0; k < 2 * h; k++) a += hr[k] * W[s.s_dw + (int64_t)k * gd + o];
     dn[(int64_t)(row0 + r) * gd + o] = a > 0.0f ? a : 0.0f;
   }
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *
     const int r = q / V, v = q % V;
     float a = W[s.s_lb + v];
     const float *dr = dn + (int64_t)(row0 + r) * gd;
-    #pragma unroll 8
+#pragma unroll 8
     for (int o = 0; o < gd; o++) a += dr[o] * W[s.s_lw + (int64_t)o * V + v];
     lg[(int64_t)(row0 + r) * V + v] = a;
   }
@@ -146,7 +148,7 @@ __global__ __launch_bounds__(256) void gru_du_kernel(TfShape s, const float *W, 
   if (q >= s.bs * gd) return;
   const int j = q / gd, o = q % gd;
   float a = 0.0f;
-  #pragma unroll 8
+#pragma unroll 8
   for (int v = 0; v < V; v++) a += dz[(int64_t)j * V + v] * W[s.s_lw + (int64_t)o * V + v];
   du[q] = dn[q] > 0.0f ? a : 0.0f;
 }
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(256) void gru_dgrad_kernel(TfShape s, const float *
   float a = 0.0f;
   if (q < n_lw) {
     const int o = q / V, v = q % V;
-    #pragma unroll 8
+#pragma unroll 8
     for (int j = 0; j < bs; j++) a += dn[(int64_t)j * gd + o] * dz[(int64_t)j * V + v];
     gr[s.s_lw + q] = a;
   } else if (q < n_lw + n_lb) {
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(256) void gru_dgrad_kernel(TfShape s, const float *
     gr[s.s_lb + v] = a;
   } else if (q < n_lw + n_lb + n_dw) {
     const int r = q - n_lw - n_lb, k = r / gd, o = r % gd;
-    #pragma unroll 8
+#pragma unroll 8
     for (int j = 0; j < bs; j++) a += feat(j, k) * du[(int64_t)j * gd + o];
     gr[s.s_dw + r] = a;
   } else if (q < n_lw + n_lb + n_dw + n_db) {
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(256) void gru_dgrad_kernel(TfShape s, const float *
     gr[s.s_db + o] = a;
   } else {
     const int r = q - n_lw - n_lb - n_dw - n_db, j = r / F, k = r % F;
-    #pragma unroll 8
+#pragma unroll 8
     for (int o = 0; o < gd; o++) a += du[(int64_t)j * gd + o] * W[s.s_dw + (int64_t)k * gd + o];
     dfeat[r] = a;
   }
@@ -239,9 +241,11 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
     for (int r = 0; r < rows; r++) {
       const float *x = xs + (r * t + p) * E;
       float a = bi, b = bh;
+#pragma unroll 8
       for (int k = 0; k < E; k++) a += wi[k] * x[k];
       if (step > 0) {
         const float *hp = hsq + (r * t + pp) * F + d * h;
+#pragma unroll 8
         for (int k = 0; k < h; k++) b += wh[k] * hp[k];
       }
       ga[(r * 2 + d) * G + g] = a;
@@ -290,11 +294,13 @@ __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t 
       // dh of the previous position (unit g) and dx (component g) of this one
       if (g < h && step > 0) {
         float a = 0.0f;
+#pragma unroll 8
         for (int q = 0; q < G; q++) a += whh[(d * G + q) * LH + g] * gh[o + q];
         dh[(r * 2 + d) * h + g] += a;
       }
       for (int e = g; e < E; e += G) {
         float a = 0.0f;
+#pragma unroll 8
         for (int q = 0; q < G; q++) a += wih[(d * G + q) * LE + e] * gi[o + q];
         de[(d * V + tk) * E + e] += a;
       }

@@ -821,12 +821,15 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
         float a = bi, b = bh;
         if (l == 0) {
           const float *x = xs + (r * t + p) * E;
+#pragma unroll 8
           for (int k = 0; k < E; k++) a += wi[k] * x[k];
         } else {
           const float *x = seq + (r * t + p) * 2 * h;
+#pragma unroll 8
           for (int k = 0; k < 2 * h; k++) a += wi[k] * x[k];
         }
         const float *hp = hs + (r * 2 + d) * h;
+#pragma unroll 8
         for (int k = 0; k < h; k++) b += wh[k] * hp[k];
         ga[(r * 2 + d) * G + g] = a;
         gb[(r * 2 + d) * G + g] = b;
@@ -852,7 +855,7 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
     const int r = q / s.gd, o = q % s.gd;
     float a = W[s.s_db + o];
     const float *hr = hs + r * 2 * h;
-    #pragma unroll 8
+#pragma unroll 8
     for (int k = 0; k < 2 * h; k++) a += hr[k] * W[s.s_dw + (int64_t)k * s.gd + o];
     dn[r * s.gd + o] = a > 0.0f ? a : 0.0f;
   }
@@ -861,7 +864,7 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
     const int r = q / V, v = q % V;
     float a = W[s.s_lb + v];
     const float *dr = dn + r * s.gd;
-    #pragma unroll 8
+#pragma unroll 8
     for (int o = 0; o < s.gd; o++) a += dr[o] * W[s.s_lw + (int64_t)o * V + v];
     lu[slot * sLu + (int64_t)(row0 + r) * V + v] = a;
   }
