@@ -872,8 +872,8 @@ __global__ void bigru_kernel(TfShape s, const TfState *st, const float *W, const
 
 // rows per workgroup of bigru_kernel and its LDS bytes (0: does not fit):
 // at most 2 rows, so that a step's grid holds bs / 2 workgroups per block
-// (the rows of a workgroup run one after another, and no value depends on
-// how they are grouped)
+// (measured faster than 1 or 8 rows per workgroup; the rows of a workgroup
+// run one after another, and no value depends on how they are grouped)
 int bigru_rows(const TfShape &s, size_t &bytes) {
   const int h = s.gh, G = 3 * h, IN = s.gl == 2 && 2 * h > s.sE ? 2 * h : s.sE;
   for (int R = 2; R >= 1; R >>= 1) {
