@@ -116,9 +116,21 @@ def test_paper_widths(gpu, orc):
     assert abs(rel) <= 0.005
 
 
+@pytest.mark.parametrize("n", [20, 3 * 16 * 8 + 2])
+def test_short_inputs_store_the_initialisation(gpu, orc, n):
+    """Fewer tokens than bs, or fewer steps than t: the stored model is the
+    seeded initialisation, bit for bit as the oracle stores it."""
+    cfg = _cfg(n_blocks=1, block_len=None)
+    a = _dna(n, 45)
+    blob = gpu.compress(cfg, _cuda(a))
+    assert cbf.parse(blob)["private"] == cbf.parse(orc.compress(cfg, a))["private"]
+    assert np.array_equal(gpu.decompress(blob).cpu().numpy(), a)
+
+
 def test_errors(gpu):
     a = _dna(5000, 44)
-    for bad, code in [(dict(gru_layers=2), -1), (dict(static_E=40), -7), (dict(gru_h=70), -7)]:
+    for bad, code in [(dict(gru_layers=2), -1), (dict(static_E=40), -7), (dict(gru_h=70), -7),
+                      (dict(selector="auto", ms_threshold=1000, gru_layers=2), -1)]:
         with pytest.raises(gpu.PmklcError) as e:
             gpu.compress(_cfg(**bad), _cuda(a))
         assert e.value.code == code, bad

@@ -167,3 +167,17 @@ def test_container(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.compress(dict(cfg, gru_layers=2), a)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("n", [20, 3 * 8 * 5 + 2])
+def test_short_inputs_store_the_initialisation(orc, n):
+    """Fewer tokens than bs (no training block) or fewer steps than t (no
+    learned step): the stored model is the seeded initialisation."""
+    cfg = _cfg(k=3, s=3, t=5, bs=8, n_blocks=1)
+    a = synth.generate(synth.Recipe(n=n, order=2, seed=93))
+    blob = orc.compress(cfg, a)
+    stored = np.frombuffer(cbf.parse(blob)["private"], dtype=np.float32)
+    init = orc.static_init(cfg, cfg["seed"] ^ 0x5350524D).astype(np.float32)
+    assert np.array_equal(stored, init)
+    assert np.array_equal(orc.decompress(blob), a)
+
