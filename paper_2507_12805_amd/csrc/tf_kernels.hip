@@ -500,7 +500,7 @@ __global__ void attn_fwd_kernel(TfShape s, const TfState *st, const float *Q, co
   for (int p0 = 0; p0 < t; p0 += pc) {
     const int np = min(pc, t - p0);
     __syncthreads();   // q written; the previous chunk read
-#pragma unroll 8
+#pragma unroll 32
     for (int p = 0; p < np; p++) ks[p * LA + x] = kv[(int64_t)(p0 + p) * 2 * A + x];
     __syncthreads();
     for (int u = x; u < H * np; u += A) {
@@ -520,7 +520,7 @@ __global__ void attn_fwd_kernel(TfShape s, const TfState *st, const float *Q, co
   const float inv = 1.0f / sum;
   float o = 0.0f;
   float *arow = att + slot * sAtt + ((int64_t)row * H + h) * t;
-#pragma unroll 8
+#pragma unroll 32
   for (int p = 0; p < t; p++) {
     const float a = __expf(sh[p] - mx) * inv;
     o += a * kv[(int64_t)p * 2 * A + A + x];
@@ -552,7 +552,7 @@ __global__ void attn_bwd_kernel(TfShape s, const TfState *st, const float *Q, co
   for (int p0 = 0; p0 < t; p0 += pc) {
     const int np = min(pc, t - p0);
     __syncthreads();
-#pragma unroll 8
+#pragma unroll 32
     for (int p = 0; p < np; p++) {
       vs[p * LA + x] = kv[(int64_t)(p0 + p) * 2 * A + A + x];
       dkv[(int64_t)(p0 + p) * 2 * A + A + x] = arow[p0 + p] * dox;
@@ -571,7 +571,7 @@ __global__ void attn_bwd_kernel(TfShape s, const TfState *st, const float *Q, co
   float dot = 0.0f;
   for (int p = 0; p < t; p++) dot += arow[p] * dh_[p];
   float dq = 0.0f;
-#pragma unroll 8
+#pragma unroll 32
   for (int p = 0; p < t; p++) {
     const float ds = arow[p] * (dh_[p] - dot) * scale;
     dq += ds * kv[(int64_t)p * 2 * A + x];
