@@ -270,6 +270,9 @@ typedef struct pmklc_timing {
    * backward split into 8 input gradient, 9 output-layer update + embedding
    * scatter, 10 first-layer update). Zero otherwise. */
   uint64_t phase_ticks[12];
+  uint32_t f1_units;      /* hidden tiles per first-layer MFMA unit the autotuner chose for the
+                             global-weight matrix-core kernel (4 or 2); 0 for the other kernels */
+  uint32_t reserved;
 } pmklc_timing;
 pmklc_status pmklc_last_timing(pmklc_timing *t);
 

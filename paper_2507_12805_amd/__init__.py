@@ -51,7 +51,8 @@ class _Config(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_float), ("call_ms", ctypes.c_float), ("model_rows", ctypes.c_uint64),
                 ("coded_tokens", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("launches", ctypes.c_uint32),
-                ("threads", ctypes.c_uint32), ("wall_khz", ctypes.c_uint32), ("phase_ticks", ctypes.c_uint64 * 12)]
+                ("threads", ctypes.c_uint32), ("wall_khz", ctypes.c_uint32), ("phase_ticks", ctypes.c_uint64 * 12),
+                ("f1_units", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p

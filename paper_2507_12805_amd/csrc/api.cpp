@@ -196,6 +196,7 @@ struct Model {
   Dims d;
   LdsLayout lay;
   int nt;
+  int f1 = -1;   // the global-weight kernel's F1 unit (launch_step_mfma), chosen with nt
   int kind;
   TfShape tf;   // the Transformer DM's shape (is_tf(kind))
 };
@@ -686,14 +687,15 @@ pmklc_status sprm_layout(Arena &A, const pmklc_config *c, uint64_t tokens_max, S
 hipError_t launch_kind(const Model &m, const StepArgs &a, const StepArgs *a_dev, int grid, int nt, hipStream_t st) {
   if (m.kind == kGeneric) return launch_step(a, grid, nt, st);
   if (m.kind == kChipBf16) return launch_step_chip(a, a_dev, grid, st);
-  return launch_step_mfma(a, a_dev, grid, m.kind == kMfmaBf16, nt, st);
+  return launch_step_mfma(a, a_dev, grid, m.kind == kMfmaBf16, nt, m.f1, st);
 }
 
 // One synthetic block of t + 64 steps (constant tokens) in encode mode,
 // best of two runs, with the candidate width, in the trial region of the
 // caller's workspace (region: trial_bytes(m) bytes).
-hipError_t time_candidate(Model m, int nt, uint8_t *region, uint64_t cap, hipStream_t st, float *ms) {
+hipError_t time_candidate(Model m, int nt, int f1, uint8_t *region, uint64_t cap, hipStream_t st, float *ms) {
   m.nt = nt;
+  m.f1 = f1;
   const uint32_t L = (uint32_t)m.d.t + 64;
   const Sizes z = trial_sizes(m);
   Work w;
@@ -847,14 +849,17 @@ void fill_blockdesc(const Model &m, const std::vector<SeqBlock> &sb, const Plan 
 thread_local pmklc_timing g_last = {};
 
 // ------------------------------------------------------------- autotuner
-// Picks the threads per workgroup of the step kernel (4 or 8 waves) for a
-// model shape by timing a short synthetic block with each candidate, and
-// caches the choice for the process. The choice never changes a value:
+// Picks the step kernel's launch shape for a model shape by timing a short
+// synthetic block with each candidate, and caches the choice for the
+// process: the threads per workgroup (4 or 8 waves, which also fix the
+// fused B3/B4 chunking, HCH and TB) and, for the global-weight matrix-core
+// kernel with hidden widths in multiples of 64, the F1 unit (four or two
+// hidden tiles per gathered context fragment). No choice changes a value:
 // every output element is computed by one thread or wave in a fixed order
-// whatever the workgroup size. PMKLC_NT=256|512 forces a width.
+// whatever the launch shape. PMKLC_NT=256|512 and PMKLC_F1=4|2 force them.
 struct TuneEntry {
   int kind, bs, H0, H1, V, E, t, nh, stat, opt;
-  int nt;
+  int nt, f1;
 };
 std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
@@ -862,38 +867,52 @@ std::vector<TuneEntry> g_tune;
 // tune = false (the no-allocation entry point): no trial runs, which would
 // create timing events; the cached choice, else the widest candidate.
 int choose_nt(Model &m, const Work &w, hipStream_t st, bool tune = true) {
-  const char *env = getenv("PMKLC_NT");
-  std::vector<int> cands;
+  const char *env = getenv("PMKLC_NT"), *env_f1 = getenv("PMKLC_F1");
+  std::vector<int> nts;
   if (m.kind == kGeneric) {
-    cands = {256};
-    if (m.d.bs <= 512) cands.push_back(512);
+    nts = {256};
+    if (m.d.bs <= 512) nts.push_back(512);
   } else if (m.kind == kChipBf16) {
-    cands = {512};   // its register-resident weights are laid out for 8 waves
+    nts = {512};   // its register-resident weights are laid out for 8 waves
   } else {
-    cands = {256, 512};
+    nts = {256, 512};
   }
-  if (m.d.bs > 256) cands.erase(std::remove(cands.begin(), cands.end(), 256), cands.end());
+  if (m.d.bs > 256) nts.erase(std::remove(nts.begin(), nts.end(), 256), nts.end());
   if (env) {
-    int f = atoi(env);
-    if (std::find(cands.begin(), cands.end(), f) != cands.end()) return f;
+    const int f = atoi(env);
+    if (std::find(nts.begin(), nts.end(), f) != nts.end()) nts = {f};
   }
-  if (cands.size() == 1 || !m.d.model_on) return cands[0];
-  TuneEntry key{m.kind, m.d.bs, m.d.H[0], m.d.H[1], m.d.V, m.d.E, m.d.t, m.d.nh, m.d.static_on, m.d.optimizer, 0};
+  // the F1 unit: a choice only for the global-weight kernel at hidden widths
+  // in multiples of 64 (four hidden tiles per unit need them)
+  std::vector<int> f1s = {-1};
+  if ((m.kind == kMfmaBf16 || m.kind == kMfmaF32) && (m.d.H[0] / 16) % 4 == 0) {
+    f1s = {1, 0};
+    if (env_f1) f1s = {atoi(env_f1) == 2 ? 0 : 1};
+  }
+  m.f1 = f1s[0];
+  if ((nts.size() == 1 && f1s.size() == 1) || !m.d.model_on) return nts.back();
+  TuneEntry key{m.kind, m.d.bs, m.d.H[0], m.d.H[1], m.d.V, m.d.E, m.d.t, m.d.nh, m.d.static_on, m.d.optimizer, 0, 0};
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (const TuneEntry &e : g_tune)
     if (e.kind == key.kind && e.bs == key.bs && e.H0 == key.H0 && e.H1 == key.H1 && e.V == key.V && e.E == key.E &&
-        e.t == key.t && e.nh == key.nh && e.stat == key.stat && e.opt == key.opt)
+        e.t == key.t && e.nh == key.nh && e.stat == key.stat && e.opt == key.opt &&
+        std::find(nts.begin(), nts.end(), e.nt) != nts.end() && std::find(f1s.begin(), f1s.end(), e.f1) != f1s.end()) {
+      m.f1 = e.f1;
       return e.nt;
-  if (!tune) return cands.back();
-  int best = cands.back();
+    }
+  if (!tune) return nts.back();
+  int best = nts.back(), best_f1 = f1s[0];
   float best_ms = 1e30f;
-  for (int nt : cands) {
-    float ms = 0.0f;
-    if (time_candidate(m, nt, w.tune, w.tune_bytes, st, &ms) != hipSuccess) continue;
-    if (ms < best_ms) { best_ms = ms; best = nt; }
-  }
+  for (int nt : nts)
+    for (int f1 : f1s) {
+      float ms = 0.0f;
+      if (time_candidate(m, nt, f1, w.tune, w.tune_bytes, st, &ms) != hipSuccess) continue;
+      if (ms < best_ms) { best_ms = ms; best = nt; best_f1 = f1; }
+    }
   key.nt = best;
+  key.f1 = best_f1;
   g_tune.push_back(key);
+  m.f1 = best_f1;
   return best;
 }
 
@@ -938,6 +957,7 @@ pmklc_status run_step(Model m, const Work &w, int mode, const std::vector<BlockD
                       hipStream_t st, StepTimer *tm = nullptr, bool tune = true, float *params_out = nullptr) {
   m.nt = choose_nt(m, w, st, tune);
   g_last.threads = (uint32_t)m.nt;
+  g_last.f1_units = m.kind == kMfmaBf16 || m.kind == kMfmaF32 ? ((m.d.H[0] / 16) % 4 == 0 && m.f1 != 0 ? 4u : 2u) : 0u;
   StepArgs a;
   memset(&a, 0, sizeof a);
   a.d = m.d;

@@ -116,7 +116,11 @@ __host__ __device__ inline uint32_t w1_frag_index(int d, int h, int D) {
 hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStream_t st);
 
 hipError_t launch_step(const StepArgs &a, int grid, int nt, hipStream_t st);
-hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, hipStream_t st);
+// f1: the first layer's MFMA unit, 1 = four hidden tiles per unit (hidden
+// widths in multiples of 64), 0 = two, -1 = four where the width allows;
+// like nt it never changes a value
+hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, int f1,
+                            hipStream_t st);
 // the on-chip BF16 kernel: shapes compiled in, and its launch (512 threads)
 bool chip_supports(const Dims &d);
 hipError_t launch_step_chip(const StepArgs &a, const StepArgs *a_dev, int grid, hipStream_t st);

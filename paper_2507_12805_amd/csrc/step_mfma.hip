@@ -33,14 +33,15 @@ hipError_t launch_w1_frag(const float *W1, int D, int H, uint16_t *out, hipStrea
 
 // a_dev: a device copy of `a` (kernel arguments are read through it).
 // nt: 256 or 512 threads per workgroup; the choice never changes a value.
-hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, hipStream_t st) {
+hipError_t launch_step_mfma(const StepArgs &a, const StepArgs *a_dev, int grid, bool bf16, int nt, int f1,
+                            hipStream_t st) {
   // the BF16 kernel reads and writes W1 through its BF16 copies: refuse to
   // launch without them
   if (bf16 && (!a.w1f || (a.d.static_on && (!a.s1f || !a.stat)))) return hipErrorInvalidValue;
   const size_t lds = (size_t)a.lay.total;
   const int mt = a.d.bs / 16;
   const bool adam = a.d.optimizer == 1;
-  const bool f1_fours = (a.d.H[0] / 16) % 4 == 0;
+  const bool f1_fours = (a.d.H[0] / 16) % 4 == 0 && f1 != 0;
   if (nt != 256 && nt != 512) return hipErrorInvalidValue;
   const bool w = nt == 512;
   if (bf16) {

@@ -194,21 +194,33 @@ def test_plain_and_batched_schedules_give_identical_bytes(gpu):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp32_valu"])
-def test_autotuner_choices_give_identical_bytes(gpu, precision, monkeypatch):
-    """Every workgroup width the autotuner may pick yields the same container
-    (BF16: the global-weight kernel, which has two widths; the on-chip
-    kernel has one)."""
+@pytest.mark.parametrize("hidden", [32, 64])
+def test_autotuner_choices_give_identical_bytes(gpu, precision, hidden, monkeypatch):
+    """Every launch shape the autotuner may pick yields the same container:
+    both workgroup widths, and for the global-weight matrix-core kernel at
+    a hidden width of 64 both F1 units (four or two hidden tiles per unit);
+    the on-chip kernel has one shape."""
     monkeypatch.setenv("PMKLC_NO_CHIP", "1")
     a = _dna(60000, seed=21, n_rate=0.001)
-    cfg = model_small(n_blocks=3, precision=precision)
+    cfg = model_small(n_blocks=3, precision=precision, hidden=[hidden])
+    mfma = precision != "fp32_valu"
+    f1s = ["4", "2"] if mfma and hidden % 64 == 0 else [None]
     blobs = []
     for nt in ["256", "512"]:
-        monkeypatch.setenv("PMKLC_NT", nt)
-        blobs.append(gpu.compress(cfg, _cuda(a)))
-        assert gpu.last_timing()["threads"] == int(nt)
+        for f1 in f1s:
+            monkeypatch.setenv("PMKLC_NT", nt)
+            if f1:
+                monkeypatch.setenv("PMKLC_F1", f1)
+            blobs.append(gpu.compress(cfg, _cuda(a)))
+            tm = gpu.last_timing()
+            assert tm["threads"] == int(nt)
+            assert tm["f1_units"] == (int(f1) if f1 else (2 if mfma else 0))
     monkeypatch.delenv("PMKLC_NT")
-    blobs.append(gpu.compress(cfg, _cuda(a)))
-    assert blobs[0] == blobs[1] == blobs[2]
+    monkeypatch.delenv("PMKLC_F1", raising=False)
+    blobs.append(gpu.compress(cfg, _cuda(a)))          # the autotuner's own choice
+    print(f"{precision} hidden {hidden}: chose {gpu.last_timing()['threads']} threads, "
+          f"F1 units of {gpu.last_timing()['f1_units']}")
+    assert all(b == blobs[0] for b in blobs)
     assert np.array_equal(gpu.decompress(blobs[0]).cpu().numpy(), a)
 
 
