@@ -52,8 +52,9 @@ __device__ __forceinline__ int ctx_tok(const uint8_t *tok, uint64_t Lp, int i, i
 // Forward of the rows [row0, row0 + R) of step i.  seq[row][p][2h] receives
 // the state after position p of each direction (forward half, backward
 // half); dn[row][gd] the post-ReLU Dense output; lg[row][V] the logits.
-// LDS: W_ih [2][G][E], W_hh [2][G][h], states [R][2][h], pre-activations
-// [R][2][G] twice, the rows' context embeddings [R][t][E].
+// LDS: W_ih [2][G][E + 1], W_hh [2][G][h + 1] (rows padded), states
+// [R][2][h], pre-activations [R][2][G] twice, the rows' context embeddings
+// [R][t][E].
 __global__ __launch_bounds__(384) void gru_fwd_kernel(TfShape s, const uint8_t *tok, uint64_t Lp, int i,
                                                       const float *W, float *seq, float *dn, float *lg, int R) {
   extern __shared__ float sm[];
@@ -198,9 +199,10 @@ __global__ __launch_bounds__(256) void gru_dgrad_kernel(TfShape s, const float *
 // position's embedding row.  part[blockIdx.x] receives this workgroup's
 // gradient of the GRU tensors (their layout from s_wih[0][0]) and, after
 // them, of the embedding per direction [2][V][E].
-// LDS: W_ih [2][G][E], W_hh [2][G][h], pre-activations [R][2][G] twice,
-// input and hidden rows [R][2][G] twice, dh [R][2][h], embedding [2][V][E],
-// the rows' context embeddings [R][t][E] and kept states [R][t][2h].
+// LDS: W_ih [2][G][E + 1], W_hh [2][G][h + 1] (rows padded), pre-activations
+// [R][2][G] twice, input and hidden rows [R][2][G] twice, dh [R][2][h],
+// embedding [2][V][E], the rows' context embeddings [R][t][E] and kept
+// states [R][t][2h].
 __global__ __launch_bounds__(384) void gru_bptt_kernel(TfShape s, const uint8_t *tok, uint64_t Lp, int i,
                                                        const float *W, const float *seq, const float *dfeat,
                                                        float *part, int64_t part_stride, int R) {
