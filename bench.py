@@ -17,6 +17,14 @@ blocks, the container size against the FP64 oracle's on the whole input
 (tests/golden), ``roofline`` for the step kernel (the learning + coding
 loop, >99% of the time) from HIP-event timings, and ``cpu_baseline``, the
 FP64 oracle on a bounded sample of the same workload on the host cores.
+
+Other workloads (``--workload``): static64 (64 MiB, frozen static model
+mixed by Eq. 1), archive (the 64-file archive with model passing), tf32m
+(the paper's Transformer dynamic model on 32 MiB), fourth4g (4 GiB, 1024
+blocks, the 1.1 M-parameter Adam model on the launch-sequence loop),
+bigru64 (the static64 input with the paper's one-layer BiGRU as the
+private static model, trained on the input), small256k; ``--encoder``
+times the standalone GskE encoder instead.
 """
 import argparse
 import json
