@@ -177,9 +177,18 @@ constexpr int kPer = kBM * kCK / kGT;   // elements of each operand per thread a
 
 template <bool BF16, bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
-  const int slot = blockIdx.z / g.split, slice = blockIdx.z % g.split;
+  // XCD-aware tile order: workgroups are dealt to the 8 XCDs (each with its
+  // own L2) round robin by linear id; logical tile `tile` gives XCD k one
+  // contiguous range of tiles, so neighbouring tiles (the N tiles of one M
+  // row, which read the same A tile) share an L2.  A bijection of the grid:
+  // every tile is still computed once, the same way.
+  const uint32_t gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+  const uint32_t lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z), xcd = lin % 8, full = total / 8;
+  const uint32_t tile = xcd * full + min(xcd, total % 8) + lin / 8;
+  const int tz = (int)(tile / (gx * gy)), ty = (int)((tile / gx) % gy), tx = (int)(tile % gx);
+  const int slot = tz / g.split, slice = tz % g.split;
   if (slot >= g.st->nact) return;
-  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+  const int m0 = ty * kBM, n0 = tx * kBN;
   const int M = g.M + (TA ? g.aug : 0);
   const float *A = TA && (g.oh || g.oh_mod) ? nullptr : g.A + slot * g.sA;
   const uint8_t *oh = g.oh ? g.oh + slot * g.sOh : nullptr;
