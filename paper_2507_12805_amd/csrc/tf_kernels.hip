@@ -63,6 +63,13 @@ struct Gemm {
   const uint8_t *oh;
   int64_t sOh;
   int oh_mod;
+  // virtual X (the MLP's first-layer input, either layout; A is null): X[r][k]
+  // = emb[slot sEmb + key(r, k / xE) xE + k % xE], key = oh[slot sOh + r xt + k / xE]
+  // (the step's context tokens): the concatenated context embeddings,
+  // never written out
+  const float *emb;
+  int64_t sEmb;
+  int xE, xt;
   const TfState *st;
   int opt;
   float lr, b1, b2, eps;
@@ -190,8 +197,18 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
   if (slot >= g.st->nact) return;
   const int m0 = ty * kBM, n0 = tx * kBN;
   const int M = g.M + (TA ? g.aug : 0);
-  const float *A = TA && (g.oh || g.oh_mod) ? nullptr : g.A + slot * g.sA;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const float *A = g.emb || (TA && (g.oh || g.oh_mod)) ? nullptr : g.A + slot * g.sA;
+  const float *emb = g.emb ? g.emb + slot * g.sEmb : nullptr;
   const uint8_t *oh = g.oh ? g.oh + slot * g.sOh : nullptr;
+  // element (r, k) of the virtual X
+  auto xv = [&](int r, int k) -> float { return emb[(int)oh[(int64_t)r * g.xt + k / g.xE] * g.xE + k % g.xE]; };
+  // 4 of them along k (one embedding row: xE % 4 == 0 when g.va)
+  auto xv4 = [&](int r, int k, float *x) {
+    const f4 v = *reinterpret_cast<const f4 *>(emb + (int)oh[(int64_t)r * g.xt + k / g.xE] * g.xE + k % g.xE);
+#pragma unroll
+    for (int c = 0; c < 4; c++) x[c] = v[c];
+  };
   const float *B = g.B + slot * g.sB;
   int kbeg = 0, kend = g.K;
   if (g.split > 1) {
@@ -225,7 +242,6 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
     kk = (e & 15) * 4;
   };
   const int sub_mn = (tid & 15) * 4, sub_k = (tid >> 4) * 4;
-  typedef float f4 __attribute__((ext_vector_type(4)));
   float pa[kPer], pb[kPer];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -235,7 +251,14 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
         int mm, kk;
         kgroup(u, mm, kk);
         const int gm = m0 + mm, gk = k0 + kk;
-        if (g.va && gm < M && gk + 3 < kend) {
+        if (emb) {
+          if (g.va && gm < M && gk + 3 < kend) {
+            xv4(gm, gk, x);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; c++) x[c] = gm < M && gk + c < kend ? xv(gm, gk + c) : 0.0f;
+          }
+        } else if (g.va && gm < M && gk + 3 < kend) {
           const f4 v = *reinterpret_cast<const f4 *>(A + (int64_t)gm * g.lda + gk);
 #pragma unroll
           for (int c = 0; c < 4; c++) x[c] = v[c];
@@ -245,7 +268,17 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
         }
       } else {
         const int gm = m0 + sub_mn, gk = k0 + sub_k + u;
-        if (oh || g.oh_mod) {
+        if (emb) {
+          if (g.va && gk < kend && gm + 3 < g.M) {
+            xv4(gk, gm, x);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+              const int gmc = gm + c;
+              x[c] = gmc < M && gk < kend ? (gmc == g.M ? 1.0f : xv(gk, gmc)) : 0.0f;
+            }
+          }
+        } else if (oh || g.oh_mod) {
           const int key = gk < kend ? (oh ? (int)oh[gk] : gk % g.oh_mod) : -1;
 #pragma unroll
           for (int c = 0; c < 4; c++) x[c] = gm + c < M && key == gm + c ? 1.0f : 0.0f;
@@ -445,7 +478,7 @@ hipError_t gemm(const TfShape &s, Gemm g, int nslots, hipStream_t st) {
       if (x % 4) return false;
     return true;
   };
-  g.va = g.A && al(g.A, {g.lda, g.sA});
+  g.va = g.emb ? al(g.emb, {g.sEmb, g.xE}) : g.A && al(g.A, {g.lda, g.sA});
   g.vb = al(g.B, {g.ldb, g.sB});
   g.vc = al(g.C, {g.ldc, g.sC}) && (!g.bias || al(g.bias, {g.sBias})) && (!g.mask || al(g.mask, {g.ldm, g.sMask})) &&
          (!g.m || (al(g.m, {g.sMV}) && g.v && al(g.v, {g.sMV}))) &&
@@ -485,6 +518,24 @@ __global__ __launch_bounds__(256) void gather_kernel(TfShape s, const TfState *s
   const float pe = s.off_pos >= 0 ? W[s.off_pos + (int64_t)p * s.E + e] : 0.0f;   // the MLP has none
   X[slot * sX + q] = W[s.off_emb + (int64_t)c * s.E + e] + pe;
   if (e == 0) tokstep[slot * sTok + rp] = (uint8_t)c;   // the embedding gradient's one-hot keys
+}
+
+// the step's context tokens only (the MLP reads its X virtually):
+// tokstep[slot][row t + p]
+__global__ __launch_bounds__(256) void tokstep_kernel(TfShape s, const TfState *st, const TfSlot *desc,
+                                                      const uint8_t *toks, const uint8_t *ctx, uint8_t *tokstep,
+                                                      int64_t sTok, int *err) {
+  const int slot = blockIdx.y;
+  if (slot >= st->nact) return;
+  const int64_t rp = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (rp >= (int64_t)s.bs * s.t) return;
+  const int p = (int)(rp % s.t), row = (int)(rp / s.t);
+  int c = ctx_token(s, desc[slot], toks, ctx, st->i, row, p);
+  if (c >= s.V) {
+    atomicOr(err, 1);
+    c = 0;
+  }
+  tokstep[slot * sTok + rp] = (uint8_t)c;
 }
 
 // Attention at the last position, one workgroup per (row, slot), one thread
@@ -936,6 +987,19 @@ Gemm mk(const Ctx &c, const float *A, int64_t lda, int64_t sA, const float *B, i
 }
 // a weight-gradient product or column sum whose epilogue updates the
 // weight at parameter offset `off` (kUpdate) or stores its gradient (kGrad)
+// the MLP's first-layer input X read virtually from the embedding and the
+// step's context tokens (see Gemm::emb) instead of from a gathered copy
+void virtual_x(const Ctx &c, Gemm &g) {
+  g.A = nullptr;
+  g.sA = 0;
+  g.emb = c.W + c.s.off_emb;
+  g.sEmb = c.s.stride;
+  g.xE = c.s.E;
+  g.xt = c.s.t;
+  g.oh = c.b.tokstep;
+  g.sOh = c.b.sTok;
+}
+
 Gemm wgt(const Ctx &c, Gemm g, int64_t off) {
   if (c.gW) {
     g.C = c.gW + off;
@@ -1060,18 +1124,19 @@ hipError_t mlp_forward(const Ctx &c, int *err) {
   const int bs = s.bs, t = s.t, E = s.E;
   const int64_t S = s.stride;
   float *W = c.W;
-  const int64_t nx = (int64_t)bs * t * E;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((nx + 255) / 256), c.n), dim3(256), 0, c.st, s, b.state,
-                     b.slots_desc, c.toks, c.ctx, W, b.X, b.sX, b.tokstep, b.sTok, err);
+  const int64_t nrp = (int64_t)bs * t;
+  hipLaunchKernelGGL(tokstep_kernel, dim3((unsigned)((nrp + 255) / 256), c.n), dim3(256), 0, c.st, s, b.state,
+                     b.slots_desc, c.toks, c.ctx, b.tokstep, b.sTok, err);
   TRY(hipGetLastError());
   const int dims[4] = {t * E, s.H0, s.H1, s.V};
-  const float *in = b.X;
-  int64_t ldi = t * E, si = b.sX;
+  const float *in = nullptr;   // the first layer reads X virtually
+  int64_t ldi = t * E, si = 0;
   for (int l = 0; l <= s.nh; l++) {
     const int N = l == s.nh ? s.V : dims[l + 1];
     float *out = l == s.nh ? b.logits : b.act[l];
     const int64_t so = l == s.nh ? b.sLog : b.sAct[l];
     Gemm g = mk(c, in, ldi, si, W + s.off_W[l], N, S, out, N, so, bs, N, (int)ldi);
+    if (l == 0) virtual_x(c, g);
     g.bias = W + s.off_b[l];
     g.sBias = S;
     g.relu = l < s.nh;
@@ -1095,11 +1160,12 @@ hipError_t mlp_backward(const Ctx &c) {
     const int din_n = dims[l], N = l == s.nh ? V : dims[l + 1];
     const float *dout = l == s.nh ? b.logits : b.dact[l];
     const int64_t so = l == s.nh ? b.sLog : b.sAct[l];
-    const float *in = l == 0 ? b.X : b.act[l - 1];
-    const int64_t si = l == 0 ? b.sX : b.sAct[l - 1];
+    const float *in = l == 0 ? nullptr : b.act[l - 1];   // layer 0: X, read virtually
+    const int64_t si = l == 0 ? 0 : b.sAct[l - 1];
     float *din = l == 0 ? b.dX : b.dact[l - 1];
+    const int64_t sdin = l == 0 ? b.sX : b.sAct[l - 1];
     // din = dout W_l^T, masked by the ReLU that produced `in` (not for x)
-    Gemm g = mk(c, dout, N, so, W + s.off_W[l], N, S, din, din_n, si, bs, din_n, N);
+    Gemm g = mk(c, dout, N, so, W + s.off_W[l], N, S, din, din_n, sdin, bs, din_n, N);
     if (l > 0) {
       g.mask = in;
       g.ldm = din_n;
@@ -1108,6 +1174,7 @@ hipError_t mlp_backward(const Ctx &c) {
     TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
     // W_l and b_l: in^T dout with a ones row for the bias, which follows W_l
     g = wgt(c, mk(c, in, din_n, si, dout, N, so, nullptr, N, 0, din_n, N, bs), s.off_W[l]);
+    if (l == 0) virtual_x(c, g);
     g.aug = 1;
     TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
   }
