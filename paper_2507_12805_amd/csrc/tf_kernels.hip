@@ -1271,8 +1271,10 @@ uint64_t tf_bufs_carve(const TfShape &s, int n, float *base, TfBufs &b) {
   };
   int64_t dummy;
   if (s.arch == 0) {
-    b.X = take(bs * t * E, b.sX);
-    b.dX = take(bs * t * E, dummy);
+    // the MLP reads its X virtually (Gemm::emb): only dX is kept, and sX
+    // is its slot stride
+    b.X = nullptr;
+    b.dX = take(bs * t * E, b.sX);
     const int64_t hw[2] = {s.H0, s.H1};
     for (int l = 0; l < 2; l++) {
       b.act[l] = take(l < s.nh ? bs * hw[l] : 0, b.sAct[l]);
