@@ -405,8 +405,48 @@ __global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
 #pragma unroll
       for (int c = 0; c < 4; c++) Cs[(wm + 16 * i + 4 * q + c) * (kBN + 1) + wn + 16 * j + r] = acc[i][j][c];
   __syncthreads();
+  constexpr int kU = kBM * kBN / (4 * kGT);   // 4-column groups per thread
+  if constexpr (EPI == kUpdate) {
+    // Adam over a tile whose columns are all in range: every group's
+    // weight and moments are loaded before the first is updated, so a
+    // thread has 12 16-byte loads in flight instead of 3 (the stores of one
+    // group would otherwise order the next group's loads behind them).
+    // Each element is updated by the same operations as in epilogue4.
+    if (g.vc && g.m && n0 + kBN <= g.N) {
+      float *Cb = g.C + slot * g.sC, *Mb = g.m + slot * g.sMV, *Vb = g.v + slot * g.sMV;
+      f4 wt[kU], mm[kU], vv[kU];
 #pragma unroll
-  for (int u = 0; u < kBM * kBN / (4 * kGT); u++) {
+      for (int u = 0; u < kU; u++) {
+        const int e = tid + kGT * u, row = m0 + (e >> 4);
+        const int64_t at = (int64_t)row * g.ldc + n0 + (e & 15) * 4;
+        if (row < M) {
+          wt[u] = *reinterpret_cast<const f4 *>(Cb + at);
+          mm[u] = *reinterpret_cast<const f4 *>(Mb + at);
+          vv[u] = *reinterpret_cast<const f4 *>(Vb + at);
+        }
+      }
+      const Opt o = make_opt(g);
+#pragma unroll
+      for (int u = 0; u < kU; u++) {
+        const int e = tid + kGT * u, rl = e >> 4, cl = (e & 15) * 4, row = m0 + rl;
+        if (row >= M) continue;
+        const int64_t at = (int64_t)row * g.ldc + n0 + cl;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+          float mc = mm[u][c], vc = vv[u][c];
+          wt[u][c] -= opt_delta(o, Cs[rl * (kBN + 1) + cl + c], &mc, &vc);
+          mm[u][c] = mc;
+          vv[u][c] = vc;
+        }
+        *reinterpret_cast<f4 *>(Cb + at) = wt[u];
+        *reinterpret_cast<f4 *>(Mb + at) = mm[u];
+        *reinterpret_cast<f4 *>(Vb + at) = vv[u];
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kU; u++) {
     const int e = tid + kGT * u, rl = e >> 4, cl = (e & 15) * 4, row = m0 + rl, col = n0 + cl;
     if (row >= M) continue;
     float x[4];
