@@ -182,8 +182,11 @@ constexpr int kLdB = kCK + 8;           // BF16 LDS row (elements)
 constexpr int kLdF = kCK + 1;           // FP32 LDS row (elements)
 constexpr int kPer = kBM * kCK / kGT;   // elements of each operand per thread and chunk (16)
 
+// Compiled for at least 4 waves per SIMD: at most 128 registers per lane
+// (vector and accumulation together, no spills), so that four workgroups
+// share a CU and hide each other's memory latency on grids of many blocks.
 template <bool BF16, bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(kGT) void gemm_kernel(Gemm g) {
+__global__ __launch_bounds__(kGT, 4) void gemm_kernel(Gemm g) {
   // XCD-aware tile order: workgroups are dealt to the 8 XCDs (each with its
   // own L2) round robin by linear id; logical tile `tile` gives XCD k one
   // contiguous range of tiles, so neighbouring tiles (the N tiles of one M
