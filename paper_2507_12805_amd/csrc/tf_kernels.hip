@@ -76,6 +76,12 @@ struct Gemm {
   // 16-byte accesses allowed (base 16-byte aligned, every stride a multiple
   // of 4 floats): va / vb for the operands' loads, vc for the epilogue's
   int va, vb, vc;
+  // BF16 storage (element strides unchanged, the pointers reinterpreted):
+  // hc, kStore writes C rounded to BF16 (to nearest even, as the operand
+  // staging rounds); hb, the BF16 product reads B (not TB) from BF16.  A
+  // product that rounds its operands to BF16 anyway reads the same values
+  // from half the bytes.
+  int hb, hc;
 };
 
 __device__ __forceinline__ Opt make_opt(const Gemm &g) {
@@ -96,7 +102,10 @@ __device__ __forceinline__ void epilogue(const Gemm &g, int slot, int slice, int
     if (g.bias) x += g.bias[slot * g.sBias + col];
     if (g.relu) x = x > 0.0f ? x : 0.0f;
     if (g.mask && !(g.mask[slot * g.sMask + (int64_t)row * g.ldm + col] > 0.0f)) x = 0.0f;
-    g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
+    if (g.hc)
+      reinterpret_cast<__bf16 *>(g.C)[slot * g.sC + (int64_t)row * g.ldc + col] = (__bf16)x;
+    else
+      g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
   } else if constexpr (EPI == kGrad) {
     g.C[slot * g.sC + (int64_t)row * g.ldc + col] = x;
   } else if constexpr (EPI == kAccum) {
@@ -134,7 +143,15 @@ __device__ __forceinline__ void epilogue4(const Gemm &g, int slot, int slice, in
       for (int c = 0; c < 4; c++)
         if (!(k[c] > 0.0f)) y[c] = 0.0f;
     }
-    *reinterpret_cast<f4 *>(g.C + slot * g.sC + (int64_t)row * g.ldc + col) = y;
+    if (g.hc) {
+      typedef __bf16 h4 __attribute__((ext_vector_type(4)));
+      h4 z;
+#pragma unroll
+      for (int c = 0; c < 4; c++) z[c] = (__bf16)y[c];
+      *reinterpret_cast<h4 *>(reinterpret_cast<__bf16 *>(g.C) + slot * g.sC + (int64_t)row * g.ldc + col) = z;
+    } else {
+      *reinterpret_cast<f4 *>(g.C + slot * g.sC + (int64_t)row * g.ldc + col) = y;
+    }
   } else if constexpr (EPI == kGrad) {
     *reinterpret_cast<f4 *>(g.C + slot * g.sC + (int64_t)row * g.ldc + col) = y;
   } else if constexpr (EPI == kAccum) {
@@ -309,6 +326,18 @@ __global__ __launch_bounds__(kGT, 4) void gemm_kernel(Gemm g) {
         } else {
 #pragma unroll
           for (int c = 0; c < 4; c++) y[c] = gn < g.N && gk + c < kend ? B[(int64_t)gn * g.ldb + gk + c] : 0.0f;
+        }
+      } else if (BF16 && g.hb) {
+        const int gn = n0 + sub_mn, gk = k0 + sub_k + u;
+        const __bf16 *Bh = reinterpret_cast<const __bf16 *>(g.B) + slot * g.sB;
+        if (g.vb && gk < kend && gn + 3 < g.N) {
+          typedef __bf16 h4 __attribute__((ext_vector_type(4)));
+          const h4 v = *reinterpret_cast<const h4 *>(Bh + (int64_t)gk * g.ldb + gn);
+#pragma unroll
+          for (int c = 0; c < 4; c++) y[c] = (float)v[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; c++) y[c] = gn + c < g.N && gk < kend ? (float)Bh[(int64_t)gk * g.ldb + gn + c] : 0.0f;
         }
       } else {
         const int gn = n0 + sub_mn, gk = k0 + sub_k + u;
@@ -512,6 +541,7 @@ hipError_t gemm_go(Gemm g, int nslots, hipStream_t st) {
 // C[M x N] = op(A) op(B) (+ epilogue) over nslots batch entries
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(const TfShape &s, Gemm g, int nslots, hipStream_t st) {
+  if ((g.hb && (TB || !s.bf16)) || (g.hc && EPI != kStore)) return hipErrorInvalidValue;
   // the partial sums must fit the slot's buffer (sized from the shape, so
   // the choice still depends on the shape alone)
   g.split = split_for(g.M + g.aug, g.N, g.K, g.sPart);
@@ -1213,6 +1243,8 @@ hipError_t mlp_backward(const Ctx &c) {
       g.mask = in;
       g.ldm = din_n;
       g.sMask = si;
+    } else {
+      g.hc = s.bf16;   // dX: read only by the embedding product below
     }
     TRY((gemm<false, true, kStore>(s, g, c.n, c.st)));
     // W_l and b_l: in^T dout with a ones row for the bias, which follows W_l
@@ -1221,10 +1253,12 @@ hipError_t mlp_backward(const Ctx &c) {
     g.aug = 1;
     TRY((gemm<true, false, EPI>(s, g, c.n, c.st)));
   }
-  // dEmb = onehot(tokens)^T dX, dX viewed as [bs t][E]
+  // dEmb = onehot(tokens)^T dX, dX viewed as [bs t][E]; in BF16 it was
+  // stored rounded as this product would round it
   Gemm g = wgt(c, mk(c, nullptr, 0, 0, b.dX, E, b.sX, nullptr, E, 0, V, E, bs * t), s.off_emb);
   g.oh = b.tokstep;
   g.sOh = b.sTok;
+  g.hb = s.bf16;
   return gemm<true, false, EPI>(s, g, c.n, c.st);
 }
 
