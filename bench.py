@@ -156,9 +156,11 @@ def workload(name: str, scale: float = 1.0):
                 "SGD 0.1) with the paper's one-layer BiGRU (embedding 16, 32 units per direction, Dense 128) as "
                 "the static private model, trained on the input (8192 steps) and mixed by Eq. 1")
     elif name == "fourth4g":
-        rec, cfg = W.cfg4()
+        n = int((1 << 32) * scale) // 1024 * 1024
+        rec, cfg = W.cfg4(n=n)
         static = None
-        desc = ("fourth4g: 4 GiB order-3 synthetic DNA (5% repeats), 1024 equal blocks, (3,3)-mers, t=64, E=64, "
+        size = "4 GiB" if n == 1 << 32 else f"{n} bases of"
+        desc = (f"fourth4g: {size} order-3 synthetic DNA (5% repeats), 1024 equal blocks, (3,3)-mers, t=64, E=64, "
                 "hidden [256, 256], bs=128, Adam 1e-3")
     elif name == "small256k":
         rec, cfg = W.cfg1()
@@ -261,7 +263,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="uneven1g", choices=["static64", "small256k", "uneven1g", "archive", "tf32m",
                                                                 "fourth4g", "bigru64"])
-    ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive")
+    ap.add_argument("--scale", type=float, default=1.0, help="size scale for uneven1g / archive / fourth4g")
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp32_valu"])
     ap.add_argument("--no-fp32-compare", action="store_true",
                     help="skip the batched FP32 compress+decompress measured beside the main precision")
