@@ -1,7 +1,8 @@
 """The synthetic inputs against the recipe they are stated to follow (the
 stand-ins for the paper's genomes): alphabet and determinism, the order-m
 Markov rows (Dirichlet(0.5) draws from the recipe's seed, with and without
-the GC tilt), the share of the sequence covered by planted repeats, the N-run
+the GC tilt), the share of the sequence covered by planted repeats (forward and
+reverse-complemented), the N-run
 rate and lengths, the lognormal block lengths and the archive's ranges.
 Every expected value comes from the recipe's definition, not from the
 generator."""
@@ -71,6 +72,31 @@ def test_planted_repeats_cover_the_stated_share():
         _repeated_32mer_share(synth.generate(Recipe(**base)))
     expect = 0.05 * (275 - 31) / 275
     assert abs(extra - expect) <= 0.15 * expect, extra
+
+
+def _revcomp_32mer_share(a):
+    """Share of positions whose 32-mer's reverse complement occurred earlier."""
+    c = CODE[a].astype(np.uint64)
+    n = len(c) - 31
+    fwd = np.zeros(n, dtype=np.uint64)
+    rc = np.zeros(n, dtype=np.uint64)
+    for j in range(32):
+        fwd = (fwd << np.uint64(2)) | c[j:j + n]
+        rc = (rc << np.uint64(2)) | (np.uint64(3) - c[31 - j:31 - j + n])
+    uniq, first = np.unique(fwd, return_index=True)
+    at = np.minimum(np.searchsorted(uniq, rc), len(uniq) - 1)
+    return float(np.mean((uniq[at] == rc) & (first[at] < np.arange(n))))
+
+
+def test_reverse_complement_repeats():
+    """With p_rc = 1 every planted piece is the reverse complement of an
+    earlier one: the same 4.4% of positions, found through the reverse
+    complement and not as forward copies."""
+    base = dict(n=1 << 22, order=3, seed=14)
+    a0, a1 = synth.generate(Recipe(**base)), synth.generate(Recipe(**base, rho=0.05, p_revcomp=1.0))
+    expect = 0.05 * (275 - 31) / 275
+    assert abs(_revcomp_32mer_share(a1) - _revcomp_32mer_share(a0) - expect) <= 0.15 * expect
+    assert abs(_repeated_32mer_share(a1) - _repeated_32mer_share(a0)) <= 0.25 * expect
 
 
 def test_n_runs_rate_and_lengths():
